@@ -1,0 +1,157 @@
+/*
+ * pc.h - convolution-product expansions on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the convolution-product expansion of order m
+ * (introduction, eq. 1.4)
+ *
+ *     H_m u = sum_{k=1..m} h_k * (w_k . u)
+ *
+ * and its adjoint  H_m^* v = sum_k w_k . (h~_k * v),  h~_k[l] = h_k[-l],
+ * on periodic 1D signals of N samples and periodic 2D images of N1 x N2
+ * pixels (the extension of section 5.2).  "*" is the circular convolution of
+ * section 3.5, written 0-based:  (h * z)[i] = sum_j h[(i - j) mod N] z[j];
+ * in 2D the index pairs are taken modulo (N1, N2).  "." is the pointwise
+ * product.  Windows w_k and impulse responses h_k are real; h_k is given in
+ * lag layout (index 0 = zero lag, negative lags wrap to the end).  Results
+ * are computed in FP32 with the DFT identity of section 3.5; no
+ * normalisation is applied to h_k, the 1/N of the inverse transform is the
+ * only scale.
+ *
+ * Conventions for every call:
+ *   - every function returns a pc_status; nothing aborts or throws;
+ *   - PC_ERROR_* codes leave a thread-local message in pc_last_error();
+ *   - "device" pointers are HIP device memory on the plan's device,
+ *     "host" pointers are ordinary host memory;
+ *   - streams are hipStream_t values passed as void* (NULL = null stream);
+ *   - layouts are row-major and contiguous: a batch of 1D signals is
+ *     batch x N floats, a batch of images batch x N1 x N2 floats (N2
+ *     contiguous).
+ */
+#ifndef PC_H_
+#define PC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pc_plan_s* pc_plan;
+
+typedef enum {
+  PC_SUCCESS = 0,
+  PC_ERROR_INVALID_VALUE = 1, /* null pointer, bad count, aliasing, ... */
+  PC_ERROR_UNSUPPORTED = 2,   /* valid request this build has no kernel for */
+  PC_ERROR_OUT_OF_MEMORY = 3, /* device allocation failed */
+  PC_ERROR_HIP = 4,           /* a HIP runtime call failed (message has the HIP error) */
+  PC_ERROR_INVALID_PLAN = 5   /* null, destroyed or foreign plan handle */
+} pc_status;
+
+/* Window formats. */
+enum {
+  /* m dense windows: m x N floats (1D) or m x N1 x N2 floats (2D). */
+  PC_W_DENSE = 0,
+  /* 2D only: a tensor grid of separable windows
+   *   w_{k1*m_cols + k2}[n1, n2] = a_{k1}[n1] * b_{k2}[n2],
+   * with m = m_rows * m_cols.  The buffer holds the m_rows row-axis factors
+   * a (m_rows x N1 floats) followed by the m_cols column-axis factors b
+   * (m_cols x N2 floats). */
+  PC_W_SEPARABLE = 1
+};
+
+typedef struct {
+  int32_t ndim;     /* 1 or 2 */
+  int32_t m;        /* number of terms, >= 1 */
+  int64_t n0;       /* 1D: N; 2D: N1 (rows) */
+  int64_t n1;       /* 1D: must be 1; 2D: N2 (columns, contiguous) */
+  int64_t batch;    /* largest number of signals / images per apply call, >= 1 */
+  int32_t w_format; /* PC_W_DENSE or PC_W_SEPARABLE */
+  int32_t m_rows;   /* separable only: number of row-axis factors */
+  int32_t m_cols;   /* separable only: number of column-axis factors */
+  uint32_t flags;   /* reserved, must be 0 */
+} pc_plan_desc;
+
+/* Supported sizes.
+ *   1D:  N in {2^a, 3*2^a : 64 <= N <= 8192} (one workgroup per transform)
+ *        or N = R*L with L in {8192, 6144} and R in {2, 4, 8, 16}
+ *        (16384 ... 131072; four-step split).
+ *   2D:  N1, N2 in {2^a, 3*2^a : 64 <= N <= 8192}.
+ * Other sizes return PC_ERROR_UNSUPPORTED. */
+
+/*
+ * pc_plan_create - build the operator H_m of eq. 1.4 on one device.
+ *
+ *   out      (out) receives the plan handle; set to NULL on failure.
+ *   desc     (host) sizes, term count, batch capacity and window format.
+ *   windows  (host) the windows w_k in the layout given by desc->w_format.
+ *   h        (host) the impulse responses h_k, lag layout: m x N floats
+ *            (1D) or m x N1 x N2 floats (2D).
+ *   stream   stream used for the plan-time work (the spectra F^* h_k of
+ *            section 3.5, computed on the device).
+ *
+ * The call is synchronous: it returns once the plan is ready.  The plan
+ * copies what it needs (windows compacted to their support, spectra,
+ * twiddle tables, workspaces sized for desc->batch); the caller may free
+ * `windows` and `h` afterwards.  The plan is bound to the device current
+ * at creation and may be used from one stream at a time (its workspace is
+ * shared by its calls).
+ * Errors: INVALID_VALUE (null pointers, ndim not 1/2, m < 1, batch < 1,
+ * n1 != 1 in 1D, m != m_rows*m_cols, flags != 0), UNSUPPORTED (sizes above),
+ * OUT_OF_MEMORY, HIP.
+ */
+pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* windows, const float* h,
+                         void* stream);
+
+/*
+ * pc_apply - y = H_m u for `batch` signals (eq. 1.4).
+ *
+ *   u, y   (device) batch x N (1D) or batch x N1 x N2 (2D) floats; u is
+ *          read only; y is written entirely; the two must not overlap.
+ *   batch  0 <= batch <= desc->batch (0 is a no-op).
+ *   stream the work is enqueued on this stream; the call returns without
+ *          waiting for it.
+ * Errors: INVALID_PLAN, INVALID_VALUE (null or overlapping buffers, batch
+ * out of range), HIP (launch failure).
+ */
+pc_status pc_apply(pc_plan plan, const float* u, float* y, int64_t batch, void* stream);
+
+/*
+ * pc_apply_adjoint - x = H_m^* v = sum_k w_k . (h~_k * v) for `batch`
+ * signals.  Same buffer rules, errors and asynchrony as pc_apply.
+ */
+pc_status pc_apply_adjoint(pc_plan plan, const float* v, float* x, int64_t batch, void* stream);
+
+/*
+ * pc_destroy - release the plan and its device memory.  Waits for the
+ * device to finish work that may still use the plan.  Destroying a NULL or
+ * already destroyed handle returns INVALID_PLAN (a handle that was
+ * destroyed must not be used again: its memory is freed).
+ */
+pc_status pc_destroy(pc_plan plan);
+
+/* Read-only facts about a plan (for tests, benchmarks and tooling). */
+typedef struct {
+  int32_t path;          /* 0: 1D one workgroup per transform, 1: 1D four-step, 2: 2D */
+  int32_t fft_inner;     /* 1D: inner transform length L (N for path 0); 2D: N1 */
+  int32_t fft_outer;     /* 1D four-step: R = N / L; otherwise 1 (2D: N2) */
+  int32_t n_items;       /* 1D four-step: adjoint work items (term, support chunk) */
+  int64_t spectra_bytes; /* device bytes of the stored spectra */
+  int64_t window_bytes;  /* device bytes of the stored (compacted) windows */
+  int64_t workspace_bytes;
+} pc_plan_info;
+
+/* pc_plan_query - fill *info.  Errors: INVALID_PLAN, INVALID_VALUE. */
+pc_status pc_plan_query(pc_plan plan, pc_plan_info* info);
+
+/* Static text for a status code (never NULL). */
+const char* pc_status_string(pc_status status);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* pc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PC_H_ */

@@ -1,0 +1,220 @@
+"""Convolution-product expansions on MI355X: Python binding of ``libpc.so``.
+
+The expansion of order ``m`` (eq. 1.4)
+
+    H_m u = sum_k h_k * (w_k . u),      H_m^* v = sum_k w_k . (h~_k * v)
+
+is evaluated by the HIP library behind the C ABI of ``include/pc.h``.  This
+module only marshals arguments: host arrays (windows, impulse responses) are
+passed as pointers at plan creation; signals are torch CUDA tensors whose
+device pointers and the current HIP stream are handed to the library.  Every
+step of the computation runs in the library's kernels; there is no other
+implementation, and a missing library is an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple, Union
+
+import numpy as np
+
+__all__ = ["Plan", "PCError", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+           "PC_W_DENSE", "PC_W_SEPARABLE"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpc.so")
+
+PC_W_DENSE = 0
+PC_W_SEPARABLE = 1
+
+STATUS_NAMES = {
+    0: "PC_SUCCESS",
+    1: "PC_ERROR_INVALID_VALUE",
+    2: "PC_ERROR_UNSUPPORTED",
+    3: "PC_ERROR_OUT_OF_MEMORY",
+    4: "PC_ERROR_HIP",
+    5: "PC_ERROR_INVALID_PLAN",
+}
+
+# Every symbol include/pc.h declares.
+EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_plan_query",
+           "pc_status_string", "pc_last_error")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("m", ctypes.c_int32), ("n0", ctypes.c_int64),
+                ("n1", ctypes.c_int64), ("batch", ctypes.c_int64), ("w_format", ctypes.c_int32),
+                ("m_rows", ctypes.c_int32), ("m_cols", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("fft_inner", ctypes.c_int32), ("fft_outer", ctypes.c_int32),
+                ("n_items", ctypes.c_int32), ("spectra_bytes", ctypes.c_int64),
+                ("window_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+
+
+class PCError(RuntimeError):
+    """A library call returned a status other than PC_SUCCESS."""
+
+    def __init__(self, status: int, call: str, detail: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{call}: {self.name}: {detail}")
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libpc.so`` (once) and declare its signatures."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_1604_04374_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.pc_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), vp, vp, vp]
+    lib.pc_plan_create.restype = ctypes.c_int
+    for name in ("pc_apply", "pc_apply_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, i64, vp]
+        f.restype = ctypes.c_int
+    lib.pc_destroy.argtypes = [vp]
+    lib.pc_destroy.restype = ctypes.c_int
+    lib.pc_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.pc_plan_query.restype = ctypes.c_int
+    lib.pc_status_string.argtypes = [ctypes.c_int]
+    lib.pc_status_string.restype = ctypes.c_char_p
+    lib.pc_last_error.argtypes = []
+    lib.pc_last_error.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _check(lib, status: int, call: str):
+    if status != 0:
+        raise PCError(status, call, lib.pc_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream, device=None) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+class Plan:
+    """The operator ``H_m`` of eq. 1.4 resident on the current device.
+
+    Parameters
+    ----------
+    windows : array ``m x N`` / ``m x N1 x N2`` (dense), or a pair
+        ``(a, b)`` of row-axis factors ``a`` (``m1 x N1``) and column-axis
+        factors ``b`` (``m2 x N2``) for the separable grid
+        ``w_{k1*m2+k2} = a_k1 (x) b_k2``.
+    h : array ``m x N`` / ``m x N1 x N2``, impulse responses in lag layout.
+    batch : largest number of signals per call.
+    """
+
+    def __init__(self, windows: Union[np.ndarray, Tuple[np.ndarray, np.ndarray]], h: np.ndarray,
+                 batch: int = 1, stream=None):
+        self._lib = load_library()
+        self._handle = ctypes.c_void_p()
+        h = _f32(h)
+        d = PlanDesc()
+        d.m = h.shape[0]
+        d.batch = int(batch)
+        d.flags = 0
+        if isinstance(windows, (tuple, list)):
+            a, b = _f32(windows[0]), _f32(windows[1])
+            d.w_format = PC_W_SEPARABLE
+            d.m_rows, d.m_cols = a.shape[0], b.shape[0]
+            wbuf = np.ascontiguousarray(np.concatenate([a.ravel(), b.ravel()]))
+        else:
+            wbuf = _f32(windows)
+            d.w_format = PC_W_DENSE
+            d.m_rows = d.m_cols = 0
+        if h.ndim == 2:
+            d.ndim, d.n0, d.n1 = 1, h.shape[1], 1
+            self.shape = (int(h.shape[1]),)
+        elif h.ndim == 3:
+            d.ndim, d.n0, d.n1 = 2, h.shape[1], h.shape[2]
+            self.shape = (int(h.shape[1]), int(h.shape[2]))
+        else:
+            raise ValueError("h must be m x N or m x N1 x N2")
+        self.m = int(d.m)
+        self.batch = int(batch)
+        self.desc = d
+        self._wbuf, self._hbuf = wbuf, h  # keep alive for the call
+        s = _stream_ptr(stream)
+        st = self._lib.pc_plan_create(ctypes.byref(self._handle), ctypes.byref(d),
+                                      wbuf.ctypes.data_as(ctypes.c_void_p),
+                                      h.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(s))
+        _check(self._lib, st, "pc_plan_create")
+        del self._wbuf, self._hbuf
+
+    # ------------------------------------------------------------------
+    def _prep(self, x, out):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32):
+            raise TypeError("signals must be float32 CUDA tensors")
+        x = x.contiguous()
+        single = tuple(x.shape) == self.shape
+        batch = 1 if single else int(x.shape[0])
+        if not single and tuple(x.shape[1:]) != self.shape:
+            raise ValueError(f"expected shape {self.shape} or (B, *{self.shape}), got {tuple(x.shape)}")
+        if out is None:
+            out = torch.empty_like(x)
+        elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.shape == x.shape):
+            raise ValueError("out must be a contiguous float32 CUDA tensor shaped like the input")
+        return x, out, batch
+
+    def apply(self, u, out=None, stream=None):
+        """``y = H_m u`` (enqueued on ``stream``, default the current stream)."""
+        u, out, batch = self._prep(u, out)
+        st = self._lib.pc_apply(self._handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                batch, ctypes.c_void_p(_stream_ptr(stream, u.device)))
+        _check(self._lib, st, "pc_apply")
+        return out
+
+    def apply_adjoint(self, v, out=None, stream=None):
+        """``x = H_m^* v``."""
+        v, out, batch = self._prep(v, out)
+        st = self._lib.pc_apply_adjoint(self._handle, ctypes.c_void_p(v.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), batch,
+                                        ctypes.c_void_p(_stream_ptr(stream, v.device)))
+        _check(self._lib, st, "pc_apply_adjoint")
+        return out
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(self._lib, self._lib.pc_plan_query(self._handle, ctypes.byref(inf)), "pc_plan_query")
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def destroy(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            st = self._lib.pc_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+            _check(self._lib, st, "pc_destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()

@@ -1,0 +1,280 @@
+// Workgroup FFT engine for gfx950 (CDNA4, wave64).
+//
+// One L-point complex FFT is carried by T = L/P threads; thread t holds the
+// P points x[t + T*e], e = 0..P-1, in registers, both before and after the
+// transform (natural order, stride T).  The transform is a Stockham
+// autosort sequence of radix-R passes (R divides P); between passes the data
+// go through LDS, the last pass writes straight back to registers.  Because
+// input and output live at the same register slots, the spectral
+// multiply-accumulate and the inverse transform can follow the forward
+// transform without any reordering.
+//
+// Sign convention (Fourier atoms of the notation section): forward
+// X[f] = sum_n x[n] exp(-2 i pi f n / L); inverse is unnormalised with the
+// opposite sign.
+//
+// Twiddles come from a per-(L, P) table built on the host in float64 and
+// rounded once: for every pass (stride Ns, radix R) it lists
+// exp(-2 i pi q k / (Ns R)) for k < Ns, 1 <= q < R, so one butterfly reads
+// R-1 consecutive entries.  The table has L-1 entries.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pc {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+// acc + a*b
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a)*b
+__device__ __forceinline__ float2 cfma_conj(float2 acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(-a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2* x) {
+  const float c = -0.5f;
+  const float s = INV ? 0.86602540378443864676f : -0.86602540378443864676f;
+  float2 t = cadd(x[1], x[2]);
+  float2 d = csub(x[1], x[2]);
+  float2 m = make_float2(fmaf(c, t.x, x[0].x), fmaf(c, t.y, x[0].y));
+  // i*s*d
+  float2 r = make_float2(-s * d.y, s * d.x);
+  x[0] = cadd(x[0], t);
+  x[1] = cadd(m, r);
+  x[2] = csub(m, r);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  float2 a = cadd(x0, x2), b = csub(x0, x2);
+  float2 c = cadd(x1, x3), d = mul_mi<INV>(csub(x1, x3));
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, d);
+  x3 = csub(b, d);
+}
+
+// W8^k for k = 1..3, forward sign exp(-2 i pi k/8)
+template <bool INV>
+__device__ __forceinline__ float2 w8_1(float2 a) {
+  const float h = 0.70710678118654752440f;
+  // forward: a * (1 - i)/sqrt2 ; inverse: a * (1 + i)/sqrt2
+  return INV ? make_float2(h * (a.x - a.y), h * (a.x + a.y)) : make_float2(h * (a.x + a.y), h * (a.y - a.x));
+}
+template <bool INV>
+__device__ __forceinline__ float2 w8_3(float2 a) {
+  const float h = 0.70710678118654752440f;
+  // forward: a * (-1 - i)/sqrt2 ; inverse: a * (-1 + i)/sqrt2
+  return INV ? make_float2(-h * (a.x + a.y), h * (a.x - a.y)) : make_float2(h * (a.y - a.x), -h * (a.x + a.y));
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* x) {
+  // even / odd 4-point transforms, then one radix-2 combine
+  float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  o1 = w8_1<INV>(o1);
+  o2 = mul_mi<INV>(o2);
+  o3 = w8_3<INV>(o3);
+  x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+  x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
+  x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
+  x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2* x) {
+  // 16 = 4 x 4: transforms over n2 of x[n1 + 4 n2], twiddle W16^(n1 k2),
+  // transforms over n1; output index k2 + 4 k1.
+  float2 a[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    float2 y0 = x[n1], y1 = x[n1 + 4], y2 = x[n1 + 8], y3 = x[n1 + 12];
+    dft4<INV>(y0, y1, y2, y3);
+    a[n1 * 4 + 0] = y0; a[n1 * 4 + 1] = y1; a[n1 * 4 + 2] = y2; a[n1 * 4 + 3] = y3;
+  }
+  // twiddles W16^(n1*k2): n1 in 1..3, k2 in 1..3
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+  const float h = 0.70710678118654752440f;
+  const float sg = INV ? 1.0f : -1.0f;
+  // W16^1, W16^2, W16^3, W16^4 = -i(fwd), W16^6, W16^9
+  const float2 w1 = make_float2(c1, sg * s1);
+  const float2 w2 = make_float2(h, sg * h);
+  const float2 w3 = make_float2(s1, sg * c1);
+  const float2 w6 = make_float2(-h, sg * h);
+  const float2 w9 = make_float2(-c1, -sg * s1);
+  a[1 * 4 + 1] = cmul(a[1 * 4 + 1], w1);
+  a[1 * 4 + 2] = cmul(a[1 * 4 + 2], w2);
+  a[1 * 4 + 3] = cmul(a[1 * 4 + 3], w3);
+  a[2 * 4 + 1] = cmul(a[2 * 4 + 1], w2);
+  a[2 * 4 + 2] = mul_mi<INV>(a[2 * 4 + 2]);
+  a[2 * 4 + 3] = cmul(a[2 * 4 + 3], w6);
+  a[3 * 4 + 1] = cmul(a[3 * 4 + 1], w3);
+  a[3 * 4 + 2] = cmul(a[3 * 4 + 2], w6);
+  a[3 * 4 + 3] = cmul(a[3 * 4 + 3], w9);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    float2 y0 = a[0 * 4 + k2], y1 = a[1 * 4 + k2], y2 = a[2 * 4 + k2], y3 = a[3 * 4 + k2];
+    dft4<INV>(y0, y1, y2, y3);
+    x[k2 + 0] = y0; x[k2 + 4] = y1; x[k2 + 8] = y2; x[k2 + 12] = y3;
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dftR(float2* x) {
+  if constexpr (R == 2) dft2<INV>(x[0], x[1]);
+  else if constexpr (R == 3) dft3<INV>(x);
+  else if constexpr (R == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
+  else if constexpr (R == 8) dft8<INV>(x);
+  else if constexpr (R == 16) dft16<INV>(x);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// pass schedule
+// ---------------------------------------------------------------------------
+struct Sched {
+  int n;
+  int r[12];
+};
+
+// A leading radix-3 pass for L = 3 * 2^a, then passes of the largest power of
+// two dividing P (capped at 16) with a smaller last pass if needed.
+constexpr Sched make_sched(int L, int P) {
+  Sched s{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int rem = L;
+  if (rem % 3 == 0) {
+    s.r[s.n++] = 3;
+    rem /= 3;
+  }
+  int p2 = P & -P;
+  if (p2 > 16) p2 = 16;
+  while (rem > 1) {
+    int r = p2 < rem ? p2 : rem;
+    s.r[s.n++] = r;
+    rem /= r;
+  }
+  return s;
+}
+
+constexpr bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+constexpr bool sched_ok(int L, int P) {
+  if (L % P) return false;
+  int rem = L;
+  if (rem % 3 == 0) {
+    rem /= 3;
+    if (P % 3) return false;
+  }
+  if (!is_pow2(rem)) return false;
+  Sched s = make_sched(L, P);
+  for (int i = 0; i < s.n; ++i)
+    if (P % s.r[i]) return false;
+  return true;
+}
+
+// LDS word (float2) index with one pad slot per 16 entries: keeps the
+// stride-R writes of the first passes free of bank conflicts.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+template <int L>
+constexpr int lds_len() { return L + L / 16; }
+
+// ---------------------------------------------------------------------------
+// the engine
+// ---------------------------------------------------------------------------
+template <int L, int P, bool INV, int S, int Ns, int TW>
+struct FftPass {
+  static constexpr Sched sch = make_sched(L, P);
+  static constexpr int R = sch.r[S];
+  static constexpr int B = P / R;
+  static constexpr int T = L / P;
+  static constexpr bool LAST = (S == sch.n - 1);
+
+  __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + T * b;
+      const int k = j % Ns;
+      float2 x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = v[b + q * B];
+      if constexpr (Ns > 1) {
+        const float2* w = tw + TW + k * (R - 1);
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          float2 ww = w[q - 1];
+          if (INV) ww.y = -ww.y;
+          x[q] = cmul(x[q], ww);
+        }
+      }
+      dftR<R, INV>(x);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[b + q * B] = x[q];
+      } else {
+        if (b == 0) __syncthreads();  // previous readers of this LDS region are done
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) lds[lpad(base + q * Ns)] = x[q];
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < P; ++e) v[e] = lds[lpad(t + T * e)];
+      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1)>::run(v, lds, tw, t);
+    }
+  }
+};
+
+// In-place transform of the register array v (see the header comment).
+// Every thread of the workgroup must call it (it contains barriers), even
+// threads whose FFT slot is unused.
+template <int L, int P, bool INV>
+__device__ __forceinline__ void fft_wg(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
+  static_assert(sched_ok(L, P), "unsupported (L, P)");
+  FftPass<L, P, INV, 0, 1, 0>::run(v, lds, tw, t);
+}
+
+}  // namespace pc

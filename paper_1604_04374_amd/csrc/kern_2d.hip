@@ -1,0 +1,406 @@
+// 2D kernels of the convolution-product expansion on an N1 x N2 periodic
+// image (row-major, N2 contiguous); the higher-dimensional extension of
+// section 5.2 with index pairs taken modulo (N1, N2).
+//
+// The 2D transform is taken as real row transforms followed by complex
+// column transforms on the N2/2 + 1 retained column frequencies (the
+// half-spectrum of a real image).  Two real rows are packed into one complex
+// row transform and separated with the conjugate symmetry of real data.
+//
+// Forward:  rows:  RA_q = rowFFT(b_q . u)            (q = column factor)
+//           cols:  S = sum_k H_k . colFFT(a_k1 . RA_k2); T = colIFFT(S)
+//           rows:  y = rowIFFT(T) / (N1 N2)
+// Adjoint:  rows:  V = rowFFT(v)
+//           cols:  Q_q = sum_k1 a_k1 . colIFFT(conj(H_k) . colFFT(V))
+//           rows:  x = sum_q b_q . rowIFFT(Q_q) / (N1 N2)
+// With dense (non-separable) windows q runs over the m terms and a = 1,
+// b_q = w_q.
+#include "fft_engine.hpp"
+#include "pc_internal.hpp"
+
+namespace pc {
+
+#define PC_FOR_EACH_L2(X) \
+  X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) \
+  X(96) X(192) X(384) X(768) X(1536) X(3072) X(6144)
+
+// Window applied by the row kernels.
+enum RowWin { RW_NONE = 0, RW_FACTOR = 1, RW_DENSE = 2 };
+
+__device__ __forceinline__ void row_weights(const float* __restrict__ wsrc, int mode, int q, int N1, int L2, int r,
+                                            int n2, float& wa, float& wb) {
+  if (mode == RW_FACTOR) {
+    wa = wb = wsrc[(int64_t)q * L2 + n2];
+  } else if (mode == RW_DENSE) {
+    const float* base = wsrc + ((int64_t)q * N1 + r) * L2 + n2;
+    wa = base[0];
+    wb = base[L2];
+  } else {
+    wa = wb = 1.0f;
+  }
+}
+
+// Half-spectra of windowed row pairs: out[q][img][n1][0..H2).
+template <int L2>
+__global__ __launch_bounds__(ffts_per_block(L2) * fft_threads(L2)) void k_rows_fwd(
+    const float* __restrict__ x, int N1, int64_t n_img, const float* __restrict__ wsrc, int mode,
+    float2* __restrict__ out, int64_t q_stride, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L2), T = L2 / P, NF = ffts_per_block(L2), H2 = L2 / 2 + 1;
+  __shared__ float2 lds[NF * lds_len<L2>()];
+  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int64_t rp = (int64_t)blockIdx.x * NF + c;
+  const int64_t nrp = n_img * (N1 / 2);
+  const bool valid = rp < nrp;
+  const int64_t img = valid ? rp / (N1 / 2) : 0;
+  const int r = valid ? (int)(rp % (N1 / 2)) * 2 : 0;
+  const int q = blockIdx.y;
+  const float* ra = x + (img * N1 + r) * L2;
+  float2 v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int n2 = t + T * e;
+    float wa, wb;
+    row_weights(wsrc, mode, q, N1, L2, r, n2, wa, wb);
+    v[e] = valid ? make_float2(wa * ra[n2], wb * ra[n2 + L2]) : make_float2(0.f, 0.f);
+  }
+  float2* my = lds + c * lds_len<L2>();
+  fft_wg<L2, P, false>(v, my, tw, t);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < P; ++e) my[lpad(t + T * e)] = v[e];
+  __syncthreads();
+  float2* oa = out + q * q_stride + (img * N1 + r) * H2;
+  float2* ob = oa + H2;
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int f = t + T * e;
+    if (valid && f < H2) {
+      const float2 cf = my[lpad(f)];
+      const float2 cm = my[lpad(f == 0 ? 0 : L2 - f)];
+      // U_a = (C[f] + conj C[-f]) / 2,  U_b = (C[f] - conj C[-f]) / (2 i)
+      oa[f] = make_float2(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y));
+      ob[f] = make_float2(0.5f * (cf.y + cm.y), -0.5f * (cf.x - cm.x));
+    }
+  }
+}
+
+// Real row pairs from half-spectra: out[img][n1][n2] = scale * sum_q w_q . rowIFFT(in[q]).
+template <int L2>
+__global__ __launch_bounds__(ffts_per_block(L2) * fft_threads(L2)) void k_rows_inv(
+    const float2* __restrict__ in, int nq, int64_t q_stride, int N1, int64_t n_img, const float* __restrict__ wsrc,
+    int mode, float* __restrict__ out, float scale, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L2), T = L2 / P, NF = ffts_per_block(L2), H2 = L2 / 2 + 1;
+  __shared__ float2 lds[NF * lds_len<L2>()];
+  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int64_t rp = (int64_t)blockIdx.x * NF + c;
+  const int64_t nrp = n_img * (N1 / 2);
+  const bool valid = rp < nrp;
+  const int64_t img = valid ? rp / (N1 / 2) : 0;
+  const int r = valid ? (int)(rp % (N1 / 2)) * 2 : 0;
+  float2* my = lds + c * lds_len<L2>();
+  float2 acc[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+  for (int q = 0; q < nq; ++q) {
+    const float2* ia = in + q * q_stride + (img * N1 + r) * H2;
+    const float2* ib = ia + H2;
+    float2 v[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int f = t + T * e;
+      float2 a, b;
+      if (f < H2) {
+        a = valid ? ia[f] : make_float2(0.f, 0.f);
+        b = valid ? ib[f] : make_float2(0.f, 0.f);
+        if (f == 0 || f == L2 / 2) {  // the inverse real transform ignores these imaginary parts
+          a.y = 0.f;
+          b.y = 0.f;
+        }
+      } else {
+        a = valid ? cconj(ia[L2 - f]) : make_float2(0.f, 0.f);
+        b = valid ? cconj(ib[L2 - f]) : make_float2(0.f, 0.f);
+      }
+      v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
+    }
+    fft_wg<L2, P, true>(v, my, tw, t);
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      float wa, wb;
+      row_weights(wsrc, mode, q, N1, L2, r, t + T * e, wa, wb);
+      acc[e].x = fmaf(wa, v[e].x, acc[e].x);
+      acc[e].y = fmaf(wb, v[e].y, acc[e].y);
+    }
+  }
+  if (valid) {
+    float* oa = out + (img * N1 + r) * L2;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n2 = t + T * e;
+      oa[n2] = acc[e].x * scale;
+      oa[n2 + L2] = acc[e].y * scale;
+    }
+  }
+}
+
+// Column pass of the forward: T[img][:, f2] = colIFFT(sum_k H_k[:, f2] . colFFT(a_k1 . RA_k2[img][:, f2])).
+// NF columns per workgroup; consecutive lanes take consecutive columns.
+template <int L1>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
+    const float2* __restrict__ RA, int64_t q_stride, int H2, int m, int m2, int dense, const float* __restrict__ wrows,
+    const float2* __restrict__ Hs, float2* __restrict__ Tout, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  const int c = threadIdx.x % NF, t = threadIdx.x / NF;
+  const int nblk = (H2 + NF - 1) / NF;
+  const int64_t img = blockIdx.x / nblk;
+  const int f2 = (blockIdx.x % nblk) * NF + c;
+  const bool valid = f2 < H2;
+  const int64_t plane = (int64_t)L1 * H2;
+  float2* my = lds + c * lds_len<L1>();
+  float2 acc[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+  for (int k = 0; k < m; ++k) {
+    const int k1 = dense ? 0 : k / m2;
+    const int q = dense ? k : k % m2;
+    const float2* src = RA + q * q_stride + img * plane + f2;
+    float2 v[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n1 = t + T * e;
+      float2 z = valid ? src[(int64_t)n1 * H2] : make_float2(0.f, 0.f);
+      if (!dense) z = cscale(z, wrows[(int64_t)k1 * L1 + n1]);
+      v[e] = z;
+    }
+    fft_wg<L1, P, false>(v, my, tw, t);
+    const float2* Hk = Hs + (int64_t)k * plane + f2;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const float2 hv = valid ? Hk[(int64_t)(t + T * e) * H2] : make_float2(0.f, 0.f);
+      acc[e] = cfma(acc[e], hv, v[e]);
+    }
+  }
+  fft_wg<L1, P, true>(acc, my, tw, t);
+  if (valid) {
+    float2* dst = Tout + img * plane + f2;
+#pragma unroll
+    for (int e = 0; e < P; ++e) dst[(int64_t)(t + T * e) * H2] = acc[e];
+  }
+}
+
+// Column pass of the adjoint: Q_q[img][:, f2] = sum_k1 a_k1 . colIFFT(conj(H_k) . colFFT(V[img][:, f2])).
+template <int L1>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
+    const float2* __restrict__ V, int H2, int m, int m1, int m2, int dense, const float* __restrict__ wrows,
+    const float2* __restrict__ Hs, float2* __restrict__ Q, int64_t q_stride, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  const int c = threadIdx.x % NF, t = threadIdx.x / NF;
+  const int nblk = (H2 + NF - 1) / NF;
+  const int64_t img = blockIdx.x / nblk;
+  const int f2 = (blockIdx.x % nblk) * NF + c;
+  const bool valid = f2 < H2;
+  const int64_t plane = (int64_t)L1 * H2;
+  float2* my = lds + c * lds_len<L1>();
+  float2 Vh[P];
+  const float2* src = V + img * plane + f2;
+#pragma unroll
+  for (int e = 0; e < P; ++e) Vh[e] = valid ? src[(int64_t)(t + T * e) * H2] : make_float2(0.f, 0.f);
+  fft_wg<L1, P, false>(Vh, my, tw, t);
+  const int nq = dense ? m : m2;
+  const int nk1 = dense ? 1 : m1;
+  for (int q = 0; q < nq; ++q) {
+    float2 acc[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+    for (int k1 = 0; k1 < nk1; ++k1) {
+      const int k = dense ? q : k1 * m2 + q;
+      const float2* Hk = Hs + (int64_t)k * plane + f2;
+      float2 g[P];
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const float2 hv = valid ? Hk[(int64_t)(t + T * e) * H2] : make_float2(0.f, 0.f);
+        g[e] = cmulc(Vh[e], hv);
+      }
+      fft_wg<L1, P, true>(g, my, tw, t);
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const float wv = dense ? 1.0f : wrows[(int64_t)k1 * L1 + t + T * e];
+        acc[e].x = fmaf(wv, g[e].x, acc[e].x);
+        acc[e].y = fmaf(wv, g[e].y, acc[e].y);
+      }
+    }
+    if (valid) {
+      float2* dst = Q + q * q_stride + img * plane + f2;
+#pragma unroll
+      for (int e = 0; e < P; ++e) dst[(int64_t)(t + T * e) * H2] = acc[e];
+    }
+  }
+}
+
+// Column FFTs only (plan-time spectra): out[img][:, f2] = colFFT(in[img][:, f2]).
+template <int L1>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fft(
+    const float2* __restrict__ in, int H2, float2* __restrict__ out, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  const int c = threadIdx.x % NF, t = threadIdx.x / NF;
+  const int nblk = (H2 + NF - 1) / NF;
+  const int64_t img = blockIdx.x / nblk;
+  const int f2 = (blockIdx.x % nblk) * NF + c;
+  const bool valid = f2 < H2;
+  const int64_t plane = (int64_t)L1 * H2;
+  float2 v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = valid ? in[img * plane + (int64_t)(t + T * e) * H2 + f2] : make_float2(0.f, 0.f);
+  fft_wg<L1, P, false>(v, lds + c * lds_len<L1>(), tw, t);
+  if (valid) {
+#pragma unroll
+    for (int e = 0; e < P; ++e) out[img * plane + (int64_t)(t + T * e) * H2 + f2] = v[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int L2>
+static LaunchStatus rows_fwd_t(const float* x, int N1, int64_t n_img, const float* wsrc, int mode, int nq,
+                               float2* out, int64_t q_stride, const float2* tw, hipStream_t s) {
+  constexpr int NF = ffts_per_block(L2), T = fft_threads(L2);
+  const int64_t nrp = n_img * (N1 / 2);
+  const int64_t blocks = (nrp + NF - 1) / NF;
+  hipLaunchKernelGGL(k_rows_fwd<L2>, dim3((unsigned)blocks, (unsigned)nq), dim3(NF * T), 0, s, x, N1, n_img, wsrc,
+                     mode, out, q_stride, tw);
+  return hipGetLastError();
+}
+
+template <int L2>
+static LaunchStatus rows_inv_t(const float2* in, int nq, int64_t q_stride, int N1, int64_t n_img, const float* wsrc,
+                               int mode, float* out, float scale, const float2* tw, hipStream_t s) {
+  constexpr int NF = ffts_per_block(L2), T = fft_threads(L2);
+  const int64_t nrp = n_img * (N1 / 2);
+  const int64_t blocks = (nrp + NF - 1) / NF;
+  hipLaunchKernelGGL(k_rows_inv<L2>, dim3((unsigned)blocks), dim3(NF * T), 0, s, in, nq, q_stride, N1, n_img, wsrc,
+                     mode, out, scale, tw);
+  return hipGetLastError();
+}
+
+template <int L1>
+static LaunchStatus cols_fwd_t(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
+  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
+  const int nblk = (p.H2 + NF - 1) / NF;
+  hipLaunchKernelGGL(k_cols_fwd<L1>, dim3((unsigned)(nblk * n_img)), dim3(NF * T), 0, s, p.RA, q_stride, p.H2, p.m,
+                     p.m2, p.dense ? 1 : 0, p.wrows, p.Hs, p.Tws, p.tw1);
+  return hipGetLastError();
+}
+
+template <int L1>
+static LaunchStatus cols_adj_t(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
+  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
+  const int nblk = (p.H2 + NF - 1) / NF;
+  hipLaunchKernelGGL(k_cols_adj<L1>, dim3((unsigned)(nblk * n_img)), dim3(NF * T), 0, s, p.Tws, p.H2, p.m, p.m1,
+                     p.m2, p.dense ? 1 : 0, p.wrows, p.Hs, p.RA, q_stride, p.tw1);
+  return hipGetLastError();
+}
+
+template <int L1>
+static LaunchStatus cols_fft_t(const float2* in, int H2, int64_t n_img, float2* out, const float2* tw,
+                               hipStream_t s) {
+  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
+  const int nblk = (H2 + NF - 1) / NF;
+  hipLaunchKernelGGL(k_cols_fft<L1>, dim3((unsigned)(nblk * n_img)), dim3(NF * T), 0, s, in, H2, out, tw);
+  return hipGetLastError();
+}
+
+static LaunchStatus rows_fwd(int L2, const float* x, int N1, int64_t n_img, const float* wsrc, int mode, int nq,
+                             float2* out, int64_t q_stride, const float2* tw, hipStream_t s) {
+  switch (L2) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return rows_fwd_t<LL>(x, N1, n_img, wsrc, mode, nq, out, q_stride, tw, s);
+    PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+static LaunchStatus rows_inv(int L2, const float2* in, int nq, int64_t q_stride, int N1, int64_t n_img,
+                             const float* wsrc, int mode, float* out, float scale, const float2* tw, hipStream_t s) {
+  switch (L2) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return rows_inv_t<LL>(in, nq, q_stride, N1, n_img, wsrc, mode, out, scale, tw, s);
+    PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+static LaunchStatus cols_fwd(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
+  switch (p.N1) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return cols_fwd_t<LL>(p, n_img, q_stride, s);
+    PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+static LaunchStatus cols_adj(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
+  switch (p.N1) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return cols_adj_t<LL>(p, n_img, q_stride, s);
+    PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+static LaunchStatus cols_fft(int L1, const float2* in, int H2, int64_t n_img, float2* out, const float2* tw,
+                             hipStream_t s) {
+  switch (L1) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return cols_fft_t<LL>(in, H2, n_img, out, tw, s);
+    PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* scratch, hipStream_t s) {
+  const int64_t plane = (int64_t)p.N1 * p.H2;
+  LaunchStatus e = rows_fwd(p.N2, h, p.N1, p.m, nullptr, RW_NONE, 1, scratch, plane * p.m, p.tw2, s);
+  if (e != hipSuccess) return e;
+  return cols_fft(p.N1, scratch, p.H2, p.m, const_cast<float2*>(p.Hs), p.tw1, s);
+}
+
+LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s) {
+  const int64_t plane = (int64_t)p.N1 * p.H2;
+  const int64_t q_stride = plane * batch;
+  const int nq = p.dense ? p.m : p.m2;
+  LaunchStatus e = rows_fwd(p.N2, u, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, nq, p.RA, q_stride,
+                            p.tw2, s);
+  if (e != hipSuccess) return e;
+  e = cols_fwd(p, batch, q_stride, s);
+  if (e != hipSuccess) return e;
+  const float scale = 1.0f / ((float)p.N1 * (float)p.N2);
+  return rows_inv(p.N2, p.Tws, 1, 0, p.N1, batch, nullptr, RW_NONE, y, scale, p.tw2, s);
+}
+
+LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s) {
+  const int64_t plane = (int64_t)p.N1 * p.H2;
+  const int64_t q_stride = plane * batch;
+  const int nq = p.dense ? p.m : p.m2;
+  LaunchStatus e = rows_fwd(p.N2, v, p.N1, batch, nullptr, RW_NONE, 1, p.Tws, q_stride, p.tw2, s);
+  if (e != hipSuccess) return e;
+  e = cols_adj(p, batch, q_stride, s);
+  if (e != hipSuccess) return e;
+  const float scale = 1.0f / ((float)p.N1 * (float)p.N2);
+  return rows_inv(p.N2, p.RA, nq, q_stride, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, x, scale, p.tw2,
+                  s);
+}
+
+}  // namespace pc

@@ -1,0 +1,523 @@
+// Plan runtime and C ABI (include/pc.h).
+//
+// The plan turns the operator description of eq. 1.4 (m windows, m impulse
+// responses, sizes) into device-resident data laid out for the kernels:
+//   * 1D, N <= 8192: dense windows and full complex spectra F^* h_k;
+//   * 1D four-step:  windows compacted to their circular support (the
+//     compact-support idea of the complexity lemma of section 3.5), spectra
+//     in class-major order Hd[k][f1][f2] = H_k[f1 + R f2];
+//   * 2D:            window factors (or dense windows) and half-spectra
+//     rfft2(h_k), N1 x (N2/2 + 1), row-major.
+// All spectra are computed on the device by the library's own FFT kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/pc.h"
+#include "fft_engine.hpp"
+#include "pc_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pc_status fail(pc_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+pc_status fail_hip(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return (e == hipErrorOutOfMemory) ? PC_ERROR_OUT_OF_MEMORY : PC_ERROR_HIP;
+}
+
+std::mutex g_registry_mu;
+std::set<const void*> g_registry;  // live plans
+
+// Twiddle table of the workgroup FFT engine for length L (see fft_engine.hpp):
+// for each pass (stride Ns, radix R), exp(-2 i pi q k / (Ns R)) for k < Ns,
+// 1 <= q < R, in float64 then rounded once.
+std::vector<float2> engine_twiddles(int L) {
+  const int P = pc::points_per_thread(L);
+  const pc::Sched s = pc::make_sched(L, P);
+  std::vector<float2> tw;
+  tw.reserve(L);
+  long Ns = 1;
+  for (int i = 0; i < s.n; ++i) {
+    const int R = s.r[i];
+    for (long k = 0; k < Ns; ++k)
+      for (int q = 1; q < R; ++q) {
+        const double a = -2.0 * M_PI * (double)(q * k) / (double)(Ns * R);
+        tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+      }
+    Ns *= R;
+  }
+  tw.push_back(make_float2(0.f, 0.f));  // pad to L entries
+  return tw;
+}
+
+// exp(-2 i pi j / N), j < N, exact phase reduction in integers.
+std::vector<float2> unit_roots(int64_t N) {
+  std::vector<float2> w(N);
+  for (int64_t j = 0; j < N; ++j) {
+    const double a = -2.0 * M_PI * (double)j / (double)N;
+    w[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return w;
+}
+
+bool large_split(int64_t N, int& L, int& R) {
+  for (int l : {8192, 6144})
+    for (int r : {2, 4, 8, 16})
+      if ((int64_t)l * r == N) {
+        L = l;
+        R = r;
+        return true;
+      }
+  return false;
+}
+
+}  // namespace
+
+struct pc_plan_s {
+  int device = 0;
+  pc_plan_desc d{};
+  int path = 0;
+  int64_t n_total = 0;
+  pc::Small1D s1{};
+  pc::Large1D l1{};
+  pc::Plan2D p2{};
+  int64_t spectra_bytes = 0, window_bytes = 0, workspace_bytes = 0;
+  std::vector<void*> allocs;
+
+  ~pc_plan_s() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  template <class T>
+  pc_status alloc(T** out, size_t count, int64_t* account = nullptr) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      *out = nullptr;
+      return fail_hip(e, "hipMalloc");
+    }
+    allocs.push_back(p);
+    *out = reinterpret_cast<T*>(p);
+    if (account) *account += (int64_t)(count * sizeof(T));
+    return PC_SUCCESS;
+  }
+
+  template <class T>
+  pc_status upload(T** out, const std::vector<T>& host, hipStream_t s, int64_t* account = nullptr) {
+    pc_status st = alloc(out, host.size(), account);
+    if (st != PC_SUCCESS) return st;
+    if (host.empty()) return PC_SUCCESS;
+    (void)s;
+    hipError_t e = hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    return PC_SUCCESS;
+  }
+};
+
+// Plan-time staging buffer (impulse responses before their transform),
+// freed once the spectra kernels have finished.
+struct DeviceTemp {
+  void* p = nullptr;
+  ~DeviceTemp() {
+    if (p) (void)hipFree(p);
+  }
+  pc_status upload(const float* host, size_t count) {
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(float), 256));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail_hip(e, "hipMalloc");
+    }
+    e = hipMemcpy(p, host, count * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    return PC_SUCCESS;
+  }
+  const float* get() const { return static_cast<const float*>(p); }
+};
+
+namespace {
+
+pc_status check_plan(pc_plan p) {
+  if (!p) return fail(PC_ERROR_INVALID_PLAN, "plan handle is NULL");
+  std::lock_guard<std::mutex> g(g_registry_mu);
+  if (!g_registry.count(p)) return fail(PC_ERROR_INVALID_PLAN, "plan handle is not a live plan");
+  return PC_SUCCESS;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      if (hipSetDevice(dev) == hipSuccess) changed = true;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+// Minimal circular interval [o, o + S) holding every nonzero of w (S = 0 if
+// w is identically zero).
+void circular_support(const float* w, int64_t N, int64_t& o, int64_t& S) {
+  int64_t first = -1;
+  for (int64_t i = 0; i < N; ++i)
+    if (w[i] != 0.0f) {
+      first = i;
+      break;
+    }
+  if (first < 0) {
+    o = 0;
+    S = 0;
+    return;
+  }
+  // longest run of zeros on the circle, scanning from a nonzero
+  int64_t best_len = 0, best_end = first, run = 0;
+  for (int64_t t = 1; t <= N; ++t) {
+    const int64_t i = (first + t) % N;
+    if (w[i] == 0.0f) {
+      ++run;
+    } else {
+      if (run > best_len) {
+        best_len = run;
+        best_end = i;  // first nonzero after the run
+      }
+      run = 0;
+    }
+  }
+  o = best_len > 0 ? best_end : 0;
+  S = N - best_len;
+}
+
+pc_status build_small1d(pc_plan p, const float* windows, const float* h, hipStream_t s) {
+  const int L = (int)p->d.n0;
+  const int m = p->d.m;
+  pc_status st;
+  float* w = nullptr;
+  st = p->upload(&w, std::vector<float>(windows, windows + (size_t)m * L), s, &p->window_bytes);
+  if (st) return st;
+  float2* tw = nullptr;
+  st = p->upload(&tw, engine_twiddles(L), s);
+  if (st) return st;
+  DeviceTemp hd;
+  if ((st = hd.upload(h, (size_t)m * L))) return st;
+  float2* H = nullptr;
+  st = p->alloc(&H, (size_t)m * L, &p->spectra_bytes);
+  if (st) return st;
+  hipError_t e = pc::launch_spec1d_full(L, hd.get(), H, m, tw, s);
+  if (e != hipSuccess) return fail_hip(e, "spectra kernel");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "spectra kernel");
+  p->s1 = pc::Small1D{L, m, w, H, tw};
+  return PC_SUCCESS;
+}
+
+pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const float* h, hipStream_t s) {
+  const int64_t N = (int64_t)L * R;
+  const int m = p->d.m;
+  const int64_t pairs = (p->d.batch + 1) / 2;
+  pc_status st;
+  // compacted windows and adjoint work items
+  std::vector<int> off(m), len(m);
+  std::vector<int64_t> base(m);
+  std::vector<float> wc;
+  std::vector<int> it_k, it_d0;
+  std::vector<int64_t> it_out;
+  int64_t pstride = 0;
+  for (int k = 0; k < m; ++k) {
+    int64_t o, S;
+    const float* wk = windows + (size_t)k * N;
+    circular_support(wk, N, o, S);
+    off[k] = (int)o;
+    len[k] = (int)S;
+    base[k] = (int64_t)wc.size();
+    for (int64_t d = 0; d < S; ++d) wc.push_back(wk[(o + d) % N]);
+    for (int64_t c0 = 0; c0 < S; c0 += L) {
+      it_k.push_back(k);
+      it_d0.push_back((int)c0);
+      it_out.push_back(pstride);
+      pstride += std::min<int64_t>(L, S - c0);
+    }
+  }
+  pc::Large1D& q = p->l1;
+  q.L = L;
+  q.R = R;
+  q.m = m;
+  float* dwc = nullptr;
+  if ((st = p->upload(&dwc, wc, s, &p->window_bytes))) return st;
+  int *doff = nullptr, *dlen = nullptr, *dik = nullptr, *did0 = nullptr;
+  int64_t *dbase = nullptr, *diout = nullptr;
+  if ((st = p->upload(&doff, off, s))) return st;
+  if ((st = p->upload(&dlen, len, s))) return st;
+  if ((st = p->upload(&dbase, base, s))) return st;
+  if ((st = p->upload(&dik, it_k, s))) return st;
+  if ((st = p->upload(&did0, it_d0, s))) return st;
+  if ((st = p->upload(&diout, it_out, s))) return st;
+  float2 *tw = nullptr, *twN = nullptr;
+  if ((st = p->upload(&tw, engine_twiddles(L), s))) return st;
+  if ((st = p->upload(&twN, unit_roots(N), s))) return st;
+  q.wc = dwc;
+  q.w_off = doff;
+  q.w_len = dlen;
+  q.w_base = dbase;
+  q.tw = tw;
+  q.twN = twN;
+  q.n_items = (int)it_k.size();
+  q.item_k = dik;
+  q.item_d0 = did0;
+  q.item_out = diout;
+  q.p_stride = pstride;
+  float2* Hd = nullptr;
+  if ((st = p->alloc(&Hd, (size_t)m * N, &p->spectra_bytes))) return st;
+  q.Hd = Hd;
+  if ((st = p->alloc(&q.Bws, (size_t)pairs * N, &p->workspace_bytes))) return st;
+  if ((st = p->alloc(&q.Vws, (size_t)pairs * N, &p->workspace_bytes))) return st;
+  if ((st = p->alloc(&q.Pws, (size_t)pairs * std::max<int64_t>(pstride, 1), &p->workspace_bytes))) return st;
+  DeviceTemp hd;
+  if ((st = hd.upload(h, (size_t)m * N))) return st;
+  hipError_t e = pc::launch_fold_fft(q, hd.get(), m, Hd, false, s);
+  if (e != hipSuccess) return fail_hip(e, "spectra kernel");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "spectra kernel");
+  return PC_SUCCESS;
+}
+
+pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t s) {
+  const int N1 = (int)p->d.n0, N2 = (int)p->d.n1, H2 = N2 / 2 + 1;
+  const int m = p->d.m;
+  const bool dense = p->d.w_format == PC_W_DENSE;
+  pc::Plan2D& q = p->p2;
+  q.N1 = N1;
+  q.N2 = N2;
+  q.H2 = H2;
+  q.m = m;
+  q.dense = dense;
+  q.m1 = dense ? 1 : p->d.m_rows;
+  q.m2 = dense ? m : p->d.m_cols;
+  pc_status st;
+  const int64_t plane = (int64_t)N1 * H2;
+  if (dense) {
+    float* w = nullptr;
+    if ((st = p->upload(&w, std::vector<float>(windows, windows + (size_t)m * N1 * N2), s, &p->window_bytes)))
+      return st;
+    q.wcols = w;
+    q.wrows = nullptr;
+  } else {
+    float *a = nullptr, *b = nullptr;
+    const size_t na = (size_t)q.m1 * N1, nb = (size_t)q.m2 * N2;
+    if ((st = p->upload(&a, std::vector<float>(windows, windows + na), s, &p->window_bytes))) return st;
+    if ((st = p->upload(&b, std::vector<float>(windows + na, windows + na + nb), s, &p->window_bytes))) return st;
+    q.wrows = a;
+    q.wcols = b;
+  }
+  float2 *tw1 = nullptr, *tw2 = nullptr;
+  if ((st = p->upload(&tw1, engine_twiddles(N1), s))) return st;
+  if (N2 == N1) {
+    tw2 = tw1;
+  } else if ((st = p->upload(&tw2, engine_twiddles(N2), s))) {
+    return st;
+  }
+  q.tw1 = tw1;
+  q.tw2 = tw2;
+  float2* Hs = nullptr;
+  if ((st = p->alloc(&Hs, (size_t)m * plane, &p->spectra_bytes))) return st;
+  q.Hs = Hs;
+  const int64_t nq = dense ? m : q.m2;
+  const int64_t ra_planes = std::max<int64_t>(nq * p->d.batch, m);
+  if ((st = p->alloc(&q.RA, (size_t)(ra_planes * plane), &p->workspace_bytes))) return st;
+  if ((st = p->alloc(&q.Tws, (size_t)(p->d.batch * plane), &p->workspace_bytes))) return st;
+  DeviceTemp hd;
+  if ((st = hd.upload(h, (size_t)m * N1 * N2))) return st;
+  hipError_t e = pc::launch_spec2d(q, hd.get(), q.RA, s);
+  if (e != hipSuccess) return fail_hip(e, "spectra kernels");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "spectra kernels");
+  return PC_SUCCESS;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+pc_status check_apply(pc_plan p, const float* in, float* out, int64_t batch) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (batch < 0 || batch > p->d.batch)
+    return fail(PC_ERROR_INVALID_VALUE, "batch " + std::to_string(batch) + " outside [0, " +
+                                            std::to_string(p->d.batch) + "]");
+  if (batch == 0) return PC_SUCCESS;
+  if (!in || !out) return fail(PC_ERROR_INVALID_VALUE, "input or output pointer is NULL");
+  if (overlaps(in, out, (size_t)batch * p->n_total * sizeof(float)))
+    return fail(PC_ERROR_INVALID_VALUE, "input and output buffers overlap");
+  return PC_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pc_status_string(pc_status st) {
+  switch (st) {
+    case PC_SUCCESS: return "PC_SUCCESS";
+    case PC_ERROR_INVALID_VALUE: return "PC_ERROR_INVALID_VALUE";
+    case PC_ERROR_UNSUPPORTED: return "PC_ERROR_UNSUPPORTED";
+    case PC_ERROR_OUT_OF_MEMORY: return "PC_ERROR_OUT_OF_MEMORY";
+    case PC_ERROR_HIP: return "PC_ERROR_HIP";
+    case PC_ERROR_INVALID_PLAN: return "PC_ERROR_INVALID_PLAN";
+  }
+  return "PC_UNKNOWN_STATUS";
+}
+
+const char* pc_last_error(void) { return g_last_error.c_str(); }
+
+pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* windows, const float* h,
+                         void* stream) {
+  if (!out) return fail(PC_ERROR_INVALID_VALUE, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(PC_ERROR_INVALID_VALUE, "desc is NULL");
+  if (!windows || !h) return fail(PC_ERROR_INVALID_VALUE, "windows or h is NULL");
+  const pc_plan_desc d = *desc;
+  if (d.ndim != 1 && d.ndim != 2) return fail(PC_ERROR_INVALID_VALUE, "ndim must be 1 or 2");
+  if (d.m < 1) return fail(PC_ERROR_INVALID_VALUE, "m must be >= 1");
+  if (d.batch < 1) return fail(PC_ERROR_INVALID_VALUE, "batch must be >= 1");
+  if (d.flags != 0) return fail(PC_ERROR_INVALID_VALUE, "flags must be 0");
+  if (d.n0 < 1 || d.n1 < 1) return fail(PC_ERROR_INVALID_VALUE, "sizes must be positive");
+  if (d.w_format != PC_W_DENSE && d.w_format != PC_W_SEPARABLE)
+    return fail(PC_ERROR_INVALID_VALUE, "unknown window format");
+  int path = 0, L = 0, R = 1;
+  if (d.ndim == 1) {
+    if (d.n1 != 1) return fail(PC_ERROR_INVALID_VALUE, "1D plans need n1 == 1");
+    if (d.w_format != PC_W_DENSE) return fail(PC_ERROR_INVALID_VALUE, "1D plans take dense windows");
+    if (pc::fft_size_supported(d.n0)) {
+      path = 0;
+    } else if (large_split(d.n0, L, R)) {
+      path = 1;
+    } else {
+      return fail(PC_ERROR_UNSUPPORTED, "1D size " + std::to_string(d.n0) + " is not supported");
+    }
+  } else {
+    if (!pc::fft_size_supported(d.n0) || !pc::fft_size_supported(d.n1))
+      return fail(PC_ERROR_UNSUPPORTED,
+                  "2D size " + std::to_string(d.n0) + "x" + std::to_string(d.n1) + " is not supported");
+    if (d.w_format == PC_W_SEPARABLE &&
+        (d.m_rows < 1 || d.m_cols < 1 || (int64_t)d.m_rows * d.m_cols != d.m))
+      return fail(PC_ERROR_INVALID_VALUE, "separable windows need m == m_rows * m_cols");
+    path = 2;
+  }
+  pc_plan_s* p = new (std::nothrow) pc_plan_s();
+  if (!p) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  p->d = d;
+  p->path = path;
+  p->n_total = d.n0 * d.n1;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return fail_hip(e, "hipGetDevice");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pc_status st;
+  if (path == 0)
+    st = build_small1d(p, windows, h, s);
+  else if (path == 1)
+    st = build_large1d(p, L, R, windows, h, s);
+  else
+    st = build_2d(p, windows, h, s);
+  if (st != PC_SUCCESS) {
+    (void)hipStreamSynchronize(s);
+    delete p;
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_registry_mu);
+    g_registry.insert(p);
+  }
+  *out = p;
+  return PC_SUCCESS;
+}
+
+pc_status pc_apply(pc_plan p, const float* u, float* y, int64_t batch, void* stream) {
+  pc_status st = check_apply(p, u, y, batch);
+  if (st || batch == 0) return st;
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (p->path == 0)
+    e = pc::launch_fwd1d_small(p->s1, u, y, batch, s);
+  else if (p->path == 1)
+    e = pc::launch_fwd1d_large(p->l1, u, y, batch, s);
+  else
+    e = pc::launch_fwd2d(p->p2, u, y, batch, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_apply launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_apply_adjoint(pc_plan p, const float* v, float* x, int64_t batch, void* stream) {
+  pc_status st = check_apply(p, v, x, batch);
+  if (st || batch == 0) return st;
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (p->path == 0)
+    e = pc::launch_adj1d_small(p->s1, v, x, batch, s);
+  else if (p->path == 1)
+    e = pc::launch_adj1d_large(p->l1, v, x, batch, s);
+  else
+    e = pc::launch_adj2d(p->p2, v, x, batch, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_apply_adjoint launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_destroy(pc_plan p) {
+  {
+    std::lock_guard<std::mutex> g(g_registry_mu);
+    if (!p || !g_registry.count(p)) return fail(PC_ERROR_INVALID_PLAN, "plan handle is not a live plan");
+    g_registry.erase(p);
+  }
+  DeviceGuard g(p->device);
+  hipError_t e = hipDeviceSynchronize();
+  delete p;
+  if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize before free");
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!info) return fail(PC_ERROR_INVALID_VALUE, "info is NULL");
+  pc_plan_info r{};
+  r.path = p->path;
+  if (p->path == 0) {
+    r.fft_inner = p->s1.L;
+    r.fft_outer = 1;
+  } else if (p->path == 1) {
+    r.fft_inner = p->l1.L;
+    r.fft_outer = p->l1.R;
+    r.n_items = p->l1.n_items;
+  } else {
+    r.fft_inner = p->p2.N1;
+    r.fft_outer = p->p2.N2;
+  }
+  r.spectra_bytes = p->spectra_bytes;
+  r.window_bytes = p->window_bytes;
+  r.workspace_bytes = p->workspace_bytes;
+  *info = r;
+  return PC_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal interfaces between the plan runtime (pc_api.cpp) and the kernel
+// translation units.  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pc {
+
+// Launch status: hipSuccess, or hipErrorInvalidValue for a size with no
+// instantiated kernel (the plan checks sizes first, so that is a bug).
+using LaunchStatus = hipError_t;
+
+// Points per thread used for an FFT of length L (3-smooth lengths need a
+// multiple of 3).
+constexpr int points_per_thread(int L) {
+  return (L % 3 == 0) ? (L >= 1536 ? 24 : 12) : (L >= 256 ? 16 : 8);
+}
+constexpr int fft_threads(int L) { return L / points_per_thread(L); }
+// FFTs per workgroup for the batched row / column kernels.
+constexpr int ffts_per_block(int L) {
+  int t = fft_threads(L);
+  int nf = 256 / t;
+  return nf < 1 ? 1 : nf;
+}
+
+bool fft_size_supported(int64_t L);  // 64..8192, 2^a or 3*2^a
+
+// --------------------------------------------------------------------------
+// 1D, N <= 8192: everything for one signal pair in one workgroup
+// --------------------------------------------------------------------------
+struct Small1D {
+  int L;                     // N
+  int m;
+  const float* w;            // m x L windows
+  const float2* H;           // m x L full complex spectra, natural order
+  const float2* tw;          // engine twiddles for L
+};
+LaunchStatus launch_spec1d_full(int L, const float* h, float2* H, int m, const float2* tw, hipStream_t s);
+LaunchStatus launch_fwd1d_small(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s);
+LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// 1D, N = R * L (four-step): inner length L in a workgroup, R classes
+// --------------------------------------------------------------------------
+struct Large1D {
+  int L, R;                  // N = R * L
+  int m;
+  const float* wc;           // compacted window values, concatenated
+  const int* w_off;          // m: support start (mod N)
+  const int* w_len;          // m: support length (0 = empty window)
+  const int64_t* w_base;     // m: start of window k inside wc
+  const float2* Hd;          // m x R x L, Hd[k][f1][f2] = H_k[f1 + R f2]
+  const float2* tw;          // engine twiddles for L
+  const float2* twN;         // exp(-2 i pi j / N), j < N
+  // adjoint work items: (term, chunk of L samples of its support)
+  int n_items;
+  const int* item_k;
+  const int* item_d0;
+  const int64_t* item_out;   // offset of the item's samples in a pair's P block
+  int64_t p_stride;          // float2 per pair in the P block
+  // workspaces
+  float2* Bws;               // pairs x R x L
+  float2* Vws;               // pairs x R x L
+  float2* Pws;               // pairs x p_stride
+};
+LaunchStatus launch_fold_fft(const Large1D& p, const float* xa, int64_t n_sig, float2* out, bool pairs, hipStream_t s);
+LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s);
+LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// 2D, N1 x N2 (row-major, N2 contiguous), half spectra N1 x (N2/2 + 1)
+// --------------------------------------------------------------------------
+struct Plan2D {
+  int N1, N2, H2;            // H2 = N2/2 + 1
+  int m, m1, m2;             // separable: m = m1*m2, term k = k1*m2 + k2; dense: m1 = 1, m2 = m
+  bool dense;                // dense windows m x N1 x N2
+  const float* wrows;        // separable: m1 x N1 (factor along rows, a_k1[n1])
+  const float* wcols;        // separable: m2 x N2 (factor along columns, b_k2[n2]); dense: m x N1 x N2
+  const float2* Hs;          // m x N1 x H2
+  const float2* tw1;         // engine twiddles for N1
+  const float2* tw2;         // engine twiddles for N2
+  float2* RA;                // nq x batch x N1 x H2 (nq = m2 or m)
+  float2* Tws;               // batch x N1 x H2
+};
+// h (m x N1 x N2, lag layout) -> Hs; uses RA as scratch (needs m x N1 x H2)
+LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* scratch, hipStream_t s);
+LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s);
+LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s);
+
+}  // namespace pc

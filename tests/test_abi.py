@@ -1,0 +1,100 @@
+"""C ABI: the library loads, exports what include/pc.h declares, and rejects
+invalid requests before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1604_04374_amd as pcm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pc.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pcm.LIB_PATH):
+        pytest.fail("libpc.so is not built (run __graft_entry__.build())")
+    return pcm.load_library()
+
+
+def test_header_declares_the_exported_set():
+    assert _declared() == sorted(pcm.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code, name in pcm.STATUS_NAMES.items():
+        assert lib.pc_status_string(code).decode() == name
+    assert lib.pc_status_string(99).decode() == "PC_UNKNOWN_STATUS"
+
+
+def test_desc_layout_matches_header():
+    # int32 ndim, m; int64 n0, n1, batch; int32 w_format, m_rows, m_cols; uint32 flags
+    assert ctypes.sizeof(pcm.PlanDesc) == 48
+    assert pcm.PlanDesc.batch.offset == 24
+    assert ctypes.sizeof(pcm.PlanInfo) == 40
+
+
+def _create(lib, desc, w=None, h=None):
+    out = ctypes.c_void_p(123)
+    w = np.zeros(16, np.float32) if w is None else w
+    h = np.zeros(16, np.float32) if h is None else h
+    st = lib.pc_plan_create(ctypes.byref(out), ctypes.byref(desc) if desc is not None else None,
+                            w.ctypes.data_as(ctypes.c_void_p), h.ctypes.data_as(ctypes.c_void_p), None)
+    return st, out
+
+
+def _desc(**kw):
+    d = pcm.PlanDesc()
+    d.ndim, d.m, d.n0, d.n1, d.batch = 1, 4, 1024, 1, 1
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ndim=3), 1), (dict(m=0), 1), (dict(batch=0), 1), (dict(flags=1), 1),
+    (dict(n1=2), 1), (dict(w_format=7), 1), (dict(w_format=1), 1),
+    (dict(n0=1000), 2), (dict(n0=32), 2), (dict(n0=1 << 20), 2),
+    (dict(ndim=2, n0=100, n1=64), 2), (dict(ndim=2, n0=64, n1=10000), 2),
+    (dict(ndim=2, n0=64, n1=64, w_format=1, m_rows=2, m_cols=3), 1),
+])
+def test_invalid_descriptions_are_rejected(lib, kw, status):
+    st, out = _create(lib, _desc(**kw))
+    assert st == status, lib.pc_last_error()
+    assert out.value is None
+    assert lib.pc_last_error().decode() != ""
+
+
+def test_null_arguments(lib):
+    st, out = _create(lib, None)
+    assert st == 1
+    d = _desc()
+    out = ctypes.c_void_p()
+    assert lib.pc_plan_create(None, ctypes.byref(d), None, None, None) == 1
+    assert lib.pc_plan_create(ctypes.byref(out), ctypes.byref(d), None, None, None) == 1
+
+
+def test_calls_on_invalid_plans(lib):
+    assert lib.pc_apply(None, None, None, 1, None) == 5
+    assert lib.pc_apply_adjoint(None, None, None, 1, None) == 5
+    assert lib.pc_destroy(None) == 5
+    bogus = ctypes.c_void_p(0xdeadbeef)
+    assert lib.pc_apply(bogus, None, None, 1, None) == 5
+    assert lib.pc_destroy(bogus) == 5
+    info = pcm.PlanInfo()
+    assert lib.pc_plan_query(bogus, ctypes.byref(info)) == 5
+    assert "live plan" in lib.pc_last_error().decode()
