@@ -144,6 +144,28 @@ typedef struct {
 /* pc_plan_query - fill *info.  Errors: INVALID_PLAN, INVALID_VALUE. */
 pc_status pc_plan_query(pc_plan plan, pc_plan_info* info);
 
+/*
+ * Per-kernel timing.  While tracing is enabled, every kernel launched by
+ * pc_apply / pc_apply_adjoint on this plan is bracketed by two HIP events
+ * recorded on the launch stream (the events add a few microseconds per
+ * launch).  pc_plan_trace_stats waits for the recorded events, folds them
+ * into per-kernel statistics and copies up to `capacity` entries into
+ * `stats` (host memory); *count receives the number of distinct kernels.
+ * pc_plan_trace_reset drops the statistics.  Errors: INVALID_PLAN,
+ * INVALID_VALUE (null count, or null stats with capacity > 0), HIP.
+ */
+typedef struct {
+  char kernel[32];  /* kernel family, e.g. "fwd1d_large" */
+  int64_t launches;
+  double total_ms;
+  double min_ms;
+  double max_ms;
+} pc_kernel_stat;
+
+pc_status pc_plan_set_tracing(pc_plan plan, int32_t enable);
+pc_status pc_plan_trace_stats(pc_plan plan, pc_kernel_stat* stats, int32_t capacity, int32_t* count);
+pc_status pc_plan_trace_reset(pc_plan plan);
+
 /* Static text for a status code (never NULL). */
 const char* pc_status_string(pc_status status);
 

@@ -19,7 +19,7 @@ from typing import Optional, Sequence, Tuple, Union
 
 import numpy as np
 
-__all__ = ["Plan", "PCError", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+__all__ = ["Plan", "PCError", "KernelStat", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,6 +39,7 @@ STATUS_NAMES = {
 
 # Every symbol include/pc.h declares.
 EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_plan_query",
+           "pc_plan_set_tracing", "pc_plan_trace_stats", "pc_plan_trace_reset",
            "pc_status_string", "pc_last_error")
 
 
@@ -52,6 +53,11 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("fft_inner", ctypes.c_int32), ("fft_outer", ctypes.c_int32),
                 ("n_items", ctypes.c_int32), ("spectra_bytes", ctypes.c_int64),
                 ("window_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
 class PCError(RuntimeError):
@@ -86,6 +92,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_destroy.restype = ctypes.c_int
     lib.pc_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.pc_plan_query.restype = ctypes.c_int
+    lib.pc_plan_set_tracing.argtypes = [vp, ctypes.c_int32]
+    lib.pc_plan_set_tracing.restype = ctypes.c_int
+    lib.pc_plan_trace_stats.argtypes = [vp, ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.pc_plan_trace_stats.restype = ctypes.c_int
+    lib.pc_plan_trace_reset.argtypes = [vp]
+    lib.pc_plan_trace_reset.restype = ctypes.c_int
     lib.pc_status_string.argtypes = [ctypes.c_int]
     lib.pc_status_string.restype = ctypes.c_char_p
     lib.pc_last_error.argtypes = []
@@ -200,6 +213,28 @@ class Plan:
         inf = PlanInfo()
         _check(self._lib, self._lib.pc_plan_query(self._handle, ctypes.byref(inf)), "pc_plan_query")
         return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def set_tracing(self, enable: bool = True):
+        """Bracket every kernel of later calls with HIP events (see pc.h)."""
+        _check(self._lib, self._lib.pc_plan_set_tracing(self._handle, int(bool(enable))), "pc_plan_set_tracing")
+
+    def trace_stats(self) -> dict:
+        """Per-kernel {name: {launches, total_ms, min_ms, max_ms, avg_ms}} (waits for the events)."""
+        cap = 32
+        arr = (KernelStat * cap)()
+        n = ctypes.c_int32()
+        _check(self._lib, self._lib.pc_plan_trace_stats(self._handle, arr, cap, ctypes.byref(n)),
+               "pc_plan_trace_stats")
+        out = {}
+        for i in range(min(n.value, cap)):
+            r = arr[i]
+            out[r.kernel.decode()] = {"launches": r.launches, "total_ms": r.total_ms, "min_ms": r.min_ms,
+                                      "max_ms": r.max_ms,
+                                      "avg_ms": r.total_ms / r.launches if r.launches else 0.0}
+        return out
+
+    def trace_reset(self):
+        _check(self._lib, self._lib.pc_plan_trace_reset(self._handle), "pc_plan_trace_reset")
 
     def destroy(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:

@@ -149,20 +149,24 @@ static LaunchStatus spec1d_full_t(const float* h, float2* H, int m, const float2
 }
 
 template <int L>
-static LaunchStatus fwd1d_small_t(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s) {
+static LaunchStatus fwd1d_small_t(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                                  Tracer* tr) {
   constexpr int NF = ffts_per_block(L), T = fft_threads(L);
   const int64_t pairs = (batch + 1) / 2;
   const int64_t blocks = (pairs + NF - 1) / NF;
+  TraceScope ts(tr, "fwd1d_small", s);
   hipLaunchKernelGGL(k_fwd1d_small<L>, dim3((unsigned)blocks), dim3(NF * T), 0, s, u, y, batch, p.m, p.w, p.H,
                      p.tw);
   return hipGetLastError();
 }
 
 template <int L>
-static LaunchStatus adj1d_small_t(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s) {
+static LaunchStatus adj1d_small_t(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                                  Tracer* tr) {
   constexpr int NF = ffts_per_block(L), T = fft_threads(L);
   const int64_t pairs = (batch + 1) / 2;
   const int64_t blocks = (pairs + NF - 1) / NF;
+  TraceScope ts(tr, "adj1d_small", s);
   hipLaunchKernelGGL(k_adj1d_small<L>, dim3((unsigned)blocks), dim3(NF * T), 0, s, v, x, batch, p.m, p.w, p.H,
                      p.tw);
   return hipGetLastError();
@@ -179,22 +183,24 @@ LaunchStatus launch_spec1d_full(int L, const float* h, float2* H, int m, const f
   return hipErrorInvalidValue;
 }
 
-LaunchStatus launch_fwd1d_small(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s) {
+LaunchStatus launch_fwd1d_small(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                                Tracer* tr) {
   switch (p.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    return fwd1d_small_t<LL>(p, u, y, batch, s);
+    return fwd1d_small_t<LL>(p, u, y, batch, s, tr);
     PC_FOR_EACH_L(PC_CASE)
 #undef PC_CASE
   }
   return hipErrorInvalidValue;
 }
 
-LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s) {
+LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                                Tracer* tr) {
   switch (p.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    return adj1d_small_t<LL>(p, v, x, batch, s);
+    return adj1d_small_t<LL>(p, v, x, batch, s, tr);
     PC_FOR_EACH_L(PC_CASE)
 #undef PC_CASE
   }
@@ -403,60 +409,71 @@ __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x,
 
 template <int L, int R>
 static LaunchStatus fold_fft_t(const Large1D& p, const float* x, int64_t n_sig, float2* out, bool pairs,
-                               hipStream_t s) {
+                               hipStream_t s, Tracer* tr) {
   const int64_t nb = pairs ? (n_sig + 1) / 2 : n_sig;
+  TraceScope ts(tr, "fold_fft", s);
   hipLaunchKernelGGL((k_fold_fft<L, R>), dim3((unsigned)(nb * R)), dim3(fft_threads(L)), 0, s, x, n_sig, pairs, out,
                      p.tw, p.twN);
   return hipGetLastError();
 }
 
 template <int L, int R>
-static LaunchStatus fwd1d_large_t(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s) {
+static LaunchStatus fwd1d_large_t(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                                  Tracer* tr) {
   const int64_t pairs = (batch + 1) / 2;
-  hipLaunchKernelGGL((k_fwd1d_large<L, R>), dim3((unsigned)(pairs * R)), dim3(fft_threads(L)), 0, s, u, batch, p);
+  {
+    TraceScope ts(tr, "fwd1d_large", s);
+    hipLaunchKernelGGL((k_fwd1d_large<L, R>), dim3((unsigned)(pairs * R)), dim3(fft_threads(L)), 0, s, u, batch, p);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nthr = pairs * L;
+  TraceScope ts(tr, "combine1d", s);
   hipLaunchKernelGGL((k_combine1d<L, R>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p.Bws, y, batch,
                      p.twN);
   return hipGetLastError();
 }
 
 template <int L, int R>
-static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s) {
+static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                                  Tracer* tr) {
   const int64_t pairs = (batch + 1) / 2;
-  LaunchStatus e = fold_fft_t<L, R>(p, v, batch, p.Vws, true, s);
+  LaunchStatus e = fold_fft_t<L, R>(p, v, batch, p.Vws, true, s, tr);
   if (e != hipSuccess) return e;
   if (p.n_items > 0) {
+    TraceScope ts(tr, "adj1d_large", s);
     hipLaunchKernelGGL((k_adj1d_large<L, R>), dim3((unsigned)(pairs * p.n_items)), dim3(fft_threads(L)), 0, s, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const int64_t nthr = pairs * (int64_t)L * R;
+  TraceScope ts(tr, "ola1d", s);
   hipLaunchKernelGGL((k_ola1d<L, R>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p, x, batch);
   return hipGetLastError();
 }
 
 LaunchStatus launch_fold_fft(const Large1D& p, const float* x, int64_t n_sig, float2* out, bool pairs,
-                             hipStream_t s) {
+                             hipStream_t s, Tracer* tr) {
 #define PC_CASE(LL, RR) \
-  if (p.L == LL && p.R == RR) return fold_fft_t<LL, RR>(p, x, n_sig, out, pairs, s);
+  if (p.L == LL && p.R == RR) return fold_fft_t<LL, RR>(p, x, n_sig, out, pairs, s, tr);
   PC_FOR_EACH_LR(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }
 
-LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s) {
+LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                                Tracer* tr) {
 #define PC_CASE(LL, RR) \
-  if (p.L == LL && p.R == RR) return fwd1d_large_t<LL, RR>(p, u, y, batch, s);
+  if (p.L == LL && p.R == RR) return fwd1d_large_t<LL, RR>(p, u, y, batch, s, tr);
   PC_FOR_EACH_LR(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }
 
-LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s) {
+LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                                Tracer* tr) {
 #define PC_CASE(LL, RR) \
-  if (p.L == LL && p.R == RR) return adj1d_large_t<LL, RR>(p, v, x, batch, s);
+  if (p.L == LL && p.R == RR) return adj1d_large_t<LL, RR>(p, v, x, batch, s, tr);
   PC_FOR_EACH_LR(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;

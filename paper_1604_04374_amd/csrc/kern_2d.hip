@@ -313,7 +313,8 @@ static LaunchStatus cols_fft_t(const float2* in, int H2, int64_t n_img, float2* 
 }
 
 static LaunchStatus rows_fwd(int L2, const float* x, int N1, int64_t n_img, const float* wsrc, int mode, int nq,
-                             float2* out, int64_t q_stride, const float2* tw, hipStream_t s) {
+                             float2* out, int64_t q_stride, const float2* tw, hipStream_t s, Tracer* tr = nullptr) {
+  TraceScope ts(tr, "rows_fwd", s);
   switch (L2) {
 #define PC_CASE(LL) \
   case LL:          \
@@ -325,7 +326,9 @@ static LaunchStatus rows_fwd(int L2, const float* x, int N1, int64_t n_img, cons
 }
 
 static LaunchStatus rows_inv(int L2, const float2* in, int nq, int64_t q_stride, int N1, int64_t n_img,
-                             const float* wsrc, int mode, float* out, float scale, const float2* tw, hipStream_t s) {
+                             const float* wsrc, int mode, float* out, float scale, const float2* tw, hipStream_t s,
+                             Tracer* tr = nullptr) {
+  TraceScope ts(tr, "rows_inv", s);
   switch (L2) {
 #define PC_CASE(LL) \
   case LL:          \
@@ -336,7 +339,8 @@ static LaunchStatus rows_inv(int L2, const float2* in, int nq, int64_t q_stride,
   return hipErrorInvalidValue;
 }
 
-static LaunchStatus cols_fwd(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
+static LaunchStatus cols_fwd(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s, Tracer* tr) {
+  TraceScope ts(tr, "cols_fwd", s);
   switch (p.N1) {
 #define PC_CASE(LL) \
   case LL:          \
@@ -347,7 +351,8 @@ static LaunchStatus cols_fwd(const Plan2D& p, int64_t n_img, int64_t q_stride, h
   return hipErrorInvalidValue;
 }
 
-static LaunchStatus cols_adj(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
+static LaunchStatus cols_adj(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s, Tracer* tr) {
+  TraceScope ts(tr, "cols_adj", s);
   switch (p.N1) {
 #define PC_CASE(LL) \
   case LL:          \
@@ -377,30 +382,30 @@ LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* scratch, hip
   return cols_fft(p.N1, scratch, p.H2, p.m, const_cast<float2*>(p.Hs), p.tw1, s);
 }
 
-LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s) {
+LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s, Tracer* tr) {
   const int64_t plane = (int64_t)p.N1 * p.H2;
   const int64_t q_stride = plane * batch;
   const int nq = p.dense ? p.m : p.m2;
   LaunchStatus e = rows_fwd(p.N2, u, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, nq, p.RA, q_stride,
-                            p.tw2, s);
+                            p.tw2, s, tr);
   if (e != hipSuccess) return e;
-  e = cols_fwd(p, batch, q_stride, s);
+  e = cols_fwd(p, batch, q_stride, s, tr);
   if (e != hipSuccess) return e;
   const float scale = 1.0f / ((float)p.N1 * (float)p.N2);
-  return rows_inv(p.N2, p.Tws, 1, 0, p.N1, batch, nullptr, RW_NONE, y, scale, p.tw2, s);
+  return rows_inv(p.N2, p.Tws, 1, 0, p.N1, batch, nullptr, RW_NONE, y, scale, p.tw2, s, tr);
 }
 
-LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s) {
+LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s, Tracer* tr) {
   const int64_t plane = (int64_t)p.N1 * p.H2;
   const int64_t q_stride = plane * batch;
   const int nq = p.dense ? p.m : p.m2;
-  LaunchStatus e = rows_fwd(p.N2, v, p.N1, batch, nullptr, RW_NONE, 1, p.Tws, q_stride, p.tw2, s);
+  LaunchStatus e = rows_fwd(p.N2, v, p.N1, batch, nullptr, RW_NONE, 1, p.Tws, q_stride, p.tw2, s, tr);
   if (e != hipSuccess) return e;
-  e = cols_adj(p, batch, q_stride, s);
+  e = cols_adj(p, batch, q_stride, s, tr);
   if (e != hipSuccess) return e;
   const float scale = 1.0f / ((float)p.N1 * (float)p.N2);
   return rows_inv(p.N2, p.RA, nq, q_stride, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, x, scale, p.tw2,
-                  s);
+                  s, tr);
 }
 
 }  // namespace pc

@@ -85,6 +85,86 @@ bool large_split(int64_t N, int& L, int& R) {
   return false;
 }
 
+// HIP-event tracer used while a plan's tracing is on.
+struct PlanTracer final : pc::Tracer {
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  struct Stat {
+    std::string name;
+    int64_t n = 0;
+    double tot = 0, mn = 0, mx = 0;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<Stat> stats;
+  std::string cur;
+  hipEvent_t cur_a = nullptr;
+  hipError_t err = hipSuccess;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess && err == hipSuccess) err = r;
+    return e;
+  }
+  void begin(const char* kernel, hipStream_t s) override {
+    cur = kernel;
+    cur_a = get();
+    if (cur_a) {
+      hipError_t r = hipEventRecord(cur_a, s);
+      if (r != hipSuccess && err == hipSuccess) err = r;
+    }
+  }
+  void end(hipStream_t s) override {
+    hipEvent_t b = get();
+    if (!b || !cur_a) return;
+    hipError_t r = hipEventRecord(b, s);
+    if (r != hipSuccess && err == hipSuccess) err = r;
+    pending.push_back({cur, cur_a, b});
+    cur_a = nullptr;
+  }
+  hipError_t flush() {
+    for (Rec& r : pending) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess && err == hipSuccess) err = e;
+      Stat* st = nullptr;
+      for (Stat& x : stats)
+        if (x.name == r.name) st = &x;
+      if (!st) {
+        stats.push_back(Stat{r.name});
+        st = &stats.back();
+      }
+      if (st->n == 0 || ms < st->mn) st->mn = ms;
+      if (st->n == 0 || ms > st->mx) st->mx = ms;
+      st->tot += ms;
+      st->n += 1;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+    hipError_t e = err;
+    err = hipSuccess;
+    return e;
+  }
+  ~PlanTracer() override {
+    for (Rec& r : pending) {
+      (void)hipEventSynchronize(r.b);
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace
 
 struct pc_plan_s {
@@ -97,6 +177,9 @@ struct pc_plan_s {
   pc::Plan2D p2{};
   int64_t spectra_bytes = 0, window_bytes = 0, workspace_bytes = 0;
   std::vector<void*> allocs;
+  bool tracing = false;
+  PlanTracer tracer;
+  pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
   ~pc_plan_s() {
     for (void* p : allocs) (void)hipFree(p);
@@ -458,11 +541,11 @@ pc_status pc_apply(pc_plan p, const float* u, float* y, int64_t batch, void* str
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (p->path == 0)
-    e = pc::launch_fwd1d_small(p->s1, u, y, batch, s);
+    e = pc::launch_fwd1d_small(p->s1, u, y, batch, s, p->tr());
   else if (p->path == 1)
-    e = pc::launch_fwd1d_large(p->l1, u, y, batch, s);
+    e = pc::launch_fwd1d_large(p->l1, u, y, batch, s, p->tr());
   else
-    e = pc::launch_fwd2d(p->p2, u, y, batch, s);
+    e = pc::launch_fwd2d(p->p2, u, y, batch, s, p->tr());
   if (e != hipSuccess) return fail_hip(e, "pc_apply launch");
   return PC_SUCCESS;
 }
@@ -474,11 +557,11 @@ pc_status pc_apply_adjoint(pc_plan p, const float* v, float* x, int64_t batch, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (p->path == 0)
-    e = pc::launch_adj1d_small(p->s1, v, x, batch, s);
+    e = pc::launch_adj1d_small(p->s1, v, x, batch, s, p->tr());
   else if (p->path == 1)
-    e = pc::launch_adj1d_large(p->l1, v, x, batch, s);
+    e = pc::launch_adj1d_large(p->l1, v, x, batch, s, p->tr());
   else
-    e = pc::launch_adj2d(p->p2, v, x, batch, s);
+    e = pc::launch_adj2d(p->p2, v, x, batch, s, p->tr());
   if (e != hipSuccess) return fail_hip(e, "pc_apply_adjoint launch");
   return PC_SUCCESS;
 }
@@ -517,6 +600,45 @@ pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
   r.window_bytes = p->window_bytes;
   r.workspace_bytes = p->workspace_bytes;
   *info = r;
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_set_tracing(pc_plan p, int32_t enable) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  p->tracing = enable != 0;
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_trace_stats(pc_plan p, pc_kernel_stat* stats, int32_t capacity, int32_t* count) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!count || (capacity > 0 && !stats)) return fail(PC_ERROR_INVALID_VALUE, "null output pointer");
+  DeviceGuard g(p->device);
+  hipError_t e = p->tracer.flush();
+  if (e != hipSuccess) return fail_hip(e, "trace events");
+  const int32_t n = (int32_t)p->tracer.stats.size();
+  for (int32_t i = 0; i < n && i < capacity; ++i) {
+    const auto& x = p->tracer.stats[i];
+    pc_kernel_stat r{};
+    std::snprintf(r.kernel, sizeof(r.kernel), "%s", x.name.c_str());
+    r.launches = x.n;
+    r.total_ms = x.tot;
+    r.min_ms = x.mn;
+    r.max_ms = x.mx;
+    stats[i] = r;
+  }
+  *count = n;
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_trace_reset(pc_plan p) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  DeviceGuard g(p->device);
+  hipError_t e = p->tracer.flush();
+  p->tracer.stats.clear();
+  if (e != hipSuccess) return fail_hip(e, "trace events");
   return PC_SUCCESS;
 }
 

@@ -25,6 +25,25 @@ constexpr int ffts_per_block(int L) {
 
 bool fft_size_supported(int64_t L);  // 64..8192, 2^a or 3*2^a
 
+// Optional per-kernel timing: the launchers bracket every kernel with
+// begin/end (HIP events recorded on the launch stream).
+struct Tracer {
+  virtual void begin(const char* kernel, hipStream_t s) = 0;
+  virtual void end(hipStream_t s) = 0;
+  virtual ~Tracer() = default;
+};
+
+struct TraceScope {
+  Tracer* t;
+  hipStream_t s;
+  TraceScope(Tracer* tr, const char* name, hipStream_t st) : t(tr), s(st) {
+    if (t) t->begin(name, s);
+  }
+  ~TraceScope() {
+    if (t) t->end(s);
+  }
+};
+
 // --------------------------------------------------------------------------
 // 1D, N <= 8192: everything for one signal pair in one workgroup
 // --------------------------------------------------------------------------
@@ -36,8 +55,10 @@ struct Small1D {
   const float2* tw;          // engine twiddles for L
 };
 LaunchStatus launch_spec1d_full(int L, const float* h, float2* H, int m, const float2* tw, hipStream_t s);
-LaunchStatus launch_fwd1d_small(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s);
-LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s);
+LaunchStatus launch_fwd1d_small(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                                Tracer* tr = nullptr);
+LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                                Tracer* tr = nullptr);
 
 // --------------------------------------------------------------------------
 // 1D, N = R * L (four-step): inner length L in a workgroup, R classes
@@ -63,9 +84,12 @@ struct Large1D {
   float2* Vws;               // pairs x R x L
   float2* Pws;               // pairs x p_stride
 };
-LaunchStatus launch_fold_fft(const Large1D& p, const float* xa, int64_t n_sig, float2* out, bool pairs, hipStream_t s);
-LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s);
-LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s);
+LaunchStatus launch_fold_fft(const Large1D& p, const float* xa, int64_t n_sig, float2* out, bool pairs, hipStream_t s,
+                             Tracer* tr = nullptr);
+LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                                Tracer* tr = nullptr);
+LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                                Tracer* tr = nullptr);
 
 // --------------------------------------------------------------------------
 // 2D, N1 x N2 (row-major, N2 contiguous), half spectra N1 x (N2/2 + 1)
@@ -84,7 +108,9 @@ struct Plan2D {
 };
 // h (m x N1 x N2, lag layout) -> Hs; uses RA as scratch (needs m x N1 x H2)
 LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* scratch, hipStream_t s);
-LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s);
-LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s);
+LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s,
+                          Tracer* tr = nullptr);
+LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s,
+                          Tracer* tr = nullptr);
 
 }  // namespace pc
