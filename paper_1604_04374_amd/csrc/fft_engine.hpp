@@ -268,6 +268,15 @@ struct FftPass {
   }
 };
 
+// Copy an engine twiddle table (L entries) into LDS.  Every thread of the
+// workgroup calls it; it ends with a barrier.  Reading twiddles from LDS
+// keeps the per-pass global-memory round trips off the transform.
+template <int L>
+__device__ __forceinline__ void stage_twiddles(float2* tw_lds, const float2* __restrict__ tw) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw_lds[i] = tw[i];
+  __syncthreads();
+}
+
 // In-place transform of the register array v (see the header comment).
 // Every thread of the workgroup must call it (it contains barriers), even
 // threads whose FFT slot is unused.

@@ -37,13 +37,15 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_spec1d_f
     const float* __restrict__ h, float2* __restrict__ H, int m, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);
   __shared__ float2 lds[NF * lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int k = blockIdx.x * NF + c;
   const bool ok = k < m;
   float2 v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) v[e] = make_float2(ok ? h[(int64_t)k * L + t + T * e] : 0.f, 0.f);
-  fft_wg<L, P, false>(v, lds + c * lds_len<L>(), tw, t);
+  fft_wg<L, P, false>(v, lds + c * lds_len<L>(), twl, t);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < P; ++e) H[(int64_t)k * L + t + T * e] = v[e];
@@ -57,6 +59,8 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_sm
     const float2* __restrict__ H, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);
   __shared__ float2 lds[NF * lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t pair = (int64_t)blockIdx.x * NF + c;
   const int64_t sa = 2 * pair, sb = sa + 1;
@@ -80,12 +84,12 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_sm
       const float ww = wk[t + T * e];
       v[e] = make_float2(ww * ua[e], ww * ub[e]);
     }
-    fft_wg<L, P, false>(v, my, tw, t);
+    fft_wg<L, P, false>(v, my, twl, t);
     const float2* Hk = H + (int64_t)k * L;
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], Hk[t + T * e], v[e]);
   }
-  fft_wg<L, P, true>(acc, my, tw, t);
+  fft_wg<L, P, true>(acc, my, twl, t);
   const float sc = 1.0f / (float)L;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
@@ -102,6 +106,8 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_sm
     const float2* __restrict__ H, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);
   __shared__ float2 lds[NF * lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t pair = (int64_t)blockIdx.x * NF + c;
   const int64_t sa = 2 * pair, sb = sa + 1;
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_sm
     V[e] = make_float2(va ? vin[sa * L + n] : 0.f, vb ? vin[sb * L + n] : 0.f);
   }
   float2* my = lds + c * lds_len<L>();
-  fft_wg<L, P, false>(V, my, tw, t);
+  fft_wg<L, P, false>(V, my, twl, t);
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_sm
     float2 g[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) g[e] = cmulc(V[e], Hk[t + T * e]);
-    fft_wg<L, P, true>(g, my, tw, t);
+    fft_wg<L, P, true>(g, my, twl, t);
     const float* wk = w + (int64_t)k * L;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
@@ -211,58 +217,132 @@ LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int6
 // N = R * L: four-step split n = n2 + L n1, f = f1 + R f2
 //
 //   X[f1 + R f2] = FFT_L(a^{f1})[f2],
-//   a^{f1}[n2]   = sum_{n1} x[n2 + L n1] exp(-2 i pi f1 (n2 + L n1) / N).
+//   a^{f1}[n2]   = W_N^{f1 n2} sum_{n1} x[n2 + L n1] W_R^{f1 n1},
 //
-// A window of compact support folds into a^{f1} from its support only.  The
-// inverse runs the same split backwards:
-//   y[n2 + L n1] = (1/N) sum_{f1} exp(+2 i pi f1 (n2 + L n1)/N) b^{f1}[n2],
+// with W_M = exp(-2 i pi / M).  A window of compact support folds into
+// a^{f1} from its support only.  The inverse runs the same split backwards:
+//   y[n2 + L n1] = (1/N) sum_{f1} W_R^{-f1 n1} W_N^{-f1 n2} b^{f1}[n2],
 //   b^{f1} = unnormalised inverse FFT_L of the class-f1 spectrum.
+// W_N^{f1 n2} comes from the class table twC[f1 * L + n2] (coalesced in n2);
+// W_R^{j} = twN[j * L].
 // ===========================================================================
 
-// a^{f1}[n2] over the support [o, o + S) (mod N) of a (window x signal)
-// product.  wc = null means a window equal to one on the support.
 template <int L, int R>
-__device__ __forceinline__ float2 fold_one(int n2, int f1, const float* __restrict__ xa, const float* __restrict__ xb,
-                                           const float* __restrict__ wc, int o, int S,
+__device__ __forceinline__ float2 unit_root_R(const float2* __restrict__ twN, int j) {
+  return twN[(j % R) * L];
+}
+
+// a^{f1} for the thread's slots from a (window x signal) product whose
+// support [o, o + S) (mod N) is at most L long: every slot receives at most
+// one sample, found without a loop, and all loads are issued unconditionally
+// (clamped indices, zero weight off the support).
+template <int L, int R, int P>
+__device__ __forceinline__ void fold_short(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
+                                           const float* __restrict__ xb, float sb, const float* __restrict__ wc,
+                                           int o, int S, const float2* __restrict__ twC,
                                            const float2* __restrict__ twN) {
-  constexpr int N = L * R;
-  int d = n2 - (o % L);
-  if (d < 0) d += L;
-  float2 a = make_float2(0.f, 0.f);
-  for (; d < S; d += L) {
-    int n = o + d;
+  constexpr int T = L / P, N = L * R;
+  const int oL = o % L, n1a = o / L;
+  const float2 wr0 = unit_root_R<L, R>(twN, f1 * n1a);
+  const float2 wr1 = unit_root_R<L, R>(twN, f1 * (n1a + 1));
+  const float2* tc = twC + f1 * L;
+  // load phase: every load of the fold is issued before any is consumed
+  float ra[P], rb[P], rw[P];
+  float2 rt[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int n2 = t + T * e;
+    int d = n2 - oL;
+    if (d < 0) d += L;
+    const int dc = d < S ? d : 0;
+    int n = o + dc;
     if (n >= N) n -= N;
-    const float ww = wc ? wc[d] : 1.0f;
-    const float2 z = make_float2(ww * xa[n], xb ? ww * xb[n] : 0.f);
-    const unsigned ti = ((unsigned)f1 * (unsigned)n) % (unsigned)N;
-    a = cfma(a, z, twN[ti]);
+    ra[e] = xa[n];
+    rb[e] = xb[n];
+    rw[e] = wc[dc];
+    rt[e] = tc[n2];
   }
-  return a;
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int n2 = t + T * e;
+    int d = n2 - oL;
+    if (d < 0) d += L;
+    const float ww = d < S ? rw[e] : 0.f;
+    const float2 z = make_float2(ww * ra[e], ww * sb * rb[e]);
+    v[e] = cmul(z, cmul(rt[e], (oL + d >= L) ? wr1 : wr0));
+  }
+}
+
+// Same for supports longer than L (several samples per slot).
+template <int L, int R, int P>
+__device__ __forceinline__ void fold_long(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
+                                          const float* __restrict__ xb, float sb, const float* __restrict__ wc,
+                                          int o, int S, const float2* __restrict__ twC,
+                                          const float2* __restrict__ twN) {
+  constexpr int T = L / P, N = L * R;
+  const int oL = o % L;
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int n2 = t + T * e;
+    int d = n2 - oL;
+    if (d < 0) d += L;
+    float2 a = make_float2(0.f, 0.f);
+    for (; d < S; d += L) {
+      int n = o + d;
+      if (n >= N) n -= N;
+      const float ww = wc[d];
+      const float2 z = make_float2(ww * xa[n], ww * sb * xb[n]);
+      a = cfma(a, z, unit_root_R<L, R>(twN, f1 * (n / L)));
+    }
+    v[e] = cmul(a, twC[f1 * L + n2]);
+  }
 }
 
 // Class spectra of whole signals: out[(sig*R + f1)*L + f2] = X_sig[f1 + R f2].
 // pairs = true packs signals (2i, 2i+1) as one complex signal.
-template <int L, int R>
-__global__ __launch_bounds__(fft_threads(L)) void k_fold_fft(const float* __restrict__ x, int64_t n_sig, bool pairs,
+template <int L, int R, int P>
+__global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x, int64_t n_sig, bool pairs,
                                                              float2* __restrict__ out, const float2* __restrict__ tw,
+                                                             const float2* __restrict__ twC,
                                                              const float2* __restrict__ twN) {
-  constexpr int P = points_per_thread(L), T = L / P, N = L * R;
+  constexpr int T = L / P, N = L * R;
   __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, tw);
   const int t = threadIdx.x;
   const int f1 = blockIdx.x % R;
   const int64_t idx = blockIdx.x / R;
   const float* xa;
-  const float* xb = nullptr;
+  const float* xb;
+  float sb = 0.f;
   if (pairs) {
     xa = x + 2 * idx * N;
-    if (2 * idx + 1 < n_sig) xb = xa + N;
+    xb = xa;
+    if (2 * idx + 1 < n_sig) {
+      xb = xa + N;
+      sb = 1.f;
+    }
   } else {
     xa = x + idx * N;
+    xb = xa;
   }
+  float2 wr[R];
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) wr[n1] = unit_root_R<L, R>(twN, f1 * n1);
+  const float2* tc = twC + f1 * L;
   float2 v[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) v[e] = fold_one<L, R>(t + T * e, f1, xa, xb, nullptr, 0, N, twN);
-  fft_wg<L, P, false>(v, lds, tw, t);
+  for (int e = 0; e < P; ++e) {
+    const int n2 = t + T * e;
+    float2 a = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int n1 = 0; n1 < R; ++n1) {
+      const float2 z = make_float2(xa[n2 + L * n1], sb * xb[n2 + L * n1]);
+      a = cfma(a, z, wr[n1]);
+    }
+    v[e] = cmul(a, tc[n2]);
+  }
+  fft_wg<L, P, false>(v, lds, twl, t);
   float2* o = out + (idx * R + f1) * L;
 #pragma unroll
   for (int e = 0; e < P; ++e) o[t + T * e] = v[e];
@@ -270,16 +350,19 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fold_fft(const float* __rest
 
 // Forward, class f1 of one signal pair: sum_k Hd_k^{f1} . FFT_L(fold(w_k u)),
 // then the class's inverse FFT_L, stored for the combine step.
-template <int L, int R>
-__global__ __launch_bounds__(fft_threads(L)) void k_fwd1d_large(const float* __restrict__ u, int64_t batch,
-                                                                Large1D p) {
-  constexpr int P = points_per_thread(L), T = L / P, N = L * R;
+template <int L, int R, int P, bool SHORT>
+__global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__ u, int64_t batch, Large1D p) {
+  constexpr int T = L / P, N = L * R;
   __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
   const int f1 = blockIdx.x % R;
   const int64_t pair = blockIdx.x / R;
   const float* xa = u + 2 * pair * N;
-  const float* xb = (2 * pair + 1 < batch) ? xa + N : nullptr;
+  const bool hasb = 2 * pair + 1 < batch;
+  const float* xb = hasb ? xa + N : xa;
+  const float sb = hasb ? 1.f : 0.f;
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
@@ -289,14 +372,21 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd1d_large(const float* __r
     const int o = p.w_off[k];
     const float* wc = p.wc + p.w_base[k];
     float2 v[P];
-#pragma unroll
-    for (int e = 0; e < P; ++e) v[e] = fold_one<L, R>(t + T * e, f1, xa, xb, wc, o, S, p.twN);
-    fft_wg<L, P, false>(v, lds, p.tw, t);
+    if constexpr (SHORT)
+      fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+    else
+      fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+    // the spectrum loads are issued before the transform so that their
+    // latency overlaps it
     const float2* Hk = p.Hd + ((int64_t)k * R + f1) * L;
+    float2 hv[P];
 #pragma unroll
-    for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], Hk[t + T * e], v[e]);
+    for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
+    fft_wg<L, P, false>(v, lds, twl, t);
+#pragma unroll
+    for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
   }
-  fft_wg<L, P, true>(acc, lds, p.tw, t);
+  fft_wg<L, P, true>(acc, lds, twl, t);
   float2* o = p.Bws + (pair * R + f1) * L;
 #pragma unroll
   for (int e = 0; e < P; ++e) o[t + T * e] = acc[e];
@@ -305,7 +395,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd1d_large(const float* __r
 // y[n2 + L n1] = (1/N) sum_f1 W_R^{-f1 n1} (W_N^{-f1 n2} b^{f1}[n2]).
 template <int L, int R>
 __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bws, float* __restrict__ y, int64_t batch,
-                                                   const float2* __restrict__ twN) {
+                                                   const float2* __restrict__ twC) {
   constexpr int N = L * R;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t pairs = (batch + 1) / 2;
@@ -314,7 +404,7 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
   const int n2 = (int)(gid % L);
   float2 b[R];
 #pragma unroll
-  for (int f1 = 0; f1 < R; ++f1) b[f1] = cmulc(Bws[(pair * R + f1) * L + n2], twN[f1 * n2]);
+  for (int f1 = 0; f1 < R; ++f1) b[f1] = cmulc(Bws[(pair * R + f1) * L + n2], twC[f1 * L + n2]);
   dftR<R, true>(b);
   const float sc = 1.0f / (float)N;
   const int64_t sa = 2 * pair, sb = sa + 1;
@@ -326,48 +416,58 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
   }
 }
 
-// Adjoint, one (term, support chunk) item of one signal pair:
-// g = F(conj(H_k) . V) restricted to the chunk, assembled class by class,
-// then multiplied by the window and stored for the overlap-add.
-template <int L, int R>
-__global__ __launch_bounds__(fft_threads(L)) void k_adj1d_large(Large1D p) {
-  constexpr int P = points_per_thread(L), T = L / P, N = L * R;
+// Adjoint, one (term, support chunk of at most L samples) item of one signal
+// pair: g = F(conj(H_k) . V) on the chunk, assembled class by class, times
+// the window; stored for the overlap-add.
+template <int L, int R, int P>
+__global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
+  constexpr int T = L / P;
   __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
   const int item = blockIdx.x % p.n_items;
   const int64_t pair = blockIdx.x / p.n_items;
   const int k = p.item_k[item];
   const int c0 = p.item_d0[item];
-  const int S = p.w_len[k];
-  const int Sc = (S - c0) < L ? (S - c0) : L;
-  int oc = p.w_off[k] + c0;
-  if (oc >= N) oc -= N;
-  const int ocL = oc % L;
+  const int Sc = p.item_len[item];
+  const int oc = p.item_oc[item];
+  const int ocL = oc % L, n1a = oc / L;
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
   for (int f1 = 0; f1 < R; ++f1) {
     const float2* Hk = p.Hd + ((int64_t)k * R + f1) * L;
     const float2* Vp = p.Vws + (pair * R + f1) * L;
-    float2 g[P];
-#pragma unroll
-    for (int e = 0; e < P; ++e) g[e] = cmulc(Vp[t + T * e], Hk[t + T * e]);
-    fft_wg<L, P, true>(g, lds, p.tw, t);
+    float2 g[P], hv[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      int dd = t + T * e - ocL;
+      g[e] = Vp[t + T * e];
+      hv[e] = Hk[t + T * e];
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) g[e] = cmulc(g[e], hv[e]);
+    fft_wg<L, P, true>(g, lds, twl, t);
+    const float2 wr0 = unit_root_R<L, R>(p.twN, f1 * n1a);
+    const float2 wr1 = unit_root_R<L, R>(p.twN, f1 * (n1a + 1));
+    const float2* tc = p.twC + f1 * L;
+    float2 rt[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) rt[e] = tc[t + T * e];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n2 = t + T * e;
+      int dd = n2 - ocL;
       if (dd < 0) dd += L;
-      if (dd < Sc) {
-        int n = oc + dd;
-        if (n >= N) n -= N;
-        const unsigned ti = ((unsigned)f1 * (unsigned)n) % (unsigned)N;
-        acc[e] = cfma(acc[e], g[e], cconj(p.twN[ti]));
-      }
+      const float2 c = cmulc(g[e], cmul(rt[e], (ocL + dd >= L) ? wr1 : wr0));
+      const float keep = dd < Sc ? 1.f : 0.f;
+      acc[e].x = fmaf(keep, c.x, acc[e].x);
+      acc[e].y = fmaf(keep, c.y, acc[e].y);
     }
   }
   const float* wc = p.wc + p.w_base[k] + c0;
   float2* out = p.Pws + pair * p.p_stride + p.item_out[item];
-  const float sc = 1.0f / (float)N;
+  const float sc = 1.0f / (float)(L * R);
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     int dd = t + T * e - ocL;
@@ -376,7 +476,8 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj1d_large(Large1D p) {
   }
 }
 
-// x[n] = sum over items covering n of their stored products.
+// x[n] = sum over the items covering n of their stored products; the items
+// that can cover a sample are listed per tile of 256 samples.
 template <int L, int R>
 __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x, int64_t batch) {
   constexpr int N = L * R;
@@ -386,63 +487,76 @@ __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x,
   const int64_t pair = gid / N;
   const int n = (int)(gid % N);
   const float2* base = p.Pws + pair * p.p_stride;
+  const int tile = n >> 8;
   float2 acc = make_float2(0.f, 0.f);
-  for (int it = 0; it < p.n_items; ++it) {
-    const int k = p.item_k[it];
-    const int c0 = p.item_d0[it];
-    const int S = p.w_len[k];
-    const int Sc = (S - c0) < L ? (S - c0) : L;
-    int oc = p.w_off[k] + c0;
-    if (oc >= N) oc -= N;
-    int dd = n - oc;
+  for (int j = p.tile_off[tile]; j < p.tile_off[tile + 1]; ++j) {
+    const int it = p.tile_items[j];
+    int dd = n - p.item_oc[it];
     if (dd < 0) dd += N;
-    if (dd < Sc) acc = cadd(acc, base[p.item_out[it] + dd]);
+    if (dd < p.item_len[it]) acc = cadd(acc, base[p.item_out[it] + dd]);
   }
   const int64_t sa = 2 * pair, sb = sa + 1;
   x[sa * N + n] = acc.x;
   if (sb < batch) x[sb * N + n] = acc.y;
 }
 
-#define PC_FOR_EACH_LR(X)                                               \
-  X(8192, 2) X(8192, 4) X(8192, 8) X(8192, 16) X(6144, 2) X(6144, 4) \
-  X(6144, 8) X(6144, 16)
+// (L, R, P) instantiations of the four-step kernels; P (points per thread)
+// is a plan-time choice.
+#define PC_FOR_EACH_LRP(X)                                                          \
+  X(8192, 2, 16) X(8192, 4, 16) X(8192, 8, 16) X(8192, 16, 16) X(8192, 2, 8)      \
+  X(8192, 4, 8) X(8192, 8, 8) X(8192, 16, 8) X(6144, 2, 24) X(6144, 4, 24)        \
+  X(6144, 8, 24) X(6144, 16, 24) X(6144, 2, 12) X(6144, 4, 12) X(6144, 8, 12)     \
+  X(6144, 16, 12)
 
-template <int L, int R>
+bool fourstep_variant_supported(int L, int R, int P) {
+#define PC_CASE(LL, RR, PP) \
+  if (L == LL && R == RR && P == PP) return true;
+  PC_FOR_EACH_LRP(PC_CASE)
+#undef PC_CASE
+  return false;
+}
+
+template <int L, int R, int P>
 static LaunchStatus fold_fft_t(const Large1D& p, const float* x, int64_t n_sig, float2* out, bool pairs,
                                hipStream_t s, Tracer* tr) {
   const int64_t nb = pairs ? (n_sig + 1) / 2 : n_sig;
   TraceScope ts(tr, "fold_fft", s);
-  hipLaunchKernelGGL((k_fold_fft<L, R>), dim3((unsigned)(nb * R)), dim3(fft_threads(L)), 0, s, x, n_sig, pairs, out,
-                     p.tw, p.twN);
+  hipLaunchKernelGGL((k_fold_fft<L, R, P>), dim3((unsigned)(nb * R)), dim3(L / P), 0, s, x, n_sig, pairs, out, p.tw,
+                     p.twC, p.twN);
   return hipGetLastError();
 }
 
-template <int L, int R>
+template <int L, int R, int P>
 static LaunchStatus fwd1d_large_t(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
                                   Tracer* tr) {
   const int64_t pairs = (batch + 1) / 2;
   {
     TraceScope ts(tr, "fwd1d_large", s);
-    hipLaunchKernelGGL((k_fwd1d_large<L, R>), dim3((unsigned)(pairs * R)), dim3(fft_threads(L)), 0, s, u, batch, p);
+    if (p.short_support)
+      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, true>), dim3((unsigned)(pairs * R)), dim3(L / P), 0, s, u, batch,
+                         p);
+    else
+      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, false>), dim3((unsigned)(pairs * R)), dim3(L / P), 0, s, u, batch,
+                         p);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nthr = pairs * L;
   TraceScope ts(tr, "combine1d", s);
   hipLaunchKernelGGL((k_combine1d<L, R>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p.Bws, y, batch,
-                     p.twN);
+                     p.twC);
   return hipGetLastError();
 }
 
-template <int L, int R>
+template <int L, int R, int P>
 static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
                                   Tracer* tr) {
   const int64_t pairs = (batch + 1) / 2;
-  LaunchStatus e = fold_fft_t<L, R>(p, v, batch, p.Vws, true, s, tr);
+  LaunchStatus e = fold_fft_t<L, R, P>(p, v, batch, p.Vws, true, s, tr);
   if (e != hipSuccess) return e;
   if (p.n_items > 0) {
     TraceScope ts(tr, "adj1d_large", s);
-    hipLaunchKernelGGL((k_adj1d_large<L, R>), dim3((unsigned)(pairs * p.n_items)), dim3(fft_threads(L)), 0, s, p);
+    hipLaunchKernelGGL((k_adj1d_large<L, R, P>), dim3((unsigned)(pairs * p.n_items)), dim3(L / P), 0, s, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -454,27 +568,27 @@ static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, in
 
 LaunchStatus launch_fold_fft(const Large1D& p, const float* x, int64_t n_sig, float2* out, bool pairs,
                              hipStream_t s, Tracer* tr) {
-#define PC_CASE(LL, RR) \
-  if (p.L == LL && p.R == RR) return fold_fft_t<LL, RR>(p, x, n_sig, out, pairs, s, tr);
-  PC_FOR_EACH_LR(PC_CASE)
+#define PC_CASE(LL, RR, PP) \
+  if (p.L == LL && p.R == RR && p.P == PP) return fold_fft_t<LL, RR, PP>(p, x, n_sig, out, pairs, s, tr);
+  PC_FOR_EACH_LRP(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }
 
 LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
                                 Tracer* tr) {
-#define PC_CASE(LL, RR) \
-  if (p.L == LL && p.R == RR) return fwd1d_large_t<LL, RR>(p, u, y, batch, s, tr);
-  PC_FOR_EACH_LR(PC_CASE)
+#define PC_CASE(LL, RR, PP) \
+  if (p.L == LL && p.R == RR && p.P == PP) return fwd1d_large_t<LL, RR, PP>(p, u, y, batch, s, tr);
+  PC_FOR_EACH_LRP(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }
 
 LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
                                 Tracer* tr) {
-#define PC_CASE(LL, RR) \
-  if (p.L == LL && p.R == RR) return adj1d_large_t<LL, RR>(p, v, x, batch, s, tr);
-  PC_FOR_EACH_LR(PC_CASE)
+#define PC_CASE(LL, RR, PP) \
+  if (p.L == LL && p.R == RR && p.P == PP) return adj1d_large_t<LL, RR, PP>(p, v, x, batch, s, tr);
+  PC_FOR_EACH_LRP(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }

@@ -47,6 +47,8 @@ __global__ __launch_bounds__(ffts_per_block(L2) * fft_threads(L2)) void k_rows_f
     float2* __restrict__ out, int64_t q_stride, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L2), T = L2 / P, NF = ffts_per_block(L2), H2 = L2 / 2 + 1;
   __shared__ float2 lds[NF * lds_len<L2>()];
+  __shared__ float2 twl[L2];
+  stage_twiddles<L2>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t rp = (int64_t)blockIdx.x * NF + c;
   const int64_t nrp = n_img * (N1 / 2);
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(ffts_per_block(L2) * fft_threads(L2)) void k_rows_f
     v[e] = valid ? make_float2(wa * ra[n2], wb * ra[n2 + L2]) : make_float2(0.f, 0.f);
   }
   float2* my = lds + c * lds_len<L2>();
-  fft_wg<L2, P, false>(v, my, tw, t);
+  fft_wg<L2, P, false>(v, my, twl, t);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < P; ++e) my[lpad(t + T * e)] = v[e];
@@ -91,6 +93,8 @@ __global__ __launch_bounds__(ffts_per_block(L2) * fft_threads(L2)) void k_rows_i
     int mode, float* __restrict__ out, float scale, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L2), T = L2 / P, NF = ffts_per_block(L2), H2 = L2 / 2 + 1;
   __shared__ float2 lds[NF * lds_len<L2>()];
+  __shared__ float2 twl[L2];
+  stage_twiddles<L2>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t rp = (int64_t)blockIdx.x * NF + c;
   const int64_t nrp = n_img * (N1 / 2);
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(ffts_per_block(L2) * fft_threads(L2)) void k_rows_i
       }
       v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
     }
-    fft_wg<L2, P, true>(v, my, tw, t);
+    fft_wg<L2, P, true>(v, my, twl, t);
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       float wa, wb;
@@ -150,6 +154,8 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
     const float2* __restrict__ Hs, float2* __restrict__ Tout, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  stage_twiddles<L1>(twl, tw);
   const int c = threadIdx.x % NF, t = threadIdx.x / NF;
   const int nblk = (H2 + NF - 1) / NF;
   const int64_t img = blockIdx.x / nblk;
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
       if (!dense) z = cscale(z, wrows[(int64_t)k1 * L1 + n1]);
       v[e] = z;
     }
-    fft_wg<L1, P, false>(v, my, tw, t);
+    fft_wg<L1, P, false>(v, my, twl, t);
     const float2* Hk = Hs + (int64_t)k * plane + f2;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
@@ -180,7 +186,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
       acc[e] = cfma(acc[e], hv, v[e]);
     }
   }
-  fft_wg<L1, P, true>(acc, my, tw, t);
+  fft_wg<L1, P, true>(acc, my, twl, t);
   if (valid) {
     float2* dst = Tout + img * plane + f2;
 #pragma unroll
@@ -195,6 +201,8 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
     const float2* __restrict__ Hs, float2* __restrict__ Q, int64_t q_stride, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  stage_twiddles<L1>(twl, tw);
   const int c = threadIdx.x % NF, t = threadIdx.x / NF;
   const int nblk = (H2 + NF - 1) / NF;
   const int64_t img = blockIdx.x / nblk;
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   const float2* src = V + img * plane + f2;
 #pragma unroll
   for (int e = 0; e < P; ++e) Vh[e] = valid ? src[(int64_t)(t + T * e) * H2] : make_float2(0.f, 0.f);
-  fft_wg<L1, P, false>(Vh, my, tw, t);
+  fft_wg<L1, P, false>(Vh, my, twl, t);
   const int nq = dense ? m : m2;
   const int nk1 = dense ? 1 : m1;
   for (int q = 0; q < nq; ++q) {
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
         const float2 hv = valid ? Hk[(int64_t)(t + T * e) * H2] : make_float2(0.f, 0.f);
         g[e] = cmulc(Vh[e], hv);
       }
-      fft_wg<L1, P, true>(g, my, tw, t);
+      fft_wg<L1, P, true>(g, my, twl, t);
 #pragma unroll
       for (int e = 0; e < P; ++e) {
         const float wv = dense ? 1.0f : wrows[(int64_t)k1 * L1 + t + T * e];
@@ -244,6 +252,8 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
     const float2* __restrict__ in, int H2, float2* __restrict__ out, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  stage_twiddles<L1>(twl, tw);
   const int c = threadIdx.x % NF, t = threadIdx.x / NF;
   const int nblk = (H2 + NF - 1) / NF;
   const int64_t img = blockIdx.x / nblk;
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   float2 v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) v[e] = valid ? in[img * plane + (int64_t)(t + T * e) * H2 + f2] : make_float2(0.f, 0.f);
-  fft_wg<L1, P, false>(v, lds + c * lds_len<L1>(), tw, t);
+  fft_wg<L1, P, false>(v, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < P; ++e) out[img * plane + (int64_t)(t + T * e) * H2 + f2] = v[e];

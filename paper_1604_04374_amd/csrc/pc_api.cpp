@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -45,8 +46,8 @@ std::set<const void*> g_registry;  // live plans
 // Twiddle table of the workgroup FFT engine for length L (see fft_engine.hpp):
 // for each pass (stride Ns, radix R), exp(-2 i pi q k / (Ns R)) for k < Ns,
 // 1 <= q < R, in float64 then rounded once.
-std::vector<float2> engine_twiddles(int L) {
-  const int P = pc::points_per_thread(L);
+std::vector<float2> engine_twiddles(int L, int P = 0) {
+  if (P == 0) P = pc::points_per_thread(L);
   const pc::Sched s = pc::make_sched(L, P);
   std::vector<float2> tw;
   tw.reserve(L);
@@ -314,56 +315,105 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   const int m = p->d.m;
   const int64_t pairs = (p->d.batch + 1) / 2;
   pc_status st;
-  // compacted windows and adjoint work items
+  // compacted windows and adjoint work items (term, chunk of <= L samples)
   std::vector<int> off(m), len(m);
   std::vector<int64_t> base(m);
   std::vector<float> wc;
-  std::vector<int> it_k, it_d0;
+  std::vector<int> it_k, it_d0, it_oc, it_len;
   std::vector<int64_t> it_out;
   int64_t pstride = 0;
+  bool short_support = true;
   for (int k = 0; k < m; ++k) {
     int64_t o, S;
     const float* wk = windows + (size_t)k * N;
     circular_support(wk, N, o, S);
     off[k] = (int)o;
     len[k] = (int)S;
+    if (S > L) short_support = false;
     base[k] = (int64_t)wc.size();
     for (int64_t d = 0; d < S; ++d) wc.push_back(wk[(o + d) % N]);
     for (int64_t c0 = 0; c0 < S; c0 += L) {
       it_k.push_back(k);
       it_d0.push_back((int)c0);
+      it_oc.push_back((int)((o + c0) % N));
+      const int64_t cl = std::min<int64_t>(L, S - c0);
+      it_len.push_back((int)cl);
       it_out.push_back(pstride);
-      pstride += std::min<int64_t>(L, S - c0);
+      pstride += cl;
     }
   }
+  // items that intersect each tile of 256 samples
+  const int64_t n_tiles = N / 256;
+  std::vector<int> tile_off(n_tiles + 1, 0), tile_items;
+  {
+    std::vector<std::vector<int>> lists(n_tiles);
+    for (size_t i = 0; i < it_k.size(); ++i) {
+      const int64_t a = it_oc[i], l = it_len[i];
+      const int64_t t0 = a / 256, t1 = (a + l - 1) / 256;  // may run past n_tiles: wraps
+      for (int64_t tt = t0; tt <= t1; ++tt) lists[tt % n_tiles].push_back((int)i);
+    }
+    for (int64_t tt = 0; tt < n_tiles; ++tt) {
+      auto& v = lists[tt];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      tile_off[tt] = (int)tile_items.size();
+      tile_items.insert(tile_items.end(), v.begin(), v.end());
+    }
+    tile_off[n_tiles] = (int)tile_items.size();
+  }
+  // class modulation table twC[f1 * L + n2] = exp(-2 i pi f1 n2 / N)
+  std::vector<float2> twC((size_t)N);
+  for (int f1 = 0; f1 < R; ++f1)
+    for (int n2 = 0; n2 < L; ++n2) {
+      const int64_t j = ((int64_t)f1 * n2) % N;
+      const double a = -2.0 * M_PI * (double)j / (double)N;
+      twC[(size_t)f1 * L + n2] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
   pc::Large1D& q = p->l1;
   q.L = L;
   q.R = R;
+  q.P = pc::points_per_thread(L);
+  if (const char* env = std::getenv("PC_FOURSTEP_P")) {  // tuning override
+    const int want = std::atoi(env);
+    if (pc::fourstep_variant_supported(L, R, want)) q.P = want;
+  }
   q.m = m;
+  q.short_support = short_support;
   float* dwc = nullptr;
   if ((st = p->upload(&dwc, wc, s, &p->window_bytes))) return st;
-  int *doff = nullptr, *dlen = nullptr, *dik = nullptr, *did0 = nullptr;
+  int *doff = nullptr, *dlen = nullptr, *dik = nullptr, *did0 = nullptr, *dioc = nullptr, *dilen = nullptr;
+  int *dtoff = nullptr, *dtit = nullptr;
   int64_t *dbase = nullptr, *diout = nullptr;
   if ((st = p->upload(&doff, off, s))) return st;
   if ((st = p->upload(&dlen, len, s))) return st;
   if ((st = p->upload(&dbase, base, s))) return st;
   if ((st = p->upload(&dik, it_k, s))) return st;
   if ((st = p->upload(&did0, it_d0, s))) return st;
+  if ((st = p->upload(&dioc, it_oc, s))) return st;
+  if ((st = p->upload(&dilen, it_len, s))) return st;
   if ((st = p->upload(&diout, it_out, s))) return st;
-  float2 *tw = nullptr, *twN = nullptr;
-  if ((st = p->upload(&tw, engine_twiddles(L), s))) return st;
+  if ((st = p->upload(&dtoff, tile_off, s))) return st;
+  if ((st = p->upload(&dtit, tile_items, s))) return st;
+  float2 *tw = nullptr, *twN = nullptr, *dtwC = nullptr;
+  if ((st = p->upload(&tw, engine_twiddles(L, q.P), s))) return st;
   if ((st = p->upload(&twN, unit_roots(N), s))) return st;
+  if ((st = p->upload(&dtwC, twC, s))) return st;
   q.wc = dwc;
   q.w_off = doff;
   q.w_len = dlen;
   q.w_base = dbase;
   q.tw = tw;
   q.twN = twN;
+  q.twC = dtwC;
   q.n_items = (int)it_k.size();
   q.item_k = dik;
   q.item_d0 = did0;
+  q.item_oc = dioc;
+  q.item_len = dilen;
   q.item_out = diout;
   q.p_stride = pstride;
+  q.tile_off = dtoff;
+  q.tile_items = dtit;
   float2* Hd = nullptr;
   if ((st = p->alloc(&Hd, (size_t)m * N, &p->spectra_bytes))) return st;
   q.Hd = Hd;

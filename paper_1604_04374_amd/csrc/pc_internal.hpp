@@ -65,6 +65,7 @@ LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int6
 // --------------------------------------------------------------------------
 struct Large1D {
   int L, R;                  // N = R * L
+  int P;                     // points per thread of the inner transform (plan-time choice)
   int m;
   const float* wc;           // compacted window values, concatenated
   const int* w_off;          // m: support start (mod N)
@@ -73,17 +74,25 @@ struct Large1D {
   const float2* Hd;          // m x R x L, Hd[k][f1][f2] = H_k[f1 + R f2]
   const float2* tw;          // engine twiddles for L
   const float2* twN;         // exp(-2 i pi j / N), j < N
-  // adjoint work items: (term, chunk of L samples of its support)
+  const float2* twC;         // class table: twC[f1 * L + n2] = exp(-2 i pi f1 n2 / N)
+  bool short_support;        // every window support is at most L long
+  // adjoint work items: (term, chunk of at most L samples of its support)
   int n_items;
   const int* item_k;
-  const int* item_d0;
+  const int* item_d0;        // chunk start inside the term's support
+  const int* item_oc;        // chunk origin on the circle
+  const int* item_len;       // chunk length (<= L)
   const int64_t* item_out;   // offset of the item's samples in a pair's P block
   int64_t p_stride;          // float2 per pair in the P block
+  // overlap-add: items that can cover each tile of 256 samples (CSR)
+  const int* tile_off;       // N/256 + 1 entries
+  const int* tile_items;
   // workspaces
   float2* Bws;               // pairs x R x L
   float2* Vws;               // pairs x R x L
   float2* Pws;               // pairs x p_stride
 };
+bool fourstep_variant_supported(int L, int R, int P);
 LaunchStatus launch_fold_fft(const Large1D& p, const float* xa, int64_t n_sig, float2* out, bool pairs, hipStream_t s,
                              Tracer* tr = nullptr);
 LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
