@@ -26,6 +26,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -41,28 +43,84 @@ def log(msg):
 
 # ---------------------------------------------------------------------------
 # algorithmic work of the expansion (nominal FFT counts: 2.5 N log2 N flops
-# per real transform of N points; complex MAC 8 flops per bin; one flop per
-# windowed sample)
+# per real transform of N points, 5 N log2 N per complex one; complex MAC 8
+# flops per bin; one flop per windowed sample).  Bytes: the signals read and
+# written, the m half-spectra and the windows' nonzero samples, per direction.
 # ---------------------------------------------------------------------------
 
-def algorithmic_counts_1d(n, m, batch, support_sum, inner_l, outer_r):
-    nspec = n // 2 + 1
-    fft = 2.5 * n * math.log2(n)
-    per_sig_fwd = (m + 1) * fft + 8.0 * m * nspec + support_sum
-    kernel_flops = {
-        # forward: m transforms, MAC, windows, inner part of the inverse
-        "fwd1d_large": batch * (m * fft + 8.0 * m * nspec + support_sum + 2.5 * n * math.log2(inner_l)),
-        "combine1d": batch * (2.5 * n * math.log2(outer_r)),
-        # adjoint: the forward transform of v, then m inverse transforms + MAC + windows
-        "fold_fft": batch * fft,
-        "adj1d_large": batch * (m * fft + 8.0 * m * nspec + support_sum),
-        "ola1d": batch * float(n),
-        "fwd1d_small": batch * per_sig_fwd,
-        "adj1d_small": batch * per_sig_fwd,
-    }
-    bytes_dir = batch * n * 4 * 2 + m * nspec * 8 + support_sum * 4
-    return {"flops_per_step": 2 * batch * per_sig_fwd, "bytes_per_step": 2 * bytes_dir,
-            "kernel_flops": kernel_flops}
+def _lg(x):
+    return math.log2(x) if x > 1 else 0.0
+
+
+def algorithmic_counts(p, info):
+    """Per-step (forward + adjoint) flops and bytes, and per-kernel-family
+    flops and bytes for one plan of workload ``p`` (batch ``p.batch``)."""
+    B, m = p.batch, p.m
+    ntot = p.n_total
+    support_sum = int(np.count_nonzero(p.dense_windows())) if p.ndim == 1 else (
+        int(np.count_nonzero(p.w_rows)) * p.shape[1] + int(np.count_nonzero(p.w_cols)) * p.shape[0]
+        if p.separable else int(np.count_nonzero(p.w)))
+    if p.ndim == 1:
+        n = p.shape[0]
+        nspec = n // 2 + 1
+        fft = 2.5 * n * _lg(n)
+        per_sig = (m + 1) * fft + 8.0 * m * nspec + support_sum
+        L, R = info["fft_inner"], max(info["fft_outer"], 1)
+        kf = {
+            "fwd1d_large": B * (m * fft + 8.0 * m * nspec + support_sum + 2.5 * n * _lg(L)),
+            "combine1d": B * 2.5 * n * _lg(R),
+            "fold_fft": B * fft,
+            "adj1d_large": B * (m * fft + 8.0 * m * nspec + support_sum),
+            "ola1d": B * float(n),
+            "fwd1d_small": B * per_sig,
+            "adj1d_small": B * per_sig,
+        }
+        spec_bytes = m * nspec * 8
+        kb = {"fwd1d_large": B * n * 4 + spec_bytes + support_sum * 4, "adj1d_large": spec_bytes + support_sum * 4,
+              "fwd1d_small": B * n * 8 + spec_bytes + support_sum * 4,
+              "adj1d_small": B * n * 8 + spec_bytes + support_sum * 4}
+    else:
+        n1, n2 = p.shape
+        h2 = n2 // 2 + 1
+        nq = m if not p.separable else p.w_cols.shape[0]
+        m1 = 1 if not p.separable else p.w_rows.shape[0]
+        per_sig = (m + 1) * 2.5 * ntot * _lg(ntot) + 8.0 * m * n1 * h2 + support_sum
+        rowfft = 2.5 * n1 * n2 * _lg(n2)
+        colfft = 5.0 * n1 * h2 * _lg(n1)
+        spec_bytes = m * n1 * h2 * 8
+        kf = {"rows_fwd": B * (nq + 1) * rowfft, "rows_inv": B * (nq + 1) * rowfft,
+              "cols_fwd": B * ((m + 1) * colfft + 8.0 * m * n1 * h2),
+              "cols_adj": B * ((m + 1) * colfft + 8.0 * m * n1 * h2)}
+        kb = {"cols_fwd": spec_bytes, "cols_adj": spec_bytes,
+              # the row passes read the signal and write the result once per direction
+              "rows_fwd": 2 * B * ntot * 4, "rows_inv": 2 * B * ntot * 4}
+    bytes_dir = B * ntot * 4 * 2 + m * (ntot // p.shape[-1]) * (p.shape[-1] // 2 + 1) * 8 + support_sum * 4
+    return {"flops_per_step": 2 * B * per_sig, "bytes_per_step": 2 * bytes_dir, "kernel_flops": kf,
+            "kernel_bytes": kb}
+
+
+WORKLOADS = {
+    "c1": "1D N=1024, m=8 hat windows, Gaussian h_k (sigma 0.01 + 0.02 y), batch 1",
+    "c2": "1D batch 64 x N=65536, m=32 cubic B-spline windows, Gaussian h_k; step = H_m u + H_m^* u",
+    "c3": "2D 1024x1024, m=16 (4x4 separable hat grid), anisotropic Gaussian PSF 1->4 px, batch 1",
+    "c4": "256 uneven 2D instances, sides in {128,192,256,384,512}, m in {4,9,16}, one plan each",
+    "c5": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1",
+}
+
+
+def make_problems(name):
+    import workloads as wl
+    if name == "c1":
+        return [wl.config_c1()]
+    if name == "c2":
+        return [wl.config_c2()]
+    if name == "c3":
+        return [wl.config_c3()]
+    if name == "c4":
+        return wl.config_c4()
+    if name == "c5":
+        return [wl.config_c5()]
+    raise SystemExit(f"unknown workload {name}")
 
 
 def source_digest(files):
@@ -98,6 +156,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU work budget for the oracle baseline (0 disables it)")
     ap.add_argument("--no-trace", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS),
+                    help="c2 (default) is the reported configuration; the others are extra reports")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes 5 times (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -105,31 +167,46 @@ def main():
               "(the expansion shards with no communication across signals: see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1604_04374_amd as pcm
-    import workloads as wl
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
 
-    p = wl.config_c2()
-    B, N, m = p.batch, p.shape[0], p.m
-    log(f"[bench] workload {p.name}: building plan")
-    plan = pcm.Plan(p.w, p.h, batch=B)
-    info = plan.info()
-    u = torch.from_numpy(p.u).to(dev)
-    y = torch.empty_like(u)
-    x = torch.empty_like(u)
-    support_sum = int(np.count_nonzero(p.w))  # windows' nonzero samples (compact supports)
-    counts = algorithmic_counts_1d(N, m, B, support_sum, info["fft_inner"], max(info["fft_outer"], 1))
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
+        return
+
+    probs = make_problems(args.workload)
+    log(f"[bench] workload {args.workload}: {len(probs)} plan(s)")
+    jobs = []
+    counts = {"flops_per_step": 0.0, "bytes_per_step": 0.0, "kernel_flops": {}, "kernel_bytes": {}}
+    for p in probs:
+        wins = (p.w_rows, p.w_cols) if p.separable else p.w
+        plan = pcm.Plan(wins, p.h, batch=p.batch)
+        u = torch.from_numpy(p.u).to(dev)
+        jobs.append((p, plan, u, torch.empty_like(u), torch.empty_like(u)))
+        c = algorithmic_counts(p, plan.info())
+        counts["flops_per_step"] += c["flops_per_step"]
+        counts["bytes_per_step"] += c["bytes_per_step"]
+        for key in ("kernel_flops", "kernel_bytes"):
+            for k, v in c[key].items():
+                counts[key][k] = counts[key].get(k, 0.0) + v
+    samples_per_step = sum(2 * p.batch * p.n_total for p in probs)
 
     def step():
-        plan.apply(u, out=y)
-        plan.apply_adjoint(u, out=x)
+        for _, plan, u, y, x in jobs:
+            plan.apply(u, out=y)
+            plan.apply_adjoint(u, out=x)
 
     log(f"[bench] warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -142,56 +219,82 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    samples_per_step = 2 * B * N
     value = samples_per_step / (ms_per_step * 1e-3)
 
     roofline = None
     kernels = {}
     if not args.no_trace:
         log(f"[bench] per-kernel event pass ({args.steps} steps)")
-        plan.set_tracing(True)
-        plan.trace_reset()
+        for _, plan, _, _, _ in jobs:
+            plan.set_tracing(True)
+            plan.trace_reset()
         for _ in range(args.steps):
             step()
-        kernels = plan.trace_stats()
-        plan.set_tracing(False)
-        dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
-        name, st = dom
-        flops = counts["kernel_flops"].get(name)
-        if flops is not None and st["avg_ms"] > 0:
-            achieved = flops / (st["avg_ms"] * 1e-3) / 1e12
+        for _, plan, _, _, _ in jobs:
+            for k, v in plan.trace_stats().items():
+                agg = kernels.setdefault(k, {"launches": 0, "total_ms": 0.0})
+                agg["launches"] += v["launches"]
+                agg["total_ms"] += v["total_ms"]
+            plan.set_tracing(False)
+        for v in kernels.values():
+            v["avg_ms"] = v["total_ms"] / max(v["launches"], 1)
+        name, st = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
+        # per-launch algorithmic work: totals per step / launches per step
+        launches_per_step = st["launches"] / args.steps
+        flops = counts["kernel_flops"].get(name, 0.0) / launches_per_step
+        nbytes = counts["kernel_bytes"].get(name, 0.0) / launches_per_step
+        t_s = st["avg_ms"] * 1e-3
+        if probs[0].ndim == 1:
+            achieved = flops / t_s / 1e12
             roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                        "traffic": read_traffic(name, "c2"),
-                        "avg_launch_ms": round(st["avg_ms"], 5),
-                        "flops_per_launch": flops}
+                        "traffic": read_traffic(name, args.workload),
+                        "avg_launch_ms": round(st["avg_ms"], 5), "flops_per_launch": flops}
+        else:
+            achieved = nbytes / t_s / 1e9
+            roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                        "traffic": read_traffic(name, args.workload),
+                        "avg_launch_ms": round(st["avg_ms"], 5), "bytes_per_launch": nbytes,
+                        "alu_tflops": round(flops / t_s / 1e12, 3)}
     hbm_gbps = counts["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
+    p = probs[0]
+    B = p.batch
+    _, _, _, y, x = jobs[0]
 
     cpu = None
     err = None
     if args.cpu_seconds > 0:
         from oracle import expansion as ex
         log("[bench] CPU oracle baseline")
-        w64 = p.dense_windows()
-        h64 = p.h.astype(np.float64)
-        y_gpu = y.cpu().numpy()
-        x_gpu = x.cpu().numpy()
-        done = 0
         errs = []
         tc = 0.0
-        while done < B and (tc < args.cpu_seconds or done == 0):
-            uu = p.u[done:done + 1].astype(np.float64)
-            c0 = time.perf_counter()
-            ry = ex.apply_fft(uu, w64, h64)
-            rx = ex.adjoint_fft(uu, w64, h64)
-            tc += time.perf_counter() - c0
-            errs.append(float(np.linalg.norm(y_gpu[done] - ry[0]) / np.linalg.norm(ry[0])))
-            errs.append(float(np.linalg.norm(x_gpu[done] - rx[0]) / np.linalg.norm(rx[0])))
-            done += 1
-        cpu = {"value": round(2 * done * N / tc, 1), "unit": "samples/s", "cores": ex.workers(),
+        n_sig = 0
+        done_samples = 0
+        total_sig = sum(q.batch for q in probs)
+        for q, _, _, yq, xq in jobs:
+            if tc >= args.cpu_seconds and n_sig > 0:
+                break
+            w64 = q.dense_windows()
+            h64 = q.h.astype(np.float64)
+            y_gpu = yq.cpu().numpy()
+            x_gpu = xq.cpu().numpy()
+            for b in range(q.batch):
+                if tc >= args.cpu_seconds and n_sig > 0:
+                    break
+                uu = q.u[b:b + 1].astype(np.float64)
+                c0 = time.perf_counter()
+                ry = ex.apply_fft(uu, w64, h64)
+                rx = ex.adjoint_fft(uu, w64, h64)
+                tc += time.perf_counter() - c0
+                errs.append(float(np.linalg.norm(y_gpu[b] - ry[0]) / np.linalg.norm(ry[0])))
+                errs.append(float(np.linalg.norm(x_gpu[b] - rx[0]) / np.linalg.norm(rx[0])))
+                n_sig += 1
+                done_samples += 2 * q.n_total
+        cpu = {"value": round(done_samples / tc, 1), "unit": "samples/s", "cores": ex.workers(),
                "kind": "oracle",
-               "sample": f"{done} of {B} signals, forward + adjoint, float64 FFT form (scipy.fft, "
+               "sample": f"{n_sig} of {total_sig} signals, forward + adjoint, float64 FFT form (scipy.fft, "
                          f"{ex.workers()} workers), {tc:.1f} s"}
         err = max(errs)
 
@@ -208,9 +311,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1D batch 64 x N=65536, m=32 cubic B-spline windows, Gaussian h_k; "
-                               "step = H_m u + H_m^* u",
-                   "batch": B, "n": N, "m": m},
+        "config": {"workload": WORKLOADS[args.workload], "key": args.workload, "plans": len(probs),
+                   "batch": B, "shape": list(p.shape), "m": p.m},
         "roofline": roofline,
         "hbm": {"alg_bytes_per_step": counts["bytes_per_step"], "achieved_GBps": round(hbm_gbps, 1),
                 "peak_GBps": HBM_PEAK_GBPS, "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4)},
@@ -220,7 +322,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    plan.destroy()
+    for _, plan, _, _, _ in jobs:
+        plan.destroy()
 
 
 if __name__ == "__main__":

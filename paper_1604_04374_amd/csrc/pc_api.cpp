@@ -470,12 +470,16 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   if ((st = p->alloc(&Hs, (size_t)m * plane, &p->spectra_bytes))) return st;
   q.Hs = Hs;
   const int64_t nq = dense ? m : q.m2;
-  const int64_t ra_planes = std::max<int64_t>(nq * p->d.batch, m);
-  if ((st = p->alloc(&q.RA, (size_t)(ra_planes * plane), &p->workspace_bytes))) return st;
+  if ((st = p->alloc(&q.RA, (size_t)(nq * p->d.batch * plane), &p->workspace_bytes))) return st;
   if ((st = p->alloc(&q.Tws, (size_t)(p->d.batch * plane), &p->workspace_bytes))) return st;
+  q.col_groups = pc::col_groups_for(H2, p->d.batch, (int)nq);
+  q.Part = nullptr;
+  if (q.col_groups > 1 &&
+      (st = p->alloc(&q.Part, (size_t)(q.col_groups * p->d.batch * plane), &p->workspace_bytes)))
+    return st;
   DeviceTemp hd;
   if ((st = hd.upload(h, (size_t)m * N1 * N2))) return st;
-  hipError_t e = pc::launch_spec2d(q, hd.get(), q.RA, s);
+  hipError_t e = pc::launch_spec2d(q, hd.get(), Hs, s);
   if (e != hipSuccess) return fail_hip(e, "spectra kernels");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e, "spectra kernels");

@@ -109,14 +109,17 @@ struct Plan2D {
   bool dense;                // dense windows m x N1 x N2
   const float* wrows;        // separable: m1 x N1 (factor along rows, a_k1[n1])
   const float* wcols;        // separable: m2 x N2 (factor along columns, b_k2[n2]); dense: m x N1 x N2
-  const float2* Hs;          // m x N1 x H2
+  const float2* Hs;          // m planes, column-major: Hs[k][f2][f1]
   const float2* tw1;         // engine twiddles for N1
   const float2* tw2;         // engine twiddles for N2
-  float2* RA;                // nq x batch x N1 x H2 (nq = m2 or m)
-  float2* Tws;               // batch x N1 x H2
+  float2* RA;                // nq x batch planes (nq = m2 or m), column-major [f2][n1]
+  float2* Tws;               // batch planes
+  int col_groups;            // term groups of the forward column pass
+  float2* Part;              // col_groups x batch planes of partial spectra (col_groups > 1)
 };
-// h (m x N1 x N2, lag layout) -> Hs; uses RA as scratch (needs m x N1 x H2)
-LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* scratch, hipStream_t s);
+int col_groups_for(int H2, int64_t batch, int nq);
+// h (m x N1 x N2, lag layout) -> Hs (computed in place in Hs)
+LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* Hs, hipStream_t s);
 LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s,
                           Tracer* tr = nullptr);
 LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s,
