@@ -60,6 +60,14 @@ enum {
   PC_W_SEPARABLE = 1
 };
 
+/* Plan flags. */
+enum {
+  /* Allocate, at plan creation, the workspace pc_grad_spectra needs (one
+   * spectrum-sized buffer); without it pc_grad_spectra returns
+   * PC_ERROR_INVALID_VALUE. */
+  PC_PLAN_GRADIENTS = 1u
+};
+
 typedef struct {
   int32_t ndim;     /* 1 or 2 */
   int32_t m;        /* number of terms, >= 1 */
@@ -69,7 +77,7 @@ typedef struct {
   int32_t w_format; /* PC_W_DENSE or PC_W_SEPARABLE */
   int32_t m_rows;   /* separable only: number of row-axis factors */
   int32_t m_cols;   /* separable only: number of column-axis factors */
-  uint32_t flags;   /* reserved, must be 0 */
+  uint32_t flags;   /* PC_PLAN_* bits; other bits must be 0 */
 } pc_plan_desc;
 
 /* Supported sizes.
@@ -97,7 +105,7 @@ typedef struct {
  * at creation and may be used from one stream at a time (its workspace is
  * shared by its calls).
  * Errors: INVALID_VALUE (null pointers, ndim not 1/2, m < 1, batch < 1,
- * n1 != 1 in 1D, m != m_rows*m_cols, flags != 0), UNSUPPORTED (sizes above),
+ * n1 != 1 in 1D, m != m_rows*m_cols, unknown flag bits), UNSUPPORTED (sizes above),
  * OUT_OF_MEMORY, HIP.
  */
 pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* windows, const float* h,
@@ -165,6 +173,40 @@ typedef struct {
 pc_status pc_plan_set_tracing(pc_plan plan, int32_t enable);
 pc_status pc_plan_trace_stats(pc_plan plan, pc_kernel_stat* stats, int32_t capacity, int32_t* count);
 pc_status pc_plan_trace_reset(pc_plan plan);
+
+/*
+ * Spectra as parameters.  The operator's spectra F^* h_k (section 3.5) can be
+ * read and replaced, in the natural layout of a real FFT:
+ *   1D: m x (N/2 + 1) complex64 (interleaved re, im), spec[k][f];
+ *   2D: m x N1 x (N2/2 + 1) complex64, spec[k][f1][f2] (the layout of a 2D
+ *       real FFT over the last axis, then a complex FFT over the first).
+ * The represented h_k are real: on import, the imaginary parts of the 1D DC
+ * and Nyquist bins are ignored, as an inverse real transform ignores them;
+ * in 2D the imaginary parts discarded after the column transforms (DC and
+ * Nyquist columns) are ignored the same way.  Both calls are enqueued on
+ * `stream` and return without waiting.  `spec` is device memory.
+ * Errors: INVALID_PLAN, INVALID_VALUE (null pointer), HIP.
+ */
+pc_status pc_plan_set_spectra(pc_plan plan, const void* spec, void* stream);
+pc_status pc_plan_get_spectra(pc_plan plan, void* spec, void* stream);
+
+/*
+ * pc_grad_spectra - gradient of a scalar loss L with respect to the spectra,
+ * given the input u of y = H_m u and the upstream gradient gy = dL/dy:
+ *   gspec[k][f] = (c_f / N) sum_b conj(F^*(w_k . u_b)[f]) (F^* gy_b)[f],
+ * N the number of samples per signal, c_f = 1 on the bins of the last axis
+ * that stand alone (DC, Nyquist), 2 on those that stand for a conjugate
+ * pair; complex convention dL/dRe + i dL/dIm, summed over the batch.  Layout
+ * of gspec as for pc_plan_set_spectra.  The windowed spectra F^*(w_k . u_b)
+ * are recomputed from u rather than stored.  The plan must have been
+ * created with PC_PLAN_GRADIENTS.  u, gy: device, batch x N floats; gspec:
+ * device.  Enqueued on `stream`, returns without waiting; uses the plan's
+ * workspace (not concurrently with other calls on the plan).
+ * Errors: INVALID_PLAN, INVALID_VALUE (null pointers, batch out of range,
+ * plan without PC_PLAN_GRADIENTS), HIP.
+ */
+pc_status pc_grad_spectra(pc_plan plan, const float* u, const float* gy, void* gspec, int64_t batch,
+                          void* stream);
 
 /* Static text for a status code (never NULL). */
 const char* pc_status_string(pc_status status);

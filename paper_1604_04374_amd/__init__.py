@@ -19,7 +19,7 @@ from typing import Optional, Sequence, Tuple, Union
 
 import numpy as np
 
-__all__ = ["Plan", "PCError", "KernelStat", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+__all__ = ["Plan", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,8 +39,11 @@ STATUS_NAMES = {
 
 # Every symbol include/pc.h declares.
 EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_plan_query",
+           "pc_plan_set_spectra", "pc_plan_get_spectra", "pc_grad_spectra",
            "pc_plan_set_tracing", "pc_plan_trace_stats", "pc_plan_trace_reset",
            "pc_status_string", "pc_last_error")
+
+PC_PLAN_GRADIENTS = 1
 
 
 class PlanDesc(ctypes.Structure):
@@ -92,6 +95,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_destroy.restype = ctypes.c_int
     lib.pc_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.pc_plan_query.restype = ctypes.c_int
+    lib.pc_plan_set_spectra.argtypes = [vp, vp, vp]
+    lib.pc_plan_set_spectra.restype = ctypes.c_int
+    lib.pc_plan_get_spectra.argtypes = [vp, vp, vp]
+    lib.pc_plan_get_spectra.restype = ctypes.c_int
+    lib.pc_grad_spectra.argtypes = [vp, vp, vp, vp, i64, vp]
+    lib.pc_grad_spectra.restype = ctypes.c_int
     lib.pc_plan_set_tracing.argtypes = [vp, ctypes.c_int32]
     lib.pc_plan_set_tracing.restype = ctypes.c_int
     lib.pc_plan_trace_stats.argtypes = [vp, ctypes.POINTER(KernelStat), ctypes.c_int32,
@@ -140,14 +149,14 @@ class Plan:
     """
 
     def __init__(self, windows: Union[np.ndarray, Tuple[np.ndarray, np.ndarray]], h: np.ndarray,
-                 batch: int = 1, stream=None):
+                 batch: int = 1, stream=None, gradients: bool = False):
         self._lib = load_library()
         self._handle = ctypes.c_void_p()
         h = _f32(h)
         d = PlanDesc()
         d.m = h.shape[0]
         d.batch = int(batch)
-        d.flags = 0
+        d.flags = PC_PLAN_GRADIENTS if gradients else 0
         if isinstance(windows, (tuple, list)):
             a, b = _f32(windows[0]), _f32(windows[1])
             d.w_format = PC_W_SEPARABLE
@@ -213,6 +222,52 @@ class Plan:
         inf = PlanInfo()
         _check(self._lib, self._lib.pc_plan_query(self._handle, ctypes.byref(inf)), "pc_plan_query")
         return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    @property
+    def spectra_shape(self):
+        """Shape of the natural-layout spectra: (m, N/2+1) or (m, N1, N2/2+1)."""
+        return (self.m,) + tuple(self.shape[:-1]) + (self.shape[-1] // 2 + 1,)
+
+    def get_spectra(self, out=None, stream=None):
+        """The operator's spectra as a complex64 CUDA tensor (real-FFT layout)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.spectra_shape, dtype=torch.complex64, device="cuda")
+        self._check_spec(out)
+        st = self._lib.pc_plan_get_spectra(self._handle, ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(_stream_ptr(stream, out.device)))
+        _check(self._lib, st, "pc_plan_get_spectra")
+        return out
+
+    def set_spectra(self, spec, stream=None):
+        """Replace the operator's spectra (complex64 CUDA tensor, real-FFT layout)."""
+        spec = spec.contiguous()
+        self._check_spec(spec)
+        st = self._lib.pc_plan_set_spectra(self._handle, ctypes.c_void_p(spec.data_ptr()),
+                                           ctypes.c_void_p(_stream_ptr(stream, spec.device)))
+        _check(self._lib, st, "pc_plan_set_spectra")
+
+    def grad_spectra(self, u, gy, out=None, stream=None):
+        """dL/dspec given the forward input u and dL/dy (see pc_grad_spectra)."""
+        import torch
+        u, _, batch = self._prep(u, None)
+        gy = gy.contiguous()
+        if gy.shape != u.shape or gy.dtype != torch.float32 or not gy.is_cuda:
+            raise ValueError("gy must be a float32 CUDA tensor shaped like u")
+        if out is None:
+            out = torch.empty(self.spectra_shape, dtype=torch.complex64, device=u.device)
+        self._check_spec(out)
+        st = self._lib.pc_grad_spectra(self._handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), batch,
+                                       ctypes.c_void_p(_stream_ptr(stream, u.device)))
+        _check(self._lib, st, "pc_grad_spectra")
+        return out
+
+    def _check_spec(self, t):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex64 and t.is_contiguous()
+                and tuple(t.shape) == self.spectra_shape):
+            raise ValueError(f"spectra must be a contiguous complex64 CUDA tensor of shape {self.spectra_shape}")
 
     def set_tracing(self, enable: bool = True):
         """Bracket every kernel of later calls with HIP events (see pc.h)."""

@@ -508,6 +508,9 @@ __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x,
   X(6144, 8, 24) X(6144, 16, 24) X(6144, 2, 12) X(6144, 4, 12) X(6144, 8, 12)     \
   X(6144, 16, 12)
 
+#define PC_FOR_EACH_LR(X)                                                                              \
+  X(8192, 2) X(8192, 4) X(8192, 8) X(8192, 16) X(6144, 2) X(6144, 4) X(6144, 8) X(6144, 16)
+
 bool fourstep_variant_supported(int L, int R, int P) {
 #define PC_CASE(LL, RR, PP) \
   if (L == LL && R == RR && P == PP) return true;
@@ -588,6 +591,308 @@ LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int6
                                 Tracer* tr) {
 #define PC_CASE(LL, RR, PP) \
   if (p.L == LL && p.R == RR && p.P == PP) return adj1d_large_t<LL, RR, PP>(p, v, x, batch, s, tr);
+  PC_FOR_EACH_LRP(PC_CASE)
+#undef PC_CASE
+  return hipErrorInvalidValue;
+}
+
+// ===========================================================================
+// Spectra as parameters: import / export in the natural half-spectrum layout
+// spec[k][f], f <= N/2 (the layout of a real FFT), and the gradient of a
+// scalar loss with respect to them.
+//
+// The internal spectra are full and Hermitian (they multiply pair-packed
+// complex signals), so an imported half-spectrum is extended by conjugate
+// symmetry with the imaginary parts at DC and Nyquist dropped, the values an
+// inverse real transform ignores.
+//
+// Gradient: with Z = F^*(w_k . u) and Gh = F^*(dL/dy) for a real signal, the
+// gradient with respect to spec[k][f] (convention dL/dRe + i dL/dIm) is
+// (c_f / N) conj(Z[f]) Gh[f], c_f = 1 at DC and Nyquist, 2 elsewhere.  For a
+// pair-packed signal with full spectra A = F^*(w_k . (u_a + i u_b)) and
+// C = F^*(g_a + i g_b), the sum over the two signals of conj(Z[f]) Gh[f] is
+// (E[f] + conj(E[-f])) / 2 with E = conj(A) . C, so the kernels accumulate E
+// over pairs and combine f with -f at the end.
+// ===========================================================================
+
+__device__ __forceinline__ float half_weight(int f, int n) { return (f == 0 || 2 * f == n) ? 1.f : 2.f; }
+
+__device__ __forceinline__ float2 hermitian_value(const float2* __restrict__ half, int f, int n) {
+  if (2 * f <= n) {
+    float2 v = half[f];
+    if (f == 0 || 2 * f == n) v.y = 0.f;
+    return v;
+  }
+  return cconj(half[n - f]);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_import1d_small(const float2* __restrict__ spec, float2* __restrict__ H, int m) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m * L) return;
+  const int k = (int)(gid / L), f = (int)(gid % L);
+  H[gid] = hermitian_value(spec + (int64_t)k * (L / 2 + 1), f, L);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_export1d_small(const float2* __restrict__ H, float2* __restrict__ spec,
+                                                        int m) {
+  constexpr int NH = L / 2 + 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m * NH) return;
+  const int k = (int)(gid / NH), f = (int)(gid % NH);
+  spec[gid] = H[(int64_t)k * L + f];
+}
+
+// Full spectra of pair-packed signals: out[pair][f] = F^*(x_a + i x_b)[f].
+template <int L>
+__global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fft_pairs_small(
+    const float* __restrict__ x, int64_t batch, float2* __restrict__ out, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);
+  __shared__ float2 lds[NF * lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, tw);
+  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int64_t pair = (int64_t)blockIdx.x * NF + c;
+  const int64_t sa = 2 * pair, sb = sa + 1;
+  const bool va = sa < batch, vb = sb < batch;
+  float2 v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int n = t + T * e;
+    v[e] = make_float2(va ? x[sa * L + n] : 0.f, vb ? x[sb * L + n] : 0.f);
+  }
+  fft_wg<L, P, false>(v, lds + c * lds_len<L>(), twl, t);
+  if (va) {
+#pragma unroll
+    for (int e = 0; e < P; ++e) out[pair * L + t + T * e] = v[e];
+  }
+}
+
+// gspec[k][f] for f <= N/2, one term per FFT slot, looping over the pairs.
+template <int L>
+__global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_grad1d_small(
+    const float* __restrict__ u, int64_t batch, int m, const float* __restrict__ w, const float2* __restrict__ Gc,
+    float2* __restrict__ gspec, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L), NH = L / 2 + 1;
+  __shared__ float2 lds[NF * lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, tw);
+  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int kraw = blockIdx.x * NF + c;
+  const bool ok = kraw < m;
+  const int k = ok ? kraw : m - 1;
+  float2* my = lds + c * lds_len<L>();
+  const float* wk = w + (int64_t)k * L;
+  float2 acc[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+  const int64_t pairs = (batch + 1) / 2;
+  for (int64_t pr = 0; pr < pairs; ++pr) {
+    const int64_t sa = 2 * pr, sb = sa + 1;
+    const bool vb = sb < batch;
+    float2 v[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n = t + T * e;
+      const float ww = wk[n];
+      v[e] = make_float2(ww * u[sa * L + n], vb ? ww * u[sb * L + n] : 0.f);
+    }
+    fft_wg<L, P, false>(v, my, twl, t);
+#pragma unroll
+    for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], Gc[pr * L + t + T * e]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < P; ++e) my[lpad(t + T * e)] = acc[e];
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int f = t + T * e;
+      if (f < NH) {
+        const float2 a = my[lpad(f)];
+        const float2 b = my[lpad(f == 0 ? 0 : L - f)];
+        const float sc = 0.5f * half_weight(f, L) / (float)L;
+        gspec[(int64_t)k * NH + f] = make_float2(sc * (a.x + b.x), sc * (a.y - b.y));
+      }
+    }
+  }
+}
+
+// ---- four-step layout -------------------------------------------------------
+
+template <int L, int R>
+__global__ __launch_bounds__(256) void k_import1d_large(const float2* __restrict__ spec, float2* __restrict__ Hd,
+                                                        int m) {
+  constexpr int N = L * R;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m * N) return;
+  const int k = (int)(gid / N);
+  const int rem = (int)(gid % N);
+  const int f1 = rem / L, f2 = rem % L;
+  Hd[gid] = hermitian_value(spec + (int64_t)k * (N / 2 + 1), f1 + R * f2, N);
+}
+
+template <int L, int R>
+__global__ __launch_bounds__(256) void k_export1d_large(const float2* __restrict__ Hd, float2* __restrict__ spec,
+                                                        int m) {
+  constexpr int N = L * R, NH = N / 2 + 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m * NH) return;
+  const int k = (int)(gid / NH), f = (int)(gid % NH);
+  spec[gid] = Hd[((int64_t)k * R + f % R) * L + f / R];
+}
+
+// E_k^{f1} = sum over pairs of conj(FFT_L(fold(w_k u))) . Gdec^{f1}, one
+// (term, class) per workgroup.
+template <int L, int R, int P, bool SHORT>
+__global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict__ u, int64_t batch, Large1D p,
+                                                        float2* __restrict__ E) {
+  constexpr int T = L / P, N = L * R;
+  __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 twl[L];
+  stage_twiddles<L>(twl, p.tw);
+  const int t = threadIdx.x;
+  const int f1 = blockIdx.x % R;
+  const int k = blockIdx.x / R;
+  const int S = p.w_len[k];
+  const int o = p.w_off[k];
+  const float* wc = p.wc + p.w_base[k];
+  float2 acc[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+  const int64_t pairs = (batch + 1) / 2;
+  if (S > 0) {
+    for (int64_t pr = 0; pr < pairs; ++pr) {
+      const float* xa = u + 2 * pr * N;
+      const bool hasb = 2 * pr + 1 < batch;
+      const float* xb = hasb ? xa + N : xa;
+      const float sb = hasb ? 1.f : 0.f;
+      float2 v[P];
+      if constexpr (SHORT)
+        fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+      else
+        fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+      const float2* Gp = p.Vws + (pr * R + f1) * L;
+      float2 gv[P];
+#pragma unroll
+      for (int e = 0; e < P; ++e) gv[e] = Gp[t + T * e];
+      fft_wg<L, P, false>(v, lds, twl, t);
+#pragma unroll
+      for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
+    }
+  }
+  float2* out = E + ((int64_t)k * R + f1) * L;
+#pragma unroll
+  for (int e = 0; e < P; ++e) out[t + T * e] = acc[e];
+}
+
+template <int L, int R>
+__global__ __launch_bounds__(256) void k_grad_export1d_large(const float2* __restrict__ E, float2* __restrict__ gspec,
+                                                             int m) {
+  constexpr int N = L * R, NH = N / 2 + 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m * NH) return;
+  const int k = (int)(gid / NH), f = (int)(gid % NH);
+  const int fm = (N - f) % N;
+  const float2 a = E[((int64_t)k * R + f % R) * L + f / R];
+  const float2 b = E[((int64_t)k * R + fm % R) * L + fm / R];
+  const float sc = 0.5f * half_weight(f, N) / (float)N;
+  gspec[gid] = make_float2(sc * (a.x + b.x), sc * (a.y - b.y));
+}
+
+// ---- launchers --------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+LaunchStatus launch_spectra1d(const Small1D* ps, const Large1D* pl, const float2* in, float2* out, bool import,
+                              hipStream_t s) {
+  if (ps) {
+    const Small1D& p = *ps;
+    switch (p.L) {
+#define PC_CASE(LL)                                                                                              \
+  case LL:                                                                                                       \
+    if (import)                                                                                                  \
+      hipLaunchKernelGGL(k_import1d_small<LL>, dim3(blocks_for((int64_t)p.m * LL)), dim3(256), 0, s, in,         \
+                         const_cast<float2*>(p.H), p.m);                                                         \
+    else                                                                                                         \
+      hipLaunchKernelGGL(k_export1d_small<LL>, dim3(blocks_for((int64_t)p.m * (LL / 2 + 1))), dim3(256), 0, s,   \
+                         p.H, out, p.m);                                                                         \
+    return hipGetLastError();
+      PC_FOR_EACH_L(PC_CASE)
+#undef PC_CASE
+    }
+    return hipErrorInvalidValue;
+  }
+  const Large1D& p = *pl;
+#define PC_CASE(LL, RR)                                                                                           \
+  if (p.L == LL && p.R == RR) {                                                                                   \
+    if (import)                                                                                                   \
+      hipLaunchKernelGGL((k_import1d_large<LL, RR>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, s,   \
+                         in, const_cast<float2*>(p.Hd), p.m);                                                     \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_export1d_large<LL, RR>), dim3(blocks_for((int64_t)p.m * (LL * RR / 2 + 1))),          \
+                         dim3(256), 0, s, p.Hd, out, p.m);                                                        \
+    return hipGetLastError();                                                                                     \
+  }
+  PC_FOR_EACH_LR(PC_CASE)
+#undef PC_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+static LaunchStatus grad1d_small_t(const Small1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                                   float2* work, hipStream_t s) {
+  constexpr int NF = ffts_per_block(L), T = fft_threads(L);
+  const int64_t pairs = (batch + 1) / 2;
+  hipLaunchKernelGGL(k_fft_pairs_small<L>, dim3((unsigned)((pairs + NF - 1) / NF)), dim3(NF * T), 0, s, gy, batch,
+                     work, p.tw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad1d_small<L>, dim3((unsigned)((p.m + NF - 1) / NF)), dim3(NF * T), 0, s, u, batch, p.m,
+                     p.w, work, gspec, p.tw);
+  return hipGetLastError();
+}
+
+LaunchStatus launch_grad1d_small(const Small1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                                 float2* work, hipStream_t s, Tracer* tr) {
+  TraceScope ts(tr, "grad1d_small", s);
+  switch (p.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return grad1d_small_t<LL>(p, u, gy, gspec, batch, work, s);
+    PC_FOR_EACH_L(PC_CASE)
+#undef PC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L, int R, int P>
+static LaunchStatus grad1d_large_t(const Large1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                                   float2* E, hipStream_t s, Tracer* tr) {
+  LaunchStatus e = fold_fft_t<L, R, P>(p, gy, batch, p.Vws, true, s, tr);
+  if (e != hipSuccess) return e;
+  {
+    TraceScope ts(tr, "grad1d_large", s);
+    if (p.short_support)
+      hipLaunchKernelGGL((k_grad1d_large<L, R, P, true>), dim3((unsigned)(p.m * R)), dim3(L / P), 0, s, u, batch, p,
+                         E);
+    else
+      hipLaunchKernelGGL((k_grad1d_large<L, R, P, false>), dim3((unsigned)(p.m * R)), dim3(L / P), 0, s, u, batch, p,
+                         E);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_grad_export1d_large<L, R>), dim3(blocks_for((int64_t)p.m * (L * R / 2 + 1))), dim3(256), 0, s,
+                     E, gspec, p.m);
+  return hipGetLastError();
+}
+
+LaunchStatus launch_grad1d_large(const Large1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                                 float2* E, hipStream_t s, Tracer* tr) {
+#define PC_CASE(LL, RR, PP) \
+  if (p.L == LL && p.R == RR && p.P == PP) return grad1d_large_t<LL, RR, PP>(p, u, gy, gspec, batch, E, s, tr);
   PC_FOR_EACH_LRP(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;

@@ -516,4 +516,146 @@ LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t bat
                   s, tr);
 }
 
+// ===========================================================================
+// Spectra as parameters (natural layout spec[k][f1][f2], f2 <= N2/2, the
+// layout of a real 2D FFT) and the gradient of a scalar loss with respect to
+// them: dL/dspec[k][f1][f2] = (c_f2 / N) sum_b conj(Z_kb[f1][f2]) Gh_b[f1][f2]
+// with Z_kb = F^*(w_k . u_b), Gh_b = F^*(dL/dy_b), N = N1 N2, and c_f2 = 1 at
+// the DC and Nyquist columns (whose imaginary parts the inverse real
+// transform discards after the column transform), 2 elsewhere.
+// ===========================================================================
+
+// Tiled transpose between natural [k][f1][f2] (f2 contiguous) and internal
+// [k][f2][f1] (f1 contiguous), with a scale per f2 column.
+template <bool TO_INTERNAL>
+__global__ __launch_bounds__(256) void k_transpose_spec(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                        int N1, int H2, int scale_mode, float inv_n) {
+  __shared__ float2 tile[32][33];
+  const int k = blockIdx.z;
+  const int64_t plane = (int64_t)N1 * H2;
+  // tile origin: a = f1 block, b = f2 block
+  const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
+  for (int i = ty; i < 32; i += 8) {
+    const int f1 = a0 + i, f2 = b0 + tx;       // natural: read/write along f2
+    const int g1 = a0 + tx, g2 = b0 + i;       // internal: read/write along f1
+    if (TO_INTERNAL) {
+      if (f1 < N1 && f2 < H2) tile[i][tx] = src[k * plane + (int64_t)f1 * H2 + f2];
+    } else {
+      if (g1 < N1 && g2 < H2) tile[tx][i] = src[k * plane + (int64_t)g2 * N1 + g1];
+    }
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int f1 = a0 + i, f2 = b0 + tx;
+    const int g1 = a0 + tx, g2 = b0 + i;
+    if (TO_INTERNAL) {
+      if (g1 < N1 && g2 < H2) dst[k * plane + (int64_t)g2 * N1 + g1] = tile[tx][i];
+    } else if (f1 < N1 && f2 < H2) {
+      float2 v = tile[i][tx];
+      if (scale_mode) {
+        const float c = (f2 == 0 || f2 == H2 - 1) ? inv_n : 2.f * inv_n;  // DC and Nyquist columns
+        v = cscale(v, c);
+      }
+      dst[k * plane + (int64_t)f1 * H2 + f2] = v;
+    }
+  }
+}
+
+// E_k[f2][:] = sum_b conj(colFFT(a_k1 . RA_k2[b][f2][:])) . Gh[b][f2][:], one
+// (column, term) per FFT slot.
+template <int L1>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d_cols(
+    const float2* __restrict__ RA, int64_t q_stride, const float2* __restrict__ Gh, int64_t batch, int H2, int m1,
+    int m2, int dense, const float* __restrict__ wrows, float2* __restrict__ E, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  stage_twiddles<L1>(twl, tw);
+  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int nblk = (H2 + NF - 1) / NF;
+  const int f2raw = blockIdx.x * NF + c;
+  const bool valid = f2raw < H2;
+  const int f2 = valid ? f2raw : H2 - 1;
+  const int k = blockIdx.y;
+  (void)nblk;
+  const int k1 = dense ? 0 : k / m2, q = dense ? k : k % m2;
+  (void)m1;
+  const int64_t plane = (int64_t)L1 * H2;
+  float2* my = lds + c * lds_len<L1>();
+  float2 acc[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+  for (int64_t b = 0; b < batch; ++b) {
+    const float2* col = RA + q * q_stride + b * plane + (int64_t)f2 * L1;
+    const float2* gcol = Gh + b * plane + (int64_t)f2 * L1;
+    float2 v[P], gv[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      v[e] = col[t + T * e];
+      gv[e] = gcol[t + T * e];
+      if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+    }
+    fft_wg<L1, P, false>(v, my, twl, t);
+#pragma unroll
+    for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
+  }
+  if (valid) {
+    float2* dst = E + (int64_t)k * plane + (int64_t)f2 * L1;
+#pragma unroll
+    for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
+  }
+}
+
+template <int L1>
+static LaunchStatus grad2d_cols_t(const Plan2D& p, int64_t batch, int64_t q_stride, float2* E, hipStream_t s) {
+  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
+  const int nblk = (p.H2 + NF - 1) / NF;
+  hipLaunchKernelGGL(k_grad2d_cols<L1>, dim3((unsigned)nblk, (unsigned)p.m), dim3(NF * T), 0, s, p.RA, q_stride,
+                     p.Tws, batch, p.H2, p.m1, p.m2, p.dense ? 1 : 0, p.wrows, E, p.tw1);
+  return hipGetLastError();
+}
+
+LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bool import, hipStream_t s) {
+  const dim3 grid((unsigned)((p.H2 + 31) / 32), (unsigned)((p.N1 + 31) / 32), (unsigned)p.m);
+  if (import)
+    hipLaunchKernelGGL(k_transpose_spec<true>, grid, dim3(256), 0, s, in, const_cast<float2*>(p.Hs), p.N1, p.H2, 0,
+                       1.f);
+  else
+    hipLaunchKernelGGL(k_transpose_spec<false>, grid, dim3(256), 0, s, p.Hs, out, p.N1, p.H2, 0, 1.f);
+  return hipGetLastError();
+}
+
+LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                           float2* E, hipStream_t s, Tracer* tr) {
+  const int64_t plane = (int64_t)p.N1 * p.H2;
+  const int64_t q_stride = plane * batch;
+  const int nq = p.dense ? p.m : p.m2;
+  LaunchStatus e = rows_fwd(p.N2, u, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, nq, p.RA, q_stride,
+                            p.tw2, s, tr);
+  if (e != hipSuccess) return e;
+  e = rows_fwd(p.N2, gy, p.N1, batch, nullptr, RW_NONE, 1, p.Tws, q_stride, p.tw2, s, tr);
+  if (e != hipSuccess) return e;
+  e = cols_fft(p.N1, p.Tws, p.H2, batch, p.tw1, s, tr);
+  if (e != hipSuccess) return e;
+  {
+    TraceScope ts(tr, "grad2d_cols", s);
+    switch (p.N1) {
+#define PC_CASE(LL)                                      \
+  case LL:                                               \
+    e = grad2d_cols_t<LL>(p, batch, q_stride, E, s);     \
+    break;
+      PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((unsigned)((p.H2 + 31) / 32), (unsigned)((p.N1 + 31) / 32), (unsigned)p.m);
+  hipLaunchKernelGGL(k_transpose_spec<false>, grid, dim3(256), 0, s, E, gspec, p.N1, p.H2, 1,
+                     1.0f / ((float)p.N1 * (float)p.N2));
+  return hipGetLastError();
+}
+
 }  // namespace pc

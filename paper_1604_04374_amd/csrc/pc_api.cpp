@@ -180,6 +180,8 @@ struct pc_plan_s {
   std::vector<void*> allocs;
   bool tracing = false;
   PlanTracer tracer;
+  float2* grad_ws = nullptr;  // PC_PLAN_GRADIENTS workspace
+  int64_t spec_count = 0;     // complex values of the natural-layout spectra
   pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
   ~pc_plan_s() {
@@ -533,7 +535,7 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
   if (d.ndim != 1 && d.ndim != 2) return fail(PC_ERROR_INVALID_VALUE, "ndim must be 1 or 2");
   if (d.m < 1) return fail(PC_ERROR_INVALID_VALUE, "m must be >= 1");
   if (d.batch < 1) return fail(PC_ERROR_INVALID_VALUE, "batch must be >= 1");
-  if (d.flags != 0) return fail(PC_ERROR_INVALID_VALUE, "flags must be 0");
+  if (d.flags & ~(uint32_t)PC_PLAN_GRADIENTS) return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
   if (d.n0 < 1 || d.n1 < 1) return fail(PC_ERROR_INVALID_VALUE, "sizes must be positive");
   if (d.w_format != PC_W_DENSE && d.w_format != PC_W_SEPARABLE)
     return fail(PC_ERROR_INVALID_VALUE, "unknown window format");
@@ -575,6 +577,15 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
     st = build_large1d(p, L, R, windows, h, s);
   else
     st = build_2d(p, windows, h, s);
+  if (st == PC_SUCCESS) {
+    p->spec_count = (int64_t)d.m * (d.ndim == 1 ? d.n0 / 2 + 1 : d.n0 * (d.n1 / 2 + 1));
+    if (d.flags & PC_PLAN_GRADIENTS) {
+      // 1D: pair spectra (pairs x N) or the per-class accumulators (m x N); 2D: m planes
+      const int64_t pairs = (d.batch + 1) / 2;
+      const int64_t n = path == 0 ? pairs * d.n0 : path == 1 ? (int64_t)d.m * d.n0 : d.m * d.n0 * (d.n1 / 2 + 1);
+      st = p->alloc(&p->grad_ws, (size_t)n, &p->workspace_bytes);
+    }
+  }
   if (st != PC_SUCCESS) {
     (void)hipStreamSynchronize(s);
     delete p;
@@ -654,6 +665,64 @@ pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
   r.window_bytes = p->window_bytes;
   r.workspace_bytes = p->workspace_bytes;
   *info = r;
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_set_spectra(pc_plan p, const void* spec, void* stream) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!spec) return fail(PC_ERROR_INVALID_VALUE, "spec is NULL");
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float2* in = static_cast<const float2*>(spec);
+  hipError_t e;
+  if (p->path == 0)
+    e = pc::launch_spectra1d(&p->s1, nullptr, in, nullptr, true, s);
+  else if (p->path == 1)
+    e = pc::launch_spectra1d(nullptr, &p->l1, in, nullptr, true, s);
+  else
+    e = pc::launch_spectra2d(p->p2, in, nullptr, true, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_plan_set_spectra launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_get_spectra(pc_plan p, void* spec, void* stream) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!spec) return fail(PC_ERROR_INVALID_VALUE, "spec is NULL");
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* out = static_cast<float2*>(spec);
+  hipError_t e;
+  if (p->path == 0)
+    e = pc::launch_spectra1d(&p->s1, nullptr, nullptr, out, false, s);
+  else if (p->path == 1)
+    e = pc::launch_spectra1d(nullptr, &p->l1, nullptr, out, false, s);
+  else
+    e = pc::launch_spectra2d(p->p2, nullptr, out, false, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_plan_get_spectra launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_grad_spectra(pc_plan p, const float* u, const float* gy, void* gspec, int64_t batch, void* stream) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!p->grad_ws) return fail(PC_ERROR_INVALID_VALUE, "plan was created without PC_PLAN_GRADIENTS");
+  if (batch < 1 || batch > p->d.batch)
+    return fail(PC_ERROR_INVALID_VALUE, "batch " + std::to_string(batch) + " outside [1, " +
+                                            std::to_string(p->d.batch) + "]");
+  if (!u || !gy || !gspec) return fail(PC_ERROR_INVALID_VALUE, "null pointer");
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* out = static_cast<float2*>(gspec);
+  hipError_t e;
+  if (p->path == 0)
+    e = pc::launch_grad1d_small(p->s1, u, gy, out, batch, p->grad_ws, s, p->tr());
+  else if (p->path == 1)
+    e = pc::launch_grad1d_large(p->l1, u, gy, out, batch, p->grad_ws, s, p->tr());
+  else
+    e = pc::launch_grad2d(p->p2, u, gy, out, batch, p->grad_ws, s, p->tr());
+  if (e != hipSuccess) return fail_hip(e, "pc_grad_spectra launch");
   return PC_SUCCESS;
 }
 

@@ -125,4 +125,15 @@ LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t bat
 LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s,
                           Tracer* tr = nullptr);
 
+// Spectra as parameters (natural real-FFT layout) and their gradients.
+LaunchStatus launch_spectra1d(const Small1D* ps, const Large1D* pl, const float2* in, float2* out, bool import,
+                              hipStream_t s);
+LaunchStatus launch_grad1d_small(const Small1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                                 float2* work, hipStream_t s, Tracer* tr = nullptr);
+LaunchStatus launch_grad1d_large(const Large1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                                 float2* E, hipStream_t s, Tracer* tr = nullptr);
+LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bool import, hipStream_t s);
+LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
+                           float2* E, hipStream_t s, Tracer* tr = nullptr);
+
 }  // namespace pc
