@@ -8,7 +8,7 @@
  *
  * and its adjoint  H_m^* v = sum_k w_k . (h~_k * v),  h~_k[l] = h_k[-l],
  * on periodic 1D signals of N samples and periodic 2D images of N1 x N2
- * pixels (the extension of section 5.2).  "*" is the circular convolution of
+ * pixels (the extension of section 6.2).  "*" is the circular convolution of
  * section 3.5, written 0-based:  (h * z)[i] = sum_j h[(i - j) mod N] z[j];
  * in 2D the index pairs are taken modulo (N1, N2).  "." is the pointwise
  * product.  Windows w_k and impulse responses h_k are real; h_k is given in
@@ -207,6 +207,42 @@ pc_status pc_plan_get_spectra(pc_plan plan, void* spec, void* stream);
  */
 pc_status pc_grad_spectra(pc_plan plan, const float* u, const float* gy, void* gspec, int64_t batch,
                           void* stream);
+
+/*
+ * Uneven batches.  A batch runs many 2D operators of different sizes and
+ * term counts together: every pass of the evaluation is one launch per
+ * transform length (the work of all instances with that row or column
+ * length shares the launch), and the sequence of launches of each direction
+ * is captured once into a HIP graph, so that one pc_batch_apply call is one
+ * graph launch.
+ *
+ *   plans        (host array of count handles) 2D plans; they must outlive
+ *                the batch and must not be used by other calls while the
+ *                batch runs (the batch uses their workspaces).
+ *   inputs       (host array of count device pointers) each instance's input,
+ *                plan batch x N1 x N2 floats (the plan's full batch).
+ *   fwd_outputs  (host array) where pc_batch_apply writes H_i inputs[i].
+ *   adj_outputs  (host array) where pc_batch_apply_adjoint writes
+ *                H_i^* inputs[i].  Entries of either array may be NULL if
+ *                that direction is never used; outputs must not overlap
+ *                inputs.
+ *   flags        PC_BATCH_NO_GRAPH: launch the passes directly instead of
+ *                through the captured graphs.
+ *   stream       used to build the graphs; creation is synchronous.
+ * Errors: INVALID_VALUE (count < 1, null arrays or entries, a plan that is
+ * not 2D, overlapping buffers), INVALID_PLAN, OUT_OF_MEMORY, HIP.
+ */
+typedef struct pc_batch_s* pc_batch;
+enum { PC_BATCH_NO_GRAPH = 1u };
+pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, const float* const* inputs,
+                          float* const* fwd_outputs, float* const* adj_outputs, uint32_t flags, void* stream);
+/* Enqueue the whole batch on `stream`; returns without waiting.  Errors:
+ * INVALID_VALUE (null or destroyed batch, or a direction whose outputs were
+ * not given), HIP. */
+pc_status pc_batch_apply(pc_batch batch, void* stream);
+pc_status pc_batch_apply_adjoint(pc_batch batch, void* stream);
+/* Release the batch (waits for the device first). */
+pc_status pc_batch_destroy(pc_batch batch);
 
 /* Static text for a status code (never NULL). */
 const char* pc_status_string(pc_status status);

@@ -11,7 +11,7 @@ Modules
                definition, section 3.5's convolution), the explicit DFT
                matrices of section 3.5, and a float64 FFT library call.
 ``dense``      the dense quadrature of the integral operator (eq. 1.1) built
-               from its TVIR (introduction, Example 1).
+               from its TVIR (introduction, Example 3.1).
 ``construct``  the L2 projection of section 4.2 (used only by the
                approximation-rate test).
 ``grads``      gradients of ``0.5 ||H_m u - f||^2`` with respect to ``u`` and

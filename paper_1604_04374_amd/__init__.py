@@ -19,7 +19,7 @@ from typing import Optional, Sequence, Tuple, Union
 
 import numpy as np
 
-__all__ = ["Plan", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+__all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,7 +41,10 @@ STATUS_NAMES = {
 EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_plan_query",
            "pc_plan_set_spectra", "pc_plan_get_spectra", "pc_grad_spectra",
            "pc_plan_set_tracing", "pc_plan_trace_stats", "pc_plan_trace_reset",
+           "pc_batch_create", "pc_batch_apply", "pc_batch_apply_adjoint", "pc_batch_destroy",
            "pc_status_string", "pc_last_error")
+
+PC_BATCH_NO_GRAPH = 1
 
 PC_PLAN_GRADIENTS = 1
 
@@ -108,6 +111,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_plan_trace_stats.restype = ctypes.c_int
     lib.pc_plan_trace_reset.argtypes = [vp]
     lib.pc_plan_trace_reset.restype = ctypes.c_int
+    lib.pc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_uint32, vp]
+    lib.pc_batch_create.restype = ctypes.c_int
+    for name in ("pc_batch_apply", "pc_batch_apply_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp]
+        f.restype = ctypes.c_int
+    lib.pc_batch_destroy.argtypes = [vp]
+    lib.pc_batch_destroy.restype = ctypes.c_int
     lib.pc_status_string.argtypes = [ctypes.c_int]
     lib.pc_status_string.restype = ctypes.c_char_p
     lib.pc_last_error.argtypes = []
@@ -308,3 +320,53 @@ class Plan:
 
     def __exit__(self, *exc):
         self.destroy()
+
+
+class Batch:
+    """Many 2D operators of uneven sizes run together (see pc_batch_create).
+
+    ``plans``: list of 2D :class:`Plan`; ``inputs``: list of CUDA tensors
+    (each the plan's full batch); outputs are allocated here unless given.
+    ``apply()`` enqueues H_i inputs[i] for every instance with one graph
+    launch; ``apply_adjoint()`` the adjoints.  The tensors are kept alive by
+    the batch object and must not be reallocated.
+    """
+
+    def __init__(self, plans, inputs, fwd_outputs=None, adj_outputs=None, graph: bool = True, stream=None):
+        import torch
+        self._lib = load_library()
+        self.plans = list(plans)
+        self.inputs = [x.contiguous() for x in inputs]
+        self.fwd = list(fwd_outputs) if fwd_outputs is not None else [torch.empty_like(x) for x in self.inputs]
+        self.adj = list(adj_outputs) if adj_outputs is not None else [torch.empty_like(x) for x in self.inputs]
+        n = len(self.plans)
+        arr = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(x.data_ptr() if hasattr(x, "data_ptr") else x)  # noqa: E731
+                                                  for x in xs])
+        self._handle = ctypes.c_void_p()
+        hp = (ctypes.c_void_p * n)(*[p._handle.value for p in self.plans])
+        st = self._lib.pc_batch_create(ctypes.byref(self._handle), n, hp, arr(self.inputs), arr(self.fwd),
+                                       arr(self.adj), 0 if graph else PC_BATCH_NO_GRAPH,
+                                       ctypes.c_void_p(_stream_ptr(stream)))
+        _check(self._lib, st, "pc_batch_create")
+
+    def apply(self, stream=None):
+        _check(self._lib, self._lib.pc_batch_apply(self._handle, ctypes.c_void_p(_stream_ptr(stream))),
+               "pc_batch_apply")
+        return self.fwd
+
+    def apply_adjoint(self, stream=None):
+        _check(self._lib, self._lib.pc_batch_apply_adjoint(self._handle, ctypes.c_void_p(_stream_ptr(stream))),
+               "pc_batch_apply_adjoint")
+        return self.adj
+
+    def destroy(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            st = self._lib.pc_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+            _check(self._lib, st, "pc_batch_destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

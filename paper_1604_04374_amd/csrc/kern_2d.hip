@@ -1,6 +1,6 @@
 // 2D kernels of the convolution-product expansion on an N1 x N2 periodic
 // image (row-major, N2 contiguous); the higher-dimensional extension of
-// section 5.2 with index pairs taken modulo (N1, N2).
+// section 6.2 with index pairs taken modulo (N1, N2).
 //
 // The 2D transform is taken as real row transforms followed by complex
 // column transforms on the N2/2 + 1 retained column frequencies (the
@@ -22,6 +22,8 @@
 //           rows:  x = sum_q b_q . rowIFFT(Q_q) / (N1 N2)
 // With dense (non-separable) windows q runs over the m terms, a = 1 and
 // b_q = w_q.
+#include <vector>
+
 #include "fft_engine.hpp"
 #include "pc_internal.hpp"
 
@@ -48,6 +50,13 @@ __device__ __forceinline__ void row_weights(const float* __restrict__ wsrc, int 
 }
 
 // ---------------------------------------------------------------------------
+// Launches are table-driven: every block reads a BlockRef (job, image,
+// block, factor) and its job's descriptor, so one launch serves every
+// instance whose transforms have the kernel's length, whatever their other
+// dimension, term count or window format.  A single plan is the one-job case.
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
 // row kernels: G row pairs (2G rows) per workgroup
 // ---------------------------------------------------------------------------
 
@@ -59,29 +68,32 @@ constexpr int row_pairs_per_block(int L2) {
   return g;
 }
 
-// Half-spectra of windowed rows, transposed: out[q][img][f2][n1], f2 < H2.
+// Half-spectra of windowed rows, transposed: sout[q][img][f2][n1], f2 < H2.
 template <int L2>
 __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_rows_fwd(
-    const float* __restrict__ x, int N1, const float* __restrict__ wsrc, int mode, float2* __restrict__ out,
-    int64_t q_stride, const float2* __restrict__ tw) {
+    const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
+    const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L2), T = L2 / P, G = row_pairs_per_block(L2), H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
   stage_twiddles<L2>(twl, tw);
+  const BlockRef bm = bmap[blockIdx.x];
+  const RowJob& jb = jobs[bm.job];
+  const int N1 = jb.N1;
+  const float* x = jb.x ? jb.x : x_arg;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int blocks_per_img = N1 / (2 * G);
-  const int64_t img = blockIdx.x / blocks_per_img;
-  const int r0 = (blockIdx.x % blocks_per_img) * 2 * G;
+  const int64_t img = bm.img;
+  const int r0 = bm.blk * 2 * G;
   const int r = r0 + 2 * c;
-  const int q = blockIdx.y;
+  const int q = bm.q;
   const float* ra = x + (img * N1 + r) * L2;
   float2 v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
     float wa, wb;
-    row_weights(wsrc, mode, q, N1, L2, r, n2, wa, wb);
+    row_weights(jb.wsrc, jb.mode, q, N1, L2, r, n2, wa, wb);
     v[e] = make_float2(wa * ra[n2], wb * ra[n2 + L2]);
   }
   float2* my = lds + c * lds_len<L2>();
@@ -111,7 +123,7 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
     }
   }
   __syncthreads();
-  float2* o = out + (int64_t)q * q_stride + img * ((int64_t)H2 * N1) + r0;
+  float2* o = jb.sout + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
   for (int idx = threadIdx.x; idx < H2 * 2 * G; idx += NT) {
     const int f = idx / (2 * G), ri = idx % (2 * G);
     o[(int64_t)f * N1 + ri] = lds[idx];
@@ -119,27 +131,30 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
 }
 
 // Real rows from transposed half-spectra:
-// out[img][n1][n2] = scale * sum_q w_q . rowIFFT(in[q][img][:, n1]).
+// y[img][n1][n2] = scale * sum_{q < nq} w_q . rowIFFT(sin[q][img][:, n1]).
 template <int L2>
 __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_rows_inv(
-    const float2* __restrict__ in, int nq, int64_t q_stride, int N1, const float* __restrict__ wsrc, int mode,
-    float* __restrict__ out, float scale, const float2* __restrict__ tw) {
+    const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
+    const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L2), T = L2 / P, G = row_pairs_per_block(L2), H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
   stage_twiddles<L2>(twl, tw);
+  const BlockRef bm = bmap[blockIdx.x];
+  const RowJob& jb = jobs[bm.job];
+  const int N1 = jb.N1;
+  float* yout = jb.y ? jb.y : y_arg;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int blocks_per_img = N1 / (2 * G);
-  const int64_t img = blockIdx.x / blocks_per_img;
-  const int r0 = (blockIdx.x % blocks_per_img) * 2 * G;
+  const int64_t img = bm.img;
+  const int r0 = bm.blk * 2 * G;
   const int r = r0 + 2 * c;
   float2* my = lds + c * lds_len<L2>();
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  for (int q = 0; q < nq; ++q) {
-    const float2* src = in + (int64_t)q * q_stride + img * ((int64_t)H2 * N1) + r0;
+  for (int q = 0; q < jb.nq; ++q) {
+    const float2* src = jb.sin + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
     __syncthreads();  // the previous transform is done with LDS
     for (int idx = threadIdx.x; idx < H2 * 2 * G; idx += NT) {
       const int f = idx / (2 * G), ri = idx % (2 * G);
@@ -168,17 +183,17 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       float wa, wb;
-      row_weights(wsrc, mode, q, N1, L2, r, t + T * e, wa, wb);
+      row_weights(jb.wsrc, jb.mode, q, N1, L2, r, t + T * e, wa, wb);
       acc[e].x = fmaf(wa, v[e].x, acc[e].x);
       acc[e].y = fmaf(wb, v[e].y, acc[e].y);
     }
   }
-  float* oa = out + (img * N1 + r) * L2;
+  float* oa = yout + (img * N1 + r) * L2;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
-    oa[n2] = acc[e].x * scale;
-    oa[n2 + L2] = acc[e].y * scale;
+    oa[n2] = acc[e].x * jb.scale;
+    oa[n2 + L2] = acc[e].y * jb.scale;
   }
 }
 
@@ -186,29 +201,29 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
 // column kernels: NF columns per workgroup, each column contiguous
 // ---------------------------------------------------------------------------
 
-// Forward column pass for the term group blockIdx.y: the group takes the
-// column factors q in [q0, q1) and, for each, every row factor k1 (the
-// column of RA_q is loaded once and reused for all of them).
-// ngroups == 1: T = colIFFT(S) is written directly; otherwise the partial
-// spectrum S_g goes to part[g] for the summing kernel.
+// Forward column pass for the term group bm.q: the group takes the column
+// factors q in [q0, q1) and, for each, every row factor k1 (the column of
+// src_q is loaded once and reused for all of them).  ngroups == 1: the
+// inverse column transform of the sum is written to dst; otherwise the
+// partial spectrum goes to part[group] for k_cols_sum_inv.
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
-    const float2* __restrict__ RA, int64_t q_stride, int H2, int m1, int m2, int dense,
-    const float* __restrict__ wrows, const float2* __restrict__ Hs, int ngroups, float2* __restrict__ Tout,
-    float2* __restrict__ part, int64_t part_stride, const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
   stage_twiddles<L1>(twl, tw);
+  const BlockRef bm = bmap[blockIdx.x];
+  const ColJob& jb = jobs[bm.job];
+  const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense, ngroups = jb.ngroups;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int nblk = (H2 + NF - 1) / NF;
-  const int64_t img = blockIdx.x / nblk;
-  const int f2raw = (blockIdx.x % nblk) * NF + c;
+  const int64_t img = bm.img;
+  const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
   const int f2 = valid ? f2raw : H2 - 1;  // idle slots recompute a valid column and store nothing
   const int64_t plane = (int64_t)L1 * H2;
   const int nq = dense ? m1 * m2 : m2;  // dense windows: q runs over all terms
-  const int g = blockIdx.y;
+  const int g = bm.q;
   const int q0 = (int)((int64_t)nq * g / ngroups), q1 = (int)((int64_t)nq * (g + 1) / ngroups);
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
@@ -216,18 +231,18 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
   for (int q = q0; q < q1; ++q) {
-    const float2* col = RA + q * q_stride + img * plane + (int64_t)f2 * L1;
+    const float2* col = jb.src + q * jb.q_stride + img * plane + (int64_t)f2 * L1;
     float2 cv[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) cv[e] = col[t + T * e];
     for (int k1 = 0; k1 < nk1; ++k1) {
       const int k = dense ? q : k1 * m2 + q;
-      const float2* Hk = Hs + (int64_t)k * plane + (int64_t)f2 * L1;
+      const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
       float2 hv[P], v[P];
 #pragma unroll
       for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
 #pragma unroll
-      for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+      for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], jb.wrows[(int64_t)k1 * L1 + t + T * e]);
       fft_wg<L1, P, false>(v, my, twl, t);
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
@@ -236,69 +251,71 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   if (ngroups == 1) {
     fft_wg<L1, P, true>(acc, my, twl, t);
     if (valid) {
-      float2* dst = Tout + img * plane + (int64_t)f2 * L1;
+      float2* dst = jb.dst + img * plane + (int64_t)f2 * L1;
 #pragma unroll
       for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
     }
   } else if (valid) {
-    float2* dst = part + g * part_stride + img * plane + (int64_t)f2 * L1;
+    float2* dst = jb.part + g * jb.part_stride + img * plane + (int64_t)f2 * L1;
 #pragma unroll
     for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
   }
 }
 
-// T[img][f2][:] = colIFFT(sum_g part[g][img][f2][:]).
+// dst[img][f2][:] = colIFFT(sum_g part[g][img][f2][:]).
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_sum_inv(
-    const float2* __restrict__ part, int64_t part_stride, int ngroups, int H2, float2* __restrict__ Tout,
-    const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
   stage_twiddles<L1>(twl, tw);
+  const BlockRef bm = bmap[blockIdx.x];
+  const ColJob& jb = jobs[bm.job];
+  const int H2 = jb.H2;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int nblk = (H2 + NF - 1) / NF;
-  const int64_t img = blockIdx.x / nblk;
-  const int f2raw = (blockIdx.x % nblk) * NF + c;
+  const int64_t img = bm.img;
+  const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
   const int f2 = valid ? f2raw : H2 - 1;
   const int64_t off = img * ((int64_t)L1 * H2) + (int64_t)f2 * L1;
   float2 acc[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) acc[e] = part[off + t + T * e];
-  for (int g = 1; g < ngroups; ++g) {
+  for (int e = 0; e < P; ++e) acc[e] = jb.part[off + t + T * e];
+  for (int g = 1; g < jb.ngroups; ++g) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], part[g * part_stride + off + t + T * e]);
+    for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], jb.part[g * jb.part_stride + off + t + T * e]);
   }
   fft_wg<L1, P, true>(acc, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) Tout[off + t + T * e] = acc[e];
+    for (int e = 0; e < P; ++e) jb.dst[off + t + T * e] = acc[e];
   }
 }
 
-// Adjoint column pass, one (column, q) per FFT slot:
-// Q_q[img][f2][:] = sum_k1 a_k1 . colIFFT(conj(H_k) . Vh[img][f2][:]).
+// Adjoint column pass, one (column, q = bm.q) per FFT slot:
+// dst_q[img][f2][:] = sum_k1 a_k1 . colIFFT(conj(H_k) . src[img][f2][:]).
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
-    const float2* __restrict__ Vh, int H2, int m1, int m2, int dense, const float* __restrict__ wrows,
-    const float2* __restrict__ Hs, float2* __restrict__ Q, int64_t q_stride, const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
   stage_twiddles<L1>(twl, tw);
+  const BlockRef bm = bmap[blockIdx.x];
+  const ColJob& jb = jobs[bm.job];
+  const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int nblk = (H2 + NF - 1) / NF;
-  const int64_t img = blockIdx.x / nblk;
-  const int f2raw = (blockIdx.x % nblk) * NF + c;
+  const int64_t img = bm.img;
+  const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
   const int f2 = valid ? f2raw : H2 - 1;
-  const int q = blockIdx.y;
+  const int q = bm.q;
   const int64_t plane = (int64_t)L1 * H2;
   const int64_t coff = img * plane + (int64_t)f2 * L1;
   float2 vh[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) vh[e] = Vh[coff + t + T * e];
+  for (int e = 0; e < P; ++e) vh[e] = jb.src[coff + t + T * e];
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
   float2 acc[P];
@@ -306,169 +323,72 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
   for (int k1 = 0; k1 < nk1; ++k1) {
     const int k = dense ? q : k1 * m2 + q;
-    const float2* Hk = Hs + (int64_t)k * plane + (int64_t)f2 * L1;
+    const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
     float2 g[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], Hk[t + T * e]);
     fft_wg<L1, P, true>(g, my, twl, t);
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      const float wv = dense ? 1.0f : wrows[(int64_t)k1 * L1 + t + T * e];
+      const float wv = dense ? 1.0f : jb.wrows[(int64_t)k1 * L1 + t + T * e];
       acc[e].x = fmaf(wv, g[e].x, acc[e].x);
       acc[e].y = fmaf(wv, g[e].y, acc[e].y);
     }
   }
   if (valid) {
-    float2* dst = Q + q * q_stride + coff;
+    float2* dst = jb.dst + q * jb.q_stride + coff;
 #pragma unroll
     for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
   }
 }
 
-// In-place column FFTs: io[img][f2][:] = colFFT(io[img][f2][:]).
+// In-place column FFTs of dst: dst[img][f2][:] = colFFT(dst[img][f2][:]).
 template <int L1>
-__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fft(float2* __restrict__ io, int H2,
-                                                                                 const float2* __restrict__ tw) {
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fft(
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
   stage_twiddles<L1>(twl, tw);
+  const BlockRef bm = bmap[blockIdx.x];
+  const ColJob& jb = jobs[bm.job];
+  const int H2 = jb.H2;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int nblk = (H2 + NF - 1) / NF;
-  const int64_t img = blockIdx.x / nblk;
-  const int f2raw = (blockIdx.x % nblk) * NF + c;
+  const int64_t img = bm.img;
+  const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
   const int f2 = valid ? f2raw : H2 - 1;
   const int64_t off = img * ((int64_t)L1 * H2) + (int64_t)f2 * L1;
   float2 v[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) v[e] = io[off + t + T * e];
+  for (int e = 0; e < P; ++e) v[e] = jb.dst[off + t + T * e];
   fft_wg<L1, P, false>(v, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) io[off + t + T * e] = v[e];
+    for (int e = 0; e < P; ++e) jb.dst[off + t + T * e] = v[e];
   }
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// host side: block maps and launches
 // ---------------------------------------------------------------------------
-template <int L2>
-static LaunchStatus rows_fwd_t(const float* x, int N1, int64_t n_img, const float* wsrc, int mode, int nq,
-                               float2* out, int64_t q_stride, const float2* tw, hipStream_t s) {
-  constexpr int G = row_pairs_per_block(L2), T = fft_threads(L2);
-  const int64_t blocks = n_img * (N1 / (2 * G));
-  hipLaunchKernelGGL(k_rows_fwd<L2>, dim3((unsigned)blocks, (unsigned)nq), dim3(G * T), 0, s, x, N1, wsrc, mode, out,
-                     q_stride, tw);
-  return hipGetLastError();
+int row_block_rows(int L2) { return 2 * row_pairs_per_block(L2); }
+int col_block_cols(int L1) { return ffts_per_block(L1); }
+int row_threads(int L2) { return row_pairs_per_block(L2) * fft_threads(L2); }
+int col_threads(int L1) { return ffts_per_block(L1) * fft_threads(L1); }
+
+void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq) {
+  const int nb = N1 / row_block_rows(L2);
+  for (int64_t img = 0; img < n_img; ++img)
+    for (int b = 0; b < nb; ++b)
+      for (int q = 0; q < nq; ++q) out.push_back(BlockRef{job, (int)img, b, q});
 }
 
-template <int L2>
-static LaunchStatus rows_inv_t(const float2* in, int nq, int64_t q_stride, int N1, int64_t n_img, const float* wsrc,
-                               int mode, float* out, float scale, const float2* tw, hipStream_t s) {
-  constexpr int G = row_pairs_per_block(L2), T = fft_threads(L2);
-  const int64_t blocks = n_img * (N1 / (2 * G));
-  hipLaunchKernelGGL(k_rows_inv<L2>, dim3((unsigned)blocks), dim3(G * T), 0, s, in, nq, q_stride, N1, wsrc, mode, out,
-                     scale, tw);
-  return hipGetLastError();
-}
-
-template <int L1>
-static LaunchStatus cols_fwd_t(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
-  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
-  const int nblk = (p.H2 + NF - 1) / NF;
-  const int64_t plane = (int64_t)L1 * p.H2;
-  const int ng = p.col_groups;
-  hipLaunchKernelGGL(k_cols_fwd<L1>, dim3((unsigned)(nblk * n_img), (unsigned)ng), dim3(NF * T), 0, s, p.RA,
-                     q_stride, p.H2, p.m1, p.m2, p.dense ? 1 : 0, p.wrows, p.Hs, ng, p.Tws, p.Part, plane * n_img,
-                     p.tw1);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || ng == 1) return e;
-  hipLaunchKernelGGL(k_cols_sum_inv<L1>, dim3((unsigned)(nblk * n_img)), dim3(NF * T), 0, s, p.Part, plane * n_img,
-                     ng, p.H2, p.Tws, p.tw1);
-  return hipGetLastError();
-}
-
-template <int L1>
-static LaunchStatus cols_adj_t(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s) {
-  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
-  const int nblk = (p.H2 + NF - 1) / NF;
-  const int nq = p.dense ? p.m : p.m2;
-  hipLaunchKernelGGL(k_cols_adj<L1>, dim3((unsigned)(nblk * n_img), (unsigned)nq), dim3(NF * T), 0, s, p.Tws, p.H2,
-                     p.m1, p.m2, p.dense ? 1 : 0, p.wrows, p.Hs, p.RA, q_stride, p.tw1);
-  return hipGetLastError();
-}
-
-template <int L1>
-static LaunchStatus cols_fft_t(float2* io, int H2, int64_t n_img, const float2* tw, hipStream_t s) {
-  constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
-  const int nblk = (H2 + NF - 1) / NF;
-  hipLaunchKernelGGL(k_cols_fft<L1>, dim3((unsigned)(nblk * n_img)), dim3(NF * T), 0, s, io, H2, tw);
-  return hipGetLastError();
-}
-
-static LaunchStatus rows_fwd(int L2, const float* x, int N1, int64_t n_img, const float* wsrc, int mode, int nq,
-                             float2* out, int64_t q_stride, const float2* tw, hipStream_t s, Tracer* tr = nullptr) {
-  TraceScope ts(tr, "rows_fwd", s);
-  switch (L2) {
-#define PC_CASE(LL) \
-  case LL:          \
-    return rows_fwd_t<LL>(x, N1, n_img, wsrc, mode, nq, out, q_stride, tw, s);
-    PC_FOR_EACH_L2(PC_CASE)
-#undef PC_CASE
-  }
-  return hipErrorInvalidValue;
-}
-
-static LaunchStatus rows_inv(int L2, const float2* in, int nq, int64_t q_stride, int N1, int64_t n_img,
-                             const float* wsrc, int mode, float* out, float scale, const float2* tw, hipStream_t s,
-                             Tracer* tr = nullptr) {
-  TraceScope ts(tr, "rows_inv", s);
-  switch (L2) {
-#define PC_CASE(LL) \
-  case LL:          \
-    return rows_inv_t<LL>(in, nq, q_stride, N1, n_img, wsrc, mode, out, scale, tw, s);
-    PC_FOR_EACH_L2(PC_CASE)
-#undef PC_CASE
-  }
-  return hipErrorInvalidValue;
-}
-
-static LaunchStatus cols_fwd(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s, Tracer* tr) {
-  TraceScope ts(tr, "cols_fwd", s);
-  switch (p.N1) {
-#define PC_CASE(LL) \
-  case LL:          \
-    return cols_fwd_t<LL>(p, n_img, q_stride, s);
-    PC_FOR_EACH_L2(PC_CASE)
-#undef PC_CASE
-  }
-  return hipErrorInvalidValue;
-}
-
-static LaunchStatus cols_adj(const Plan2D& p, int64_t n_img, int64_t q_stride, hipStream_t s, Tracer* tr) {
-  TraceScope ts(tr, "cols_adj", s);
-  switch (p.N1) {
-#define PC_CASE(LL) \
-  case LL:          \
-    return cols_adj_t<LL>(p, n_img, q_stride, s);
-    PC_FOR_EACH_L2(PC_CASE)
-#undef PC_CASE
-  }
-  return hipErrorInvalidValue;
-}
-
-static LaunchStatus cols_fft(int L1, float2* io, int H2, int64_t n_img, const float2* tw, hipStream_t s,
-                             Tracer* tr = nullptr) {
-  TraceScope ts(tr, "cols_fft", s);
-  switch (L1) {
-#define PC_CASE(LL) \
-  case LL:          \
-    return cols_fft_t<LL>(io, H2, n_img, tw, s);
-    PC_FOR_EACH_L2(PC_CASE)
-#undef PC_CASE
-  }
-  return hipErrorInvalidValue;
+void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H2, int L1, int nsub) {
+  const int nb = (H2 + col_block_cols(L1) - 1) / col_block_cols(L1);
+  for (int64_t img = 0; img < n_img; ++img)
+    for (int b = 0; b < nb; ++b)
+      for (int q = 0; q < nsub; ++q) out.push_back(BlockRef{job, (int)img, b, q});
 }
 
 int col_groups_for(int H2, int64_t batch, int nq) {
@@ -481,39 +401,116 @@ int col_groups_for(int H2, int64_t batch, int nq) {
   return g < nq ? g : nq;
 }
 
-LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* Hs, hipStream_t s) {
-  const int64_t plane = (int64_t)p.N1 * p.H2;
-  LaunchStatus e = rows_fwd(p.N2, h, p.N1, p.m, nullptr, RW_NONE, 1, Hs, plane * p.m, p.tw2, s);
+LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg, float* y_arg, hipStream_t s,
+                        Tracer* tr) {
+  if (nblocks <= 0) return hipSuccess;
+  TraceScope ts(tr, kernel_kind_name(ls.kind), s);
+  const dim3 grid((unsigned)nblocks), block((unsigned)ls.threads);
+  const RowJob* rj = static_cast<const RowJob*>(ls.jobs);
+  const ColJob* cj = static_cast<const ColJob*>(ls.jobs);
+  switch (ls.kind) {
+    case KK_ROWS_FWD:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_rows_fwd<LL>, grid, block, 0, s, rj, ls.bmap, x_arg, ls.tw); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
+    case KK_ROWS_INV:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_rows_inv<LL>, grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
+    case KK_COLS_FWD:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_cols_fwd<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
+    case KK_COLS_SUM:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_cols_sum_inv<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
+    case KK_COLS_ADJ:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_cols_adj<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
+    case KK_COLS_FFT:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_cols_fft<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+const char* kernel_kind_name(int kind) {
+  switch (kind) {
+    case KK_ROWS_FWD: return "rows_fwd";
+    case KK_ROWS_INV: return "rows_inv";
+    case KK_COLS_FWD: return "cols_fwd";
+    case KK_COLS_SUM: return "cols_sum";
+    case KK_COLS_ADJ: return "cols_adj";
+    case KK_COLS_FFT: return "cols_fft";
+  }
+  return "unknown";
+}
+
+// A single plan's launch with batch images: the block maps are image-major,
+// so a smaller batch launches a prefix of the map.
+static LaunchStatus run(const LaunchSet& ls, int64_t batch, const float* x, float* y, hipStream_t s, Tracer* tr) {
+  return launch_set(ls, ls.blocks_per_img * batch, x, y, s, tr);
+}
+
+LaunchStatus launch_spec2d(const Plan2D& p, const float* h, hipStream_t s) {
+  LaunchStatus e = launch_set(p.spec_rows, p.spec_rows.blocks, h, nullptr, s, nullptr);
   if (e != hipSuccess) return e;
-  return cols_fft(p.N1, Hs, p.H2, p.m, p.tw1, s);
+  return launch_set(p.spec_cols, p.spec_cols.blocks, nullptr, nullptr, s, nullptr);
 }
 
 LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s, Tracer* tr) {
-  const int64_t plane = (int64_t)p.N1 * p.H2;
-  const int64_t q_stride = plane * batch;
-  const int nq = p.dense ? p.m : p.m2;
-  LaunchStatus e = rows_fwd(p.N2, u, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, nq, p.RA, q_stride,
-                            p.tw2, s, tr);
-  if (e != hipSuccess) return e;
-  e = cols_fwd(p, batch, q_stride, s, tr);
-  if (e != hipSuccess) return e;
-  const float scale = 1.0f / ((float)p.N1 * (float)p.N2);
-  return rows_inv(p.N2, p.Tws, 1, 0, p.N1, batch, nullptr, RW_NONE, y, scale, p.tw2, s, tr);
+  LaunchStatus e = run(p.fwd_rows, batch, u, nullptr, s, tr);
+  if (e == hipSuccess) e = run(p.fwd_cols, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess && p.col_groups > 1) e = run(p.fwd_sum, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess) e = run(p.fwd_rows_out, batch, nullptr, y, s, tr);
+  return e;
 }
 
 LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s, Tracer* tr) {
-  const int64_t plane = (int64_t)p.N1 * p.H2;
-  const int64_t q_stride = plane * batch;
-  const int nq = p.dense ? p.m : p.m2;
-  LaunchStatus e = rows_fwd(p.N2, v, p.N1, batch, nullptr, RW_NONE, 1, p.Tws, q_stride, p.tw2, s, tr);
-  if (e != hipSuccess) return e;
-  e = cols_fft(p.N1, p.Tws, p.H2, batch, p.tw1, s, tr);
-  if (e != hipSuccess) return e;
-  e = cols_adj(p, batch, q_stride, s, tr);
-  if (e != hipSuccess) return e;
-  const float scale = 1.0f / ((float)p.N1 * (float)p.N2);
-  return rows_inv(p.N2, p.RA, nq, q_stride, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, x, scale, p.tw2,
-                  s, tr);
+  LaunchStatus e = run(p.adj_rows, batch, v, nullptr, s, tr);
+  if (e == hipSuccess) e = run(p.adj_fft, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess) e = run(p.adj_cols, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess) e = run(p.adj_rows_out, batch, nullptr, x, s, tr);
+  return e;
 }
 
 // ===========================================================================
@@ -629,14 +626,12 @@ LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bo
 LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
                            float2* E, hipStream_t s, Tracer* tr) {
   const int64_t plane = (int64_t)p.N1 * p.H2;
-  const int64_t q_stride = plane * batch;
-  const int nq = p.dense ? p.m : p.m2;
-  LaunchStatus e = rows_fwd(p.N2, u, p.N1, batch, p.wcols, p.dense ? RW_DENSE : RW_FACTOR, nq, p.RA, q_stride,
-                            p.tw2, s, tr);
+  const int64_t q_stride = plane * p.batch_cap;
+  LaunchStatus e = run(p.fwd_rows, batch, u, nullptr, s, tr);  // RA_q = rowFFT(b_q . u)
   if (e != hipSuccess) return e;
-  e = rows_fwd(p.N2, gy, p.N1, batch, nullptr, RW_NONE, 1, p.Tws, q_stride, p.tw2, s, tr);
+  e = run(p.adj_rows, batch, gy, nullptr, s, tr);              // Tws = rowFFT(gy)
   if (e != hipSuccess) return e;
-  e = cols_fft(p.N1, p.Tws, p.H2, batch, p.tw1, s, tr);
+  e = run(p.adj_fft, batch, nullptr, nullptr, s, tr);          // Tws = colFFT(Tws)
   if (e != hipSuccess) return e;
   {
     TraceScope ts(tr, "grad2d_cols", s);

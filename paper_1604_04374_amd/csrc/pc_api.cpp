@@ -4,7 +4,7 @@
 // responses, sizes) into device-resident data laid out for the kernels:
 //   * 1D, N <= 8192: dense windows and full complex spectra F^* h_k;
 //   * 1D four-step:  windows compacted to their circular support (the
-//     compact-support idea of the complexity lemma of section 3.5), spectra
+//     compact-support idea of the complexity lemma of section 3.5 (Lemma 3.2)), spectra
 //     in class-major order Hd[k][f1][f2] = H_k[f1 + R f2];
 //   * 2D:            window factors (or dense windows) and half-spectra
 //     rfft2(h_k), N1 x (N2/2 + 1), row-major.
@@ -431,9 +431,30 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   return PC_SUCCESS;
 }
 
+template <class J>
+pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vector<J>& jobs,
+                   const std::vector<pc::BlockRef>& bm, int64_t per_img, const float2* tw, hipStream_t s) {
+  J* dj = nullptr;
+  pc::BlockRef* db = nullptr;
+  pc_status st = p->upload(&dj, jobs, s);
+  if (st) return st;
+  if ((st = p->upload(&db, bm, s))) return st;
+  const bool rows = kind == pc::KK_ROWS_FWD || kind == pc::KK_ROWS_INV;
+  ls.kind = kind;
+  ls.L = L;
+  ls.threads = rows ? pc::row_threads(L) : pc::col_threads(L);
+  ls.jobs = dj;
+  ls.bmap = db;
+  ls.blocks = (int64_t)bm.size();
+  ls.blocks_per_img = per_img;
+  ls.tw = tw;
+  return PC_SUCCESS;
+}
+
 pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t s) {
   const int N1 = (int)p->d.n0, N2 = (int)p->d.n1, H2 = N2 / 2 + 1;
   const int m = p->d.m;
+  const int64_t cap = p->d.batch;
   const bool dense = p->d.w_format == PC_W_DENSE;
   pc::Plan2D& q = p->p2;
   q.N1 = N1;
@@ -441,6 +462,7 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   q.H2 = H2;
   q.m = m;
   q.dense = dense;
+  q.batch_cap = cap;
   q.m1 = dense ? 1 : p->d.m_rows;
   q.m2 = dense ? m : p->d.m_cols;
   pc_status st;
@@ -471,17 +493,79 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   float2* Hs = nullptr;
   if ((st = p->alloc(&Hs, (size_t)m * plane, &p->spectra_bytes))) return st;
   q.Hs = Hs;
-  const int64_t nq = dense ? m : q.m2;
-  if ((st = p->alloc(&q.RA, (size_t)(nq * p->d.batch * plane), &p->workspace_bytes))) return st;
-  if ((st = p->alloc(&q.Tws, (size_t)(p->d.batch * plane), &p->workspace_bytes))) return st;
-  q.col_groups = pc::col_groups_for(H2, p->d.batch, (int)nq);
+  const int nq = dense ? m : q.m2;
+  if ((st = p->alloc(&q.RA, (size_t)(nq * cap * plane), &p->workspace_bytes))) return st;
+  if ((st = p->alloc(&q.Tws, (size_t)(cap * plane), &p->workspace_bytes))) return st;
+  q.col_groups = pc::col_groups_for(H2, cap, nq);
   q.Part = nullptr;
-  if (q.col_groups > 1 &&
-      (st = p->alloc(&q.Part, (size_t)(q.col_groups * p->d.batch * plane), &p->workspace_bytes)))
+  if (q.col_groups > 1 && (st = p->alloc(&q.Part, (size_t)(q.col_groups * cap * plane), &p->workspace_bytes)))
     return st;
+
+  // launch tables
+  const int mode = dense ? 2 : 1;
+  const float scale = 1.0f / ((float)N1 * (float)N2);
+  const int rpi = N1 / pc::row_block_rows(N2);                    // row blocks per image
+  const int cpi = (H2 + pc::col_block_cols(N1) - 1) / pc::col_block_cols(N1);  // column blocks per image
+  std::vector<pc::BlockRef> bm;
+  {  // forward: rows of b_q . u -> RA
+    pc::RowJob j{nullptr, nullptr, q.wcols, mode, N1, 0, 0.f, nullptr, q.RA, plane * cap};
+    bm.clear();
+    pc::append_row_blocks(bm, 0, cap, N1, N2, nq);
+    if ((st = make_set(p, q.fwd_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, (int64_t)rpi * nq, tw2, s)))
+      return st;
+  }
+  pc::ColJob cf{q.RA, q.Tws, q.Part, Hs, q.wrows, plane * cap, plane * cap, H2, q.m1, q.m2, dense ? 1 : 0,
+                q.col_groups};
+  bm.clear();
+  pc::append_col_blocks(bm, 0, cap, H2, N1, q.col_groups);
+  if ((st = make_set(p, q.fwd_cols, pc::KK_COLS_FWD, N1, std::vector<pc::ColJob>{cf}, bm,
+                     (int64_t)cpi * q.col_groups, tw1, s)))
+    return st;
+  bm.clear();
+  pc::append_col_blocks(bm, 0, cap, H2, N1, 1);
+  if ((st = make_set(p, q.fwd_sum, pc::KK_COLS_SUM, N1, std::vector<pc::ColJob>{cf}, bm, cpi, tw1, s))) return st;
+  {  // forward: rows of T -> y
+    pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 1, scale, q.Tws, nullptr, 0};
+    bm.clear();
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
+    if ((st = make_set(p, q.fwd_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s)))
+      return st;
+  }
+  {  // adjoint: rows of v -> Tws
+    pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 0, 0.f, nullptr, q.Tws, plane * cap};
+    bm.clear();
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
+    if ((st = make_set(p, q.adj_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s))) return st;
+  }
+  pc::ColJob ca{q.Tws, q.RA, nullptr, Hs, q.wrows, plane * cap, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+  pc::ColJob cfft{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+  bm.clear();
+  pc::append_col_blocks(bm, 0, cap, H2, N1, 1);
+  if ((st = make_set(p, q.adj_fft, pc::KK_COLS_FFT, N1, std::vector<pc::ColJob>{cfft}, bm, cpi, tw1, s))) return st;
+  bm.clear();
+  pc::append_col_blocks(bm, 0, cap, H2, N1, nq);
+  if ((st = make_set(p, q.adj_cols, pc::KK_COLS_ADJ, N1, std::vector<pc::ColJob>{ca}, bm, (int64_t)cpi * nq, tw1, s)))
+    return st;
+  {  // adjoint: sum_q b_q . rows of Q_q -> x
+    pc::RowJob j{nullptr, nullptr, q.wcols, mode, N1, nq, scale, q.RA, nullptr, plane * cap};
+    bm.clear();
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
+    if ((st = make_set(p, q.adj_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s)))
+      return st;
+  }
+  {  // spectra: rows of h_k -> Hs, then columns in place
+    pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 0, 0.f, nullptr, Hs, plane * m};
+    bm.clear();
+    pc::append_row_blocks(bm, 0, m, N1, N2, 1);
+    if ((st = make_set(p, q.spec_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s))) return st;
+    pc::ColJob c{nullptr, Hs, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+    bm.clear();
+    pc::append_col_blocks(bm, 0, m, H2, N1, 1);
+    if ((st = make_set(p, q.spec_cols, pc::KK_COLS_FFT, N1, std::vector<pc::ColJob>{c}, bm, cpi, tw1, s))) return st;
+  }
   DeviceTemp hd;
   if ((st = hd.upload(h, (size_t)m * N1 * N2))) return st;
-  hipError_t e = pc::launch_spec2d(q, hd.get(), Hs, s);
+  hipError_t e = pc::launch_spec2d(q, hd.get(), s);
   if (e != hipSuccess) return fail_hip(e, "spectra kernels");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e, "spectra kernels");
@@ -509,7 +593,251 @@ pc_status check_apply(pc_plan p, const float* in, float* out, int64_t batch) {
 
 }  // namespace
 
+struct pc_batch_s {
+  int device = 0;
+  std::vector<pc_plan> plans;
+  std::vector<void*> allocs;
+  std::vector<pc::LaunchSet> fwd_seq, adj_seq;
+  bool has_fwd = false, has_adj = false, use_graph = true;
+  hipGraph_t gf = nullptr, ga = nullptr;
+  hipGraphExec_t ef = nullptr, ea = nullptr;
+  ~pc_batch_s() {
+    if (ef) (void)hipGraphExecDestroy(ef);
+    if (ea) (void)hipGraphExecDestroy(ea);
+    if (gf) (void)hipGraphDestroy(gf);
+    if (ga) (void)hipGraphDestroy(ga);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <class T>
+  pc_status upload(T** out, const std::vector<T>& host) {
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, std::max<size_t>(host.size() * sizeof(T), 256));
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc");
+    allocs.push_back(d);
+    e = hipMemcpy(d, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    *out = static_cast<T*>(d);
+    return PC_SUCCESS;
+  }
+};
+
+namespace {
+
+std::set<const void*> g_batches;  // live batches (guarded by g_registry_mu)
+
+template <class J>
+pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L, const std::vector<J>& jobs,
+                    const std::vector<pc::BlockRef>& bm, const float2* tw) {
+  if (jobs.empty()) return PC_SUCCESS;
+  J* dj = nullptr;
+  pc::BlockRef* db = nullptr;
+  pc_status st = b->upload(&dj, jobs);
+  if (st) return st;
+  if ((st = b->upload(&db, bm))) return st;
+  pc::LaunchSet ls;
+  const bool rows = kind == pc::KK_ROWS_FWD || kind == pc::KK_ROWS_INV;
+  ls.kind = kind;
+  ls.L = L;
+  ls.threads = rows ? pc::row_threads(L) : pc::col_threads(L);
+  ls.jobs = dj;
+  ls.bmap = db;
+  ls.blocks = (int64_t)bm.size();
+  ls.tw = tw;
+  seq.push_back(ls);
+  return PC_SUCCESS;
+}
+
+pc_status run_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s) {
+  for (const pc::LaunchSet& ls : seq) {
+    hipError_t e = pc::launch_set(ls, ls.blocks, nullptr, nullptr, s, nullptr);
+    if (e != hipSuccess) return fail_hip(e, "batch launch");
+  }
+  return PC_SUCCESS;
+}
+
+pc_status capture(const std::vector<pc::LaunchSet>& seq, hipStream_t cs, hipGraph_t* g, hipGraphExec_t* ex) {
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
+  pc_status st = run_seq(seq, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+  *g = graph;
+  e = hipGraphInstantiate(ex, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+  return PC_SUCCESS;
+}
+
+pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa) {
+  // group instances by row length (N2) and by column length (N1)
+  std::vector<int> n2s, n1s;
+  for (pc_plan p : b->plans) {
+    if (std::find(n2s.begin(), n2s.end(), p->p2.N2) == n2s.end()) n2s.push_back(p->p2.N2);
+    if (std::find(n1s.begin(), n1s.end(), p->p2.N1) == n1s.end()) n1s.push_back(p->p2.N1);
+  }
+  std::vector<pc::LaunchSet> rows_in_f, cols_f, rows_out_f, rows_in_a, fft_a, cols_a, rows_out_a;
+  pc_status st;
+  for (int L2 : n2s) {
+    std::vector<pc::RowJob> jf, jfo, ja, jao;
+    std::vector<pc::BlockRef> bf, bfo, ba, bao;
+    const float2* tw = nullptr;
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+      const pc::Plan2D& q = b->plans[i]->p2;
+      if (q.N2 != L2) continue;
+      tw = q.tw2;
+      const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
+      const int nq = q.dense ? q.m : q.m2, mode = q.dense ? 2 : 1;
+      const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
+      if (fo[i]) {
+        pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq);
+        jf.push_back(pc::RowJob{in[i], nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap});
+        pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1);
+        jfo.push_back(pc::RowJob{nullptr, fo[i], nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0});
+      }
+      if (fa[i]) {
+        pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
+        ja.push_back(pc::RowJob{in[i], nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap});
+        pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1);
+        jao.push_back(pc::RowJob{nullptr, fa[i], q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap});
+      }
+    }
+    if ((st = batch_set(b, rows_in_f, pc::KK_ROWS_FWD, L2, jf, bf, tw))) return st;
+    if ((st = batch_set(b, rows_out_f, pc::KK_ROWS_INV, L2, jfo, bfo, tw))) return st;
+    if ((st = batch_set(b, rows_in_a, pc::KK_ROWS_FWD, L2, ja, ba, tw))) return st;
+    if ((st = batch_set(b, rows_out_a, pc::KK_ROWS_INV, L2, jao, bao, tw))) return st;
+  }
+  for (int L1 : n1s) {
+    std::vector<pc::ColJob> jf, jt, ja;
+    std::vector<pc::BlockRef> bf, bt, ba;
+    const float2* tw = nullptr;
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+      const pc::Plan2D& q = b->plans[i]->p2;
+      if (q.N1 != L1) continue;
+      tw = q.tw1;
+      const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
+      const int nq = q.dense ? q.m : q.m2, dense = q.dense ? 1 : 0;
+      if (fo[i]) {  // one term group: the many instances already fill the device
+        pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
+        jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+      }
+      if (fa[i]) {
+        pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
+        jt.push_back(pc::ColJob{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, q.H2, q.m1, q.m2, dense, 1});
+        pc::append_col_blocks(ba, (int)ja.size(), cap, q.H2, L1, nq);
+        ja.push_back(pc::ColJob{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+      }
+    }
+    if ((st = batch_set(b, cols_f, pc::KK_COLS_FWD, L1, jf, bf, tw))) return st;
+    if ((st = batch_set(b, fft_a, pc::KK_COLS_FFT, L1, jt, bt, tw))) return st;
+    if ((st = batch_set(b, cols_a, pc::KK_COLS_ADJ, L1, ja, ba, tw))) return st;
+  }
+  for (auto* v : {&rows_in_f, &cols_f, &rows_out_f}) b->fwd_seq.insert(b->fwd_seq.end(), v->begin(), v->end());
+  for (auto* v : {&rows_in_a, &fft_a, &cols_a, &rows_out_a})
+    b->adj_seq.insert(b->adj_seq.end(), v->begin(), v->end());
+  return PC_SUCCESS;
+}
+
+pc_status check_batch(pc_batch b) {
+  std::lock_guard<std::mutex> g(g_registry_mu);
+  if (!b || !g_batches.count(b)) return fail(PC_ERROR_INVALID_VALUE, "batch handle is not a live batch");
+  return PC_SUCCESS;
+}
+
+}  // namespace
+
 extern "C" {
+
+pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, const float* const* inputs,
+                          float* const* fwd_outputs, float* const* adj_outputs, uint32_t flags, void* stream) {
+  if (!out) return fail(PC_ERROR_INVALID_VALUE, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !plans || !inputs || (!fwd_outputs && !adj_outputs))
+    return fail(PC_ERROR_INVALID_VALUE, "count < 1 or null arrays");
+  if (flags & ~(uint32_t)PC_BATCH_NO_GRAPH) return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
+  std::vector<const float*> in(count);
+  std::vector<float*> fo(count, nullptr), fa(count, nullptr);
+  int device = -1;
+  for (int i = 0; i < count; ++i) {
+    pc_status st = check_plan(plans[i]);
+    if (st) return st;
+    const pc_plan p = plans[i];
+    if (p->path != 2) return fail(PC_ERROR_INVALID_VALUE, "batches take 2D plans");
+    if (device < 0) device = p->device;
+    if (p->device != device) return fail(PC_ERROR_INVALID_VALUE, "plans of a batch must share a device");
+    in[i] = inputs[i];
+    if (fwd_outputs) fo[i] = fwd_outputs[i];
+    if (adj_outputs) fa[i] = adj_outputs[i];
+    if (!in[i] || (fwd_outputs && !fo[i]) || (adj_outputs && !fa[i]))
+      return fail(PC_ERROR_INVALID_VALUE, "null buffer for instance " + std::to_string(i));
+    const size_t bytes = (size_t)(p->d.batch * p->n_total) * sizeof(float);
+    if ((fo[i] && overlaps(in[i], fo[i], bytes)) || (fa[i] && overlaps(in[i], fa[i], bytes)))
+      return fail(PC_ERROR_INVALID_VALUE, "input and output buffers overlap for instance " + std::to_string(i));
+  }
+  pc_batch_s* b = new (std::nothrow) pc_batch_s();
+  if (!b) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  b->device = device;
+  b->plans.assign(plans, plans + count);
+  b->has_fwd = fwd_outputs != nullptr;
+  b->has_adj = adj_outputs != nullptr;
+  b->use_graph = !(flags & PC_BATCH_NO_GRAPH);
+  DeviceGuard g(device);
+  pc_status st = build_batch(b, in.data(), fo.data(), fa.data());
+  if (!st && b->use_graph) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      st = fail_hip(e, "hipStreamCreate");
+    } else {
+      if (b->has_fwd) st = capture(b->fwd_seq, cs, &b->gf, &b->ef);
+      if (!st && b->has_adj) st = capture(b->adj_seq, cs, &b->ga, &b->ea);
+      (void)hipStreamDestroy(cs);
+    }
+  }
+  (void)stream;
+  if (st) {
+    delete b;
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_registry_mu);
+    g_batches.insert(b);
+  }
+  *out = b;
+  return PC_SUCCESS;
+}
+
+static pc_status batch_run(pc_batch b, bool adjoint, void* stream) {
+  pc_status st = check_batch(b);
+  if (st) return st;
+  if (adjoint ? !b->has_adj : !b->has_fwd)
+    return fail(PC_ERROR_INVALID_VALUE, "the batch was created without outputs for this direction");
+  DeviceGuard g(b->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!b->use_graph) return run_seq(adjoint ? b->adj_seq : b->fwd_seq, s);
+  hipError_t e = hipGraphLaunch(adjoint ? b->ea : b->ef, s);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_batch_apply(pc_batch b, void* stream) { return batch_run(b, false, stream); }
+pc_status pc_batch_apply_adjoint(pc_batch b, void* stream) { return batch_run(b, true, stream); }
+
+pc_status pc_batch_destroy(pc_batch b) {
+  {
+    std::lock_guard<std::mutex> lk(g_registry_mu);
+    if (!b || !g_batches.count(b)) return fail(PC_ERROR_INVALID_VALUE, "batch handle is not a live batch");
+    g_batches.erase(b);
+  }
+  DeviceGuard g(b->device);
+  hipError_t e = hipDeviceSynchronize();
+  delete b;
+  if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize before free");
+  return PC_SUCCESS;
+}
 
 const char* pc_status_string(pc_status st) {
   switch (st) {

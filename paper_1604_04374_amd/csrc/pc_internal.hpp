@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace pc {
 
 // Launch status: hipSuccess, or hipErrorInvalidValue for a size with no
@@ -103,23 +105,84 @@ LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int6
 // --------------------------------------------------------------------------
 // 2D, N1 x N2 (row-major, N2 contiguous), half spectra N1 x (N2/2 + 1)
 // --------------------------------------------------------------------------
+
+// One instance of a row pass (row transforms of length N2).
+struct RowJob {
+  const float* x;      // input images (row-forward); null: the launch's pointer argument
+  float* y;            // output images (row-inverse); null: the launch's pointer argument
+  const float* wsrc;   // window source (see RowWin in the 2D kernels)
+  int mode;            // 0 none, 1 column factors b_q[n2], 2 dense windows w_q[n1][n2]
+  int N1;              // rows per image
+  int nq;              // row-inverse: factor planes accumulated
+  float scale;         // row-inverse: output scale
+  const float2* sin;   // row-inverse: input planes [q][img][f2][n1]
+  float2* sout;        // row-forward: output planes [q][img][f2][n1]
+  int64_t q_stride;    // elements between factor planes
+};
+
+// One instance of a column pass (column transforms of length N1).
+struct ColJob {
+  const float2* src;   // input planes
+  float2* dst;         // output planes (in place for the transform-only pass)
+  float2* part;        // partial sums of the forward pass (ngroups > 1)
+  const float2* Hs;    // spectra, m planes [k][f2][f1]
+  const float* wrows;  // row-axis window factors a_k1[n1] (separable)
+  int64_t q_stride;    // between factor planes of src (forward) / dst (adjoint)
+  int64_t part_stride;
+  int H2, m1, m2, dense, ngroups;
+};
+
+// Block of a table-driven launch: job, image, block within the image,
+// factor or term group.
+struct BlockRef {
+  int job, img, blk, q;
+};
+
+enum KernelKind { KK_ROWS_FWD = 0, KK_ROWS_INV, KK_COLS_FWD, KK_COLS_SUM, KK_COLS_ADJ, KK_COLS_FFT };
+
+// A prepared launch: kernel kind and length, device tables, block counts.
+struct LaunchSet {
+  int kind = 0;
+  int L = 0;
+  int threads = 0;
+  const void* jobs = nullptr;      // device RowJob[] or ColJob[]
+  const BlockRef* bmap = nullptr;  // device
+  int64_t blocks = 0;              // blocks of the whole table
+  int64_t blocks_per_img = 0;      // single plans: blocks per image (prefix launches)
+  const float2* tw = nullptr;      // engine twiddles for L
+};
+
 struct Plan2D {
   int N1, N2, H2;            // H2 = N2/2 + 1
   int m, m1, m2;             // separable: m = m1*m2, term k = k1*m2 + k2; dense: m1 = 1, m2 = m
   bool dense;                // dense windows m x N1 x N2
+  int64_t batch_cap;         // images the workspaces hold
   const float* wrows;        // separable: m1 x N1 (factor along rows, a_k1[n1])
   const float* wcols;        // separable: m2 x N2 (factor along columns, b_k2[n2]); dense: m x N1 x N2
   const float2* Hs;          // m planes, column-major: Hs[k][f2][f1]
   const float2* tw1;         // engine twiddles for N1
   const float2* tw2;         // engine twiddles for N2
-  float2* RA;                // nq x batch planes (nq = m2 or m), column-major [f2][n1]
-  float2* Tws;               // batch planes
+  float2* RA;                // nq x batch_cap planes (nq = m2 or m), column-major [f2][n1]
+  float2* Tws;               // batch_cap planes
   int col_groups;            // term groups of the forward column pass
-  float2* Part;              // col_groups x batch planes of partial spectra (col_groups > 1)
+  float2* Part;              // col_groups x batch_cap planes of partial spectra (col_groups > 1)
+  LaunchSet fwd_rows, fwd_cols, fwd_sum, fwd_rows_out;
+  LaunchSet adj_rows, adj_fft, adj_cols, adj_rows_out;
+  LaunchSet spec_rows, spec_cols;
 };
+
 int col_groups_for(int H2, int64_t batch, int nq);
-// h (m x N1 x N2, lag layout) -> Hs (computed in place in Hs)
-LaunchStatus launch_spec2d(const Plan2D& p, const float* h, float2* Hs, hipStream_t s);
+int row_block_rows(int L2);
+int col_block_cols(int L1);
+int row_threads(int L2);
+int col_threads(int L1);
+void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq);
+void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H2, int L1, int nsub);
+const char* kernel_kind_name(int kind);
+LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg, float* y_arg, hipStream_t s,
+                        Tracer* tr);
+// h (m x N1 x N2, lag layout) -> Hs, through the plan's spectra launch sets
+LaunchStatus launch_spec2d(const Plan2D& p, const float* h, hipStream_t s);
 LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s,
                           Tracer* tr = nullptr);
 LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s,

@@ -224,7 +224,7 @@ def test_adjoint_identity(fwd, adj):
 
 
 def test_example3_two_terms_are_exact():
-    # Example 3 is a sum of two tensor products: with the two indicator
+    # Example 3.3 is a sum of two tensor products: with the two indicator
     # windows and the two Gaussians as filters, H_2 = H to rounding.
     n = 512
     T = wl.example3_tvir(0.05, 0.1)
@@ -300,8 +300,8 @@ def _proj_errors(sigma_fn, deg, ms, n=1024):
 
 @pytest.mark.parametrize("deg", [1, 3])
 def test_projection_rate_smooth_kernel(deg):
-    # Corollary 4.2: for T(x, .) in H^s and degree >= s the HS error decays at
-    # least like m^{-s}; Example 1's width field is smooth, so s = degree.
+    # Corollary 4.3: for T(x, .) in H^s and degree >= s the HS error decays at
+    # least like m^{-s}; Example 3.1 width field is smooth, so s = degree.
     ms = [8, 16, 32, 64]
     errs = _proj_errors(wl.example1_sigma, deg, ms)
     assert all(a > b for a, b in zip(errs, errs[1:]))

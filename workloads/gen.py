@@ -12,7 +12,7 @@ Discrete model shared by every consumer:
   point ``y``.  Impulse responses ``h_k`` are samples of ``T(., c_k)`` at a
   window centre ``c_k`` (the interpolation setting of section 4.4).
 * Gaussians are unit-mass densities with standard deviation ``sigma``
-  (Example 1); they are sampled, never cell-averaged or renormalised.
+  (Example 3.1); they are sampled, never cell-averaged or renormalised.
 * B-spline windows follow the cardinal B-spline definition of the notation
   section: ``B_{0,m}`` is the indicator of width ``1/m`` and
   ``B_{a,m} = m B_{0,m} * B_{a-1,m}``, i.e. the centred cardinal B-spline of
@@ -61,7 +61,7 @@ def lag_unit(n: int) -> np.ndarray:
 
 
 def gaussian(x, sigma):
-    """Unit-mass Gaussian density of standard deviation ``sigma`` (Example 1)."""
+    """Unit-mass Gaussian density of standard deviation ``sigma`` (Example 3.1)."""
     x = np.asarray(x, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
     return np.exp(-x * x / (2.0 * sigma * sigma)) / (math.sqrt(2.0 * math.pi) * sigma)
@@ -135,19 +135,19 @@ def expand_separable(w_rows: np.ndarray, w_cols: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def tvir_gaussian(sigma_fn: Callable[[np.ndarray], np.ndarray]):
-    """TVIR of Example 1: ``T(x, y) = g_{sigma(y)}(x)`` (sigma at the source)."""
+    """TVIR of Example 3.1: ``T(x, y) = g_{sigma(y)}(x)`` (sigma at the source)."""
     def T(x, y):
         return gaussian(x, sigma_fn(np.asarray(y, dtype=np.float64)))
     return T
 
 
 def example1_sigma(y):
-    """The smooth width field used for Example 1 in Figure 1."""
+    """The smooth width field used for Example 3.1 in Figure 1."""
     return 0.08 + 0.02 * np.cos(2.0 * np.pi * np.asarray(y, np.float64))
 
 
 def example3_tvir(sigma1: float = 0.05, sigma2: float = 0.1):
-    """Example 3: two Gaussians switched by the indicator of |y| <= 1/4.
+    """Example 3.3: two Gaussians switched by the indicator of |y| <= 1/4.
 
     ``y`` is read on the centred circle [-1/2, 1/2).
     """
