@@ -105,6 +105,8 @@ WORKLOADS = {
     "c3": "2D 1024x1024, m=16 (4x4 separable hat grid), anisotropic Gaussian PSF 1->4 px, batch 1",
     "c4": "256 uneven 2D instances, sides in {128,192,256,384,512}, m in {4,9,16}, one plan each",
     "c5": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1",
+    "c5ad": "2D 2048x2048, m=64 tiles: autograd step of 0.5||H_m u - f||^2 (forward, adjoint for du, "
+            "spectra gradient), against the plain forward + adjoint",
 }
 
 
@@ -118,7 +120,7 @@ def make_problems(name):
         return [wl.config_c3()]
     if name == "c4":
         return wl.config_c4()
-    if name == "c5":
+    if name in ("c5", "c5ad"):
         return [wl.config_c5()]
     raise SystemExit(f"unknown workload {name}")
 
@@ -203,10 +205,47 @@ def main():
                 counts[key][k] = counts[key].get(k, 0.0) + v
     samples_per_step = sum(2 * p.batch * p.n_total for p in probs)
 
-    def step():
+    def step_plans():
         for _, plan, u, y, x in jobs:
             plan.apply(u, out=y)
             plan.apply_adjoint(u, out=x)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    extra = {}
+    step = step_plans
+    if args.workload == "c4":
+        # all instances in one graph launch per direction, against the loop of single plans
+        batch = pcm.Batch([j[1] for j in jobs], [j[2] for j in jobs],
+                          fwd_outputs=[j[3] for j in jobs], adj_outputs=[j[4] for j in jobs])
+
+        def step_batch():
+            batch.apply()
+            batch.apply_adjoint()
+        extra["single_plans_ms_per_step"] = round(timed(step_plans, max(args.steps // 4, 2)), 5)
+        step = step_batch
+    elif args.workload == "c5ad":
+        from paper_1604_04374_amd.autograd import ExpansionOperator
+        p0 = probs[0]
+        op = ExpansionOperator((p0.w_rows, p0.w_cols), p0.h, batch=1)
+        u_ad = jobs[0][2].clone().requires_grad_(True)
+        f_ad = torch.randn_like(u_ad)
+
+        def step_autograd():
+            u_ad.grad = None
+            op.spec.grad = None
+            loss = 0.5 * torch.sum((op(u_ad) - f_ad) ** 2)
+            loss.backward()
+        extra["plain_ms_per_step"] = round(timed(step_plans, args.steps), 5)
+        step = step_autograd
 
     log(f"[bench] warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -223,7 +262,7 @@ def main():
 
     roofline = None
     kernels = {}
-    if not args.no_trace:
+    if not args.no_trace and step is step_plans:
         log(f"[bench] per-kernel event pass ({args.steps} steps)")
         for _, plan, _, _, _ in jobs:
             plan.set_tracing(True)
@@ -259,6 +298,10 @@ def main():
                         "avg_launch_ms": round(st["avg_ms"], 5), "bytes_per_launch": nbytes,
                         "alu_tflops": round(flops / t_s / 1e12, 3)}
     hbm_gbps = counts["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
+    if roofline is None and step is not step_plans:
+        roofline = {"bound": "hbm", "kernel": "whole step (graph or autograd launches)",
+                    "achieved": round(hbm_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4), "traffic": None}
     p = probs[0]
     B = p.batch
     _, _, _, y, x = jobs[0]
@@ -320,6 +363,7 @@ def main():
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kernels.items()},
         "max_rel_l2_vs_oracle": err,
         "cpu_baseline": cpu,
+        **extra,
     }
     print(json.dumps(line), flush=True)
     for _, plan, _, _, _ in jobs:
