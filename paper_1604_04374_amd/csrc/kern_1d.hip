@@ -219,11 +219,19 @@ LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int6
 //   X[f1 + R f2] = FFT_L(a^{f1})[f2],
 //   a^{f1}[n2]   = W_N^{f1 n2} sum_{n1} x[n2 + L n1] W_R^{f1 n1},
 //
-// with W_M = exp(-2 i pi / M).  A window of compact support folds into
-// a^{f1} from its support only.  The inverse runs the same split backwards:
+// with W_M = exp(-2 i pi / M).  The inverse runs the same split backwards:
 //   y[n2 + L n1] = (1/N) sum_{f1} W_R^{-f1 n1} W_N^{-f1 n2} b^{f1}[n2],
 //   b^{f1} = unnormalised inverse FFT_L of the class-f1 spectrum.
-// W_N^{f1 n2} comes from the class table twC[f1 * L + n2] (coalesced in n2);
+//
+// A windowed term z = w_k . u with support [o, o + S) is transformed from its
+// own origin: with z'[d] = z[o + d],
+//   Z[f] = W_N^{f o} sum_d z'[d] W_N^{f d},
+// so the fold reads the support contiguously (d = slot index) and the phase
+// W_N^{f o} is carried by the stored spectra, Hd[k][f1][f2] =
+// H_k[f] W_N^{f o_k} with f = f1 + R f2.  The adjoint uses the same frame:
+// conj(Hd_k) already carries the phase W_N^{-f o_k} that restricting the
+// inverse transform to the window needs.
+// W_N^{f1 d} comes from the class table twC[f1 * L + d] (coalesced in d);
 // W_R^{j} = twN[j * L].
 // ===========================================================================
 
@@ -232,69 +240,59 @@ __device__ __forceinline__ float2 unit_root_R(const float2* __restrict__ twN, in
   return twN[(j % R) * L];
 }
 
-// a^{f1} for the thread's slots from a (window x signal) product whose
-// support [o, o + S) (mod N) is at most L long: every slot receives at most
-// one sample, found without a loop, and all loads are issued unconditionally
-// (clamped indices, zero weight off the support).
+// a^{f1}[d] = W_N^{f1 d} z[o + d] for a windowed term whose support
+// [o, o + S) is at most L long (every slot d receives at most one sample).
+// All loads are issued before any is used, with clamped indices and a zero
+// weight off the support.
 template <int L, int R, int P>
 __device__ __forceinline__ void fold_short(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
                                            const float* __restrict__ xb, float sb, const float* __restrict__ wc,
                                            int o, int S, const float2* __restrict__ twC,
                                            const float2* __restrict__ twN) {
   constexpr int T = L / P, N = L * R;
-  const int oL = o % L, n1a = o / L;
-  const float2 wr0 = unit_root_R<L, R>(twN, f1 * n1a);
-  const float2 wr1 = unit_root_R<L, R>(twN, f1 * (n1a + 1));
+  (void)twN;
   const float2* tc = twC + f1 * L;
-  // load phase: every load of the fold is issued before any is consumed
   float ra[P], rb[P], rw[P];
   float2 rt[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    const int n2 = t + T * e;
-    int d = n2 - oL;
-    if (d < 0) d += L;
+    const int d = t + T * e;
     const int dc = d < S ? d : 0;
     int n = o + dc;
     if (n >= N) n -= N;
     ra[e] = xa[n];
     rb[e] = xb[n];
     rw[e] = wc[dc];
-    rt[e] = tc[n2];
+    rt[e] = tc[d];
   }
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    const int n2 = t + T * e;
-    int d = n2 - oL;
-    if (d < 0) d += L;
+    const int d = t + T * e;
     const float ww = d < S ? rw[e] : 0.f;
-    const float2 z = make_float2(ww * ra[e], ww * sb * rb[e]);
-    v[e] = cmul(z, cmul(rt[e], (oL + d >= L) ? wr1 : wr0));
+    v[e] = cmul(make_float2(ww * ra[e], ww * sb * rb[e]), rt[e]);
   }
 }
 
-// Same for supports longer than L (several samples per slot).
+// Same for supports longer than L: a^{f1}[d] = W_N^{f1 d} sum_c z[o + d + c L] W_R^{f1 c}.
 template <int L, int R, int P>
 __device__ __forceinline__ void fold_long(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
                                           const float* __restrict__ xb, float sb, const float* __restrict__ wc,
                                           int o, int S, const float2* __restrict__ twC,
                                           const float2* __restrict__ twN) {
   constexpr int T = L / P, N = L * R;
-  const int oL = o % L;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    const int n2 = t + T * e;
-    int d = n2 - oL;
-    if (d < 0) d += L;
+    const int d0 = t + T * e;
     float2 a = make_float2(0.f, 0.f);
-    for (; d < S; d += L) {
+    int c = 0;
+    for (int d = d0; d < S; d += L, ++c) {
       int n = o + d;
       if (n >= N) n -= N;
       const float ww = wc[d];
       const float2 z = make_float2(ww * xa[n], ww * sb * xb[n]);
-      a = cfma(a, z, unit_root_R<L, R>(twN, f1 * (n / L)));
+      a = cfma(a, z, unit_root_R<L, R>(twN, f1 * c));
     }
-    v[e] = cmul(a, twC[f1 * L + n2]);
+    v[e] = cmul(a, twC[f1 * L + d0]);
   }
 }
 
@@ -431,36 +429,51 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   const int k = p.item_k[item];
   const int c0 = p.item_d0[item];
   const int Sc = p.item_len[item];
-  const int oc = p.item_oc[item];
-  const int ocL = oc % L, n1a = oc / L;
+  const int chunk = c0 / L;  // chunks start at multiples of L inside the support
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  for (int f1 = 0; f1 < R; ++f1) {
-    const float2* Hk = p.Hd + ((int64_t)k * R + f1) * L;
-    const float2* Vp = p.Vws + (pair * R + f1) * L;
-    float2 g[P], hv[P];
+  // class 0's inputs; each iteration prefetches the next class's inputs
+  // before its inverse transform
+  float2 vn[P], hn[P];
+  {
+    const float2* Hk = p.Hd + (int64_t)k * R * L;
+    const float2* Vp = p.Vws + pair * R * L;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      g[e] = Vp[t + T * e];
-      hv[e] = Hk[t + T * e];
+      vn[e] = Vp[t + T * e];
+      hn[e] = Hk[t + T * e];
     }
+  }
+  for (int f1 = 0; f1 < R; ++f1) {
+    float2 g[P];
 #pragma unroll
-    for (int e = 0; e < P; ++e) g[e] = cmulc(g[e], hv[e]);
+    for (int e = 0; e < P; ++e) g[e] = cmulc(vn[e], hn[e]);
+    if (f1 + 1 < R) {
+      const float2* Hk = p.Hd + ((int64_t)k * R + f1 + 1) * L;
+      const float2* Vp = p.Vws + (pair * R + f1 + 1) * L;
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        vn[e] = Vp[t + T * e];
+        hn[e] = Hk[t + T * e];
+      }
+    }
     fft_wg<L, P, true>(g, lds, twl, t);
-    const float2 wr0 = unit_root_R<L, R>(p.twN, f1 * n1a);
-    const float2 wr1 = unit_root_R<L, R>(p.twN, f1 * (n1a + 1));
+    // W_N^{-f1 d} from the class table; chunks after the first also carry
+    // the class factor W_R^{-f1 chunk}
     const float2* tc = p.twC + f1 * L;
     float2 rt[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) rt[e] = tc[t + T * e];
+    if (chunk != 0) {
+      const float2 u = unit_root_R<L, R>(p.twN, f1 * chunk);
+#pragma unroll
+      for (int e = 0; e < P; ++e) rt[e] = cmul(rt[e], u);
+    }
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      const int n2 = t + T * e;
-      int dd = n2 - ocL;
-      if (dd < 0) dd += L;
-      const float2 c = cmulc(g[e], cmul(rt[e], (ocL + dd >= L) ? wr1 : wr0));
-      const float keep = dd < Sc ? 1.f : 0.f;
+      const float2 c = cmulc(g[e], rt[e]);
+      const float keep = (t + T * e) < Sc ? 1.f : 0.f;
       acc[e].x = fmaf(keep, c.x, acc[e].x);
       acc[e].y = fmaf(keep, c.y, acc[e].y);
     }
@@ -470,9 +483,8 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   const float sc = 1.0f / (float)(L * R);
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    int dd = t + T * e - ocL;
-    if (dd < 0) dd += L;
-    if (dd < Sc) out[dd] = cscale(acc[e], wc[dd] * sc);
+    const int d = t + T * e;
+    if (d < Sc) out[d] = cscale(acc[e], wc[d] * sc);
   }
 }
 
@@ -722,26 +734,50 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_grad1d_s
 
 // ---- four-step layout -------------------------------------------------------
 
+// The four-step path stores its spectra in the frame of each window's origin
+// o_k: Hd[k][f1][f2] = H_k[f] W_N^{f o_k}, f = f1 + R f2.
+template <int L, int R>
+__device__ __forceinline__ float2 origin_phase(const float2* __restrict__ twN, int f, int o) {
+  constexpr int N = L * R;
+  return twN[(int)(((int64_t)f * o) % N)];
+}
+
 template <int L, int R>
 __global__ __launch_bounds__(256) void k_import1d_large(const float2* __restrict__ spec, float2* __restrict__ Hd,
-                                                        int m) {
+                                                        int m, const int* __restrict__ w_off,
+                                                        const float2* __restrict__ twN) {
   constexpr int N = L * R;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)m * N) return;
   const int k = (int)(gid / N);
   const int rem = (int)(gid % N);
-  const int f1 = rem / L, f2 = rem % L;
-  Hd[gid] = hermitian_value(spec + (int64_t)k * (N / 2 + 1), f1 + R * f2, N);
+  const int f1 = rem / L, f2 = rem % L, f = f1 + R * f2;
+  Hd[gid] = cmul(hermitian_value(spec + (int64_t)k * (N / 2 + 1), f, N), origin_phase<L, R>(twN, f, w_off[k]));
 }
 
 template <int L, int R>
 __global__ __launch_bounds__(256) void k_export1d_large(const float2* __restrict__ Hd, float2* __restrict__ spec,
-                                                        int m) {
+                                                        int m, const int* __restrict__ w_off,
+                                                        const float2* __restrict__ twN) {
   constexpr int N = L * R, NH = N / 2 + 1;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)m * NH) return;
   const int k = (int)(gid / NH), f = (int)(gid % NH);
-  spec[gid] = Hd[((int64_t)k * R + f % R) * L + f / R];
+  spec[gid] = cmulc(Hd[((int64_t)k * R + f % R) * L + f / R], origin_phase<L, R>(twN, f, w_off[k]));
+}
+
+// In place: natural-frame spectra (from the whole-signal transform of h_k)
+// to the window-origin frame.
+template <int L, int R>
+__global__ __launch_bounds__(256) void k_origin_phase1d(float2* __restrict__ Hd, int m, const int* __restrict__ w_off,
+                                                        const float2* __restrict__ twN) {
+  constexpr int N = L * R;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m * N) return;
+  const int k = (int)(gid / N);
+  const int rem = (int)(gid % N);
+  const int f = rem / L + R * (rem % L);
+  Hd[gid] = cmul(Hd[gid], origin_phase<L, R>(twN, f, w_off[k]));
 }
 
 // E_k^{f1} = sum over pairs of conj(FFT_L(fold(w_k u))) . Gdec^{f1}, one
@@ -790,14 +826,17 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
 
 template <int L, int R>
 __global__ __launch_bounds__(256) void k_grad_export1d_large(const float2* __restrict__ E, float2* __restrict__ gspec,
-                                                             int m) {
+                                                             int m, const int* __restrict__ w_off,
+                                                             const float2* __restrict__ twN) {
   constexpr int N = L * R, NH = N / 2 + 1;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)m * NH) return;
   const int k = (int)(gid / NH), f = (int)(gid % NH);
   const int fm = (N - f) % N;
-  const float2 a = E[((int64_t)k * R + f % R) * L + f / R];
-  const float2 b = E[((int64_t)k * R + fm % R) * L + fm / R];
+  // E was accumulated with the windowed transforms in the window-origin
+  // frame; the natural-frame product carries conj(W_N^{f o_k})
+  const float2 a = cmulc(E[((int64_t)k * R + f % R) * L + f / R], origin_phase<L, R>(twN, f, w_off[k]));
+  const float2 b = cmulc(E[((int64_t)k * R + fm % R) * L + fm / R], origin_phase<L, R>(twN, fm, w_off[k]));
   const float sc = 0.5f * half_weight(f, N) / (float)N;
   gspec[gid] = make_float2(sc * (a.x + b.x), sc * (a.y - b.y));
 }
@@ -830,11 +869,23 @@ LaunchStatus launch_spectra1d(const Small1D* ps, const Large1D* pl, const float2
   if (p.L == LL && p.R == RR) {                                                                                   \
     if (import)                                                                                                   \
       hipLaunchKernelGGL((k_import1d_large<LL, RR>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, s,   \
-                         in, const_cast<float2*>(p.Hd), p.m);                                                     \
+                         in, const_cast<float2*>(p.Hd), p.m, p.w_off, p.twN);                                     \
     else                                                                                                          \
       hipLaunchKernelGGL((k_export1d_large<LL, RR>), dim3(blocks_for((int64_t)p.m * (LL * RR / 2 + 1))),          \
-                         dim3(256), 0, s, p.Hd, out, p.m);                                                        \
+                         dim3(256), 0, s, p.Hd, out, p.m, p.w_off, p.twN);                                        \
     return hipGetLastError();                                                                                     \
+  }
+  PC_FOR_EACH_LR(PC_CASE)
+#undef PC_CASE
+  return hipErrorInvalidValue;
+}
+
+LaunchStatus launch_origin_phase1d(const Large1D& p, float2* Hd, hipStream_t s) {
+#define PC_CASE(LL, RR)                                                                                          \
+  if (p.L == LL && p.R == RR) {                                                                                  \
+    hipLaunchKernelGGL((k_origin_phase1d<LL, RR>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, s, Hd, \
+                       p.m, p.w_off, p.twN);                                                                     \
+    return hipGetLastError();                                                                                    \
   }
   PC_FOR_EACH_LR(PC_CASE)
 #undef PC_CASE
@@ -885,7 +936,7 @@ static LaunchStatus grad1d_large_t(const Large1D& p, const float* u, const float
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_grad_export1d_large<L, R>), dim3(blocks_for((int64_t)p.m * (L * R / 2 + 1))), dim3(256), 0, s,
-                     E, gspec, p.m);
+                     E, gspec, p.m, p.w_off, p.twN);
   return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
 //   * 1D, N <= 8192: dense windows and full complex spectra F^* h_k;
 //   * 1D four-step:  windows compacted to their circular support (the
 //     compact-support idea of the complexity lemma of section 3.5 (Lemma 3.2)), spectra
-//     in class-major order Hd[k][f1][f2] = H_k[f1 + R f2];
+//     in class-major order, in the frame of each window's origin o_k:
+//     Hd[k][f1][f2] = H_k[f] W_N^{f o_k}, f = f1 + R f2;
 //   * 2D:            window factors (or dense windows) and half-spectra
 //     rfft2(h_k), N1 x (N2/2 + 1), row-major.
 // All spectra are computed on the device by the library's own FFT kernels.
@@ -425,6 +426,7 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   DeviceTemp hd;
   if ((st = hd.upload(h, (size_t)m * N))) return st;
   hipError_t e = pc::launch_fold_fft(q, hd.get(), m, Hd, false, s);
+  if (e == hipSuccess) e = pc::launch_origin_phase1d(q, Hd, s);
   if (e != hipSuccess) return fail_hip(e, "spectra kernel");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e, "spectra kernel");

@@ -73,7 +73,7 @@ struct Large1D {
   const int* w_off;          // m: support start (mod N)
   const int* w_len;          // m: support length (0 = empty window)
   const int64_t* w_base;     // m: start of window k inside wc
-  const float2* Hd;          // m x R x L, Hd[k][f1][f2] = H_k[f1 + R f2]
+  const float2* Hd;          // m x R x L, Hd[k][f1][f2] = H_k[f] W_N^{f o_k}, f = f1 + R f2
   const float2* tw;          // engine twiddles for L
   const float2* twN;         // exp(-2 i pi j / N), j < N
   const float2* twC;         // class table: twC[f1 * L + n2] = exp(-2 i pi f1 n2 / N)
@@ -97,6 +97,8 @@ struct Large1D {
 bool fourstep_variant_supported(int L, int R, int P);
 LaunchStatus launch_fold_fft(const Large1D& p, const float* xa, int64_t n_sig, float2* out, bool pairs, hipStream_t s,
                              Tracer* tr = nullptr);
+// Hd (natural frame, m x R x L) -> window-origin frame, in place
+LaunchStatus launch_origin_phase1d(const Large1D& p, float2* Hd, hipStream_t s);
 LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
                                 Tracer* tr = nullptr);
 LaunchStatus launch_adj1d_large(const Large1D& p, const float* v, float* x, int64_t batch, hipStream_t s,
