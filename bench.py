@@ -133,10 +133,11 @@ def source_digest(files):
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = ["paper_1604_04374_amd/csrc/kern_1d.hip", "paper_1604_04374_amd/csrc/fft_engine.hpp"]
+KERNEL_SOURCES = {1: ["paper_1604_04374_amd/csrc/kern_1d.hip", "paper_1604_04374_amd/csrc/fft_engine.hpp"],
+                  2: ["paper_1604_04374_amd/csrc/kern_2d.hip", "paper_1604_04374_amd/csrc/fft_engine.hpp"]}
 
 
-def read_traffic(kernel, workload):
+def read_traffic(kernel, workload, ndim):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
@@ -145,7 +146,7 @@ def read_traffic(kernel, workload):
     text = open(path).read()
     m_src = re.search(r"source_digest:\s*([0-9a-f]+)", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_src and m_b) or m_src.group(1) != source_digest(KERNEL_SOURCES):
+    if not (m_src and m_b) or m_src.group(1) != source_digest(KERNEL_SOURCES[ndim]):
         return None
     return float(m_b.group(1))
 
@@ -288,13 +289,13 @@ def main():
             roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                        "traffic": read_traffic(name, args.workload),
+                        "traffic": read_traffic(name, args.workload, probs[0].ndim),
                         "avg_launch_ms": round(st["avg_ms"], 5), "flops_per_launch": flops}
         else:
             achieved = nbytes / t_s / 1e9
             roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
                         "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                        "traffic": read_traffic(name, args.workload),
+                        "traffic": read_traffic(name, args.workload, probs[0].ndim),
                         "avg_launch_ms": round(st["avg_ms"], 5), "bytes_per_launch": nbytes,
                         "alu_tflops": round(flops / t_s / 1e12, 3)}
     hbm_gbps = counts["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
