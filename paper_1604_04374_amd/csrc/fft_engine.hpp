@@ -255,14 +255,34 @@ struct FftPass {
       } else {
         if (b == 0) __syncthreads();  // previous readers of this LDS region are done
         const int base = (j / Ns) * Ns * R + k;
+        // The padded index is base + constant whenever the R outputs stay
+        // inside one 16-entry row (Ns R divides 16; base is then a multiple
+        // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of 16).
+        if constexpr (Ns % 16 == 0) {
+          float2* dst = lds + lpad(base);
 #pragma unroll
-        for (int q = 0; q < R; ++q) lds[lpad(base + q * Ns)] = x[q];
+          for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / 16)] = x[q];
+        } else if constexpr (16 % (Ns * R) == 0) {
+          float2* dst = lds + lpad(base);
+#pragma unroll
+          for (int q = 0; q < R; ++q) dst[q * Ns] = x[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < R; ++q) lds[lpad(base + q * Ns)] = x[q];
+        }
       }
     }
     if constexpr (!LAST) {
       __syncthreads();
+      if constexpr (T % 16 == 0) {
+        // (t + T e) >> 4 = (t >> 4) + e T / 16
+        const float2* src = lds + lpad(t);
 #pragma unroll
-      for (int e = 0; e < P; ++e) v[e] = lds[lpad(t + T * e)];
+        for (int e = 0; e < P; ++e) v[e] = src[e * (T + T / 16)];
+      } else {
+#pragma unroll
+        for (int e = 0; e < P; ++e) v[e] = lds[lpad(t + T * e)];
+      }
       FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1)>::run(v, lds, tw, t);
     }
   }

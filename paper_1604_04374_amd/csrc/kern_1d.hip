@@ -240,37 +240,47 @@ __device__ __forceinline__ float2 unit_root_R(const float2* __restrict__ twN, in
   return twN[(j % R) * L];
 }
 
+// Load base[i] through a 32-bit unsigned byte offset from a uniform base, so
+// that the address is one SGPR pair plus one VGPR (no 64-bit arithmetic).
+template <class X>
+__device__ __forceinline__ X ldu(const X* __restrict__ base, uint32_t i) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(X));
+}
+
+// (o + d) mod N for o < N, d < N
+template <uint32_t N>
+__device__ __forceinline__ uint32_t wrapN(uint32_t n) {
+  if constexpr ((N & (N - 1)) == 0)
+    return n & (N - 1);
+  else
+    return min(n, n - N);  // n - N wraps above n when n < N
+}
+
 // a^{f1}[d] = W_N^{f1 d} z[o + d] for a windowed term whose support
 // [o, o + S) is at most L long (every slot d receives at most one sample).
-// All loads are issued before any is used, with clamped indices and a zero
-// weight off the support.
+// Short-support plans store every window on L samples, zero beyond S, so
+// all slots are loaded unconditionally; all loads are issued before any is
+// used.
 template <int L, int R, int P>
 __device__ __forceinline__ void fold_short(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
                                            const float* __restrict__ xb, float sb, const float* __restrict__ wc,
-                                           int o, int S, const float2* __restrict__ twC,
-                                           const float2* __restrict__ twN) {
-  constexpr int T = L / P, N = L * R;
-  (void)twN;
+                                           int o, const float2* __restrict__ twC) {
+  constexpr int T = L / P;
+  constexpr uint32_t N = (uint32_t)L * R;
   const float2* tc = twC + f1 * L;
   float ra[P], rb[P], rw[P];
   float2 rt[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    const int d = t + T * e;
-    const int dc = d < S ? d : 0;
-    int n = o + dc;
-    if (n >= N) n -= N;
-    ra[e] = xa[n];
-    rb[e] = xb[n];
-    rw[e] = wc[dc];
-    rt[e] = tc[d];
+    const uint32_t d = (uint32_t)(t + T * e);
+    const uint32_t n = wrapN<N>((uint32_t)o + d);
+    ra[e] = ldu(xa, n);
+    rb[e] = ldu(xb, n);
+    rw[e] = ldu(wc, d);
+    rt[e] = ldu(tc, d);
   }
 #pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int d = t + T * e;
-    const float ww = d < S ? rw[e] : 0.f;
-    v[e] = cmul(make_float2(ww * ra[e], ww * sb * rb[e]), rt[e]);
-  }
+  for (int e = 0; e < P; ++e) v[e] = cmul(make_float2(rw[e] * ra[e], rw[e] * sb * rb[e]), rt[e]);
 }
 
 // Same for supports longer than L: a^{f1}[d] = W_N^{f1 d} sum_c z[o + d + c L] W_R^{f1 c}.
@@ -279,20 +289,20 @@ __device__ __forceinline__ void fold_long(float2 (&v)[P], int t, int f1, const f
                                           const float* __restrict__ xb, float sb, const float* __restrict__ wc,
                                           int o, int S, const float2* __restrict__ twC,
                                           const float2* __restrict__ twN) {
-  constexpr int T = L / P, N = L * R;
+  constexpr int T = L / P;
+  constexpr uint32_t N = (uint32_t)L * R;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int d0 = t + T * e;
     float2 a = make_float2(0.f, 0.f);
     int c = 0;
     for (int d = d0; d < S; d += L, ++c) {
-      int n = o + d;
-      if (n >= N) n -= N;
-      const float ww = wc[d];
-      const float2 z = make_float2(ww * xa[n], ww * sb * xb[n]);
+      const uint32_t n = wrapN<N>((uint32_t)(o + d));
+      const float ww = ldu(wc, (uint32_t)d);
+      const float2 z = make_float2(ww * ldu(xa, n), ww * sb * ldu(xb, n));
       a = cfma(a, z, unit_root_R<L, R>(twN, f1 * c));
     }
-    v[e] = cmul(a, twC[f1 * L + d0]);
+    v[e] = cmul(a, ldu(twC, (uint32_t)(f1 * L + d0)));
   }
 }
 
@@ -371,7 +381,7 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     const float* wc = p.wc + p.w_base[k];
     float2 v[P];
     if constexpr (SHORT)
-      fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+      fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, p.twC);
     else
       fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
     // the spectrum loads are issued before the transform so that their
@@ -433,50 +443,49 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  // class 0's inputs; each iteration prefetches the next class's inputs
-  // before its inverse transform
-  float2 vn[P], hn[P];
-  {
-    const float2* Hk = p.Hd + (int64_t)k * R * L;
-    const float2* Vp = p.Vws + pair * R * L;
+  const float2* Hk = p.Hd + (int64_t)k * R * L;
+  const float2* Vp = p.Vws + pair * R * L;
+  auto load = [&](float2(&vv)[P], float2(&hh)[P], int f1) {
+    const float2* Vc = Vp + f1 * L;
+    const float2* Hc = Hk + f1 * L;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      vn[e] = Vp[t + T * e];
-      hn[e] = Hk[t + T * e];
+      vv[e] = ldu(Vc, (uint32_t)(t + T * e));
+      hh[e] = ldu(Hc, (uint32_t)(t + T * e));
     }
-  }
-  for (int f1 = 0; f1 < R; ++f1) {
-    float2 g[P];
+  };
+  // class f1: inverse FFT_L of conj(Hd) . V, back-modulated by W_N^{-f1 d}
+  // (chunks after the first also carry W_R^{-f1 chunk}) and summed
+  auto prod = [&](float2(&vv)[P], const float2(&hh)[P]) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) g[e] = cmulc(vn[e], hn[e]);
-    if (f1 + 1 < R) {
-      const float2* Hk = p.Hd + ((int64_t)k * R + f1 + 1) * L;
-      const float2* Vp = p.Vws + (pair * R + f1 + 1) * L;
-#pragma unroll
-      for (int e = 0; e < P; ++e) {
-        vn[e] = Vp[t + T * e];
-        hn[e] = Hk[t + T * e];
-      }
-    }
-    fft_wg<L, P, true>(g, lds, twl, t);
-    // W_N^{-f1 d} from the class table; chunks after the first also carry
-    // the class factor W_R^{-f1 chunk}
+    for (int e = 0; e < P; ++e) vv[e] = cmulc(vv[e], hh[e]);
+  };
+  auto step = [&](float2(&vv)[P], int f1) {
+    fft_wg<L, P, true>(vv, lds, twl, t);
     const float2* tc = p.twC + f1 * L;
     float2 rt[P];
 #pragma unroll
-    for (int e = 0; e < P; ++e) rt[e] = tc[t + T * e];
+    for (int e = 0; e < P; ++e) rt[e] = ldu(tc, (uint32_t)(t + T * e));
     if (chunk != 0) {
       const float2 u = unit_root_R<L, R>(p.twN, f1 * chunk);
 #pragma unroll
       for (int e = 0; e < P; ++e) rt[e] = cmul(rt[e], u);
     }
+    // slots at or beyond Sc accumulate values that are never stored
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      const float2 c = cmulc(g[e], rt[e]);
-      const float keep = (t + T * e) < Sc ? 1.f : 0.f;
-      acc[e].x = fmaf(keep, c.x, acc[e].x);
-      acc[e].y = fmaf(keep, c.y, acc[e].y);
-    }
+    for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], cmulc(vv[e], rt[e]));
+  };
+  // two register sets: the next class's inputs load during the current
+  // class's transform (R is even)
+  float2 va[P], ha[P], vb[P], hb[P];
+  load(va, ha, 0);
+  for (int f1 = 0; f1 < R; f1 += 2) {
+    prod(va, ha);
+    load(vb, hb, f1 + 1);
+    step(va, f1);
+    prod(vb, hb);
+    if (f1 + 2 < R) load(va, ha, f1 + 2);
+    step(vb, f1 + 1);
   }
   const float* wc = p.wc + p.w_base[k] + c0;
   float2* out = p.Pws + pair * p.p_stride + p.item_out[item];
@@ -807,7 +816,7 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
       const float sb = hasb ? 1.f : 0.f;
       float2 v[P];
       if constexpr (SHORT)
-        fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+        fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, p.twC);
       else
         fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
       const float2* Gp = p.Vws + (pr * R + f1) * L;

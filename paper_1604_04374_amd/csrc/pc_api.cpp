@@ -328,13 +328,19 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   bool short_support = true;
   for (int k = 0; k < m; ++k) {
     int64_t o, S;
-    const float* wk = windows + (size_t)k * N;
-    circular_support(wk, N, o, S);
+    circular_support(windows + (size_t)k * N, N, o, S);
     off[k] = (int)o;
     len[k] = (int)S;
     if (S > L) short_support = false;
+  }
+  for (int k = 0; k < m; ++k) {
+    const float* wk = windows + (size_t)k * N;
+    const int64_t o = off[k], S = len[k];
     base[k] = (int64_t)wc.size();
     for (int64_t d = 0; d < S; ++d) wc.push_back(wk[(o + d) % N]);
+    // short-support plans keep every window on L samples (zeros beyond its
+    // support) so that the fold loads every slot unconditionally
+    if (short_support) wc.resize((size_t)base[k] + L, 0.f);
     for (int64_t c0 = 0; c0 < S; c0 += L) {
       it_k.push_back(k);
       it_d0.push_back((int)c0);
