@@ -22,6 +22,8 @@ ARCH = "gfx950"
 # compiler otherwise forms them from float / float2 arithmetic).
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function"]
+# extra compiler flags for tuning experiments (e.g. -DPC_LDS_PAD=32)
+COMMON += os.environ.get("PC_EXTRA_FLAGS", "").split()
 
 
 def hipcc() -> str:

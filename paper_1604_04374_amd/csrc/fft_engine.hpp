@@ -214,11 +214,17 @@ constexpr bool sched_ok(int L, int P) {
   return true;
 }
 
-// LDS word (float2) index with one pad slot per 16 entries: keeps the
+// LDS word (float2) index with one pad slot per PAD entries: keeps the
 // stride-R writes of the first passes free of bank conflicts.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+#ifndef PC_LDS_PAD
+#define PC_LDS_PAD 16
+#endif
+constexpr int PAD = PC_LDS_PAD;
+constexpr int PAD_SHIFT = PAD == 16 ? 4 : PAD == 32 ? 5 : PAD == 64 ? 6 : 0;
+static_assert(PAD_SHIFT != 0, "PAD is 16, 32 or 64");
+__device__ __forceinline__ int lpad(int i) { return i + (i >> PAD_SHIFT); }
 template <int L>
-constexpr int lds_len() { return L + L / 16; }
+constexpr int lds_len() { return L + L / PAD; }
 
 // ---------------------------------------------------------------------------
 // the engine
@@ -256,13 +262,13 @@ struct FftPass {
         if (b == 0) __syncthreads();  // previous readers of this LDS region are done
         const int base = (j / Ns) * Ns * R + k;
         // The padded index is base + constant whenever the R outputs stay
-        // inside one 16-entry row (Ns R divides 16; base is then a multiple
-        // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of 16).
-        if constexpr (Ns % 16 == 0) {
+        // inside one PAD-entry row (Ns R divides PAD; base is then a multiple
+        // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of PAD).
+        if constexpr (Ns % PAD == 0) {
           float2* dst = lds + lpad(base);
 #pragma unroll
-          for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / 16)] = x[q];
-        } else if constexpr (16 % (Ns * R) == 0) {
+          for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / PAD)] = x[q];
+        } else if constexpr (PAD % (Ns * R) == 0) {
           float2* dst = lds + lpad(base);
 #pragma unroll
           for (int q = 0; q < R; ++q) dst[q * Ns] = x[q];
@@ -274,11 +280,11 @@ struct FftPass {
     }
     if constexpr (!LAST) {
       __syncthreads();
-      if constexpr (T % 16 == 0) {
-        // (t + T e) >> 4 = (t >> 4) + e T / 16
+      if constexpr (T % PAD == 0) {
+        // (t + T e) / PAD = t / PAD + e T / PAD
         const float2* src = lds + lpad(t);
 #pragma unroll
-        for (int e = 0; e < P; ++e) v[e] = src[e * (T + T / 16)];
+        for (int e = 0; e < P; ++e) v[e] = src[e * (T + T / PAD)];
       } else {
 #pragma unroll
         for (int e = 0; e < P; ++e) v[e] = lds[lpad(t + T * e)];

@@ -247,6 +247,41 @@ __device__ __forceinline__ X ldu(const X* __restrict__ base, uint32_t i) {
   return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(X));
 }
 
+// Every L-long block that the four-step kernels pass between launches (class
+// spectra Hd and Vws, class outputs Bws, gradient partials E, the modulated
+// windows cw) keeps element f2 = t + T e at block_pos(f2, T) (T = L / P):
+// the thread that holds f2 in the workgroup transform moves elements e and
+// e + 1 with one 16-byte access, and a wave's access covers 1 KiB
+// contiguously.
+template <int L, int P>
+__device__ __forceinline__ int block_elem(int j) {  // inverse of block_pos
+  constexpr int T = L / P;
+  const int blk = j / (2 * T), r = j % (2 * T);
+  return (r >> 1) + T * (2 * blk + (r & 1));
+}
+
+template <int L, int P>
+__device__ __forceinline__ void load_blk(const float2* __restrict__ b, float2 (&v)[P], int t) {
+  static_assert(P % 2 == 0, "even points per thread");
+  constexpr int T = L / P;
+  const float4* b4 = reinterpret_cast<const float4*>(b);
+#pragma unroll
+  for (int h = 0; h < P / 2; ++h) {
+    const float4 q = ldu(b4, (uint32_t)(h * T + t));
+    v[2 * h] = make_float2(q.x, q.y);
+    v[2 * h + 1] = make_float2(q.z, q.w);
+  }
+}
+
+template <int L, int P>
+__device__ __forceinline__ void store_blk(float2* __restrict__ b, const float2 (&v)[P], int t) {
+  constexpr int T = L / P;
+  float4* b4 = reinterpret_cast<float4*>(b);
+#pragma unroll
+  for (int h = 0; h < P / 2; ++h)
+    b4[h * T + t] = make_float4(v[2 * h].x, v[2 * h].y, v[2 * h + 1].x, v[2 * h + 1].y);
+}
+
 // (o + d) mod N for o < N, d < N
 template <uint32_t N>
 __device__ __forceinline__ uint32_t wrapN(uint32_t n) {
@@ -256,31 +291,27 @@ __device__ __forceinline__ uint32_t wrapN(uint32_t n) {
     return min(n, n - N);  // n - N wraps above n when n < N
 }
 
-// a^{f1}[d] = W_N^{f1 d} z[o + d] for a windowed term whose support
-// [o, o + S) is at most L long (every slot d receives at most one sample).
-// Short-support plans store every window on L samples, zero beyond S, so
-// all slots are loaded unconditionally; all loads are issued before any is
-// used.
+// a^{f1}[d] = cw_k^{f1}[d] z[o + d] with cw_k^{f1}[d] = w_k[o + d] W_N^{f1 d},
+// for a windowed term whose support [o, o + S) is at most L long (every slot
+// d receives at most one sample; cw is zero beyond S).  All loads are issued
+// before any is used.
 template <int L, int R, int P>
-__device__ __forceinline__ void fold_short(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
-                                           const float* __restrict__ xb, float sb, const float* __restrict__ wc,
-                                           int o, const float2* __restrict__ twC) {
+__device__ __forceinline__ void fold_short(float2 (&v)[P], int t, const float* __restrict__ xa,
+                                           const float* __restrict__ xb, float sb, int o,
+                                           const float2* __restrict__ cwb) {
   constexpr int T = L / P;
   constexpr uint32_t N = (uint32_t)L * R;
-  const float2* tc = twC + f1 * L;
-  float ra[P], rb[P], rw[P];
-  float2 rt[P];
+  float ra[P], rb[P];
+  float2 rc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    const uint32_t d = (uint32_t)(t + T * e);
-    const uint32_t n = wrapN<N>((uint32_t)o + d);
+    const uint32_t n = wrapN<N>((uint32_t)o + (uint32_t)(t + T * e));
     ra[e] = ldu(xa, n);
     rb[e] = ldu(xb, n);
-    rw[e] = ldu(wc, d);
-    rt[e] = ldu(tc, d);
   }
+  load_blk<L, P>(cwb, rc, t);
 #pragma unroll
-  for (int e = 0; e < P; ++e) v[e] = cmul(make_float2(rw[e] * ra[e], rw[e] * sb * rb[e]), rt[e]);
+  for (int e = 0; e < P; ++e) v[e] = cmul(make_float2(ra[e], sb * rb[e]), rc[e]);
 }
 
 // Same for supports longer than L: a^{f1}[d] = W_N^{f1 d} sum_c z[o + d + c L] W_R^{f1 c}.
@@ -351,9 +382,7 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
     v[e] = cmul(a, tc[n2]);
   }
   fft_wg<L, P, false>(v, lds, twl, t);
-  float2* o = out + (idx * R + f1) * L;
-#pragma unroll
-  for (int e = 0; e < P; ++e) o[t + T * e] = v[e];
+  store_blk<L, P>(out + (idx * R + f1) * L, v, t);
 }
 
 // Forward, class f1 of one signal pair: sum_k Hd_k^{f1} . FFT_L(fold(w_k u)),
@@ -379,29 +408,26 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     if (S == 0) continue;
     const int o = p.w_off[k];
     const float* wc = p.wc + p.w_base[k];
+    (void)wc;
     float2 v[P];
     if constexpr (SHORT)
-      fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, p.twC);
+      fold_short<L, R, P>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * L);
     else
       fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
     // the spectrum loads are issued before the transform so that their
     // latency overlaps it
-    const float2* Hk = p.Hd + ((int64_t)k * R + f1) * L;
     float2 hv[P];
-#pragma unroll
-    for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
+    load_blk<L, P>(p.Hd + ((int64_t)k * R + f1) * L, hv, t);
     fft_wg<L, P, false>(v, lds, twl, t);
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
   }
   fft_wg<L, P, true>(acc, lds, twl, t);
-  float2* o = p.Bws + (pair * R + f1) * L;
-#pragma unroll
-  for (int e = 0; e < P; ++e) o[t + T * e] = acc[e];
+  store_blk<L, P>(p.Bws + (pair * R + f1) * L, acc, t);
 }
 
 // y[n2 + L n1] = (1/N) sum_f1 W_R^{-f1 n1} (W_N^{-f1 n2} b^{f1}[n2]).
-template <int L, int R>
+template <int L, int R, int P>
 __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bws, float* __restrict__ y, int64_t batch,
                                                    const float2* __restrict__ twC) {
   constexpr int N = L * R;
@@ -411,8 +437,9 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
   const int64_t pair = gid / L;
   const int n2 = (int)(gid % L);
   float2 b[R];
+  const int bp = block_pos(n2, L / P);
 #pragma unroll
-  for (int f1 = 0; f1 < R; ++f1) b[f1] = cmulc(Bws[(pair * R + f1) * L + n2], twC[f1 * L + n2]);
+  for (int f1 = 0; f1 < R; ++f1) b[f1] = cmulc(Bws[(pair * R + f1) * L + bp], twC[f1 * L + n2]);
   dftR<R, true>(b);
   const float sc = 1.0f / (float)N;
   const int64_t sa = 2 * pair, sb = sa + 1;
@@ -426,8 +453,10 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
 
 // Adjoint, one (term, support chunk of at most L samples) item of one signal
 // pair: g = F(conj(H_k) . V) on the chunk, assembled class by class, times
-// the window; stored for the overlap-add.
-template <int L, int R, int P>
+// the window; stored for the overlap-add.  Short-support plans take the
+// window and the class modulation together from cw (one item per term,
+// chunk 0).
+template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   constexpr int T = L / P;
   __shared__ float2 lds[lds_len<L>()];
@@ -446,30 +475,29 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   const float2* Hk = p.Hd + (int64_t)k * R * L;
   const float2* Vp = p.Vws + pair * R * L;
   auto load = [&](float2(&vv)[P], float2(&hh)[P], int f1) {
-    const float2* Vc = Vp + f1 * L;
-    const float2* Hc = Hk + f1 * L;
-#pragma unroll
-    for (int e = 0; e < P; ++e) {
-      vv[e] = ldu(Vc, (uint32_t)(t + T * e));
-      hh[e] = ldu(Hc, (uint32_t)(t + T * e));
-    }
+    load_blk<L, P>(Vp + f1 * L, vv, t);
+    load_blk<L, P>(Hk + f1 * L, hh, t);
   };
-  // class f1: inverse FFT_L of conj(Hd) . V, back-modulated by W_N^{-f1 d}
-  // (chunks after the first also carry W_R^{-f1 chunk}) and summed
   auto prod = [&](float2(&vv)[P], const float2(&hh)[P]) {
 #pragma unroll
     for (int e = 0; e < P; ++e) vv[e] = cmulc(vv[e], hh[e]);
   };
+  // class f1: inverse FFT_L of conj(Hd) . V, back-modulated by W_N^{-f1 d}
+  // (chunks after the first also carry W_R^{-f1 chunk}) and summed
   auto step = [&](float2(&vv)[P], int f1) {
     fft_wg<L, P, true>(vv, lds, twl, t);
-    const float2* tc = p.twC + f1 * L;
     float2 rt[P];
+    if constexpr (SHORT) {
+      load_blk<L, P>(p.cw + ((int64_t)k * R + f1) * L, rt, t);
+    } else {
+      const float2* tc = p.twC + f1 * L;
 #pragma unroll
-    for (int e = 0; e < P; ++e) rt[e] = ldu(tc, (uint32_t)(t + T * e));
-    if (chunk != 0) {
-      const float2 u = unit_root_R<L, R>(p.twN, f1 * chunk);
+      for (int e = 0; e < P; ++e) rt[e] = ldu(tc, (uint32_t)(t + T * e));
+      if (chunk != 0) {
+        const float2 u = unit_root_R<L, R>(p.twN, f1 * chunk);
 #pragma unroll
-      for (int e = 0; e < P; ++e) rt[e] = cmul(rt[e], u);
+        for (int e = 0; e < P; ++e) rt[e] = cmul(rt[e], u);
+      }
     }
     // slots at or beyond Sc accumulate values that are never stored
 #pragma unroll
@@ -487,13 +515,21 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
     if (f1 + 2 < R) load(va, ha, f1 + 2);
     step(vb, f1 + 1);
   }
-  const float* wc = p.wc + p.w_base[k] + c0;
   float2* out = p.Pws + pair * p.p_stride + p.item_out[item];
   const float sc = 1.0f / (float)(L * R);
+  if constexpr (SHORT) {
 #pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int d = t + T * e;
-    if (d < Sc) out[d] = cscale(acc[e], wc[d] * sc);
+    for (int e = 0; e < P; ++e) {
+      const int d = t + T * e;
+      if (d < Sc) out[d] = cscale(acc[e], sc);
+    }
+  } else {
+    const float* wc = p.wc + p.w_base[k] + c0;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int d = t + T * e;
+      if (d < Sc) out[d] = cscale(acc[e], wc[d] * sc);
+    }
   }
 }
 
@@ -528,9 +564,6 @@ __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x,
   X(8192, 4, 8) X(8192, 8, 8) X(8192, 16, 8) X(6144, 2, 24) X(6144, 4, 24)        \
   X(6144, 8, 24) X(6144, 16, 24) X(6144, 2, 12) X(6144, 4, 12) X(6144, 8, 12)     \
   X(6144, 16, 12)
-
-#define PC_FOR_EACH_LR(X)                                                                              \
-  X(8192, 2) X(8192, 4) X(8192, 8) X(8192, 16) X(6144, 2) X(6144, 4) X(6144, 8) X(6144, 16)
 
 bool fourstep_variant_supported(int L, int R, int P) {
 #define PC_CASE(LL, RR, PP) \
@@ -567,7 +600,7 @@ static LaunchStatus fwd1d_large_t(const Large1D& p, const float* u, float* y, in
   if (e != hipSuccess) return e;
   const int64_t nthr = pairs * L;
   TraceScope ts(tr, "combine1d", s);
-  hipLaunchKernelGGL((k_combine1d<L, R>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p.Bws, y, batch,
+  hipLaunchKernelGGL((k_combine1d<L, R, P>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p.Bws, y, batch,
                      p.twC);
   return hipGetLastError();
 }
@@ -580,7 +613,10 @@ static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, in
   if (e != hipSuccess) return e;
   if (p.n_items > 0) {
     TraceScope ts(tr, "adj1d_large", s);
-    hipLaunchKernelGGL((k_adj1d_large<L, R, P>), dim3((unsigned)(pairs * p.n_items)), dim3(L / P), 0, s, p);
+    if (p.short_support)
+      hipLaunchKernelGGL((k_adj1d_large<L, R, P, true>), dim3((unsigned)(pairs * p.n_items)), dim3(L / P), 0, s, p);
+    else
+      hipLaunchKernelGGL((k_adj1d_large<L, R, P, false>), dim3((unsigned)(pairs * p.n_items)), dim3(L / P), 0, s, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -751,7 +787,7 @@ __device__ __forceinline__ float2 origin_phase(const float2* __restrict__ twN, i
   return twN[(int)(((int64_t)f * o) % N)];
 }
 
-template <int L, int R>
+template <int L, int R, int P>
 __global__ __launch_bounds__(256) void k_import1d_large(const float2* __restrict__ spec, float2* __restrict__ Hd,
                                                         int m, const int* __restrict__ w_off,
                                                         const float2* __restrict__ twN) {
@@ -760,11 +796,11 @@ __global__ __launch_bounds__(256) void k_import1d_large(const float2* __restrict
   if (gid >= (int64_t)m * N) return;
   const int k = (int)(gid / N);
   const int rem = (int)(gid % N);
-  const int f1 = rem / L, f2 = rem % L, f = f1 + R * f2;
+  const int f = rem / L + R * block_elem<L, P>(rem % L);
   Hd[gid] = cmul(hermitian_value(spec + (int64_t)k * (N / 2 + 1), f, N), origin_phase<L, R>(twN, f, w_off[k]));
 }
 
-template <int L, int R>
+template <int L, int R, int P>
 __global__ __launch_bounds__(256) void k_export1d_large(const float2* __restrict__ Hd, float2* __restrict__ spec,
                                                         int m, const int* __restrict__ w_off,
                                                         const float2* __restrict__ twN) {
@@ -772,12 +808,13 @@ __global__ __launch_bounds__(256) void k_export1d_large(const float2* __restrict
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)m * NH) return;
   const int k = (int)(gid / NH), f = (int)(gid % NH);
-  spec[gid] = cmulc(Hd[((int64_t)k * R + f % R) * L + f / R], origin_phase<L, R>(twN, f, w_off[k]));
+  spec[gid] =
+      cmulc(Hd[((int64_t)k * R + f % R) * L + block_pos(f / R, L / P)], origin_phase<L, R>(twN, f, w_off[k]));
 }
 
 // In place: natural-frame spectra (from the whole-signal transform of h_k)
 // to the window-origin frame.
-template <int L, int R>
+template <int L, int R, int P>
 __global__ __launch_bounds__(256) void k_origin_phase1d(float2* __restrict__ Hd, int m, const int* __restrict__ w_off,
                                                         const float2* __restrict__ twN) {
   constexpr int N = L * R;
@@ -785,7 +822,7 @@ __global__ __launch_bounds__(256) void k_origin_phase1d(float2* __restrict__ Hd,
   if (gid >= (int64_t)m * N) return;
   const int k = (int)(gid / N);
   const int rem = (int)(gid % N);
-  const int f = rem / L + R * (rem % L);
+  const int f = rem / L + R * block_elem<L, P>(rem % L);
   Hd[gid] = cmul(Hd[gid], origin_phase<L, R>(twN, f, w_off[k]));
 }
 
@@ -804,6 +841,7 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
   const int S = p.w_len[k];
   const int o = p.w_off[k];
   const float* wc = p.wc + p.w_base[k];
+  (void)wc;
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
@@ -816,24 +854,20 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
       const float sb = hasb ? 1.f : 0.f;
       float2 v[P];
       if constexpr (SHORT)
-        fold_short<L, R, P>(v, t, f1, xa, xb, sb, wc, o, p.twC);
+        fold_short<L, R, P>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * L);
       else
         fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
-      const float2* Gp = p.Vws + (pr * R + f1) * L;
       float2 gv[P];
-#pragma unroll
-      for (int e = 0; e < P; ++e) gv[e] = Gp[t + T * e];
+      load_blk<L, P>(p.Vws + (pr * R + f1) * L, gv, t);
       fft_wg<L, P, false>(v, lds, twl, t);
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
     }
   }
-  float2* out = E + ((int64_t)k * R + f1) * L;
-#pragma unroll
-  for (int e = 0; e < P; ++e) out[t + T * e] = acc[e];
+  store_blk<L, P>(E + ((int64_t)k * R + f1) * L, acc, t);
 }
 
-template <int L, int R>
+template <int L, int R, int P>
 __global__ __launch_bounds__(256) void k_grad_export1d_large(const float2* __restrict__ E, float2* __restrict__ gspec,
                                                              int m, const int* __restrict__ w_off,
                                                              const float2* __restrict__ twN) {
@@ -844,8 +878,11 @@ __global__ __launch_bounds__(256) void k_grad_export1d_large(const float2* __res
   const int fm = (N - f) % N;
   // E was accumulated with the windowed transforms in the window-origin
   // frame; the natural-frame product carries conj(W_N^{f o_k})
-  const float2 a = cmulc(E[((int64_t)k * R + f % R) * L + f / R], origin_phase<L, R>(twN, f, w_off[k]));
-  const float2 b = cmulc(E[((int64_t)k * R + fm % R) * L + fm / R], origin_phase<L, R>(twN, fm, w_off[k]));
+  constexpr int T = L / P;
+  const float2 a =
+      cmulc(E[((int64_t)k * R + f % R) * L + block_pos(f / R, T)], origin_phase<L, R>(twN, f, w_off[k]));
+  const float2 b =
+      cmulc(E[((int64_t)k * R + fm % R) * L + block_pos(fm / R, T)], origin_phase<L, R>(twN, fm, w_off[k]));
   const float sc = 0.5f * half_weight(f, N) / (float)N;
   gspec[gid] = make_float2(sc * (a.x + b.x), sc * (a.y - b.y));
 }
@@ -874,29 +911,29 @@ LaunchStatus launch_spectra1d(const Small1D* ps, const Large1D* pl, const float2
     return hipErrorInvalidValue;
   }
   const Large1D& p = *pl;
-#define PC_CASE(LL, RR)                                                                                           \
-  if (p.L == LL && p.R == RR) {                                                                                   \
-    if (import)                                                                                                   \
-      hipLaunchKernelGGL((k_import1d_large<LL, RR>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, s,   \
-                         in, const_cast<float2*>(p.Hd), p.m, p.w_off, p.twN);                                     \
-    else                                                                                                          \
-      hipLaunchKernelGGL((k_export1d_large<LL, RR>), dim3(blocks_for((int64_t)p.m * (LL * RR / 2 + 1))),          \
-                         dim3(256), 0, s, p.Hd, out, p.m, p.w_off, p.twN);                                        \
-    return hipGetLastError();                                                                                     \
+#define PC_CASE(LL, RR, PP)                                                                                     \
+  if (p.L == LL && p.R == RR && p.P == PP) {                                                                    \
+    if (import)                                                                                                 \
+      hipLaunchKernelGGL((k_import1d_large<LL, RR, PP>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, \
+                         s, in, const_cast<float2*>(p.Hd), p.m, p.w_off, p.twN);                                \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_export1d_large<LL, RR, PP>), dim3(blocks_for((int64_t)p.m * (LL * RR / 2 + 1))),    \
+                         dim3(256), 0, s, p.Hd, out, p.m, p.w_off, p.twN);                                      \
+    return hipGetLastError();                                                                                   \
   }
-  PC_FOR_EACH_LR(PC_CASE)
+  PC_FOR_EACH_LRP(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }
 
 LaunchStatus launch_origin_phase1d(const Large1D& p, float2* Hd, hipStream_t s) {
-#define PC_CASE(LL, RR)                                                                                          \
-  if (p.L == LL && p.R == RR) {                                                                                  \
-    hipLaunchKernelGGL((k_origin_phase1d<LL, RR>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, s, Hd, \
-                       p.m, p.w_off, p.twN);                                                                     \
-    return hipGetLastError();                                                                                    \
+#define PC_CASE(LL, RR, PP)                                                                                  \
+  if (p.L == LL && p.R == RR && p.P == PP) {                                                                 \
+    hipLaunchKernelGGL((k_origin_phase1d<LL, RR, PP>), dim3(blocks_for((int64_t)p.m * LL * RR)), dim3(256), 0, \
+                       s, Hd, p.m, p.w_off, p.twN);                                                          \
+    return hipGetLastError();                                                                                \
   }
-  PC_FOR_EACH_LR(PC_CASE)
+  PC_FOR_EACH_LRP(PC_CASE)
 #undef PC_CASE
   return hipErrorInvalidValue;
 }
@@ -944,8 +981,8 @@ static LaunchStatus grad1d_large_t(const Large1D& p, const float* u, const float
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_grad_export1d_large<L, R>), dim3(blocks_for((int64_t)p.m * (L * R / 2 + 1))), dim3(256), 0, s,
-                     E, gspec, p.m, p.w_off, p.twN);
+  hipLaunchKernelGGL((k_grad_export1d_large<L, R, P>), dim3(blocks_for((int64_t)p.m * (L * R / 2 + 1))), dim3(256), 0,
+                     s, E, gspec, p.m, p.w_off, p.twN);
   return hipGetLastError();
 }
 

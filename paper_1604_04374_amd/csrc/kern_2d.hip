@@ -64,7 +64,7 @@ __device__ __forceinline__ void row_weights(const float* __restrict__ wsrc, int 
 // twiddle table within 156 KiB), at most 8 (tiles of 16 rows).
 constexpr int row_pairs_per_block(int L2) {
   int g = 8;
-  while (g > 1 && (g * (L2 + L2 / 16) + L2) * 8 > 156 * 1024) g /= 2;
+  while (g > 1 && (g * (L2 + L2 / PAD) + L2) * 8 > 156 * 1024) g /= 2;
   return g;
 }
 

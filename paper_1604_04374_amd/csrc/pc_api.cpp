@@ -407,6 +407,24 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   if ((st = p->upload(&tw, engine_twiddles(L, q.P), s))) return st;
   if ((st = p->upload(&twN, unit_roots(N), s))) return st;
   if ((st = p->upload(&dtwC, twC, s))) return st;
+  // short supports: window times class modulation, in the block layout
+  q.cw = nullptr;
+  if (short_support) {
+    const int T = L / q.P;
+    std::vector<float2> cw((size_t)m * N);
+    for (int k = 0; k < m; ++k)
+      for (int f1 = 0; f1 < R; ++f1) {
+        float2* dst = cw.data() + ((size_t)k * R + f1) * L;
+        for (int d = 0; d < L; ++d) {
+          const double wv = wc[(size_t)base[k] + d];
+          const double a = -2.0 * M_PI * (double)(((int64_t)f1 * d) % N) / (double)N;
+          dst[pc::block_pos(d, T)] = make_float2((float)(wv * std::cos(a)), (float)(wv * std::sin(a)));
+        }
+      }
+    float2* dcw = nullptr;
+    if ((st = p->upload(&dcw, cw, s, &p->window_bytes))) return st;
+    q.cw = dcw;
+  }
   q.wc = dwc;
   q.w_off = doff;
   q.w_len = dlen;

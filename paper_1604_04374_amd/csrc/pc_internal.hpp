@@ -65,6 +65,13 @@ LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int6
 // --------------------------------------------------------------------------
 // 1D, N = R * L (four-step): inner length L in a workgroup, R classes
 // --------------------------------------------------------------------------
+// Position of element f2 = t + T e inside an L-long block of the four-step
+// path (T = L / P threads, e < P): elements e and e + 1 of thread t are
+// adjacent, (e / 2) 2T + 2t + e % 2.
+__host__ __device__ constexpr int block_pos(int f2, int T) {
+  return ((f2 / T) >> 1) * (2 * T) + 2 * (f2 % T) + ((f2 / T) & 1);
+}
+
 struct Large1D {
   int L, R;                  // N = R * L
   int P;                     // points per thread of the inner transform (plan-time choice)
@@ -73,7 +80,8 @@ struct Large1D {
   const int* w_off;          // m: support start (mod N)
   const int* w_len;          // m: support length (0 = empty window)
   const int64_t* w_base;     // m: start of window k inside wc
-  const float2* Hd;          // m x R x L, Hd[k][f1][f2] = H_k[f] W_N^{f o_k}, f = f1 + R f2
+  const float2* Hd;          // m x R x L, Hd[k][f1][block_pos(f2)] = H_k[f] W_N^{f o_k}, f = f1 + R f2
+  const float2* cw;          // short supports: m x R x L, cw[k][f1][block_pos(d)] = w_k[o_k + d] W_N^{f1 d}
   const float2* tw;          // engine twiddles for L
   const float2* twN;         // exp(-2 i pi j / N), j < N
   const float2* twC;         // class table: twC[f1 * L + n2] = exp(-2 i pi f1 n2 / N)
@@ -90,8 +98,8 @@ struct Large1D {
   const int* tile_off;       // N/256 + 1 entries
   const int* tile_items;
   // workspaces
-  float2* Bws;               // pairs x R x L
-  float2* Vws;               // pairs x R x L
+  float2* Bws;               // pairs x R x L (block layout)
+  float2* Vws;               // pairs x R x L (block layout)
   float2* Pws;               // pairs x p_stride
 };
 bool fourstep_variant_supported(int L, int R, int P);
