@@ -107,14 +107,17 @@ WORKLOADS = {
     "c5": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1",
     "c5ad": "2D 2048x2048, m=64 tiles: autograd step of 0.5||H_m u - f||^2 (forward, adjoint for du, "
             "spectra gradient), against the plain forward + adjoint",
+    "c2pc": "1D batch 64 x N=65536, m=32 cubic B-spline windows, Gaussian h_k, product-convolution form "
+            "G_m u = sum_k w_k . (h_k * u); step = G_m u + G_m^* u",
 }
+PRODUCT_CONVOLUTION = {"c2pc"}
 
 
 def make_problems(name):
     import workloads as wl
     if name == "c1":
         return [wl.config_c1()]
-    if name == "c2":
+    if name in ("c2", "c2pc"):
         return [wl.config_c2()]
     if name == "c3":
         return [wl.config_c3()]
@@ -195,7 +198,7 @@ def main():
     counts = {"flops_per_step": 0.0, "bytes_per_step": 0.0, "kernel_flops": {}, "kernel_bytes": {}}
     for p in probs:
         wins = (p.w_rows, p.w_cols) if p.separable else p.w
-        plan = pcm.Plan(wins, p.h, batch=p.batch)
+        plan = pcm.Plan(wins, p.h, batch=p.batch, product_convolution=args.workload in PRODUCT_CONVOLUTION)
         u = torch.from_numpy(p.u).to(dev)
         jobs.append((p, plan, u, torch.empty_like(u), torch.empty_like(u)))
         c = algorithmic_counts(p, plan.info())
@@ -329,8 +332,12 @@ def main():
                     break
                 uu = q.u[b:b + 1].astype(np.float64)
                 c0 = time.perf_counter()
-                ry = ex.apply_fft(uu, w64, h64)
-                rx = ex.adjoint_fft(uu, w64, h64)
+                if args.workload in PRODUCT_CONVOLUTION:
+                    ry = ex.apply_pc_fft(uu, w64, h64)
+                    rx = ex.adjoint_pc_fft(uu, w64, h64)
+                else:
+                    ry = ex.apply_fft(uu, w64, h64)
+                    rx = ex.adjoint_fft(uu, w64, h64)
                 tc += time.perf_counter() - c0
                 errs.append(float(np.linalg.norm(y_gpu[b] - ry[0]) / np.linalg.norm(ry[0])))
                 errs.append(float(np.linalg.norm(x_gpu[b] - rx[0]) / np.linalg.norm(rx[0])))

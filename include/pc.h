@@ -65,7 +65,17 @@ enum {
   /* Allocate, at plan creation, the workspace pc_grad_spectra needs (one
    * spectrum-sized buffer); without it pc_grad_spectra returns
    * PC_ERROR_INVALID_VALUE. */
-  PC_PLAN_GRADIENTS = 1u
+  PC_PLAN_GRADIENTS = 1u,
+  /* The plan represents the product-convolution expansion of the
+   * introduction (eq. 1.3) instead of the convolution-product one:
+   *     G_m u = sum_k w_k . (h_k * u),   G_m^* v = sum_k h~_k * (w_k . v),
+   * with the same windows, impulse responses, layouts and sizes.  pc_apply
+   * evaluates G_m, pc_apply_adjoint G_m^*; the spectra calls still read and
+   * write F^* h_k, and pc_grad_spectra differentiates through G_m.  Since
+   * G_m is the adjoint of the convolution-product operator built on the
+   * flipped responses h~_k, such a plan runs the same kernels with the two
+   * directions exchanged. */
+  PC_PLAN_PRODUCT_CONVOLUTION = 2u
 };
 
 typedef struct {
@@ -104,6 +114,8 @@ typedef struct {
  * `windows` and `h` afterwards.  The plan is bound to the device current
  * at creation and may be used from one stream at a time (its workspace is
  * shared by its calls).
+ * With PC_PLAN_PRODUCT_CONVOLUTION the plan is G_m of eq. 1.3 instead
+ * (see the flag).
  * Errors: INVALID_VALUE (null pointers, ndim not 1/2, m < 1, batch < 1,
  * n1 != 1 in 1D, m != m_rows*m_cols, unknown flag bits), UNSUPPORTED (sizes above),
  * OUT_OF_MEMORY, HIP.
@@ -112,7 +124,8 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
                          void* stream);
 
 /*
- * pc_apply - y = H_m u for `batch` signals (eq. 1.4).
+ * pc_apply - y = H_m u for `batch` signals (eq. 1.4); y = G_m u (eq. 1.3)
+ * for a product-convolution plan.
  *
  *   u, y   (device) batch x N (1D) or batch x N1 x N2 (2D) floats; u is
  *          read only; y is written entirely; the two must not overlap.
@@ -126,7 +139,8 @@ pc_status pc_apply(pc_plan plan, const float* u, float* y, int64_t batch, void* 
 
 /*
  * pc_apply_adjoint - x = H_m^* v = sum_k w_k . (h~_k * v) for `batch`
- * signals.  Same buffer rules, errors and asynchrony as pc_apply.
+ * signals (x = G_m^* v = sum_k h~_k * (w_k . v) for a product-convolution
+ * plan).  Same buffer rules, errors and asynchrony as pc_apply.
  */
 pc_status pc_apply_adjoint(pc_plan plan, const float* v, float* x, int64_t batch, void* stream);
 
@@ -193,7 +207,9 @@ pc_status pc_plan_get_spectra(pc_plan plan, void* spec, void* stream);
 /*
  * pc_grad_spectra - gradient of a scalar loss L with respect to the spectra,
  * given the input u of y = H_m u and the upstream gradient gy = dL/dy:
- *   gspec[k][f] = (c_f / N) sum_b conj(F^*(w_k . u_b)[f]) (F^* gy_b)[f],
+ *   gspec[k][f] = (c_f / N) sum_b conj(F^*(w_k . u_b)[f]) (F^* gy_b)[f]
+ * (for a product-convolution plan, y = G_m u:
+ *   gspec[k][f] = (c_f / N) sum_b conj(F^* u_b[f]) (F^*(w_k . gy_b))[f]),
  * N the number of samples per signal, c_f = 1 on the bins of the last axis
  * that stand alone (DC, Nyquist), 2 on those that stand for a conjugate
  * pair; complex convention dL/dRe + i dL/dIm, summed over the batch.  Layout
@@ -221,11 +237,14 @@ pc_status pc_grad_spectra(pc_plan plan, const float* u, const float* gy, void* g
  *                batch runs (the batch uses their workspaces).
  *   inputs       (host array of count device pointers) each instance's input,
  *                plan batch x N1 x N2 floats (the plan's full batch).
- *   fwd_outputs  (host array) where pc_batch_apply writes H_i inputs[i].
+ *   fwd_outputs  (host array) where pc_batch_apply writes H_i inputs[i]
+ *                (G_i inputs[i] for a product-convolution plan).
  *   adj_outputs  (host array) where pc_batch_apply_adjoint writes
- *                H_i^* inputs[i].  Entries of either array may be NULL if
- *                that direction is never used; outputs must not overlap
- *                inputs.
+ *                H_i^* inputs[i] (G_i^* inputs[i]).  Either array may be
+ *                NULL if that direction is never used; the entries of a
+ *                given array must not be NULL, and outputs must not overlap
+ *                inputs.  Convolution-product and product-convolution
+ *                plans may share a batch.
  *   flags        PC_BATCH_NO_GRAPH: launch the passes directly instead of
  *                through the captured graphs.
  *   stream       used to build the graphs; creation is synchronous.

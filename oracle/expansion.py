@@ -16,6 +16,10 @@ Definitions followed (section numbers of the paper):
 * The adjoint of a real expansion: ``H_m^* v = sum_k w_k . (h~_k * v)``
   with ``h~_k[l] = h_k[-l]``, i.e. ``(H_m^* v)[j] = sum_k w_k[j]
   sum_i h_k[i - j] v[i]``.
+* eq. (1.3), the product-convolution expansion (the ``*_pc_*`` functions):
+  ``G_m u = sum_k w_k . (h_k * u)``, i.e. ``(G_m u)[i] = sum_k w_k[i]
+  sum_j h_k[i - j] u[j]``, and its adjoint ``G_m^* v = sum_k h~_k *
+  (w_k . v)``, i.e. ``(G_m^* v)[j] = sum_k sum_i h_k[i - j] w_k[i] v[i]``.
 
 2D uses the same formulas with index pairs taken modulo ``(N1, N2)``.
 Inputs are real (``u``, ``w_k``, ``h_k``); the functions accept a single
@@ -32,6 +36,8 @@ __all__ = [
     "apply_direct", "adjoint_direct", "apply_direct_at", "adjoint_direct_at",
     "apply_dft", "adjoint_dft", "apply_fft", "adjoint_fft", "workers",
     "dft_matrix", "circular_conv_direct",
+    "apply_pc_direct", "adjoint_pc_direct", "apply_pc_direct_at", "adjoint_pc_direct_at",
+    "apply_pc_fft", "adjoint_pc_fft",
 ]
 
 
@@ -271,4 +277,127 @@ def adjoint_fft(v, w, h, h_spec=None):
     out = np.zeros(vb.shape)
     for k in range(w.shape[0]):
         out += w[k][None] * _irfftn(np.conj(hs[k])[None] * vh, shape, nd)
+    return out[0] if single else out
+
+
+# ----------------------------------------------------------------------------
+# eq. (1.3): the product-convolution expansion, the same three ways
+# ----------------------------------------------------------------------------
+
+def apply_pc_direct(u, w, h):
+    """``G_m u = sum_k w_k . (h_k * u)`` by direct sums; tiny grids only."""
+    w = np.asarray(w, np.float64)
+    h = np.asarray(h, np.float64)
+    nd = h.ndim - 1
+    ub, single = _batched(u, nd)
+    flat = ub.reshape(ub.shape[0], -1)
+    out = np.zeros_like(ub)
+    for k in range(w.shape[0]):
+        c = _circulant(h[k])
+        out += w[k][None] * (flat @ c.T).reshape(ub.shape)
+    return out[0] if single else out
+
+
+def adjoint_pc_direct(v, w, h):
+    """``G_m^* v = sum_k h~_k * (w_k . v)``: ``sum_k sum_i h_k[i-j] w_k[i] v[i]``."""
+    w = np.asarray(w, np.float64)
+    h = np.asarray(h, np.float64)
+    nd = h.ndim - 1
+    vb, single = _batched(v, nd)
+    out = np.zeros_like(vb)
+    for k in range(w.shape[0]):
+        c = _circulant(h[k])
+        z = (w[k][None] * vb).reshape(vb.shape[0], -1)
+        out += (z @ c).reshape(vb.shape)          # sum_i C[i, j] z[i]
+    return out[0] if single else out
+
+
+def apply_pc_direct_at(u, w, h, idx, chunk=256):
+    """Selected outputs of ``G_m u``: ``w_k[i] sum_l h_k[l] u[i - l]`` over the
+    nonzero lags ``l`` of ``h_k``."""
+    u = np.asarray(u, np.float64)
+    w = np.asarray(w, np.float64)
+    h = np.asarray(h, np.float64)
+    shape = u.shape
+    idx = np.asarray(idx)
+    out = np.zeros(idx.shape[0])
+    if len(shape) == 1:
+        n = shape[0]
+        for k in range(w.shape[0]):
+            (ls,) = _support_lags(h[k])
+            hv = h[k][ls]
+            for s in range(0, idx.shape[0], chunk):
+                ii = idx[s:s + chunk]
+                out[s:s + chunk] += w[k][ii] * (u[(ii[:, None] - ls[None, :]) % n] @ hv)
+    else:
+        n1, n2 = shape
+        i1, i2 = np.unravel_index(idx, shape)
+        for k in range(w.shape[0]):
+            l1, l2 = _support_lags(h[k])
+            hv = h[k][l1, l2]
+            for s in range(0, idx.shape[0], chunk):
+                a = i1[s:s + chunk]
+                b = i2[s:s + chunk]
+                g = u[(a[:, None] - l1[None]) % n1, (b[:, None] - l2[None]) % n2] @ hv
+                out[s:s + chunk] += w[k][a, b] * g
+    return out
+
+
+def adjoint_pc_direct_at(v, w, h, idx, chunk=256):
+    """Selected outputs of ``G_m^* v``: ``sum_k sum_l h_k[l] (w_k v)[j + l]``."""
+    v = np.asarray(v, np.float64)
+    w = np.asarray(w, np.float64)
+    h = np.asarray(h, np.float64)
+    shape = v.shape
+    idx = np.asarray(idx)
+    out = np.zeros(idx.shape[0])
+    if len(shape) == 1:
+        n = shape[0]
+        for k in range(w.shape[0]):
+            (ls,) = _support_lags(h[k])
+            hv = h[k][ls]
+            z = w[k] * v
+            for s in range(0, idx.shape[0], chunk):
+                jj = idx[s:s + chunk]
+                out[s:s + chunk] += z[(jj[:, None] + ls[None, :]) % n] @ hv
+    else:
+        n1, n2 = shape
+        j1, j2 = np.unravel_index(idx, shape)
+        for k in range(w.shape[0]):
+            l1, l2 = _support_lags(h[k])
+            hv = h[k][l1, l2]
+            z = w[k] * v
+            for s in range(0, idx.shape[0], chunk):
+                a = j1[s:s + chunk, None]
+                b = j2[s:s + chunk, None]
+                out[s:s + chunk] += z[(a + l1[None]) % n1, (b + l2[None]) % n2] @ hv
+    return out
+
+
+def apply_pc_fft(u, w, h, h_spec=None):
+    """``G_m u`` via float64 real FFTs: ``sum_k w_k . F((F^* h_k) . (F^* u))``."""
+    w = np.asarray(w, np.float64)
+    nd = w.ndim - 1
+    ub, single = _batched(u, nd)
+    shape = ub.shape[1:]
+    hs = _rfftn(np.asarray(h, np.float64), nd) if h_spec is None else h_spec
+    uh = _rfftn(ub, nd)
+    out = np.zeros(ub.shape)
+    for k in range(w.shape[0]):
+        out += w[k][None] * _irfftn(hs[k][None] * uh, shape, nd)
+    return out[0] if single else out
+
+
+def adjoint_pc_fft(v, w, h, h_spec=None):
+    """``G_m^* v`` via float64 real FFTs: ``F(sum_k conj(F^* h_k) . F^*(w_k . v))``."""
+    w = np.asarray(w, np.float64)
+    nd = w.ndim - 1
+    vb, single = _batched(v, nd)
+    shape = vb.shape[1:]
+    hs = _rfftn(np.asarray(h, np.float64), nd) if h_spec is None else h_spec
+    acc = None
+    for k in range(w.shape[0]):
+        term = np.conj(hs[k])[None] * _rfftn(w[k][None] * vb, nd)
+        acc = term if acc is None else acc + term
+    out = _irfftn(acc, shape, nd)
     return out[0] if single else out

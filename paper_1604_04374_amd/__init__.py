@@ -19,7 +19,8 @@ from typing import Optional, Sequence, Tuple, Union
 
 import numpy as np
 
-__all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+__all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
+           "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,6 +48,7 @@ EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_p
 PC_BATCH_NO_GRAPH = 1
 
 PC_PLAN_GRADIENTS = 1
+PC_PLAN_PRODUCT_CONVOLUTION = 2
 
 
 class PlanDesc(ctypes.Structure):
@@ -148,7 +150,9 @@ def _f32(a) -> np.ndarray:
 
 
 class Plan:
-    """The operator ``H_m`` of eq. 1.4 resident on the current device.
+    """The operator ``H_m`` of eq. 1.4 resident on the current device, or
+    with ``product_convolution=True`` the product-convolution operator
+    ``G_m u = sum_k w_k . (h_k * u)`` of eq. 1.3.
 
     Parameters
     ----------
@@ -158,17 +162,21 @@ class Plan:
         ``w_{k1*m2+k2} = a_k1 (x) b_k2``.
     h : array ``m x N`` / ``m x N1 x N2``, impulse responses in lag layout.
     batch : largest number of signals per call.
+    gradients : allocate the workspace of :meth:`grad_spectra`.
+    product_convolution : build ``G_m`` (eq. 1.3) instead of ``H_m``.
     """
 
     def __init__(self, windows: Union[np.ndarray, Tuple[np.ndarray, np.ndarray]], h: np.ndarray,
-                 batch: int = 1, stream=None, gradients: bool = False):
+                 batch: int = 1, stream=None, gradients: bool = False, product_convolution: bool = False):
         self._lib = load_library()
         self._handle = ctypes.c_void_p()
         h = _f32(h)
         d = PlanDesc()
         d.m = h.shape[0]
         d.batch = int(batch)
-        d.flags = PC_PLAN_GRADIENTS if gradients else 0
+        d.flags = (PC_PLAN_GRADIENTS if gradients else 0) | (
+            PC_PLAN_PRODUCT_CONVOLUTION if product_convolution else 0)
+        self.product_convolution = bool(product_convolution)
         if isinstance(windows, (tuple, list)):
             a, b = _f32(windows[0]), _f32(windows[1])
             d.w_format = PC_W_SEPARABLE

@@ -52,15 +52,16 @@ def expansion(u, spec, plan):
 
 
 class ExpansionOperator(torch.nn.Module):
-    """A convolution-product operator whose spectra are trainable.
+    """A convolution-product operator (or, with ``product_convolution=True``,
+    a product-convolution operator, eq. 1.3) whose spectra are trainable.
 
     ``windows``/``h`` as for :class:`Plan`; the initial spectra are the plan's
     transform of ``h``.
     """
 
-    def __init__(self, windows, h, batch=1):
+    def __init__(self, windows, h, batch=1, product_convolution=False):
         super().__init__()
-        self.plan = Plan(windows, h, batch=batch, gradients=True)
+        self.plan = Plan(windows, h, batch=batch, gradients=True, product_convolution=product_convolution)
         self.spec = torch.nn.Parameter(self.plan.get_spectra())
         torch.cuda.synchronize()
 

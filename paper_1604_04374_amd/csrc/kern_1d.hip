@@ -389,7 +389,7 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
 // then the class's inverse FFT_L, stored for the combine step.
 template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__ u, int64_t batch, Large1D p) {
-  constexpr int T = L / P, N = L * R;
+  constexpr int N = L * R;
   __shared__ float2 lds[lds_len<L>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, p.tw);
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(256) void k_origin_phase1d(float2* __restrict__ Hd,
 template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict__ u, int64_t batch, Large1D p,
                                                         float2* __restrict__ E) {
-  constexpr int T = L / P, N = L * R;
+  constexpr int N = L * R;
   __shared__ float2 lds[lds_len<L>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, p.tw);
@@ -887,9 +887,21 @@ __global__ __launch_bounds__(256) void k_grad_export1d_large(const float2* __res
   gspec[gid] = make_float2(sc * (a.x + b.x), sc * (a.y - b.y));
 }
 
+// out[i] = conj(in[i]); in may equal out
+__global__ __launch_bounds__(256) void k_conj(const float2* in, float2* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cconj(in[i]);
+}
+
 // ---- launchers --------------------------------------------------------------
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+LaunchStatus launch_conj(const float2* in, float2* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conj, dim3(blocks_for(n)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
 
 LaunchStatus launch_spectra1d(const Small1D* ps, const Large1D* pl, const float2* in, float2* out, bool import,
                               hipStream_t s) {

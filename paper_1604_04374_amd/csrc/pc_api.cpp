@@ -183,6 +183,11 @@ struct pc_plan_s {
   PlanTracer tracer;
   float2* grad_ws = nullptr;  // PC_PLAN_GRADIENTS workspace
   int64_t spec_count = 0;     // complex values of the natural-layout spectra
+  // product-convolution plan (eq. 1.3): built on the flipped responses, runs
+  // the convolution-product directions exchanged; its stored spectra are
+  // conj(F^* h_k), converted at the spectra calls through conj_ws
+  bool pconv = false;
+  float2* conj_ws = nullptr;
   pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
   ~pc_plan_s() {
@@ -698,6 +703,17 @@ pc_status capture(const std::vector<pc::LaunchSet>& seq, hipStream_t cs, hipGrap
   return PC_SUCCESS;
 }
 
+// Launch lists of one batch call.  Each call (apply, apply_adjoint) runs a
+// forward-type chain (windowed row FFTs, term-split column pass with the
+// spectral sum, inverse rows) for the instances that need the
+// convolution-product direction, and an adjoint-type chain (row FFTs, column
+// FFTs, per-(column, factor) adjoint columns, windowed inverse rows) for the
+// others; a product-convolution plan takes the opposite chain of a
+// convolution-product one.
+struct BatchLists {
+  std::vector<pc::LaunchSet> f_rows_in, f_cols, f_rows_out, a_rows_in, a_fft, a_cols, a_rows_out;
+};
+
 pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa) {
   // group instances by row length (N2) and by column length (N1)
   std::vector<int> n2s, n1s;
@@ -705,66 +721,87 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
     if (std::find(n2s.begin(), n2s.end(), p->p2.N2) == n2s.end()) n2s.push_back(p->p2.N2);
     if (std::find(n1s.begin(), n1s.end(), p->p2.N1) == n1s.end()) n1s.push_back(p->p2.N1);
   }
-  std::vector<pc::LaunchSet> rows_in_f, cols_f, rows_out_f, rows_in_a, fft_a, cols_a, rows_out_a;
+  BatchLists lists[2];  // [0]: pc_batch_apply, [1]: pc_batch_apply_adjoint
+  // instance i, call c: output buffer and whether it takes the forward-type chain
+  auto out_of = [&](size_t i, int c) -> float* { return c == 0 ? fo[i] : fa[i]; };
+  auto fwd_type = [&](size_t i, int c) { return (c == 0) != b->plans[i]->pconv; };
   pc_status st;
-  for (int L2 : n2s) {
-    std::vector<pc::RowJob> jf, jfo, ja, jao;
-    std::vector<pc::BlockRef> bf, bfo, ba, bao;
-    const float2* tw = nullptr;
-    for (size_t i = 0; i < b->plans.size(); ++i) {
-      const pc::Plan2D& q = b->plans[i]->p2;
-      if (q.N2 != L2) continue;
-      tw = q.tw2;
-      const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
-      const int nq = q.dense ? q.m : q.m2, mode = q.dense ? 2 : 1;
-      const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
-      if (fo[i]) {
-        pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq);
-        jf.push_back(pc::RowJob{in[i], nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap});
-        pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1);
-        jfo.push_back(pc::RowJob{nullptr, fo[i], nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0});
+  for (int c = 0; c < 2; ++c) {
+    BatchLists& bl = lists[c];
+    for (int L2 : n2s) {
+      std::vector<pc::RowJob> jf, jfo, ja, jao;
+      std::vector<pc::BlockRef> bf, bfo, ba, bao;
+      const float2* tw = nullptr;
+      for (size_t i = 0; i < b->plans.size(); ++i) {
+        const pc::Plan2D& q = b->plans[i]->p2;
+        float* out = out_of(i, c);
+        if (q.N2 != L2 || !out) continue;
+        tw = q.tw2;
+        const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
+        const int nq = q.dense ? q.m : q.m2, mode = q.dense ? 2 : 1;
+        const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
+        if (fwd_type(i, c)) {
+          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq);
+          jf.push_back(pc::RowJob{in[i], nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap});
+          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1);
+          jfo.push_back(pc::RowJob{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0});
+        } else {
+          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
+          ja.push_back(pc::RowJob{in[i], nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap});
+          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1);
+          jao.push_back(pc::RowJob{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap});
+        }
       }
-      if (fa[i]) {
-        pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
-        ja.push_back(pc::RowJob{in[i], nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap});
-        pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1);
-        jao.push_back(pc::RowJob{nullptr, fa[i], q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap});
-      }
+      if ((st = batch_set(b, bl.f_rows_in, pc::KK_ROWS_FWD, L2, jf, bf, tw))) return st;
+      if ((st = batch_set(b, bl.f_rows_out, pc::KK_ROWS_INV, L2, jfo, bfo, tw))) return st;
+      if ((st = batch_set(b, bl.a_rows_in, pc::KK_ROWS_FWD, L2, ja, ba, tw))) return st;
+      if ((st = batch_set(b, bl.a_rows_out, pc::KK_ROWS_INV, L2, jao, bao, tw))) return st;
     }
-    if ((st = batch_set(b, rows_in_f, pc::KK_ROWS_FWD, L2, jf, bf, tw))) return st;
-    if ((st = batch_set(b, rows_out_f, pc::KK_ROWS_INV, L2, jfo, bfo, tw))) return st;
-    if ((st = batch_set(b, rows_in_a, pc::KK_ROWS_FWD, L2, ja, ba, tw))) return st;
-    if ((st = batch_set(b, rows_out_a, pc::KK_ROWS_INV, L2, jao, bao, tw))) return st;
-  }
-  for (int L1 : n1s) {
-    std::vector<pc::ColJob> jf, jt, ja;
-    std::vector<pc::BlockRef> bf, bt, ba;
-    const float2* tw = nullptr;
-    for (size_t i = 0; i < b->plans.size(); ++i) {
-      const pc::Plan2D& q = b->plans[i]->p2;
-      if (q.N1 != L1) continue;
-      tw = q.tw1;
-      const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
-      const int nq = q.dense ? q.m : q.m2, dense = q.dense ? 1 : 0;
-      if (fo[i]) {  // one term group: the many instances already fill the device
-        pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
-        jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+    for (int L1 : n1s) {
+      std::vector<pc::ColJob> jf, jt, ja;
+      std::vector<pc::BlockRef> bf, bt, ba;
+      const float2* tw = nullptr;
+      for (size_t i = 0; i < b->plans.size(); ++i) {
+        const pc::Plan2D& q = b->plans[i]->p2;
+        if (q.N1 != L1 || !out_of(i, c)) continue;
+        tw = q.tw1;
+        const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
+        const int nq = q.dense ? q.m : q.m2, dense = q.dense ? 1 : 0;
+        if (fwd_type(i, c)) {  // one term group: the many instances already fill the device
+          pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
+          jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+        } else {
+          pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
+          jt.push_back(pc::ColJob{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, q.H2, q.m1, q.m2, dense, 1});
+          pc::append_col_blocks(ba, (int)ja.size(), cap, q.H2, L1, nq);
+          ja.push_back(pc::ColJob{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+        }
       }
-      if (fa[i]) {
-        pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
-        jt.push_back(pc::ColJob{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, q.H2, q.m1, q.m2, dense, 1});
-        pc::append_col_blocks(ba, (int)ja.size(), cap, q.H2, L1, nq);
-        ja.push_back(pc::ColJob{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
-      }
+      if ((st = batch_set(b, bl.f_cols, pc::KK_COLS_FWD, L1, jf, bf, tw))) return st;
+      if ((st = batch_set(b, bl.a_fft, pc::KK_COLS_FFT, L1, jt, bt, tw))) return st;
+      if ((st = batch_set(b, bl.a_cols, pc::KK_COLS_ADJ, L1, ja, ba, tw))) return st;
     }
-    if ((st = batch_set(b, cols_f, pc::KK_COLS_FWD, L1, jf, bf, tw))) return st;
-    if ((st = batch_set(b, fft_a, pc::KK_COLS_FFT, L1, jt, bt, tw))) return st;
-    if ((st = batch_set(b, cols_a, pc::KK_COLS_ADJ, L1, ja, ba, tw))) return st;
   }
-  for (auto* v : {&rows_in_f, &cols_f, &rows_out_f}) b->fwd_seq.insert(b->fwd_seq.end(), v->begin(), v->end());
-  for (auto* v : {&rows_in_a, &fft_a, &cols_a, &rows_out_a})
-    b->adj_seq.insert(b->adj_seq.end(), v->begin(), v->end());
+  for (int c = 0; c < 2; ++c) {
+    std::vector<pc::LaunchSet>& seq = c == 0 ? b->fwd_seq : b->adj_seq;
+    BatchLists& bl = lists[c];
+    for (auto* v : {&bl.f_rows_in, &bl.a_rows_in, &bl.f_cols, &bl.a_fft, &bl.a_cols, &bl.f_rows_out, &bl.a_rows_out})
+      seq.insert(seq.end(), v->begin(), v->end());
+  }
   return PC_SUCCESS;
+}
+
+// The convolution-product directions of a plan (eq. 1.4 and its adjoint).
+hipError_t run_forward(pc_plan p, const float* u, float* y, int64_t batch, hipStream_t s) {
+  if (p->path == 0) return pc::launch_fwd1d_small(p->s1, u, y, batch, s, p->tr());
+  if (p->path == 1) return pc::launch_fwd1d_large(p->l1, u, y, batch, s, p->tr());
+  return pc::launch_fwd2d(p->p2, u, y, batch, s, p->tr());
+}
+
+hipError_t run_adjoint(pc_plan p, const float* v, float* x, int64_t batch, hipStream_t s) {
+  if (p->path == 0) return pc::launch_adj1d_small(p->s1, v, x, batch, s, p->tr());
+  if (p->path == 1) return pc::launch_adj1d_large(p->l1, v, x, batch, s, p->tr());
+  return pc::launch_adj2d(p->p2, v, x, batch, s, p->tr());
 }
 
 pc_status check_batch(pc_batch b) {
@@ -889,7 +926,8 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
   if (d.ndim != 1 && d.ndim != 2) return fail(PC_ERROR_INVALID_VALUE, "ndim must be 1 or 2");
   if (d.m < 1) return fail(PC_ERROR_INVALID_VALUE, "m must be >= 1");
   if (d.batch < 1) return fail(PC_ERROR_INVALID_VALUE, "batch must be >= 1");
-  if (d.flags & ~(uint32_t)PC_PLAN_GRADIENTS) return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
+  if (d.flags & ~(uint32_t)(PC_PLAN_GRADIENTS | PC_PLAN_PRODUCT_CONVOLUTION))
+    return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
   if (d.n0 < 1 || d.n1 < 1) return fail(PC_ERROR_INVALID_VALUE, "sizes must be positive");
   if (d.w_format != PC_W_DENSE && d.w_format != PC_W_SEPARABLE)
     return fail(PC_ERROR_INVALID_VALUE, "unknown window format");
@@ -924,6 +962,18 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
     return fail_hip(e, "hipGetDevice");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  p->pconv = (d.flags & PC_PLAN_PRODUCT_CONVOLUTION) != 0;
+  // G_m = (convolution-product operator of the flipped responses)^*
+  std::vector<float> flipped;
+  if (p->pconv) {
+    const int64_t n0 = d.n0, n1 = d.n1;
+    flipped.resize((size_t)d.m * n0 * n1);
+    for (int64_t k = 0; k < d.m; ++k)
+      for (int64_t i = 0; i < n0; ++i)
+        for (int64_t j = 0; j < n1; ++j)
+          flipped[(size_t)((k * n0 + i) * n1 + j)] = h[(size_t)((k * n0 + (n0 - i) % n0) * n1 + (n1 - j) % n1)];
+    h = flipped.data();
+  }
   pc_status st;
   if (path == 0)
     st = build_small1d(p, windows, h, s);
@@ -933,6 +983,9 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
     st = build_2d(p, windows, h, s);
   if (st == PC_SUCCESS) {
     p->spec_count = (int64_t)d.m * (d.ndim == 1 ? d.n0 / 2 + 1 : d.n0 * (d.n1 / 2 + 1));
+    if (p->pconv) st = p->alloc(&p->conj_ws, (size_t)p->spec_count, &p->workspace_bytes);
+  }
+  if (st == PC_SUCCESS) {
     if (d.flags & PC_PLAN_GRADIENTS) {
       // 1D: pair spectra (pairs x N) or the per-class accumulators (m x N); 2D: m planes
       const int64_t pairs = (d.batch + 1) / 2;
@@ -957,14 +1010,8 @@ pc_status pc_apply(pc_plan p, const float* u, float* y, int64_t batch, void* str
   pc_status st = check_apply(p, u, y, batch);
   if (st || batch == 0) return st;
   DeviceGuard g(p->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  if (p->path == 0)
-    e = pc::launch_fwd1d_small(p->s1, u, y, batch, s, p->tr());
-  else if (p->path == 1)
-    e = pc::launch_fwd1d_large(p->l1, u, y, batch, s, p->tr());
-  else
-    e = pc::launch_fwd2d(p->p2, u, y, batch, s, p->tr());
+  hipError_t e = p->pconv ? run_adjoint(p, u, y, batch, static_cast<hipStream_t>(stream))
+                          : run_forward(p, u, y, batch, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e, "pc_apply launch");
   return PC_SUCCESS;
 }
@@ -973,14 +1020,8 @@ pc_status pc_apply_adjoint(pc_plan p, const float* v, float* x, int64_t batch, v
   pc_status st = check_apply(p, v, x, batch);
   if (st || batch == 0) return st;
   DeviceGuard g(p->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  if (p->path == 0)
-    e = pc::launch_adj1d_small(p->s1, v, x, batch, s, p->tr());
-  else if (p->path == 1)
-    e = pc::launch_adj1d_large(p->l1, v, x, batch, s, p->tr());
-  else
-    e = pc::launch_adj2d(p->p2, v, x, batch, s, p->tr());
+  hipError_t e = p->pconv ? run_forward(p, v, x, batch, static_cast<hipStream_t>(stream))
+                          : run_adjoint(p, v, x, batch, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e, "pc_apply_adjoint launch");
   return PC_SUCCESS;
 }
@@ -1030,6 +1071,11 @@ pc_status pc_plan_set_spectra(pc_plan p, const void* spec, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float2* in = static_cast<const float2*>(spec);
   hipError_t e;
+  if (p->pconv) {  // the plan stores the spectra of the flipped responses
+    e = pc::launch_conj(in, p->conj_ws, p->spec_count, s);
+    if (e != hipSuccess) return fail_hip(e, "pc_plan_set_spectra launch");
+    in = p->conj_ws;
+  }
   if (p->path == 0)
     e = pc::launch_spectra1d(&p->s1, nullptr, in, nullptr, true, s);
   else if (p->path == 1)
@@ -1054,6 +1100,7 @@ pc_status pc_plan_get_spectra(pc_plan p, void* spec, void* stream) {
     e = pc::launch_spectra1d(nullptr, &p->l1, nullptr, out, false, s);
   else
     e = pc::launch_spectra2d(p->p2, nullptr, out, false, s);
+  if (e == hipSuccess && p->pconv) e = pc::launch_conj(out, out, p->spec_count, s);
   if (e != hipSuccess) return fail_hip(e, "pc_plan_get_spectra launch");
   return PC_SUCCESS;
 }
@@ -1069,13 +1116,18 @@ pc_status pc_grad_spectra(pc_plan p, const float* u, const float* gy, void* gspe
   DeviceGuard g(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   float2* out = static_cast<float2*>(gspec);
+  // product-convolution: sum_b conj(F^* u_b) F^*(w_k . gy_b) is the
+  // conjugate of the convolution-product sum with u and gy exchanged
+  const float* a = p->pconv ? gy : u;
+  const float* b = p->pconv ? u : gy;
   hipError_t e;
   if (p->path == 0)
-    e = pc::launch_grad1d_small(p->s1, u, gy, out, batch, p->grad_ws, s, p->tr());
+    e = pc::launch_grad1d_small(p->s1, a, b, out, batch, p->grad_ws, s, p->tr());
   else if (p->path == 1)
-    e = pc::launch_grad1d_large(p->l1, u, gy, out, batch, p->grad_ws, s, p->tr());
+    e = pc::launch_grad1d_large(p->l1, a, b, out, batch, p->grad_ws, s, p->tr());
   else
-    e = pc::launch_grad2d(p->p2, u, gy, out, batch, p->grad_ws, s, p->tr());
+    e = pc::launch_grad2d(p->p2, a, b, out, batch, p->grad_ws, s, p->tr());
+  if (e == hipSuccess && p->pconv) e = pc::launch_conj(out, out, p->spec_count, s);
   if (e != hipSuccess) return fail_hip(e, "pc_grad_spectra launch");
   return PC_SUCCESS;
 }

@@ -105,6 +105,8 @@ struct Large1D {
 bool fourstep_variant_supported(int L, int R, int P);
 LaunchStatus launch_fold_fft(const Large1D& p, const float* xa, int64_t n_sig, float2* out, bool pairs, hipStream_t s,
                              Tracer* tr = nullptr);
+// out[i] = conj(in[i]), i < n (in may equal out)
+LaunchStatus launch_conj(const float2* in, float2* out, int64_t n, hipStream_t s);
 // Hd (natural frame, m x R x L) -> window-origin frame, in place
 LaunchStatus launch_origin_phase1d(const Large1D& p, float2* Hd, hipStream_t s);
 LaunchStatus launch_fwd1d_large(const Large1D& p, const float* u, float* y, int64_t batch, hipStream_t s,

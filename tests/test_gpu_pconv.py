@@ -1,0 +1,180 @@
+"""Product-convolution plans (eq. 1.3) on the GPU against the FP64 oracle:
+forward and adjoint, spectra access, spectra gradient, autograd and batches
+that mix both kinds of plans.  Tolerance: relative L2 <= 1e-5 per signal."""
+import numpy as np
+import pytest
+import scipy.fft as sfft
+
+import workloads as wl
+from gpu_util import per_instance_rel, plan_args, rel_l2
+from oracle import expansion as ex, grads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_04374_amd as pcm
+    pcm.load_library()
+
+
+def _problems():
+    return [
+        wl.config_c1(),
+        wl.small_1d(1536, 5, 3, 3, seed=61, sigma_fn=lambda y: 0.01 + 0.02 * y),
+        wl.small_1d(16384, 6, 3, 3, seed=62, sigma_fn=wl.gen.c2_sigma),   # four-step, short supports
+        wl.small_1d(16384, 2, 1, 3, seed=63, sigma_fn=wl.gen.c2_sigma),   # four-step, supports > L
+        wl.small_1d(24576, 5, 1, 2, seed=64, sigma_fn=wl.gen.c2_sigma),
+        wl.small_2d(64, 96, 2, 3, 3, seed=65, kind="hat"),
+        wl.small_2d(128, 128, 4, 4, 1, seed=66, kind="tile"),
+    ]
+
+
+def _plan(p, **kw):
+    import paper_1604_04374_amd as pcm
+    return pcm.Plan(plan_args(p), p.h, batch=p.batch, product_convolution=True, **kw)
+
+
+def _oracle(p, v=None, spec=None):
+    w = p.dense_windows()
+    h = None if spec is not None else p.h.astype(np.float64)
+    u = p.u.astype(np.float64)
+    vv = u if v is None else v
+    return ex.apply_pc_fft(u, w, h, h_spec=spec), ex.adjoint_pc_fft(vv, w, h, h_spec=spec)
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_forward_adjoint_vs_oracle(idx):
+    import torch
+    p = _problems()[idx]
+    print(f"[gpu] product-convolution {p.name}", flush=True)
+    u = torch.from_numpy(p.u).cuda()
+    with _plan(p) as plan:
+        y = plan.apply(u).cpu().numpy()
+        x = plan.apply_adjoint(u).cpu().numpy()
+    ry, rx = _oracle(p)
+    ey, ea = per_instance_rel(y, ry), per_instance_rel(x, rx)
+    print(f"{p.name}: fwd rel {ey:.2e} adj rel {ea:.2e}", flush=True)
+    assert ey <= TOL and ea <= TOL
+    if p.n_total <= 2048:
+        w, h = p.dense_windows(), p.h.astype(np.float64)
+        assert per_instance_rel(y, ex.apply_pc_direct(p.u.astype(np.float64), w, h)) <= TOL
+        assert per_instance_rel(x, ex.adjoint_pc_direct(p.u.astype(np.float64), w, h)) <= TOL
+
+
+def test_c2_size_against_sampled_direct_sums():
+    import torch
+    p = wl.config_c2(batch=4)
+    print(f"[gpu] product-convolution {p.name} (4 signals)", flush=True)
+    u = torch.from_numpy(p.u).cuda()
+    with _plan(p) as plan:
+        y = plan.apply(u).cpu().numpy()
+        x = plan.apply_adjoint(u).cpu().numpy()
+    ry, rx = _oracle(p)
+    assert per_instance_rel(y, ry) <= TOL and per_instance_rel(x, rx) <= TOL
+    rng = np.random.default_rng(7)
+    w, h = p.dense_windows(), p.h.astype(np.float64)
+    for b in range(p.batch):
+        idx = rng.choice(p.n_total, 128, replace=False)
+        sy = ex.apply_pc_direct_at(p.u[b].astype(np.float64), w, h, idx)
+        sx = ex.adjoint_pc_direct_at(p.u[b].astype(np.float64), w, h, idx)
+        assert rel_l2(y[b][idx], sy) <= TOL and rel_l2(x[b][idx], sx) <= TOL
+
+
+@pytest.mark.parametrize("idx", [2, 5])
+def test_adjoint_identity(idx):
+    import torch
+    p = _problems()[idx]
+    rng = np.random.default_rng(70 + idx)
+    v = rng.standard_normal(p.u.shape).astype(np.float32)
+    with _plan(p) as plan:
+        y = plan.apply(torch.from_numpy(p.u).cuda()).cpu().numpy().astype(np.float64)
+        x = plan.apply_adjoint(torch.from_numpy(v).cuda()).cpu().numpy().astype(np.float64)
+    lhs = np.sum(y * v)
+    rhs = np.sum(p.u.astype(np.float64) * x)
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(y * y) * np.sum(v.astype(np.float64) ** 2))
+
+
+@pytest.mark.parametrize("idx", [0, 2, 3, 5])
+def test_spectra_are_those_of_h_and_replace_the_operator(idx):
+    import torch
+    p = _problems()[idx]
+    axes = tuple(range(-p.ndim, 0))
+    rng = np.random.default_rng(80 + idx)
+    h2 = np.roll(p.h, 3, axis=-1) * rng.uniform(0.5, 1.5, (p.m,) + (1,) * p.ndim)
+    spec2 = sfft.rfftn(h2.astype(np.float64), axes=axes)
+    u = torch.from_numpy(p.u).cuda()
+    with _plan(p) as plan:
+        got = plan.get_spectra().cpu().numpy()
+        assert rel_l2(got, sfft.rfftn(p.h.astype(np.float64), axes=axes)) < 1e-6
+        plan.set_spectra(torch.from_numpy(spec2.astype(np.complex64)).cuda())
+        back = plan.get_spectra().cpu().numpy()
+        y = plan.apply(u).cpu().numpy()
+        x = plan.apply_adjoint(u).cpu().numpy()
+    assert rel_l2(back, spec2) < 1e-6
+    ry, rx = _oracle(p, spec=spec2.astype(np.complex64).astype(np.complex128))
+    assert per_instance_rel(y, ry) <= TOL and per_instance_rel(x, rx) <= TOL
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_grad_spectra_matches_oracle(idx):
+    import torch
+    p = _problems()[idx]
+    print(f"[gpu] product-convolution grad_spectra {p.name}", flush=True)
+    rng = np.random.default_rng(90 + idx)
+    g = rng.standard_normal(p.u.shape).astype(np.float32)
+    with _plan(p, gradients=True) as plan:
+        got = plan.grad_spectra(torch.from_numpy(p.u).cuda(), torch.from_numpy(g).cuda()).cpu().numpy()
+    ref = grads.grad_spectra_pc(p.u, g, p.dense_windows())
+    err = rel_l2(got, ref)
+    print(f"{p.name}: grad spectra rel {err:.2e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("idx", [0, 2, 5])
+def test_autograd_matches_oracle(idx):
+    import torch
+    from paper_1604_04374_amd.autograd import ExpansionOperator, expansion
+    p = _problems()[idx]
+    print(f"[gpu] product-convolution autograd {p.name}", flush=True)
+    rng = np.random.default_rng(100 + idx)
+    f = rng.standard_normal(p.u.shape).astype(np.float32)
+    op = ExpansionOperator(plan_args(p), p.h, batch=p.batch, product_convolution=True)
+    u = torch.from_numpy(p.u).cuda().requires_grad_(True)
+    y = expansion(u, op.spec, op.plan)
+    loss = 0.5 * torch.sum((y - torch.from_numpy(f).cuda()).double() ** 2)
+    loss.backward()
+    w = p.dense_windows()
+    spec = op.spec.detach().cpu().numpy().astype(np.complex128)
+    r = y.detach().cpu().numpy().astype(np.float64) - f
+    assert rel_l2(u.grad.cpu().numpy(), ex.adjoint_pc_fft(r, w, None, h_spec=spec)) <= TOL
+    assert rel_l2(op.spec.grad.cpu().numpy(), grads.grad_spectra_pc(p.u, r, w)) <= TOL
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_mixing_both_kinds(graph):
+    import torch
+    import paper_1604_04374_amd as pcm
+    probs = wl.config_c4(count=12, seed=11)
+    kinds = [i % 2 == 1 for i in range(len(probs))]
+    print(f"[gpu] mixed batch of {len(probs)} (graph={graph})", flush=True)
+    plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch, product_convolution=k) for p, k in zip(probs, kinds)]
+    inputs = [torch.from_numpy(p.u).cuda() for p in probs]
+    b = pcm.Batch(plans, inputs, graph=graph)
+    y = [t.clone() for t in b.apply()]
+    x = [t.clone() for t in b.apply_adjoint()]
+    torch.cuda.synchronize()
+    for i, (p, k) in enumerate(zip(probs, kinds)):
+        w, h, u = p.dense_windows(), p.h.astype(np.float64), p.u.astype(np.float64)
+        ry = ex.apply_pc_fft(u, w, h) if k else ex.apply_fft(u, w, h)
+        rx = ex.adjoint_pc_fft(u, w, h) if k else ex.adjoint_fft(u, w, h)
+        assert per_instance_rel(y[i].cpu().numpy(), ry) <= TOL, (p.name, k)
+        assert per_instance_rel(x[i].cpu().numpy(), rx) <= TOL, (p.name, k)
+        assert torch.allclose(y[i], plans[i].apply(inputs[i]), rtol=0, atol=1e-5 * float(y[i].abs().max()))
+    b.destroy()
+    for pl in plans:
+        pl.destroy()
