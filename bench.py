@@ -79,6 +79,26 @@ def algorithmic_counts(p, info):
         kb = {"fwd1d_large": B * n * 4 + spec_bytes + support_sum * 4, "adj1d_large": spec_bytes + support_sum * 4,
               "fwd1d_small": B * n * 8 + spec_bytes + support_sum * 4,
               "adj1d_small": B * n * 8 + spec_bytes + support_sum * 4}
+    elif info["path"] == 3:
+        # sectioned (compact supports): every section is a one-term operator
+        # on fft_inner x fft_outer samples (the sizes are equal across
+        # sections for the workloads here); the spectra are those of the
+        # sections
+        s_n, m1s, m2s = info["n_items"], info["fft_inner"], info["fft_outer"]
+        h2s = m2s // 2 + 1
+        rowfft = 2.5 * m1s * m2s * _lg(m2s)
+        colfft = 5.0 * m1s * h2s * _lg(m1s)
+        spec_bytes = s_n * m1s * h2s * 8
+        per_sig = s_n * (2 * rowfft + 2 * colfft + 8.0 * m1s * h2s) + support_sum
+        kf = {"rows_fwd": B * s_n * 2 * rowfft, "rows_inv": B * s_n * 2 * rowfft,
+              "cols_fwd": B * s_n * (2 * colfft + 8.0 * m1s * h2s),
+              "cols_adj": B * s_n * (colfft + 8.0 * m1s * h2s), "cols_fft": B * s_n * colfft}
+        kb = {"cols_fwd": spec_bytes, "cols_adj": spec_bytes,
+              "rows_fwd": 2 * B * s_n * m1s * m2s * 4, "rows_inv": 2 * B * s_n * m1s * m2s * 4,
+              "sec_gather": 2 * B * s_n * m1s * m2s * 4 * 2, "sec_scatter": 2 * B * (s_n * m1s * m2s + ntot) * 4}
+        bytes_dir = B * ntot * 4 * 2 + spec_bytes + support_sum * 4
+        return {"flops_per_step": 2 * B * per_sig, "bytes_per_step": 2 * bytes_dir, "kernel_flops": kf,
+                "kernel_bytes": kb}
     else:
         n1, n2 = p.shape
         h2 = n2 // 2 + 1
@@ -109,8 +129,12 @@ WORKLOADS = {
             "spectra gradient), against the plain forward + adjoint",
     "c2pc": "1D batch 64 x N=65536, m=32 cubic B-spline windows, Gaussian h_k, product-convolution form "
             "G_m u = sum_k w_k . (h_k * u); step = G_m u + G_m^* u",
+    "c5full": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1, evaluated on the full grid "
+              "(no sections)",
 }
 PRODUCT_CONVOLUTION = {"c2pc"}
+# batched instances must be full-grid plans; c5full measures C5 without sections
+FULL_GRID = {"c4", "c5full"}
 
 
 def make_problems(name):
@@ -123,7 +147,7 @@ def make_problems(name):
         return [wl.config_c3()]
     if name == "c4":
         return wl.config_c4()
-    if name in ("c5", "c5ad"):
+    if name in ("c5", "c5ad", "c5full"):
         return [wl.config_c5()]
     raise SystemExit(f"unknown workload {name}")
 
@@ -198,7 +222,8 @@ def main():
     counts = {"flops_per_step": 0.0, "bytes_per_step": 0.0, "kernel_flops": {}, "kernel_bytes": {}}
     for p in probs:
         wins = (p.w_rows, p.w_cols) if p.separable else p.w
-        plan = pcm.Plan(wins, p.h, batch=p.batch, product_convolution=args.workload in PRODUCT_CONVOLUTION)
+        plan = pcm.Plan(wins, p.h, batch=p.batch, product_convolution=args.workload in PRODUCT_CONVOLUTION,
+                        full_grid=args.workload in FULL_GRID)
         u = torch.from_numpy(p.u).to(dev)
         jobs.append((p, plan, u, torch.empty_like(u), torch.empty_like(u)))
         c = algorithmic_counts(p, plan.info())

@@ -75,7 +75,19 @@ enum {
    * G_m is the adjoint of the convolution-product operator built on the
    * flipped responses h~_k, such a plan runs the same kernels with the two
    * directions exchanged. */
-  PC_PLAN_PRODUCT_CONVOLUTION = 2u
+  PC_PLAN_PRODUCT_CONVOLUTION = 2u,
+  /* 2D: always evaluate on the full N1 x N2 grid.  Without this flag (and
+   * without PC_PLAN_GRADIENTS), a 2D plan whose windows and impulse
+   * responses have small supports is evaluated section by section (the
+   * compact-support complexity lemma of section 3.5, Lemma 3.2): term k
+   * runs on an M1 x M2 section with M >= p + q - 1 per axis (p, q: the
+   * circular supports of w_k and h_k), and the sections are added into the
+   * result.  The plan takes this route only when it is estimated to be at
+   * least twice as cheap; pc_plan_query reports it as path 3.  Sectioned
+   * plans keep only per-section spectra: the spectra calls return
+   * PC_ERROR_UNSUPPORTED for them, and they cannot join a batch; they
+   * always transform their full batch capacity. */
+  PC_PLAN_FULL_GRID = 4u
 };
 
 typedef struct {
@@ -154,10 +166,11 @@ pc_status pc_destroy(pc_plan plan);
 
 /* Read-only facts about a plan (for tests, benchmarks and tooling). */
 typedef struct {
-  int32_t path;          /* 0: 1D one workgroup per transform, 1: 1D four-step, 2: 2D */
-  int32_t fft_inner;     /* 1D: inner transform length L (N for path 0); 2D: N1 */
-  int32_t fft_outer;     /* 1D four-step: R = N / L; otherwise 1 (2D: N2) */
-  int32_t n_items;       /* 1D four-step: adjoint work items (term, support chunk) */
+  int32_t path;          /* 0: 1D one workgroup per transform, 1: 1D four-step, 2: 2D full grid,
+                            3: 2D sectioned */
+  int32_t fft_inner;     /* 1D: inner transform length L (N for path 0); 2D: N1 (largest M1 if sectioned) */
+  int32_t fft_outer;     /* 1D four-step: R = N / L; otherwise 1 (2D: N2, largest M2 if sectioned) */
+  int32_t n_items;       /* 1D four-step: adjoint work items (term, support chunk); sectioned: sections */
   int64_t spectra_bytes; /* device bytes of the stored spectra */
   int64_t window_bytes;  /* device bytes of the stored (compacted) windows */
   int64_t workspace_bytes;

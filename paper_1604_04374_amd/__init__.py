@@ -20,7 +20,7 @@ from typing import Optional, Sequence, Tuple, Union
 import numpy as np
 
 __all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
-           "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+           "PC_PLAN_FULL_GRID", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +49,7 @@ PC_BATCH_NO_GRAPH = 1
 
 PC_PLAN_GRADIENTS = 1
 PC_PLAN_PRODUCT_CONVOLUTION = 2
+PC_PLAN_FULL_GRID = 4
 
 
 class PlanDesc(ctypes.Structure):
@@ -164,18 +165,21 @@ class Plan:
     batch : largest number of signals per call.
     gradients : allocate the workspace of :meth:`grad_spectra`.
     product_convolution : build ``G_m`` (eq. 1.3) instead of ``H_m``.
+    full_grid : 2D: never evaluate section by section (sectioned plans,
+        ``info()["path"] == 3``, cannot read or replace their spectra).
     """
 
     def __init__(self, windows: Union[np.ndarray, Tuple[np.ndarray, np.ndarray]], h: np.ndarray,
-                 batch: int = 1, stream=None, gradients: bool = False, product_convolution: bool = False):
+                 batch: int = 1, stream=None, gradients: bool = False, product_convolution: bool = False,
+                 full_grid: bool = False):
         self._lib = load_library()
         self._handle = ctypes.c_void_p()
         h = _f32(h)
         d = PlanDesc()
         d.m = h.shape[0]
         d.batch = int(batch)
-        d.flags = (PC_PLAN_GRADIENTS if gradients else 0) | (
-            PC_PLAN_PRODUCT_CONVOLUTION if product_convolution else 0)
+        d.flags = ((PC_PLAN_GRADIENTS if gradients else 0) | (PC_PLAN_PRODUCT_CONVOLUTION if product_convolution else 0)
+                   | (PC_PLAN_FULL_GRID if full_grid else 0))
         self.product_convolution = bool(product_convolution)
         if isinstance(windows, (tuple, list)):
             a, b = _f32(windows[0]), _f32(windows[1])

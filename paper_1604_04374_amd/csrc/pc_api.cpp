@@ -188,11 +188,14 @@ struct pc_plan_s {
   // conj(F^* h_k), converted at the spectra calls through conj_ws
   bool pconv = false;
   float2* conj_ws = nullptr;
+  // sectioned 2D (path 3): one single-term sub-plan per section, run through
+  // an internal batch (its captured launch sequences)
+  pc::Sec2D sec{};
+  std::vector<pc_plan_s*> sec_sub;
+  pc_batch_s* sec_batch = nullptr;
   pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
-  ~pc_plan_s() {
-    for (void* p : allocs) (void)hipFree(p);
-  }
+  ~pc_plan_s();
 
   template <class T>
   pc_status alloc(T** out, size_t count, int64_t* account = nullptr) {
@@ -652,6 +655,12 @@ struct pc_batch_s {
   }
 };
 
+pc_plan_s::~pc_plan_s() {
+  delete sec_batch;
+  for (pc_plan_s* q : sec_sub) delete q;
+  for (void* p : allocs) (void)hipFree(p);
+}
+
 namespace {
 
 std::set<const void*> g_batches;  // live batches (guarded by g_registry_mu)
@@ -678,11 +687,17 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   return PC_SUCCESS;
 }
 
-pc_status run_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s) {
+hipError_t launch_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s, pc::Tracer* tr) {
   for (const pc::LaunchSet& ls : seq) {
-    hipError_t e = pc::launch_set(ls, ls.blocks, nullptr, nullptr, s, nullptr);
-    if (e != hipSuccess) return fail_hip(e, "batch launch");
+    hipError_t e = pc::launch_set(ls, ls.blocks, nullptr, nullptr, s, tr);
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+pc_status run_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s) {
+  hipError_t e = launch_seq(seq, s, nullptr);
+  if (e != hipSuccess) return fail_hip(e, "batch launch");
   return PC_SUCCESS;
 }
 
@@ -791,22 +806,310 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
   return PC_SUCCESS;
 }
 
+// ---------------------------------------------------------------------------
+// Sectioned 2D plans (the compact-support complexity lemma of section 3.5)
+// ---------------------------------------------------------------------------
+
+// One section: term k with window box (o, p) and response lag box (a, q) per
+// axis (origins mod N), evaluated on M1 x M2 samples.
+struct Section {
+  int k;
+  int64_t o1, p1, o2, p2, a1, q1, a2, q2;
+  int64_t M1, M2;
+};
+
+// circular supports of the nonzero rows and columns of a dense N1 x N2 array
+void box_2d(const float* a, int64_t N1, int64_t N2, int64_t& o1, int64_t& p1, int64_t& o2, int64_t& p2) {
+  std::vector<float> r((size_t)N1, 0.f), c((size_t)N2, 0.f);
+  for (int64_t i = 0; i < N1; ++i)
+    for (int64_t j = 0; j < N2; ++j)
+      if (a[i * N2 + j] != 0.0f) {
+        r[(size_t)i] = 1.f;
+        c[(size_t)j] = 1.f;
+      }
+  circular_support(r.data(), N1, o1, p1);
+  circular_support(c.data(), N2, o2, p2);
+}
+
+// smallest supported transform length >= need that is shorter than N, else N
+int64_t section_len(int64_t need, int64_t N) {
+  int64_t best = N;
+  for (int64_t L = 64; L <= 8192; L *= 2)
+    for (int64_t c : {L, 3 * L / 2})
+      if (c >= need && c < best && pc::fft_size_supported(c)) best = c;
+  return best;
+}
+
+// The sections of a 2D plan, if sectioning is at least twice as cheap as the
+// full grid (transform work: two section transforms per term against m + 1
+// full-grid transforms).
+bool plan_sections(const pc_plan_desc& d, const float* windows, const float* h, std::vector<Section>& out) {
+  const int64_t N1 = d.n0, N2 = d.n1;
+  const bool dense = d.w_format == PC_W_DENSE;
+  out.clear();
+  double c_sec = 0.0;
+  for (int k = 0; k < d.m; ++k) {
+    Section sc{};
+    sc.k = k;
+    if (dense) {
+      box_2d(windows + (size_t)k * N1 * N2, N1, N2, sc.o1, sc.p1, sc.o2, sc.p2);
+    } else {
+      const float* a = windows + (size_t)(k / d.m_cols) * N1;
+      const float* b = windows + (size_t)d.m_rows * N1 + (size_t)(k % d.m_cols) * N2;
+      circular_support(a, N1, sc.o1, sc.p1);
+      circular_support(b, N2, sc.o2, sc.p2);
+    }
+    box_2d(h + (size_t)k * N1 * N2, N1, N2, sc.a1, sc.q1, sc.a2, sc.q2);
+    if (sc.p1 == 0 || sc.p2 == 0 || sc.q1 == 0 || sc.q2 == 0) continue;  // the term is zero
+    sc.M1 = section_len(sc.p1 + sc.q1 - 1, N1);
+    sc.M2 = section_len(sc.p2 + sc.q2 - 1, N2);
+    const double n = (double)sc.M1 * (double)sc.M2;
+    c_sec += 2.0 * n * std::log2(n) + 4.0 * n;
+    out.push_back(sc);
+  }
+  const double nf = (double)N1 * (double)N2;
+  const double c_full = (double)(d.m + 1) * nf * std::log2(nf);
+  return !out.empty() && 2.0 * c_sec < c_full;
+}
+
+pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out);
+
+pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std::vector<Section>& secs,
+                      hipStream_t s) {
+  const pc_plan_desc& d = p->d;
+  const int64_t N1 = d.n0, N2 = d.n1, cap = d.batch;
+  const bool dense = d.w_format == PC_W_DENSE;
+  pc::Sec2D& q = p->sec;
+  q.N1 = (int)N1;
+  q.N2 = (int)N2;
+  q.cap = cap;
+  q.n_sec = (int)secs.size();
+  std::vector<pc::SecTerm> terms;
+  int64_t off = 0;
+  pc_status st;
+  for (const Section& sc : secs) {
+    // the single-term operator of the section: window box and shifted response
+    std::vector<float> wsub((size_t)(sc.M1 * sc.M2), 0.f), hsub((size_t)(sc.M1 * sc.M2), 0.f);
+    for (int64_t i = 0; i < sc.p1; ++i)
+      for (int64_t j = 0; j < sc.p2; ++j) {
+        const int64_t r = (sc.o1 + i) % N1, c = (sc.o2 + j) % N2;
+        float v;
+        if (dense) {
+          v = windows[((size_t)sc.k * N1 + r) * N2 + c];
+        } else {
+          v = windows[(size_t)(sc.k / d.m_cols) * N1 + r] *
+              windows[(size_t)d.m_rows * N1 + (size_t)(sc.k % d.m_cols) * N2 + c];
+        }
+        wsub[(size_t)(i * sc.M2 + j)] = v;
+      }
+    for (int64_t i = 0; i < sc.q1; ++i)
+      for (int64_t j = 0; j < sc.q2; ++j)
+        hsub[(size_t)(i * sc.M2 + j)] = h[((size_t)sc.k * N1 + (sc.a1 + i) % N1) * N2 + (sc.a2 + j) % N2];
+    pc_plan_desc sd{};
+    sd.ndim = 2;
+    sd.m = 1;
+    sd.n0 = sc.M1;
+    sd.n1 = sc.M2;
+    sd.batch = cap;
+    sd.w_format = PC_W_DENSE;
+    sd.flags = PC_PLAN_FULL_GRID;
+    pc_plan_s* sub = nullptr;
+    if ((st = create_plan(sd, wsub.data(), hsub.data(), s, &sub))) return st;
+    p->sec_sub.push_back(sub);
+    p->spectra_bytes += sub->spectra_bytes;
+    p->window_bytes += sub->window_bytes;
+    p->workspace_bytes += sub->workspace_bytes;
+    pc::SecTerm t{};
+    t.off = off;
+    t.M1 = (int)sc.M1;
+    t.M2 = (int)sc.M2;
+    t.gf1 = (int)sc.o1;
+    t.gf2 = (int)sc.o2;
+    t.ga1 = (int)((sc.o1 + sc.a1) % N1);
+    t.ga2 = (int)((sc.o2 + sc.a2) % N2);
+    t.sf1 = t.ga1;
+    t.sf2 = t.ga2;
+    t.ef1 = (int)std::min(sc.p1 + sc.q1 - 1, sc.M1);
+    t.ef2 = (int)std::min(sc.p2 + sc.q2 - 1, sc.M2);
+    t.sa1 = t.gf1;
+    t.sa2 = t.gf2;
+    t.ea1 = (int)sc.p1;
+    t.ea2 = (int)sc.p2;
+    terms.push_back(t);
+    q.max_m1 = std::max(q.max_m1, t.M1);
+    off += cap * sc.M1 * sc.M2;
+  }
+  if ((st = p->alloc(&q.Sin, (size_t)off, &p->workspace_bytes))) return st;
+  if ((st = p->alloc(&q.Sout, (size_t)off, &p->workspace_bytes))) return st;
+  pc::SecTerm* dterms = nullptr;
+  if ((st = p->upload(&dterms, terms, s))) return st;
+  q.terms = dterms;
+  // output tiles met by each section's output box, forward and adjoint
+  const int64_t tr = N1 / pc::SEC_TILE_R, tc = N2 / pc::SEC_TILE_C;
+  q.tiles2 = (int)tc;
+  for (int dir = 0; dir < 2; ++dir) {
+    std::vector<std::vector<int>> lists((size_t)(tr * tc));
+    for (size_t k = 0; k < terms.size(); ++k) {
+      const pc::SecTerm& t = terms[k];
+      const int s1 = dir ? t.sa1 : t.sf1, s2 = dir ? t.sa2 : t.sf2;
+      const int e1 = dir ? t.ea1 : t.ef1, e2 = dir ? t.ea2 : t.ef2;
+      std::vector<char> rows((size_t)tr, 0), cols((size_t)tc, 0);
+      for (int64_t i = 0; i < e1; ++i) rows[(size_t)(((s1 + i) % N1) / pc::SEC_TILE_R)] = 1;
+      for (int64_t j = 0; j < e2; ++j) cols[(size_t)(((s2 + j) % N2) / pc::SEC_TILE_C)] = 1;
+      for (int64_t a = 0; a < tr; ++a)
+        if (rows[(size_t)a])
+          for (int64_t b = 0; b < tc; ++b)
+            if (cols[(size_t)b]) lists[(size_t)(a * tc + b)].push_back((int)k);
+    }
+    std::vector<int> toff(lists.size() + 1, 0), items;
+    for (size_t t = 0; t < lists.size(); ++t) {
+      toff[t] = (int)items.size();
+      items.insert(items.end(), lists[t].begin(), lists[t].end());
+    }
+    toff[lists.size()] = (int)items.size();
+    int *doff = nullptr, *dit = nullptr;
+    if ((st = p->upload(&doff, toff, s))) return st;
+    if ((st = p->upload(&dit, items, s))) return st;
+    (dir ? q.ta_off : q.tf_off) = doff;
+    (dir ? q.ta_items : q.tf_items) = dit;
+  }
+  // the sections' transforms as one batch: launch lists and captured graphs
+  pc_batch_s* b = new (std::nothrow) pc_batch_s();
+  if (!b) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  p->sec_batch = b;
+  b->device = p->device;
+  b->plans.assign(p->sec_sub.begin(), p->sec_sub.end());
+  b->has_fwd = b->has_adj = true;
+  std::vector<const float*> in;
+  std::vector<float*> outs;
+  for (const pc::SecTerm& t : terms) {
+    in.push_back(q.Sin + t.off);
+    outs.push_back(q.Sout + t.off);
+  }
+  if ((st = build_batch(b, in.data(), outs.data(), outs.data()))) return st;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
+  st = capture(b->fwd_seq, cs, &b->gf, &b->ef);
+  if (!st) st = capture(b->adj_seq, cs, &b->ga, &b->ea);
+  (void)hipStreamDestroy(cs);
+  return st;
+}
+
+hipError_t run_sections(pc_plan p, const float* in, float* out, int64_t batch, bool adjoint, hipStream_t s) {
+  hipError_t e = pc::launch_sec_gather(p->sec, in, adjoint, batch, s, p->tr());
+  if (e != hipSuccess) return e;
+  const pc_batch_s* b = p->sec_batch;
+  if (p->tracing)  // kernel by kernel, so that each is timed
+    e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr());
+  else
+    e = hipGraphLaunch(adjoint ? b->ea : b->ef, s);
+  if (e != hipSuccess) return e;
+  return pc::launch_sec_scatter(p->sec, out, adjoint, batch, s, p->tr());
+}
+
 // The convolution-product directions of a plan (eq. 1.4 and its adjoint).
 hipError_t run_forward(pc_plan p, const float* u, float* y, int64_t batch, hipStream_t s) {
   if (p->path == 0) return pc::launch_fwd1d_small(p->s1, u, y, batch, s, p->tr());
   if (p->path == 1) return pc::launch_fwd1d_large(p->l1, u, y, batch, s, p->tr());
+  if (p->path == 3) return run_sections(p, u, y, batch, false, s);
   return pc::launch_fwd2d(p->p2, u, y, batch, s, p->tr());
 }
 
 hipError_t run_adjoint(pc_plan p, const float* v, float* x, int64_t batch, hipStream_t s) {
   if (p->path == 0) return pc::launch_adj1d_small(p->s1, v, x, batch, s, p->tr());
   if (p->path == 1) return pc::launch_adj1d_large(p->l1, v, x, batch, s, p->tr());
+  if (p->path == 3) return run_sections(p, v, x, batch, true, s);
   return pc::launch_adj2d(p->p2, v, x, batch, s, p->tr());
 }
 
 pc_status check_batch(pc_batch b) {
   std::lock_guard<std::mutex> g(g_registry_mu);
   if (!b || !g_batches.count(b)) return fail(PC_ERROR_INVALID_VALUE, "batch handle is not a live batch");
+  return PC_SUCCESS;
+}
+
+pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out) {
+  if (d.ndim != 1 && d.ndim != 2) return fail(PC_ERROR_INVALID_VALUE, "ndim must be 1 or 2");
+  if (d.m < 1) return fail(PC_ERROR_INVALID_VALUE, "m must be >= 1");
+  if (d.batch < 1) return fail(PC_ERROR_INVALID_VALUE, "batch must be >= 1");
+  if (d.flags & ~(uint32_t)(PC_PLAN_GRADIENTS | PC_PLAN_PRODUCT_CONVOLUTION | PC_PLAN_FULL_GRID))
+    return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
+  if (d.n0 < 1 || d.n1 < 1) return fail(PC_ERROR_INVALID_VALUE, "sizes must be positive");
+  if (d.w_format != PC_W_DENSE && d.w_format != PC_W_SEPARABLE)
+    return fail(PC_ERROR_INVALID_VALUE, "unknown window format");
+  int path = 0, L = 0, R = 1;
+  if (d.ndim == 1) {
+    if (d.n1 != 1) return fail(PC_ERROR_INVALID_VALUE, "1D plans need n1 == 1");
+    if (d.w_format != PC_W_DENSE) return fail(PC_ERROR_INVALID_VALUE, "1D plans take dense windows");
+    if (pc::fft_size_supported(d.n0)) {
+      path = 0;
+    } else if (large_split(d.n0, L, R)) {
+      path = 1;
+    } else {
+      return fail(PC_ERROR_UNSUPPORTED, "1D size " + std::to_string(d.n0) + " is not supported");
+    }
+  } else {
+    if (!pc::fft_size_supported(d.n0) || !pc::fft_size_supported(d.n1))
+      return fail(PC_ERROR_UNSUPPORTED,
+                  "2D size " + std::to_string(d.n0) + "x" + std::to_string(d.n1) + " is not supported");
+    if (d.w_format == PC_W_SEPARABLE &&
+        (d.m_rows < 1 || d.m_cols < 1 || (int64_t)d.m_rows * d.m_cols != d.m))
+      return fail(PC_ERROR_INVALID_VALUE, "separable windows need m == m_rows * m_cols");
+    path = 2;
+  }
+  pc_plan_s* p = new (std::nothrow) pc_plan_s();
+  if (!p) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  p->d = d;
+  p->path = path;
+  p->n_total = d.n0 * d.n1;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return fail_hip(e, "hipGetDevice");
+  }
+  p->pconv = (d.flags & PC_PLAN_PRODUCT_CONVOLUTION) != 0;
+  // G_m = (convolution-product operator of the flipped responses)^*
+  std::vector<float> flipped;
+  if (p->pconv) {
+    const int64_t n0 = d.n0, n1 = d.n1;
+    flipped.resize((size_t)d.m * n0 * n1);
+    for (int64_t k = 0; k < d.m; ++k)
+      for (int64_t i = 0; i < n0; ++i)
+        for (int64_t j = 0; j < n1; ++j)
+          flipped[(size_t)((k * n0 + i) * n1 + j)] = h[(size_t)((k * n0 + (n0 - i) % n0) * n1 + (n1 - j) % n1)];
+    h = flipped.data();
+  }
+  std::vector<Section> secs;
+  if (path == 2 && !(d.flags & (PC_PLAN_GRADIENTS | PC_PLAN_FULL_GRID)) && plan_sections(d, windows, h, secs))
+    p->path = path = 3;
+  pc_status st;
+  if (path == 0)
+    st = build_small1d(p, windows, h, s);
+  else if (path == 1)
+    st = build_large1d(p, L, R, windows, h, s);
+  else if (path == 2)
+    st = build_2d(p, windows, h, s);
+  else
+    st = build_sec2d(p, windows, h, secs, s);
+  if (st == PC_SUCCESS) {
+    p->spec_count = (int64_t)d.m * (d.ndim == 1 ? d.n0 / 2 + 1 : d.n0 * (d.n1 / 2 + 1));
+    if (p->pconv && path != 3) st = p->alloc(&p->conj_ws, (size_t)p->spec_count, &p->workspace_bytes);
+  }
+  if (st == PC_SUCCESS) {
+    if (d.flags & PC_PLAN_GRADIENTS) {
+      // 1D: pair spectra (pairs x N) or the per-class accumulators (m x N); 2D: m planes
+      const int64_t pairs = (d.batch + 1) / 2;
+      const int64_t n = path == 0 ? pairs * d.n0 : path == 1 ? (int64_t)d.m * d.n0 : d.m * d.n0 * (d.n1 / 2 + 1);
+      st = p->alloc(&p->grad_ws, (size_t)n, &p->workspace_bytes);
+    }
+  }
+  if (st != PC_SUCCESS) {
+    (void)hipStreamSynchronize(s);
+    delete p;
+    return st;
+  }
+  *out = p;
   return PC_SUCCESS;
 }
 
@@ -828,7 +1131,8 @@ pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, co
     pc_status st = check_plan(plans[i]);
     if (st) return st;
     const pc_plan p = plans[i];
-    if (p->path != 2) return fail(PC_ERROR_INVALID_VALUE, "batches take 2D plans");
+    if (p->path != 2)
+      return fail(PC_ERROR_INVALID_VALUE, "batches take 2D full-grid plans (sectioned plans: use PC_PLAN_FULL_GRID)");
     if (device < 0) device = p->device;
     if (p->device != device) return fail(PC_ERROR_INVALID_VALUE, "plans of a batch must share a device");
     in[i] = inputs[i];
@@ -922,82 +1226,9 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
   *out = nullptr;
   if (!desc) return fail(PC_ERROR_INVALID_VALUE, "desc is NULL");
   if (!windows || !h) return fail(PC_ERROR_INVALID_VALUE, "windows or h is NULL");
-  const pc_plan_desc d = *desc;
-  if (d.ndim != 1 && d.ndim != 2) return fail(PC_ERROR_INVALID_VALUE, "ndim must be 1 or 2");
-  if (d.m < 1) return fail(PC_ERROR_INVALID_VALUE, "m must be >= 1");
-  if (d.batch < 1) return fail(PC_ERROR_INVALID_VALUE, "batch must be >= 1");
-  if (d.flags & ~(uint32_t)(PC_PLAN_GRADIENTS | PC_PLAN_PRODUCT_CONVOLUTION))
-    return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
-  if (d.n0 < 1 || d.n1 < 1) return fail(PC_ERROR_INVALID_VALUE, "sizes must be positive");
-  if (d.w_format != PC_W_DENSE && d.w_format != PC_W_SEPARABLE)
-    return fail(PC_ERROR_INVALID_VALUE, "unknown window format");
-  int path = 0, L = 0, R = 1;
-  if (d.ndim == 1) {
-    if (d.n1 != 1) return fail(PC_ERROR_INVALID_VALUE, "1D plans need n1 == 1");
-    if (d.w_format != PC_W_DENSE) return fail(PC_ERROR_INVALID_VALUE, "1D plans take dense windows");
-    if (pc::fft_size_supported(d.n0)) {
-      path = 0;
-    } else if (large_split(d.n0, L, R)) {
-      path = 1;
-    } else {
-      return fail(PC_ERROR_UNSUPPORTED, "1D size " + std::to_string(d.n0) + " is not supported");
-    }
-  } else {
-    if (!pc::fft_size_supported(d.n0) || !pc::fft_size_supported(d.n1))
-      return fail(PC_ERROR_UNSUPPORTED,
-                  "2D size " + std::to_string(d.n0) + "x" + std::to_string(d.n1) + " is not supported");
-    if (d.w_format == PC_W_SEPARABLE &&
-        (d.m_rows < 1 || d.m_cols < 1 || (int64_t)d.m_rows * d.m_cols != d.m))
-      return fail(PC_ERROR_INVALID_VALUE, "separable windows need m == m_rows * m_cols");
-    path = 2;
-  }
-  pc_plan_s* p = new (std::nothrow) pc_plan_s();
-  if (!p) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
-  p->d = d;
-  p->path = path;
-  p->n_total = d.n0 * d.n1;
-  hipError_t e = hipGetDevice(&p->device);
-  if (e != hipSuccess) {
-    delete p;
-    return fail_hip(e, "hipGetDevice");
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  p->pconv = (d.flags & PC_PLAN_PRODUCT_CONVOLUTION) != 0;
-  // G_m = (convolution-product operator of the flipped responses)^*
-  std::vector<float> flipped;
-  if (p->pconv) {
-    const int64_t n0 = d.n0, n1 = d.n1;
-    flipped.resize((size_t)d.m * n0 * n1);
-    for (int64_t k = 0; k < d.m; ++k)
-      for (int64_t i = 0; i < n0; ++i)
-        for (int64_t j = 0; j < n1; ++j)
-          flipped[(size_t)((k * n0 + i) * n1 + j)] = h[(size_t)((k * n0 + (n0 - i) % n0) * n1 + (n1 - j) % n1)];
-    h = flipped.data();
-  }
-  pc_status st;
-  if (path == 0)
-    st = build_small1d(p, windows, h, s);
-  else if (path == 1)
-    st = build_large1d(p, L, R, windows, h, s);
-  else
-    st = build_2d(p, windows, h, s);
-  if (st == PC_SUCCESS) {
-    p->spec_count = (int64_t)d.m * (d.ndim == 1 ? d.n0 / 2 + 1 : d.n0 * (d.n1 / 2 + 1));
-    if (p->pconv) st = p->alloc(&p->conj_ws, (size_t)p->spec_count, &p->workspace_bytes);
-  }
-  if (st == PC_SUCCESS) {
-    if (d.flags & PC_PLAN_GRADIENTS) {
-      // 1D: pair spectra (pairs x N) or the per-class accumulators (m x N); 2D: m planes
-      const int64_t pairs = (d.batch + 1) / 2;
-      const int64_t n = path == 0 ? pairs * d.n0 : path == 1 ? (int64_t)d.m * d.n0 : d.m * d.n0 * (d.n1 / 2 + 1);
-      st = p->alloc(&p->grad_ws, (size_t)n, &p->workspace_bytes);
-    }
-  }
-  if (st != PC_SUCCESS) {
-    (void)hipStreamSynchronize(s);
-    delete p;
-    return st;
-  }
+  pc_plan_s* p = nullptr;
+  pc_status st = create_plan(*desc, windows, h, static_cast<hipStream_t>(stream), &p);
+  if (st) return st;
   {
     std::lock_guard<std::mutex> g(g_registry_mu);
     g_registry.insert(p);
@@ -1052,9 +1283,15 @@ pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
     r.fft_inner = p->l1.L;
     r.fft_outer = p->l1.R;
     r.n_items = p->l1.n_items;
-  } else {
+  } else if (p->path == 2) {
     r.fft_inner = p->p2.N1;
     r.fft_outer = p->p2.N2;
+  } else {
+    for (pc_plan_s* q : p->sec_sub) {
+      r.fft_inner = std::max(r.fft_inner, (int32_t)q->d.n0);
+      r.fft_outer = std::max(r.fft_outer, (int32_t)q->d.n1);
+    }
+    r.n_items = p->sec.n_sec;
   }
   r.spectra_bytes = p->spectra_bytes;
   r.window_bytes = p->window_bytes;
@@ -1066,6 +1303,8 @@ pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
 pc_status pc_plan_set_spectra(pc_plan p, const void* spec, void* stream) {
   pc_status st = check_plan(p);
   if (st) return st;
+  if (p->path == 3)
+    return fail(PC_ERROR_UNSUPPORTED, "sectioned plans keep per-section spectra (create the plan with PC_PLAN_FULL_GRID)");
   if (!spec) return fail(PC_ERROR_INVALID_VALUE, "spec is NULL");
   DeviceGuard g(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1089,6 +1328,8 @@ pc_status pc_plan_set_spectra(pc_plan p, const void* spec, void* stream) {
 pc_status pc_plan_get_spectra(pc_plan p, void* spec, void* stream) {
   pc_status st = check_plan(p);
   if (st) return st;
+  if (p->path == 3)
+    return fail(PC_ERROR_UNSUPPORTED, "sectioned plans keep per-section spectra (create the plan with PC_PLAN_FULL_GRID)");
   if (!spec) return fail(PC_ERROR_INVALID_VALUE, "spec is NULL");
   DeviceGuard g(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -211,4 +211,43 @@ LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bo
 LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
                            float2* E, hipStream_t s, Tracer* tr = nullptr);
 
+// --------------------------------------------------------------------------
+// 2D sectioned evaluation (compact supports; the complexity lemma of section
+// 3.5, Lemma 3.2).  Term k only touches the p-sample box of its window and
+// produces a (p + q - 1)-sample box of output (q: the box of h_k), so it is
+// evaluated on its own M1 x M2 section (M >= p + q - 1 per axis, or M = N)
+// by a single-term sub-operator, and the sections are added back.
+// --------------------------------------------------------------------------
+struct SecTerm {
+  int64_t off;        // staging offset (floats) of the term's block: cap x M1 x M2
+  int M1, M2;         // section size
+  int gf1, gf2;       // forward: input box origin (the window box)
+  int ga1, ga2;       // adjoint: input box origin (the output box)
+  int sf1, sf2;       // forward: output box origin
+  int ef1, ef2;       // forward: output box extent (p + q - 1, at most M)
+  int sa1, sa2;       // adjoint: output box origin (the window box)
+  int ea1, ea2;       // adjoint: output box extent (p)
+};
+struct Sec2D {
+  int N1, N2, n_sec;
+  int64_t cap;
+  int max_m1;                 // largest M1 over the sections
+  const SecTerm* terms;       // n_sec entries (device)
+  float* Sin;                 // section inputs (staging)
+  float* Sout;                // section outputs (staging)
+  // output tiles of SEC_TILE_R x SEC_TILE_C pixels: sections whose output
+  // box meets each tile (CSR, section order), forward and adjoint
+  int tiles2;
+  const int* tf_off;
+  const int* tf_items;
+  const int* ta_off;
+  const int* ta_items;
+};
+constexpr int SEC_TILE_R = 8, SEC_TILE_C = 32;
+// staging <- input boxes of the first `batch` images
+LaunchStatus launch_sec_gather(const Sec2D& q, const float* x, bool adjoint, int64_t batch, hipStream_t s,
+                               Tracer* tr);
+// every output pixel of the first `batch` images <- sum of the sections covering it
+LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr);
+
 }  // namespace pc

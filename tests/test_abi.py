@@ -66,7 +66,7 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(ndim=3), 1), (dict(m=0), 1), (dict(batch=0), 1), (dict(flags=4), 1),
+    (dict(ndim=3), 1), (dict(m=0), 1), (dict(batch=0), 1), (dict(flags=8), 1),
     (dict(n1=2), 1), (dict(w_format=7), 1), (dict(w_format=1), 1),
     (dict(n0=1000), 2), (dict(n0=32), 2), (dict(n0=1 << 20), 2),
     (dict(ndim=2, n0=100, n1=64), 2), (dict(ndim=2, n0=64, n1=10000), 2),

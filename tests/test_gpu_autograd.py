@@ -44,7 +44,7 @@ def test_get_spectra_is_the_real_fft_of_h(idx):
     import paper_1604_04374_amd as pcm
     p = _problems()[idx]
     print(f"[gpu] get_spectra {p.name}", flush=True)
-    with pcm.Plan(plan_args(p), p.h, batch=p.batch) as plan:
+    with pcm.Plan(plan_args(p), p.h, batch=p.batch, full_grid=True) as plan:
         s = plan.get_spectra()
         torch.cuda.synchronize()
         got = s.cpu().numpy()
@@ -62,7 +62,7 @@ def test_set_spectra_replaces_the_operator(idx):
     h2 = np.roll(p.h, 3, axis=-1) * rng.uniform(0.5, 1.5, (p.m,) + (1,) * p.ndim)
     spec2 = sfft.rfftn(h2.astype(np.float64), axes=tuple(range(-p.ndim, 0)))
     u = torch.from_numpy(p.u).cuda()
-    with pcm.Plan(plan_args(p), p.h, batch=p.batch) as plan:
+    with pcm.Plan(plan_args(p), p.h, batch=p.batch, full_grid=True) as plan:
         plan.set_spectra(torch.from_numpy(spec2.astype(np.complex64)).cuda())
         y = plan.apply(u).cpu().numpy()
         x = plan.apply_adjoint(u).cpu().numpy()

@@ -23,7 +23,7 @@ def _setup(count, seed=4):
     import torch
     import paper_1604_04374_amd as pcm
     probs = wl.config_c4(count=count, seed=seed)
-    plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch) for p in probs]
+    plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch, full_grid=True) for p in probs]
     inputs = [torch.from_numpy(p.u).cuda() for p in probs]
     return probs, plans, inputs
 

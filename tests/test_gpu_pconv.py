@@ -108,7 +108,7 @@ def test_spectra_are_those_of_h_and_replace_the_operator(idx):
     h2 = np.roll(p.h, 3, axis=-1) * rng.uniform(0.5, 1.5, (p.m,) + (1,) * p.ndim)
     spec2 = sfft.rfftn(h2.astype(np.float64), axes=axes)
     u = torch.from_numpy(p.u).cuda()
-    with _plan(p) as plan:
+    with _plan(p, full_grid=True) as plan:
         got = plan.get_spectra().cpu().numpy()
         assert rel_l2(got, sfft.rfftn(p.h.astype(np.float64), axes=axes)) < 1e-6
         plan.set_spectra(torch.from_numpy(spec2.astype(np.complex64)).cuda())
@@ -162,7 +162,8 @@ def test_batch_mixing_both_kinds(graph):
     probs = wl.config_c4(count=12, seed=11)
     kinds = [i % 2 == 1 for i in range(len(probs))]
     print(f"[gpu] mixed batch of {len(probs)} (graph={graph})", flush=True)
-    plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch, product_convolution=k) for p, k in zip(probs, kinds)]
+    plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch, product_convolution=k, full_grid=True)
+             for p, k in zip(probs, kinds)]
     inputs = [torch.from_numpy(p.u).cuda() for p in probs]
     b = pcm.Batch(plans, inputs, graph=graph)
     y = [t.clone() for t in b.apply()]

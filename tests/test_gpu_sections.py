@@ -1,0 +1,151 @@
+"""Sectioned 2D evaluation (compact supports, section 3.5 Lemma 3.2) against
+the FP64 oracle, the full-grid plans and the direct sums.
+
+Problems are built so that the plan takes the sectioned route (checked via
+``info()["path"] == 3``): tile windows and narrow PSFs; hat windows whose
+boxes wrap around the image edges; a grid that is sectioned along one axis
+only; product-convolution plans; several images with partial batches.
+Tolerance: relative L2 <= 1e-5 per image."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import per_instance_rel, plan_args, rel_l2
+from oracle import expansion as ex
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_04374_amd as pcm
+    pcm.load_library()
+
+
+def _narrow(a, b):
+    return lambda p1, p2: a + b * (p1 + p2) / 1024.0
+
+
+def _problems():
+    return [
+        wl.small_2d(256, 256, 4, 4, 2, seed=120, kind="tile", sig_y_fn=_narrow(1.0, 0.5), sig_x_fn=_narrow(1.2, 0.3)),
+        wl.small_2d(512, 512, 8, 8, 1, seed=121, kind="hat", sig_y_fn=_narrow(1.0, 1.0), sig_x_fn=_narrow(1.5, 0.5)),
+        wl.small_2d(128, 512, 1, 8, 3, seed=122, kind="tile", sig_y_fn=_narrow(1.0, 0.2), sig_x_fn=_narrow(1.0, 0.5)),
+        wl.small_2d(384, 192, 6, 3, 1, seed=123, kind="tile", sig_y_fn=_narrow(0.8, 0.4), sig_x_fn=_narrow(1.0, 0.4)),
+    ]
+
+
+def _run(p, batch=None, **kw):
+    import torch
+    import paper_1604_04374_amd as pcm
+    u = torch.from_numpy(p.u).cuda()
+    if batch is not None:
+        u = u[:batch].contiguous()
+    with pcm.Plan(plan_args(p), p.h, batch=p.batch, **kw) as plan:
+        info = plan.info()
+        y = plan.apply(u).cpu().numpy()
+        x = plan.apply_adjoint(u).cpu().numpy()
+    return info, y, x
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_sectioned_matches_oracle_and_full_grid(idx):
+    p = _problems()[idx]
+    print(f"[gpu] sectioned {p.name}", flush=True)
+    info, y, x = _run(p)
+    print(f"{p.name}: path {info['path']} sections {info['n_items']} "
+          f"{info['fft_inner']}x{info['fft_outer']}", flush=True)
+    assert info["path"] == 3
+    w, h, u = p.dense_windows(), p.h.astype(np.float64), p.u.astype(np.float64)
+    ey = per_instance_rel(y, ex.apply_fft(u, w, h))
+    ea = per_instance_rel(x, ex.adjoint_fft(u, w, h))
+    print(f"{p.name}: fwd rel {ey:.2e} adj rel {ea:.2e}", flush=True)
+    assert ey <= TOL and ea <= TOL
+    finfo, yf, xf = _run(p, full_grid=True)
+    assert finfo["path"] == 2
+    assert per_instance_rel(y, yf) <= TOL and per_instance_rel(x, xf) <= TOL
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_sampled_direct_sums(idx):
+    p = _problems()[idx]
+    info, y, x = _run(p)
+    assert info["path"] == 3
+    rng = np.random.default_rng(130 + idx)
+    w, h = p.dense_windows(), p.h.astype(np.float64)
+    for b in range(p.batch):
+        idxs = rng.choice(p.n_total, 256, replace=False)
+        u = p.u[b].astype(np.float64)
+        assert rel_l2(y[b].ravel()[idxs], ex.apply_direct_at(u, w, h, idxs)) <= TOL
+        assert rel_l2(x[b].ravel()[idxs], ex.adjoint_direct_at(u, w, h, idxs)) <= TOL
+
+
+@pytest.mark.parametrize("idx", [0, 2])
+def test_partial_batch(idx):
+    p = _problems()[idx]
+    info, y, x = _run(p, batch=p.batch - 1)
+    assert info["path"] == 3 and y.shape[0] == p.batch - 1
+    w, h, u = p.dense_windows(), p.h.astype(np.float64), p.u[:p.batch - 1].astype(np.float64)
+    assert per_instance_rel(y, ex.apply_fft(u, w, h)) <= TOL
+    assert per_instance_rel(x, ex.adjoint_fft(u, w, h)) <= TOL
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_product_convolution_sectioned(idx):
+    p = _problems()[idx]
+    print(f"[gpu] sectioned product-convolution {p.name}", flush=True)
+    info, y, x = _run(p, product_convolution=True)
+    assert info["path"] == 3
+    w, h, u = p.dense_windows(), p.h.astype(np.float64), p.u.astype(np.float64)
+    assert per_instance_rel(y, ex.apply_pc_fft(u, w, h)) <= TOL
+    assert per_instance_rel(x, ex.adjoint_pc_fft(u, w, h)) <= TOL
+
+
+def test_repeatable_bitwise_and_traced():
+    import torch
+    import paper_1604_04374_amd as pcm
+    p = _problems()[1]
+    u = torch.from_numpy(p.u).cuda()
+    with pcm.Plan(plan_args(p), p.h, batch=p.batch) as plan:
+        y1 = plan.apply(u).clone()
+        x1 = plan.apply_adjoint(u).clone()
+        plan.set_tracing(True)
+        y2 = plan.apply(u)
+        x2 = plan.apply_adjoint(u)
+        stats = plan.trace_stats()
+        plan.set_tracing(False)
+        torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(x1, x2)
+    assert "sec_gather" in stats and "sec_scatter" in stats
+
+
+def test_spectra_and_batches_need_full_grid_plans():
+    import torch
+    import paper_1604_04374_amd as pcm
+    p = _problems()[0]
+    u = torch.from_numpy(p.u).cuda()
+    with pcm.Plan(plan_args(p), p.h, batch=p.batch) as plan:
+        assert plan.info()["path"] == 3
+        with pytest.raises(pcm.PCError) as ei:
+            plan.get_spectra()
+        assert ei.value.status == 2
+        with pytest.raises(pcm.PCError) as ei:
+            pcm.Batch([plan], [u])
+        assert ei.value.status == 1
+
+
+@pytest.mark.slow
+def test_c5_full_size():
+    p = wl.config_c5()
+    print(f"[gpu] sectioned {p.name}", flush=True)
+    info, y, x = _run(p)
+    print(f"{p.name}: path {info['path']} sections {info['n_items']} "
+          f"{info['fft_inner']}x{info['fft_outer']}", flush=True)
+    assert info["path"] == 3
+    w, h, u = p.dense_windows(), p.h.astype(np.float64), p.u.astype(np.float64)
+    assert per_instance_rel(y, ex.apply_fft(u, w, h)) <= TOL
+    assert per_instance_rel(x, ex.adjoint_fft(u, w, h)) <= TOL
