@@ -90,12 +90,15 @@ def algorithmic_counts(p, info):
         colfft = 5.0 * m1s * h2s * _lg(m1s)
         spec_bytes = s_n * m1s * h2s * 8
         per_sig = s_n * (2 * rowfft + 2 * colfft + 8.0 * m1s * h2s) + support_sum
+        img_s, pl_s = m1s * m2s * 4, m1s * h2s * 8    # one section image / half-spectrum plane, bytes
         kf = {"rows_fwd": B * s_n * 2 * rowfft, "rows_inv": B * s_n * 2 * rowfft,
               "cols_fwd": B * s_n * (2 * colfft + 8.0 * m1s * h2s),
               "cols_adj": B * s_n * (colfft + 8.0 * m1s * h2s), "cols_fft": B * s_n * colfft}
-        kb = {"cols_fwd": spec_bytes, "cols_adj": spec_bytes,
-              "rows_fwd": 2 * B * s_n * m1s * m2s * 4, "rows_inv": 2 * B * s_n * m1s * m2s * 4,
-              "sec_gather": 2 * B * s_n * m1s * m2s * 4 * 2, "sec_scatter": 2 * B * (s_n * m1s * m2s + ntot) * 4}
+        # per step (forward + adjoint); each family runs once or twice per step
+        kb = {"cols_fwd": B * s_n * 2 * pl_s + spec_bytes, "cols_adj": B * s_n * 2 * pl_s + spec_bytes,
+              "cols_fft": B * s_n * 2 * pl_s,
+              "rows_fwd": 2 * B * s_n * (img_s + pl_s), "rows_inv": 2 * B * s_n * (img_s + pl_s),
+              "sec_gather": 2 * B * (ntot * 4 + s_n * img_s), "sec_scatter": 2 * B * (s_n * img_s + ntot * 4)}
         bytes_dir = B * ntot * 4 * 2 + spec_bytes + support_sum * 4
         return {"flops_per_step": 2 * B * per_sig, "bytes_per_step": 2 * bytes_dir, "kernel_flops": kf,
                 "kernel_bytes": kb}
@@ -111,9 +114,14 @@ def algorithmic_counts(p, info):
         kf = {"rows_fwd": B * (nq + 1) * rowfft, "rows_inv": B * (nq + 1) * rowfft,
               "cols_fwd": B * ((m + 1) * colfft + 8.0 * m * n1 * h2),
               "cols_adj": B * ((m + 1) * colfft + 8.0 * m * n1 * h2)}
-        kb = {"cols_fwd": spec_bytes, "cols_adj": spec_bytes,
-              # the row passes read the signal and write the result once per direction
-              "rows_fwd": 2 * B * ntot * 4, "rows_inv": 2 * B * ntot * 4}
+        plane = n1 * h2 * 8
+        # per step (forward + adjoint): the row passes move the image and the
+        # planes of the row-transformed windowed copies (nq forward, 1 adjoint
+        # and the reverse on the way out); the column passes move those planes
+        # and the spectra
+        kb = {"cols_fwd": B * (nq + 1) * plane + spec_bytes, "cols_adj": B * (nq + 1) * plane + spec_bytes,
+              "cols_fft": 2 * B * plane, "cols_sum": B * 2 * plane,
+              "rows_fwd": B * (2 * ntot * 4 + (nq + 1) * plane), "rows_inv": B * (2 * ntot * 4 + (nq + 1) * plane)}
     bytes_dir = B * ntot * 4 * 2 + m * (ntot // p.shape[-1]) * (p.shape[-1] // 2 + 1) * 8 + support_sum * 4
     return {"flops_per_step": 2 * B * per_sig, "bytes_per_step": 2 * bytes_dir, "kernel_flops": kf,
             "kernel_bytes": kb}
@@ -133,8 +141,9 @@ WORKLOADS = {
               "(no sections)",
 }
 PRODUCT_CONVOLUTION = {"c2pc"}
-# batched instances must be full-grid plans; c5full measures C5 without sections
-FULL_GRID = {"c4", "c5full"}
+# batched instances must be full-grid plans; c5full measures C5 without sections;
+# the autograd step (gradients) runs on the full grid, and so do its counts
+FULL_GRID = {"c4", "c5full", "c5ad"}
 
 
 def make_problems(name):
