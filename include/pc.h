@@ -238,6 +238,60 @@ pc_status pc_grad_spectra(pc_plan plan, const float* u, const float* gy, void* g
                           void* stream);
 
 /*
+ * pc_plan_set_responses - replace the impulse responses h_k of a plan by
+ * device data (m x N or m x N1 x N2 floats, lag layout, as for
+ * pc_plan_create) and recompute its spectra F^* h_k on the device; the
+ * windows are unchanged.  Enqueued on `stream`, returns without waiting; h
+ * may be freed once the stream has passed the call.  With the construction
+ * calls below it keeps the whole construction of an operator on the device.
+ * Errors: INVALID_PLAN, INVALID_VALUE (null h), UNSUPPORTED (sectioned plans,
+ * whose sections follow the supports of the responses they were built
+ * with), HIP.
+ */
+pc_status pc_plan_set_responses(pc_plan plan, const float* h, void* stream);
+
+/*
+ * Construction of the impulse responses from a time-varying impulse
+ * response (TVIR) T(x, y) (section 4).  The windows w_k are given; for every
+ * lag x, the coefficients c_k(x) are
+ *   pc_construct_project:      the L2 projection of T(x, .) onto the span of
+ *                              the windows (section 4.2; with B-spline
+ *                              windows the approximation of Corollary 4.3):
+ *                              (W W^T) c(x) = W T(x, .)^T on the grid;
+ *   pc_construct_interpolate:  the interpolation at m nodes y_i
+ *                              (section 4.4): sum_k c_k(x) w_k(y_i) = T(x, y_i);
+ * and h_k[x] = c_k(x) / n, n the number of grid points (the quadrature
+ * weight of the grid).  Grids are flat: 1D signals of n samples, or 2D
+ * images with n = N1 N2 and row-major flat indices for lags, positions and
+ * nodes.
+ *
+ *   n        grid points, a positive multiple of 16.
+ *   m        number of windows, 1 <= m <= 128.
+ *   rows     number of lags given (the TVIR rows that can be nonzero).
+ *   lags     (host) rows distinct flat lag indices in [0, n), lag layout.
+ *   tvir     (device, projection) rows x n floats: row r = T(lag r, y_j)
+ *            over all positions j; 16-byte aligned.
+ *   samples  (device, interpolation) rows x m floats: T(lag r, y_i) at the
+ *            m nodes.
+ *   nodes    (host, interpolation) m distinct flat positions y_i.
+ *   windows  (device) m x n floats; 16-byte aligned for the projection.
+ *   h        (device, out) m x n floats: c_k / n at the listed lags, 0 at
+ *            every other lag.
+ *
+ * The contraction W T^T runs on the matrix cores in FP32 (partial sums over
+ * chunks of 2048 positions added in float64); the m x m factorisations
+ * (Cholesky of the Gram matrix, LU with partial pivoting of the node matrix)
+ * and the per-lag solves are float64.  Both calls are synchronous: they
+ * return once h is written (they allocate and free their workspace).
+ * Errors: INVALID_VALUE (null pointers, sizes or indices out of range,
+ * misaligned buffers, a singular Gram or node matrix), OUT_OF_MEMORY, HIP.
+ */
+pc_status pc_construct_project(int64_t n, int32_t m, int64_t rows, const float* tvir, const int64_t* lags,
+                               const float* windows, float* h, void* stream);
+pc_status pc_construct_interpolate(int64_t n, int32_t m, int64_t rows, const float* samples, const int64_t* lags,
+                                   const int64_t* nodes, const float* windows, float* h, void* stream);
+
+/*
  * Uneven batches.  A batch runs many 2D operators of different sizes and
  * term counts together: every pass of the evaluation is one launch per
  * transform length (the work of all instances with that row or column

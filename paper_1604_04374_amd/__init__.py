@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
            "PC_PLAN_FULL_GRID", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
-           "PC_W_DENSE", "PC_W_SEPARABLE"]
+           "PC_W_DENSE", "PC_W_SEPARABLE", "construct_project", "construct_interpolate"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpc.so")
@@ -42,6 +42,7 @@ STATUS_NAMES = {
 EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_plan_query",
            "pc_plan_set_spectra", "pc_plan_get_spectra", "pc_grad_spectra",
            "pc_plan_set_tracing", "pc_plan_trace_stats", "pc_plan_trace_reset",
+           "pc_plan_set_responses", "pc_construct_project", "pc_construct_interpolate",
            "pc_batch_create", "pc_batch_apply", "pc_batch_apply_adjoint", "pc_batch_destroy",
            "pc_status_string", "pc_last_error")
 
@@ -123,6 +124,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         f.restype = ctypes.c_int
     lib.pc_batch_destroy.argtypes = [vp]
     lib.pc_batch_destroy.restype = ctypes.c_int
+    lib.pc_plan_set_responses.argtypes = [vp, vp, vp]
+    lib.pc_plan_set_responses.restype = ctypes.c_int
+    lib.pc_construct_project.argtypes = [i64, ctypes.c_int32, i64, vp, vp, vp, vp, vp]
+    lib.pc_construct_project.restype = ctypes.c_int
+    lib.pc_construct_interpolate.argtypes = [i64, ctypes.c_int32, i64, vp, vp, vp, vp, vp, vp]
+    lib.pc_construct_interpolate.restype = ctypes.c_int
     lib.pc_status_string.argtypes = [ctypes.c_int]
     lib.pc_status_string.restype = ctypes.c_char_p
     lib.pc_last_error.argtypes = []
@@ -271,6 +278,20 @@ class Plan:
                                            ctypes.c_void_p(_stream_ptr(stream, spec.device)))
         _check(self._lib, st, "pc_plan_set_spectra")
 
+    def set_responses(self, h, stream=None):
+        """Replace the impulse responses by a float32 CUDA tensor (``m x N`` or
+        ``m x N1 x N2``, lag layout); the spectra are recomputed on the device."""
+        import torch
+        if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float32):
+            raise TypeError("h must be a float32 CUDA tensor")
+        h = h.contiguous()
+        if tuple(h.shape) != (self.m,) + self.shape:
+            raise ValueError(f"h must be {(self.m,) + self.shape}, got {tuple(h.shape)}")
+        self._h_keep = h  # alive until the enqueued transform has read it
+        st = self._lib.pc_plan_set_responses(self._handle, ctypes.c_void_p(h.data_ptr()),
+                                             ctypes.c_void_p(_stream_ptr(stream, h.device)))
+        _check(self._lib, st, "pc_plan_set_responses")
+
     def grad_spectra(self, u, gy, out=None, stream=None):
         """dL/dspec given the forward input u and dL/dy (see pc_grad_spectra)."""
         import torch
@@ -332,6 +353,57 @@ class Plan:
 
     def __exit__(self, *exc):
         self.destroy()
+
+
+def _lags_array(lags, n):
+    lags = np.ascontiguousarray(np.asarray(lags, dtype=np.int64))
+    if lags.ndim != 1:
+        raise ValueError("lags must be one-dimensional")
+    return lags
+
+
+def construct_project(tvir, lags, windows, stream=None):
+    """``h`` (``m x n``) of the L2 projection of the TVIR rows onto the span of
+    the windows (section 4.2).  ``tvir``: float32 CUDA ``rows x n``;
+    ``lags``: the rows' flat lag indices; ``windows``: float32 CUDA ``m x n``
+    (2D grids flattened).  Synchronous."""
+    import torch
+    lib = load_library()
+    tvir, windows = tvir.contiguous(), windows.contiguous()
+    rows, n = tvir.shape
+    m = windows.shape[0]
+    lg = _lags_array(lags, n)
+    if lg.shape[0] != rows or windows.shape[1] != n:
+        raise ValueError("tvir, lags and windows disagree in size")
+    h = torch.empty((m, n), dtype=torch.float32, device=tvir.device)
+    st = lib.pc_construct_project(n, m, rows, ctypes.c_void_p(tvir.data_ptr()), lg.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.c_void_p(windows.data_ptr()), ctypes.c_void_p(h.data_ptr()),
+                                  ctypes.c_void_p(_stream_ptr(stream, tvir.device)))
+    _check(lib, st, "pc_construct_project")
+    return h
+
+
+def construct_interpolate(samples, lags, nodes, windows, stream=None):
+    """``h`` (``m x n``) interpolating the TVIR samples at the nodes (section
+    4.4).  ``samples``: float32 CUDA ``rows x m`` (T(lag r, node i));
+    ``nodes``: m flat positions; ``windows``: float32 CUDA ``m x n``.
+    Synchronous."""
+    import torch
+    lib = load_library()
+    samples, windows = samples.contiguous(), windows.contiguous()
+    rows, m = samples.shape
+    n = windows.shape[1]
+    lg = _lags_array(lags, n)
+    nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64))
+    if lg.shape[0] != rows or windows.shape[0] != m or nd.shape != (m,):
+        raise ValueError("samples, lags, nodes and windows disagree in size")
+    h = torch.empty((m, n), dtype=torch.float32, device=samples.device)
+    st = lib.pc_construct_interpolate(n, m, rows, ctypes.c_void_p(samples.data_ptr()),
+                                      lg.ctypes.data_as(ctypes.c_void_p), nd.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_void_p(windows.data_ptr()), ctypes.c_void_p(h.data_ptr()),
+                                      ctypes.c_void_p(_stream_ptr(stream, samples.device)))
+    _check(lib, st, "pc_construct_interpolate")
+    return h
 
 
 class Batch:

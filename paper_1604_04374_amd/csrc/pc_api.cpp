@@ -1113,6 +1113,58 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
   return PC_SUCCESS;
 }
 
+// Temporary device buffers of one construction call, freed at return (the
+// call waits for its stream first).
+struct CallTemps {
+  std::vector<void*> ptrs;
+  ~CallTemps() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <class T>
+  pc_status alloc(T** out, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 256));
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc");
+    ptrs.push_back(q);
+    *out = static_cast<T*>(q);
+    return PC_SUCCESS;
+  }
+  template <class T>
+  pc_status upload(T** out, const T* host, size_t count) {
+    pc_status st = alloc(out, count);
+    if (st) return st;
+    hipError_t e = hipMemcpy(*out, host, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    return PC_SUCCESS;
+  }
+};
+
+pc_status check_construct(int64_t n, int32_t m, int64_t rows, const void* a, const float* windows,
+                                 const float* h, const int64_t* lags) {
+  if (!a || !windows || !h || !lags) return fail(PC_ERROR_INVALID_VALUE, "null pointer");
+  if (n < 16 || n % 16) return fail(PC_ERROR_INVALID_VALUE, "n must be a positive multiple of 16");
+  if (m < 1 || m > pc::CONSTRUCT_MAX_M)
+    return fail(PC_ERROR_INVALID_VALUE, "m must be in [1, " + std::to_string(pc::CONSTRUCT_MAX_M) + "]");
+  if (rows < 1 || rows > n) return fail(PC_ERROR_INVALID_VALUE, "rows must be in [1, n]");
+  std::vector<char> seen((size_t)n, 0);
+  for (int64_t r = 0; r < rows; ++r) {
+    if (lags[r] < 0 || lags[r] >= n || seen[(size_t)lags[r]])
+      return fail(PC_ERROR_INVALID_VALUE, "lags must be distinct and in [0, n)");
+    seen[(size_t)lags[r]] = 1;
+  }
+  return PC_SUCCESS;
+}
+
+pc_status finish_construct(hipStream_t s, const int* dfail, const char* what) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, what);
+  int bad = 0;
+  e = hipMemcpy(&bad, dfail, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, what);
+  if (bad) return fail(PC_ERROR_INVALID_VALUE, std::string(what) + ": the windows' system is singular");
+  return PC_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1371,6 +1423,96 @@ pc_status pc_grad_spectra(pc_plan p, const float* u, const float* gy, void* gspe
   if (e == hipSuccess && p->pconv) e = pc::launch_conj(out, out, p->spec_count, s);
   if (e != hipSuccess) return fail_hip(e, "pc_grad_spectra launch");
   return PC_SUCCESS;
+}
+
+pc_status pc_plan_set_responses(pc_plan p, const float* h, void* stream) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!h) return fail(PC_ERROR_INVALID_VALUE, "h is NULL");
+  if (p->path == 3)
+    return fail(PC_ERROR_UNSUPPORTED, "sectioned plans are built for the supports of their responses "
+                                      "(create the plan with PC_PLAN_FULL_GRID)");
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (p->pconv) {  // the plan holds the operator of the flipped responses
+    float* fl = reinterpret_cast<float*>(p->conj_ws);
+    e = pc::launch_flip(h, fl, p->d.m, p->d.n0, p->d.n1, s);
+    h = fl;
+  }
+  if (e == hipSuccess) {
+    if (p->path == 0) {
+      e = pc::launch_spec1d_full(p->s1.L, h, const_cast<float2*>(p->s1.H), p->d.m, p->s1.tw, s);
+    } else if (p->path == 1) {
+      float2* Hd = const_cast<float2*>(p->l1.Hd);
+      e = pc::launch_fold_fft(p->l1, h, p->d.m, Hd, false, s);
+      if (e == hipSuccess) e = pc::launch_origin_phase1d(p->l1, Hd, s);
+    } else {
+      e = pc::launch_spec2d(p->p2, h, s);
+    }
+  }
+  if (e != hipSuccess) return fail_hip(e, "pc_plan_set_responses launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_construct_project(int64_t n, int32_t m, int64_t rows, const float* tvir, const int64_t* lags,
+                               const float* windows, float* h, void* stream) {
+  pc_status st = check_construct(n, m, rows, tvir, windows, h, lags);
+  if (st) return st;
+  if ((reinterpret_cast<uintptr_t>(tvir) | reinterpret_cast<uintptr_t>(windows)) % 16)
+    return fail(PC_ERROR_INVALID_VALUE, "tvir and windows must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int splits = pc::gemm_splits(n);
+  CallTemps t;
+  float *part = nullptr, *gpart = nullptr;
+  double *rhs = nullptr, *work = nullptr, *G = nullptr;
+  int64_t* dl = nullptr;
+  int* dfail = nullptr;
+  if ((st = t.alloc(&part, (size_t)splits * rows * m)) || (st = t.alloc(&gpart, (size_t)splits * m * m)) ||
+      (st = t.alloc(&rhs, (size_t)rows * m)) || (st = t.alloc(&work, (size_t)rows * m)) ||
+      (st = t.alloc(&G, (size_t)m * m)) || (st = t.alloc(&dfail, 1)) || (st = t.upload(&dl, lags, (size_t)rows)))
+    return st;
+  hipError_t e = pc::launch_fill_zero(h, (int64_t)m * n, s);
+  // right-hand sides W T(x, .)^T for every row, and the Gram matrix W W^T
+  if (e == hipSuccess) e = pc::launch_gemm_nt(tvir, rows, windows, m, n, part, s);
+  if (e == hipSuccess) e = pc::launch_sum_splits(part, splits, rows * m, rhs, s);
+  if (e == hipSuccess) e = pc::launch_gemm_nt(windows, m, windows, m, n, gpart, s);
+  if (e == hipSuccess) e = pc::launch_sum_splits(gpart, splits, (int64_t)m * m, G, s);
+  if (e == hipSuccess) e = pc::launch_cholesky(G, m, dfail, s);
+  if (e == hipSuccess) e = pc::launch_row_solve(false, G, nullptr, m, rhs, work, rows, dl, n, h, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_construct_project launch");
+  return finish_construct(s, dfail, "pc_construct_project");
+}
+
+pc_status pc_construct_interpolate(int64_t n, int32_t m, int64_t rows, const float* samples, const int64_t* lags,
+                                   const int64_t* nodes, const float* windows, float* h, void* stream) {
+  pc_status st = check_construct(n, m, rows, samples, windows, h, lags);
+  if (st) return st;
+  if (!nodes) return fail(PC_ERROR_INVALID_VALUE, "nodes is NULL");
+  {
+    std::vector<char> seen((size_t)n, 0);
+    for (int i = 0; i < m; ++i) {
+      if (nodes[i] < 0 || nodes[i] >= n || seen[(size_t)nodes[i]])
+        return fail(PC_ERROR_INVALID_VALUE, "nodes must be distinct and in [0, n)");
+      seen[(size_t)nodes[i]] = 1;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallTemps t;
+  double *src = nullptr, *work = nullptr, *E = nullptr;
+  int64_t *dl = nullptr, *dn = nullptr;
+  int *perm = nullptr, *dfail = nullptr;
+  if ((st = t.alloc(&src, (size_t)rows * m)) || (st = t.alloc(&work, (size_t)rows * m)) ||
+      (st = t.alloc(&E, (size_t)m * m)) || (st = t.alloc(&perm, (size_t)m)) || (st = t.alloc(&dfail, 1)) ||
+      (st = t.upload(&dl, lags, (size_t)rows)) || (st = t.upload(&dn, nodes, (size_t)m)))
+    return st;
+  hipError_t e = pc::launch_fill_zero(h, (int64_t)m * n, s);
+  if (e == hipSuccess) e = pc::launch_node_matrix(windows, m, n, dn, E, s);
+  if (e == hipSuccess) e = pc::launch_lu(E, m, perm, dfail, s);
+  if (e == hipSuccess) e = pc::launch_to_double(samples, rows * m, src, s);
+  if (e == hipSuccess) e = pc::launch_row_solve(true, E, perm, m, src, work, rows, dl, n, h, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_construct_interpolate launch");
+  return finish_construct(s, dfail, "pc_construct_interpolate");
 }
 
 pc_status pc_plan_set_tracing(pc_plan p, int32_t enable) {

@@ -250,4 +250,25 @@ LaunchStatus launch_sec_gather(const Sec2D& q, const float* x, bool adjoint, int
 // every output pixel of the first `batch` images <- sum of the sections covering it
 LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr);
 
+// --------------------------------------------------------------------------
+// Construction of h_k from a TVIR (section 4.2 projection, section 4.4
+// interpolation)
+// --------------------------------------------------------------------------
+constexpr int GEMM_ROWS = 64, GEMM_COLS = 32, GEMM_CHUNK = 2048;
+constexpr int CONSTRUCT_MAX_M = 128;
+inline int gemm_splits(int64_t K) { return (int)((K + GEMM_CHUNK - 1) / GEMM_CHUNK); }
+// part[split][r][c] = sum over the split's chunk of A[r][j] B[c][j] (FP32 MFMA);
+// K % 16 == 0, rows of A and B 16-byte aligned
+LaunchStatus launch_gemm_nt(const float* A, int64_t rows, const float* B, int cols, int64_t K, float* part,
+                            hipStream_t s);
+LaunchStatus launch_sum_splits(const float* part, int splits, int64_t n, double* out, hipStream_t s);
+LaunchStatus launch_cholesky(double* G, int m, int* fail, hipStream_t s);
+LaunchStatus launch_lu(double* E, int m, int* perm, int* fail, hipStream_t s);
+LaunchStatus launch_row_solve(bool lu, const double* F, const int* perm, int m, const double* src, double* work,
+                              int64_t rows, const int64_t* lags, int64_t n, float* h, hipStream_t s);
+LaunchStatus launch_fill_zero(float* x, int64_t n, hipStream_t s);
+LaunchStatus launch_node_matrix(const float* W, int m, int64_t n, const int64_t* nodes, double* E, hipStream_t s);
+LaunchStatus launch_to_double(const float* x, int64_t n, double* y, hipStream_t s);
+LaunchStatus launch_flip(const float* in, float* out, int64_t count, int64_t n0, int64_t n1, hipStream_t s);
+
 }  // namespace pc

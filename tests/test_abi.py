@@ -98,3 +98,34 @@ def test_calls_on_invalid_plans(lib):
     info = pcm.PlanInfo()
     assert lib.pc_plan_query(bogus, ctypes.byref(info)) == 5
     assert "live plan" in lib.pc_last_error().decode()
+
+
+def _construct_args(n=1024, m=4, rows=3, lags=(0, 1, 1023), ptr=4096):
+    lg = np.asarray(lags, dtype=np.int64)
+    return n, m, rows, ctypes.c_void_p(ptr), lg.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ptr), \
+        ctypes.c_void_p(ptr), None, lg
+
+
+@pytest.mark.parametrize("kw", [dict(n=1000), dict(n=0), dict(m=0), dict(m=129), dict(rows=0),
+                                dict(lags=(0, 1, 1024)), dict(lags=(5, 5, 7)), dict(lags=(-1, 2, 3)),
+                                dict(ptr=4100)])
+def test_construct_rejects_bad_arguments(lib, kw):
+    # every case is rejected before any device work (the pointers are never touched)
+    n, m, rows, tv, lg, w, h, s, keep = _construct_args(**kw)
+    assert lib.pc_construct_project(n, m, rows, tv, lg, w, h, s) == 1, lib.pc_last_error()
+    if kw.get("ptr") is None:
+        nodes = np.arange(m, dtype=np.int64)
+        st = lib.pc_construct_interpolate(n, m, rows, tv, lg, nodes.ctypes.data_as(ctypes.c_void_p), w, h, s)
+        assert st == 1, lib.pc_last_error()
+
+
+def test_construct_rejects_bad_nodes(lib):
+    n, m, rows, tv, lg, w, h, s, keep = _construct_args()
+    for nodes in ([0, 1, 1, 3], [0, 1, 2, 1024]):
+        nd = np.asarray(nodes, dtype=np.int64)
+        assert lib.pc_construct_interpolate(n, m, rows, tv, lg, nd.ctypes.data_as(ctypes.c_void_p), w, h, s) == 1
+    assert lib.pc_construct_interpolate(n, m, rows, tv, lg, None, w, h, s) == 1
+
+
+def test_set_responses_on_invalid_plan(lib):
+    assert lib.pc_plan_set_responses(None, ctypes.c_void_p(4096), None) == 5

@@ -1,0 +1,163 @@
+"""On-device construction of the impulse responses (section 4.2 projection,
+section 4.4 interpolation) against the FP64 oracle (`oracle.construct`,
+pinned by the approximation-rate and centre-sampling tests), and the full
+on-device pipeline TVIR -> h_k -> plan -> H_m u.
+
+Tolerance.  Interpolation solves an m x m system per lag in float64 from
+float32 samples: rel-L2 <= 1e-6.  Projection contracts n positions in FP32
+on the matrix cores (chunks of 2048 added in float64), so the right-hand
+sides carry a relative error of about sqrt(2048) 2^-24 ~ 3e-6, amplified by
+at most the condition number of the windows' Gram matrix (~17 for cubic
+B-splines): rel-L2 <= 1e-5 * max(1, kappa / 10) with kappa computed here."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import rel_l2
+from oracle import construct, dense, expansion as ex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_04374_amd as pcm
+    pcm.load_library()
+
+
+def _tvir(n, sigma_fn):
+    TT = dense.tvir_matrix_1d(wl.tvir_gaussian(sigma_fn), n).astype(np.float32)
+    lags = np.nonzero(np.any(TT != 0, axis=1))[0]
+    return TT, lags
+
+
+@pytest.mark.parametrize("n,m,deg", [(1024, 8, 1), (4096, 16, 3), (6144, 12, 3), (16384, 32, 3)])
+def test_projection_matches_oracle(n, m, deg):
+    import torch
+    import paper_1604_04374_amd as pcm
+    print(f"[gpu] construct_project n={n} m={m} degree={deg}", flush=True)
+    TT, lags = _tvir(n, lambda y: 0.004 + 0.01 * np.sin(np.pi * y) ** 2)
+    W = wl.bspline_windows_1d(n, m, deg).astype(np.float32)
+    h = pcm.construct_project(torch.from_numpy(np.ascontiguousarray(TT[lags])).cuda(), lags,
+                              torch.from_numpy(W).cuda()).cpu().numpy()
+    TT64 = np.zeros((n, n))
+    TT64[lags] = TT[lags].astype(np.float64)
+    ref = construct.project(TT64, W.astype(np.float64))
+    G = W.astype(np.float64) @ W.astype(np.float64).T
+    kappa = np.linalg.cond(G)
+    err = rel_l2(h, ref)
+    print(f"n={n} m={m}: rows {len(lags)}, rel {err:.2e}, Gram condition {kappa:.1f}", flush=True)
+    assert err <= 1e-5 * max(1.0, kappa / 10)
+    unlisted = np.setdiff1d(np.arange(n), lags)
+    assert np.all(h[:, unlisted] == 0)
+
+
+@pytest.mark.parametrize("n,m,deg", [(1024, 8, 1), (4096, 16, 3), (16384, 32, 3)])
+def test_interpolation_matches_oracle(n, m, deg):
+    import torch
+    import paper_1604_04374_amd as pcm
+    print(f"[gpu] construct_interpolate n={n} m={m} degree={deg}", flush=True)
+    TT, lags = _tvir(n, lambda y: 0.004 + 0.01 * np.sin(np.pi * y) ** 2)
+    W = wl.bspline_windows_1d(n, m, deg).astype(np.float32)
+    nodes = np.array([k * n // m for k in range(m)])
+    samples = np.ascontiguousarray(TT[lags][:, nodes])
+    h = pcm.construct_interpolate(torch.from_numpy(samples).cuda(), lags, nodes,
+                                  torch.from_numpy(W).cuda()).cpu().numpy()
+    TT64 = np.zeros((n, n))
+    TT64[lags] = TT[lags].astype(np.float64)
+    ref = construct.interpolate(TT64, W.astype(np.float64), nodes)
+    err = rel_l2(h, ref)
+    print(f"n={n} m={m}: rel {err:.2e}", flush=True)
+    assert err <= 1e-6
+    if deg == 1:  # hat windows: interpolation is sampling at the centres
+        assert rel_l2(h, TT64[:, nodes].T / n) <= 1e-6
+
+
+def test_interpolation_2d_flat_grid():
+    import torch
+    import paper_1604_04374_amd as pcm
+    n1 = n2 = 64
+    p = wl.small_2d(n1, n2, 2, 2, 1, seed=140, kind="hat")
+    W = p.dense_windows().reshape(p.m, -1).astype(np.float32)
+    nodes = np.array([int(round(c1)) * n2 + int(round(c2)) for c1, c2 in p.extra["centres_px"]])
+    # samples: the PSFs (as sampled by the generator) at the nodes, per lag pixel
+    Hn = p.h.reshape(p.m, -1).astype(np.float64) * (n1 * n2)   # T(lag, node_i), TVIR units
+    lags = np.nonzero(np.any(Hn != 0, axis=0))[0]
+    samples = np.ascontiguousarray(Hn[:, lags].T.astype(np.float32))
+    h = pcm.construct_interpolate(torch.from_numpy(samples).cuda(), lags, nodes,
+                                  torch.from_numpy(W).cuda()).cpu().numpy()
+    E = W[:, nodes].T.astype(np.float64)
+    ref = np.zeros((p.m, n1 * n2))
+    ref[:, lags] = np.linalg.solve(E, samples.astype(np.float64).T) / (n1 * n2)
+    assert rel_l2(h, ref) <= 1e-6
+
+
+def test_on_device_pipeline_tvir_to_apply():
+    import torch
+    import paper_1604_04374_amd as pcm
+    n, m, batch = 16384, 16, 4
+    print(f"[gpu] TVIR -> projection -> plan -> apply, n={n}", flush=True)
+    TT, lags = _tvir(n, lambda y: 0.003 + 0.008 * np.sin(np.pi * y) ** 2)
+    W = wl.bspline_windows_1d(n, m, 3).astype(np.float32)
+    Wd = torch.from_numpy(W).cuda()
+    hd = pcm.construct_project(torch.from_numpy(np.ascontiguousarray(TT[lags])).cuda(), lags, Wd)
+    u = np.random.default_rng(141).standard_normal((batch, n)).astype(np.float32)
+    plan = pcm.Plan(W, np.zeros((m, n), np.float32), batch=batch)
+    plan.set_responses(hd)
+    ud = torch.from_numpy(u).cuda()
+    y = plan.apply(ud).cpu().numpy()
+    x = plan.apply_adjoint(ud).cpu().numpy()
+    h32 = hd.cpu().numpy()
+    ry = ex.apply_fft(u.astype(np.float64), W.astype(np.float64), h32.astype(np.float64))
+    rx = ex.adjoint_fft(u.astype(np.float64), W.astype(np.float64), h32.astype(np.float64))
+    assert max(rel_l2(a, b) for a, b in zip(y, ry)) <= 1e-5
+    assert max(rel_l2(a, b) for a, b in zip(x, rx)) <= 1e-5
+    # the same operator through host responses
+    with pcm.Plan(W, h32, batch=batch) as ref_plan:
+        y2 = ref_plan.apply(ud).cpu().numpy()
+    assert max(rel_l2(a, b) for a, b in zip(y, y2)) <= 1e-6
+    plan.destroy()
+
+
+@pytest.mark.parametrize("kind", ["small", "fourstep", "2d", "pconv"])
+def test_set_responses_matches_a_new_plan(kind):
+    import torch
+    import paper_1604_04374_amd as pcm
+    if kind == "small":
+        p = wl.small_1d(2048, 6, 3, 3, seed=150)
+    elif kind in ("fourstep", "pconv"):
+        p = wl.small_1d(16384, 8, 3, 2, seed=151, sigma_fn=wl.gen.c2_sigma)
+    else:
+        p = wl.small_2d(96, 128, 2, 2, 2, seed=152, kind="hat")
+    rng = np.random.default_rng(153)
+    h2 = (np.roll(p.h, 2, axis=-1) * rng.uniform(0.5, 1.5, (p.m,) + (1,) * p.ndim)).astype(np.float32)
+    wins = (p.w_rows, p.w_cols) if p.separable else p.w
+    pc_flag = kind == "pconv"
+    u = torch.from_numpy(p.u).cuda()
+    with pcm.Plan(wins, p.h, batch=p.batch, product_convolution=pc_flag, full_grid=True) as a, \
+            pcm.Plan(wins, h2, batch=p.batch, product_convolution=pc_flag, full_grid=True) as b:
+        a.set_responses(torch.from_numpy(h2).cuda())
+        ya, xa = a.apply(u).cpu().numpy(), a.apply_adjoint(u).cpu().numpy()
+        yb, xb = b.apply(u).cpu().numpy(), b.apply_adjoint(u).cpu().numpy()
+    assert max(rel_l2(s, t) for s, t in zip(ya, yb)) <= 1e-6
+    assert max(rel_l2(s, t) for s, t in zip(xa, xb)) <= 1e-6
+
+
+def test_singular_windows_are_reported():
+    import torch
+    import paper_1604_04374_amd as pcm
+    n, m = 1024, 4
+    W = wl.bspline_windows_1d(n, m, 1).astype(np.float32)
+    W[1] = W[0]  # linearly dependent
+    TT, lags = _tvir(n, lambda y: 0.01 + 0.0 * y)
+    with pytest.raises(pcm.PCError) as ei:
+        pcm.construct_project(torch.from_numpy(np.ascontiguousarray(TT[lags])).cuda(), lags, torch.from_numpy(W).cuda())
+    assert ei.value.status == 1
+    nodes = np.array([0, 256, 512, 768])
+    with pytest.raises(pcm.PCError) as ei:
+        pcm.construct_interpolate(torch.from_numpy(np.ascontiguousarray(TT[lags][:, nodes])).cuda(), lags, nodes,
+                                  torch.from_numpy(W).cuda())
+    assert ei.value.status == 1
