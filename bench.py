@@ -139,7 +139,10 @@ WORKLOADS = {
             "G_m u = sum_k w_k . (h_k * u); step = G_m u + G_m^* u",
     "c5full": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1, evaluated on the full grid "
               "(no sections)",
+    "c2proj": "construction: L2 projection (section 4.2) of the C2 TVIR band (all lags within 15 widths, "
+              "65536 positions) onto the 32 cubic B-spline windows, on the device",
 }
+MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PRODUCT_CONVOLUTION = {"c2pc"}
 # batched instances must be full-grid plans; c5full measures C5 without sections;
 # the autograd step (gradients) runs on the full grid, and so do its counts
@@ -224,6 +227,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
         return
+
+    if args.workload == "c2proj":
+        return bench_construct(args, torch, pcm, dev)
 
     probs = make_problems(args.workload)
     log(f"[bench] workload {args.workload}: {len(probs)} plan(s)")
@@ -410,6 +416,66 @@ def main():
     print(json.dumps(line), flush=True)
     for _, plan, _, _, _ in jobs:
         plan.destroy()
+
+
+def bench_construct(args, torch, pcm, dev):
+    """Time pc_construct_project on the C2 TVIR band (one call = every lag row)."""
+    import workloads as wl
+    n, m = 65536, 32
+    log("[bench] generating the TVIR band on the device")
+    tv, lags = wl.gen.tvir_band_torch(n, wl.gen.c2_sigma, dev)
+    W = wl.bspline_windows_1d(n, m, 3).astype(np.float32)
+    Wd = torch.from_numpy(W).to(dev)
+    rows = int(lags.shape[0])
+    steps = max(1, min(args.steps, 10))
+    log(f"[bench] {rows} rows x {n} positions; warmup {args.warmup}, timing {steps} calls")
+    for _ in range(max(args.warmup, 1)):
+        h = pcm.construct_project(tv, lags, Wd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h = pcm.construct_project(tv, lags, Wd)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    flops = 2.0 * rows * m * n + 2.0 * m * m * n
+    tvir_bytes = rows * n * 4.0
+    achieved = flops / (ms * 1e-3) / 1e12
+    roofline = {"bound": "hbm", "kernel": "construct_project (whole call: GEMM, reduction, factorisation, solves)",
+                "achieved": round(tvir_bytes / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(tvir_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
+                "mfma_tflops": round(achieved, 3), "mfma_frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4)}
+    err = cpu = None
+    if args.cpu_seconds > 0:
+        # the oracle's projection on consecutive chunks of rows, within the
+        # CPU budget; its agreement with the device result on those rows
+        from oracle import construct
+        W64 = W.astype(np.float64)
+        tc, done, num, den = 0.0, 0, 0.0, 0.0
+        hc = h.cpu().numpy()
+        for r0 in range(0, rows, 2048):
+            if tc >= args.cpu_seconds:
+                break
+            sub = tv[r0:r0 + 2048].cpu().numpy().astype(np.float64)
+            c0 = time.perf_counter()
+            ref = construct.project(sub, W64)
+            tc += time.perf_counter() - c0
+            got = hc[:, lags[r0:r0 + 2048]]
+            num += float(np.sum((got - ref) ** 2))
+            den += float(np.sum(ref ** 2))
+            done += sub.shape[0]
+        err = float(np.sqrt(num / den))
+        cpu = {"value": round(done / tc, 1), "unit": "rows/s", "cores": __import__("oracle").expansion.workers(),
+               "kind": "oracle", "sample": f"{done} of {rows} rows, float64 NumPy projection, {tc:.2f} s"}
+    line = {
+        "metric": "TVIR lag rows projected per second (n=65536, m=32 cubic B-spline windows)",
+        "value": round(rows / (ms * 1e-3), 1), "unit": "rows/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (FP32 MFMA products, float64 sums of chunks and solves)",
+        "data": "synthetic", "config": {"workload": WORKLOADS["c2proj"], "key": "c2proj", "rows": rows,
+                                        "n": n, "m": m},
+        "roofline": roofline, "alg_tflops": round(achieved, 3), "max_rel_l2_vs_oracle": err, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -36,13 +36,22 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A
   const float4* Ar = reinterpret_cast<const float4*>(A + (rok ? r : 0) * K);
   const float4* Ba = reinterpret_cast<const float4*>(B + (int64_t)(aok ? ca : 0) * K);
   const float4* Bb = reinterpret_cast<const float4*>(B + (int64_t)(bok ? cb : 0) * K);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  // out-of-range rows and columns read row 0 (valid memory) and are zeroed
+  // by a factor, so that every load is one unconditional 16-byte access
+  const float fa = rok ? 1.f : 0.f, fx = aok ? 1.f : 0.f, fy = bok ? 1.f : 0.f;
+  auto scale = [](float4 v, float f) { return make_float4(v.x * f, v.y * f, v.z * f, v.w * f); };
   floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  // operands of step k0 + 16 load while the MFMAs of step k0 issue
+  int64_t q = (k_begin >> 2) + g;  // float4 index of k0 + 4g
+  float4 an = Ar[q], xn = Ba[q], yn = Bb[q];
   for (int64_t k0 = k_begin; k0 < k_end; k0 += 16) {
-    const int64_t q = (k0 >> 2) + g;  // float4 index of k0 + 4g
-    const float4 a = rok ? Ar[q] : zero;
-    const float4 x = aok ? Ba[q] : zero;
-    const float4 y = bok ? Bb[q] : zero;
+    const float4 a = scale(an, fa), x = scale(xn, fx), y = scale(yn, fy);
+    q += 4;
+    if (k0 + 16 < k_end) {
+      an = Ar[q];
+      xn = Ba[q];
+      yn = Bb[q];
+    }
     acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x.x, acc0, 0, 0, 0);
     acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, y.x, acc1, 0, 0, 0);
     acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x.y, acc0, 0, 0, 0);

@@ -381,3 +381,26 @@ def config_c5(n=2048, tiles=8, seed=5, sigma_scale_model=1.25):
     p.extra["noise"] = _f32(rng.standard_normal((1, n, n)))
     p.extra["h_model"] = _f32(h_model)
     return p
+
+
+def tvir_band_torch(n: int, sigma_fn, device, cutoff_sigmas: float = 15.0):
+    """Rows of the TVIR ``T(lam, y) = g_{sigma(y)}(lam)`` (Example 3.1 form,
+    unit-mass Gaussian of width ``sigma(y)`` at the source ``y = j/n``) for
+    every lag within ``cutoff_sigmas`` times the largest width, generated on
+    ``device`` in float64 and stored as float32 (beyond ~14.4 widths the
+    float32 values are exact zeros).  Returns ``(rows x n tensor, lags)``
+    with ``lags`` the rows' lag indices (lag layout)."""
+    import torch
+    y = np.arange(n) / n
+    sig = np.asarray(sigma_fn(y), np.float64)
+    cut = int(math.ceil(cutoff_sigmas * sig.max() * n))
+    cut = min(cut, n // 2 - 1)
+    lags = np.concatenate([np.arange(0, cut + 1), np.arange(n - cut, n)]).astype(np.int64)
+    sig_t = torch.from_numpy(sig).to(device)
+    out = torch.empty((lags.shape[0], n), dtype=torch.float32, device=device)
+    lam_all = np.where(lags < n // 2, lags, lags - n) / n
+    norm = 1.0 / (math.sqrt(2.0 * math.pi) * sig_t)
+    for s0 in range(0, lags.shape[0], 1024):
+        lam = torch.from_numpy(lam_all[s0:s0 + 1024]).to(device)[:, None]
+        out[s0:s0 + 1024] = (torch.exp(-0.5 * (lam / sig_t[None, :]) ** 2) * norm[None, :]).float()
+    return out, lags
