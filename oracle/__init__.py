@@ -16,5 +16,7 @@ Modules
                approximation-rate test).
 ``grads``      gradients of ``0.5 ||H_m u - f||^2`` with respect to ``u`` and
                to the half-spectra of the ``h_k``.
+``wavelets``   periodic orthonormal Daubechies wavelets and Meyer's operator
+               representation (section 4.6).
 """
-from . import expansion, dense, construct, grads  # noqa: F401
+from . import expansion, dense, construct, grads, wavelets  # noqa: F401
