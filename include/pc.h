@@ -292,6 +292,48 @@ pc_status pc_construct_interpolate(int64_t n, int32_t m, int64_t rows, const flo
                                    const int64_t* nodes, const float* windows, float* h, void* stream);
 
 /*
+ * Meyer's operator representation (section 4.6).  The TVIR is expanded in a
+ * tensor basis of periodic orthonormal wavelets,
+ *   T(x, y) = sum c_{lambda,mu} psi_lambda(x) psi_mu(y),
+ * of which a few coefficients are kept; regrouped by mu (the paper's trick
+ * equation) this is the convolution-product expansion with windows
+ * w_mu = psi_mu and responses h_mu = c~_mu / n,
+ * c~_mu = sum_lambda c_{lambda,mu} psi_lambda.
+ *
+ * Wavelets: the periodic discrete wavelet transform of `levels` levels
+ * with the orthonormal lowpass filter `lowpass` (`taps` values, even,
+ * <= 20; the highpass filter is g[k] = (-1)^k lowpass[taps-1-k]) on n = 2^J
+ * samples; one level maps a (length len) to
+ *   lo[i] = sum_k h[k] a[(2i + k) mod len], hi[i] = sum_k g[k] a[(2i + k) mod len],
+ * and coefficients are in pyramid order [a_levels, d_levels, ..., d_1], so
+ * that index lambda names one basis vector psi_lambda (a row of the
+ * orthogonal transform matrix).
+ *
+ * pc_wavelet_transform - the transform (inverse = 0) or its inverse
+ *   (inverse != 0) of `count` vectors; element i of vector b is at
+ *   b * dist + i * stride in both `in` and `out` (device; distinct buffers).
+ *   A 2D transform is one call over the rows (stride 1, dist n) and one
+ *   over the columns (stride n, dist 1).  Synchronous (allocates scratch).
+ *
+ * pc_plan_create_meyer - a 1D plan (n samples, batch capacity `batch`,
+ *   plan flags as for pc_plan_create) for the kept coefficients
+ *   c[i] = c_{lam[i], mu[i]} (host arrays of `count` entries, indices in
+ *   [0, n), repeated pairs add up).  The windows psi_mu and the responses
+ *   c~_mu / n are synthesised on the device; the plan's terms are the
+ *   distinct mu in increasing order.  Synchronous, like pc_plan_create.
+ *
+ * Errors: INVALID_VALUE (null pointers, n not a power of two, levels out of
+ * range, bad taps, indices out of range, in == out), UNSUPPORTED (n not a
+ * supported 1D size), OUT_OF_MEMORY, HIP.
+ */
+pc_status pc_wavelet_transform(int32_t inverse, int64_t n, int32_t levels, int32_t taps, const float* lowpass,
+                               int64_t count, int64_t stride, int64_t dist, const float* in, float* out,
+                               void* stream);
+pc_status pc_plan_create_meyer(pc_plan* out, int64_t n, int32_t levels, int32_t taps, const float* lowpass,
+                               int64_t count, const int64_t* lam, const int64_t* mu, const float* c, int64_t batch,
+                               uint32_t flags, void* stream);
+
+/*
  * Uneven batches.  A batch runs many 2D operators of different sizes and
  * term counts together: every pass of the evaluation is one launch per
  * transform length (the work of all instances with that row or column

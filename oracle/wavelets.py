@@ -61,8 +61,13 @@ def _analysis_step(a: np.ndarray, h: np.ndarray):
     lo[i] = sum_k h[k] a[(2i + k) mod n],  hi[i] = sum_k g[k] a[(2i + k) mod n]."""
     n = a.shape[-1]
     g = _highpass(h)
-    idx = (2 * np.arange(n // 2)[:, None] + np.arange(h.shape[0])[None, :]) % n
-    return a[..., idx] @ h, a[..., idx] @ g
+    lo = np.zeros(a.shape[:-1] + (n // 2,))
+    hi = np.zeros_like(lo)
+    for k in range(h.shape[0]):
+        v = a[..., (2 * np.arange(n // 2) + k) % n]
+        lo += h[k] * v
+        hi += g[k] * v
+    return lo, hi
 
 
 def _synthesis_step(lo: np.ndarray, hi: np.ndarray, h: np.ndarray) -> np.ndarray:

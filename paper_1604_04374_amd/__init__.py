@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
            "PC_PLAN_FULL_GRID", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
-           "PC_W_DENSE", "PC_W_SEPARABLE", "construct_project", "construct_interpolate"]
+           "PC_W_DENSE", "PC_W_SEPARABLE", "construct_project", "construct_interpolate", "wavelet_transform"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpc.so")
@@ -43,6 +43,7 @@ EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_p
            "pc_plan_set_spectra", "pc_plan_get_spectra", "pc_grad_spectra",
            "pc_plan_set_tracing", "pc_plan_trace_stats", "pc_plan_trace_reset",
            "pc_plan_set_responses", "pc_construct_project", "pc_construct_interpolate",
+           "pc_wavelet_transform", "pc_plan_create_meyer",
            "pc_batch_create", "pc_batch_apply", "pc_batch_apply_adjoint", "pc_batch_destroy",
            "pc_status_string", "pc_last_error")
 
@@ -130,6 +131,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_construct_project.restype = ctypes.c_int
     lib.pc_construct_interpolate.argtypes = [i64, ctypes.c_int32, i64, vp, vp, vp, vp, vp, vp]
     lib.pc_construct_interpolate.restype = ctypes.c_int
+    lib.pc_wavelet_transform.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_int32, vp, i64, i64, i64,
+                                         vp, vp, vp]
+    lib.pc_wavelet_transform.restype = ctypes.c_int
+    lib.pc_plan_create_meyer.argtypes = [ctypes.POINTER(vp), i64, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp,
+                                         vp, i64, ctypes.c_uint32, vp]
+    lib.pc_plan_create_meyer.restype = ctypes.c_int
     lib.pc_status_string.argtypes = [ctypes.c_int]
     lib.pc_status_string.restype = ctypes.c_char_p
     lib.pc_last_error.argtypes = []
@@ -278,6 +285,35 @@ class Plan:
                                            ctypes.c_void_p(_stream_ptr(stream, spec.device)))
         _check(self._lib, st, "pc_plan_set_spectra")
 
+    @classmethod
+    def from_meyer(cls, n, levels, lowpass, lam, mu, c, batch=1, stream=None, gradients=False,
+                   product_convolution=False):
+        """Plan of Meyer's representation (section 4.6) from kept wavelet
+        coefficients c[i] = c_{lam[i], mu[i]}; terms are the distinct mu in
+        increasing order (see pc_plan_create_meyer)."""
+        self = cls.__new__(cls)
+        self._lib = load_library()
+        self._handle = ctypes.c_void_p()
+        lp = _f32(lowpass).ravel()
+        lam = np.ascontiguousarray(np.asarray(lam, np.int64))
+        mu = np.ascontiguousarray(np.asarray(mu, np.int64))
+        c = _f32(c).ravel()
+        if not (lam.shape == mu.shape == c.shape) or lam.ndim != 1:
+            raise ValueError("lam, mu and c must be 1D of equal length")
+        flags = (PC_PLAN_GRADIENTS if gradients else 0) | (PC_PLAN_PRODUCT_CONVOLUTION if product_convolution else 0)
+        st = self._lib.pc_plan_create_meyer(ctypes.byref(self._handle), int(n), int(levels), lp.shape[0],
+                                            lp.ctypes.data_as(ctypes.c_void_p), c.shape[0],
+                                            lam.ctypes.data_as(ctypes.c_void_p), mu.ctypes.data_as(ctypes.c_void_p),
+                                            c.ctypes.data_as(ctypes.c_void_p), int(batch), flags,
+                                            ctypes.c_void_p(_stream_ptr(stream)))
+        _check(self._lib, st, "pc_plan_create_meyer")
+        self.m = int(np.unique(mu).shape[0])
+        self.batch = int(batch)
+        self.shape = (int(n),)
+        self.product_convolution = bool(product_convolution)
+        self.desc = None
+        return self
+
     def set_responses(self, h, stream=None):
         """Replace the impulse responses by a float32 CUDA tensor (``m x N`` or
         ``m x N1 x N2``, lag layout); the spectra are recomputed on the device."""
@@ -404,6 +440,29 @@ def construct_interpolate(samples, lags, nodes, windows, stream=None):
                                       ctypes.c_void_p(_stream_ptr(stream, samples.device)))
     _check(lib, st, "pc_construct_interpolate")
     return h
+
+
+def wavelet_transform(x, lowpass, levels, inverse=False, axis=-1, stream=None):
+    """Periodic orthonormal DWT (or its inverse) of a float32 CUDA tensor
+    along ``axis`` (``x`` 1D, or 2D with axis 0 or 1), pyramid order."""
+    import torch
+    lib = load_library()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32) or x.dim() not in (1, 2):
+        raise TypeError("x must be a 1D or 2D float32 CUDA tensor")
+    x = x.contiguous()
+    lp = _f32(lowpass).ravel()
+    if x.dim() == 1:
+        count, n, stride, dist = 1, x.shape[0], 1, x.shape[0]
+    elif axis in (-1, 1):
+        count, n, stride, dist = x.shape[0], x.shape[1], 1, x.shape[1]
+    else:
+        count, n, stride, dist = x.shape[1], x.shape[0], x.shape[1], 1
+    out = torch.empty_like(x)
+    st = lib.pc_wavelet_transform(1 if inverse else 0, n, int(levels), lp.shape[0], lp.ctypes.data_as(ctypes.c_void_p),
+                                  count, stride, dist, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(_stream_ptr(stream, x.device)))
+    _check(lib, st, "pc_wavelet_transform")
+    return out
 
 
 class Batch:

@@ -1165,6 +1165,20 @@ pc_status finish_construct(hipStream_t s, const int* dfail, const char* what) {
   return PC_SUCCESS;
 }
 
+pc_status make_filter(int32_t taps, const float* lowpass, pc::WaveletFilter& f) {
+  if (!lowpass) return fail(PC_ERROR_INVALID_VALUE, "lowpass is NULL");
+  if (taps < 2 || taps > pc::WAVELET_MAX_TAPS || taps % 2)
+    return fail(PC_ERROR_INVALID_VALUE, "taps must be even, in [2, " + std::to_string(pc::WAVELET_MAX_TAPS) + "]");
+  f.taps = taps;
+  for (int k = 0; k < taps; ++k) {
+    f.h[k] = lowpass[k];
+    f.g[k] = (k % 2 ? -1.f : 1.f) * lowpass[taps - 1 - k];
+  }
+  return PC_SUCCESS;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
 }  // namespace
 
 extern "C" {
@@ -1513,6 +1527,89 @@ pc_status pc_construct_interpolate(int64_t n, int32_t m, int64_t rows, const flo
   if (e == hipSuccess) e = pc::launch_row_solve(true, E, perm, m, src, work, rows, dl, n, h, s);
   if (e != hipSuccess) return fail_hip(e, "pc_construct_interpolate launch");
   return finish_construct(s, dfail, "pc_construct_interpolate");
+}
+
+pc_status pc_wavelet_transform(int32_t inverse, int64_t n, int32_t levels, int32_t taps, const float* lowpass,
+                               int64_t count, int64_t stride, int64_t dist, const float* in, float* out,
+                               void* stream) {
+  pc::WaveletFilter f;
+  pc_status st = make_filter(taps, lowpass, f);
+  if (st) return st;
+  if (!is_pow2(n) || n < 2) return fail(PC_ERROR_INVALID_VALUE, "n must be a power of two >= 2");
+  if (levels < 0 || (n >> levels) < 1 || levels > 62) return fail(PC_ERROR_INVALID_VALUE, "levels out of range");
+  if (count < 1 || stride < 1 || dist < 1) return fail(PC_ERROR_INVALID_VALUE, "count, stride, dist must be >= 1");
+  if (!in || !out || in == out) return fail(PC_ERROR_INVALID_VALUE, "null or identical in/out");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallTemps t;
+  float *s1 = nullptr, *s2 = nullptr;
+  if ((st = t.alloc(&s1, (size_t)(count * (n / 2 + 1)))) || (st = t.alloc(&s2, (size_t)(count * (n / 2 + 1)))))
+    return st;
+  hipError_t e = pc::launch_wavelet(inverse != 0, n, levels, f, count, stride, dist, in, out, s1, s2, s);
+  if (e != hipSuccess) return fail_hip(e, "pc_wavelet_transform launch");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "pc_wavelet_transform");
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_create_meyer(pc_plan* out, int64_t n, int32_t levels, int32_t taps, const float* lowpass,
+                               int64_t count, const int64_t* lam, const int64_t* mu, const float* c, int64_t batch,
+                               uint32_t flags, void* stream) {
+  if (!out) return fail(PC_ERROR_INVALID_VALUE, "out is NULL");
+  *out = nullptr;
+  pc::WaveletFilter f;
+  pc_status st = make_filter(taps, lowpass, f);
+  if (st) return st;
+  if (!is_pow2(n)) return fail(PC_ERROR_INVALID_VALUE, "n must be a power of two");
+  if (levels < 0 || levels > 62 || (n >> levels) < 1) return fail(PC_ERROR_INVALID_VALUE, "levels out of range");
+  if (count < 1 || !lam || !mu || !c) return fail(PC_ERROR_INVALID_VALUE, "empty or null coefficient list");
+  std::vector<int64_t> mus(mu, mu + count);
+  for (int64_t i = 0; i < count; ++i)
+    if (lam[i] < 0 || lam[i] >= n || mu[i] < 0 || mu[i] >= n)
+      return fail(PC_ERROR_INVALID_VALUE, "coefficient indices must be in [0, n)");
+  std::sort(mus.begin(), mus.end());
+  mus.erase(std::unique(mus.begin(), mus.end()), mus.end());
+  const int64_t m2 = (int64_t)mus.size();
+  if (m2 > INT32_MAX) return fail(PC_ERROR_INVALID_VALUE, "too many terms");
+  // rows 0..m2-1: unit vectors e_mu (-> windows psi_mu); rows m2..2m2-1: the
+  // coefficient columns c_{., mu} (-> c~_mu), both synthesised on the device
+  std::vector<float> coef((size_t)(2 * m2 * n), 0.f);
+  for (int64_t i = 0; i < m2; ++i) coef[(size_t)(i * n + mus[(size_t)i])] = 1.f;
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t r = std::lower_bound(mus.begin(), mus.end(), mu[i]) - mus.begin();
+    coef[(size_t)((m2 + r) * n + lam[i])] += c[i];
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<float> syn(coef.size());
+  {
+    CallTemps t;
+    float *din = nullptr, *dout = nullptr, *s1 = nullptr, *s2 = nullptr;
+    if ((st = t.upload(&din, coef.data(), coef.size())) || (st = t.alloc(&dout, coef.size())) ||
+        (st = t.alloc(&s1, (size_t)(2 * m2 * (n / 2 + 1)))) || (st = t.alloc(&s2, (size_t)(2 * m2 * (n / 2 + 1)))))
+      return st;
+    hipError_t e = pc::launch_wavelet(true, n, levels, f, 2 * m2, 1, n, din, dout, s1, s2, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(syn.data(), dout, syn.size() * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail_hip(e, "Meyer synthesis");
+  }
+  // responses carry the grid's quadrature weight 1/n
+  const float inv_n = 1.0f / (float)n;
+  for (size_t i = (size_t)(m2 * n); i < syn.size(); ++i) syn[i] *= inv_n;
+  pc_plan_desc d{};
+  d.ndim = 1;
+  d.m = (int32_t)m2;
+  d.n0 = n;
+  d.n1 = 1;
+  d.batch = batch;
+  d.w_format = PC_W_DENSE;
+  d.flags = flags;
+  pc_plan_s* p = nullptr;
+  if ((st = create_plan(d, syn.data(), syn.data() + m2 * n, s, &p))) return st;
+  {
+    std::lock_guard<std::mutex> g(g_registry_mu);
+    g_registry.insert(p);
+  }
+  *out = p;
+  return PC_SUCCESS;
 }
 
 pc_status pc_plan_set_tracing(pc_plan p, int32_t enable) {

@@ -271,4 +271,20 @@ LaunchStatus launch_node_matrix(const float* W, int m, int64_t n, const int64_t*
 LaunchStatus launch_to_double(const float* x, int64_t n, double* y, hipStream_t s);
 LaunchStatus launch_flip(const float* in, float* out, int64_t count, int64_t n0, int64_t n1, hipStream_t s);
 
+// --------------------------------------------------------------------------
+// Periodic orthonormal wavelet transforms (section 4.6)
+// --------------------------------------------------------------------------
+constexpr int WAVELET_MAX_TAPS = 20;
+struct WaveletFilter {
+  int taps;
+  float h[WAVELET_MAX_TAPS];  // lowpass
+  float g[WAVELET_MAX_TAPS];  // highpass g[k] = (-1)^k h[taps - 1 - k]
+};
+// `levels` levels of the periodic DWT (synthesis: its inverse) of `count`
+// vectors of n samples, element i of vector b at b * dist + i * stride (in
+// and out alike); s1, s2: scratch of count * n / 2 floats each
+LaunchStatus launch_wavelet(bool synthesis, int64_t n, int levels, const WaveletFilter& f, int64_t count,
+                            int64_t stride, int64_t dist, const float* in, float* out, float* s1, float* s2,
+                            hipStream_t s);
+
 }  // namespace pc

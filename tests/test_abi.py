@@ -129,3 +129,28 @@ def test_construct_rejects_bad_nodes(lib):
 
 def test_set_responses_on_invalid_plan(lib):
     assert lib.pc_plan_set_responses(None, ctypes.c_void_p(4096), None) == 5
+
+
+@pytest.mark.parametrize("kw", [dict(n=96), dict(n=1), dict(levels=11), dict(levels=-1), dict(taps=3),
+                                dict(taps=22), dict(count=0), dict(stride=0), dict(same=True)])
+def test_wavelet_transform_rejects_bad_arguments(lib, kw):
+    lp = np.ones(kw.get("taps", 4), dtype=np.float32)
+    n = kw.get("n", 1024)
+    a = ctypes.c_void_p(4096)
+    b = a if kw.get("same") else ctypes.c_void_p(8192)
+    st = lib.pc_wavelet_transform(0, n, kw.get("levels", 3), kw.get("taps", 4), lp.ctypes.data_as(ctypes.c_void_p),
+                                  kw.get("count", 1), kw.get("stride", 1), 1024, a, b, None)
+    assert st == 1, lib.pc_last_error()
+
+
+def test_meyer_plan_rejects_bad_coefficients(lib):
+    lp = np.ones(4, dtype=np.float32)
+    out = ctypes.c_void_p()
+    for lam, mu in (([0, 1024], [0, 1]), ([0, 1], [-1, 1])):
+        la = np.asarray(lam, np.int64)
+        mu_ = np.asarray(mu, np.int64)
+        c = np.ones(2, np.float32)
+        st = lib.pc_plan_create_meyer(ctypes.byref(out), 1024, 3, 4, lp.ctypes.data_as(ctypes.c_void_p), 2,
+                                      la.ctypes.data_as(ctypes.c_void_p), mu_.ctypes.data_as(ctypes.c_void_p),
+                                      c.ctypes.data_as(ctypes.c_void_p), 1, 0, None)
+        assert st == 1 and out.value is None
