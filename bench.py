@@ -141,7 +141,11 @@ WORKLOADS = {
               "(no sections)",
     "c2proj": "construction: L2 projection (section 4.2) of the C2 TVIR band (all lags within 15 widths, "
               "65536 positions) onto the 32 cubic B-spline windows, on the device",
+    "c2meyer": "Meyer representation (section 4.6): 1D batch 64 x N=65536, 20000 kept coefficients, 4-tap "
+               "Daubechies wavelets at 11 levels, windows = the 32 coarsest scaling functions, responses "
+               "synthesised on the device; step = H_m u + H_m^* u",
 }
+MEYER_LEVELS = 11
 MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PRODUCT_CONVOLUTION = {"c2pc"}
 # batched instances must be full-grid plans; c5full measures C5 without sections;
@@ -155,6 +159,26 @@ def make_problems(name):
         return [wl.config_c1()]
     if name in ("c2", "c2pc"):
         return [wl.config_c2()]
+    if name == "c2meyer":
+        # the windows (for the algorithmic counts) are the library's own
+        # synthesis of the unit coefficient vectors; the CPU leg rebuilds
+        # windows and responses with the oracle
+        import torch
+        import paper_1604_04374_amd as pcm
+        p = wl.config_c2()
+        n = p.shape[0]
+        lam, mu, c = wl.gen.meyer_coefficients_random(n)
+        lp = np.array([1 + 3 ** 0.5, 3 + 3 ** 0.5, 3 - 3 ** 0.5, 1 - 3 ** 0.5]) / (4 * 2 ** 0.5)  # 4-tap Daubechies
+        mus = np.unique(mu)
+        e = torch.zeros((mus.shape[0], n), dtype=torch.float32, device="cuda")
+        e[torch.arange(mus.shape[0]), torch.from_numpy(mus).cuda()] = 1.0
+        p.w = pcm.wavelet_transform(e, lp, MEYER_LEVELS, inverse=True).cpu().numpy()
+        p.h = None
+        p.m = int(mus.shape[0])
+        p.extra["meyer"] = (lam, mu, c)
+        p.extra["lowpass"] = lp
+        p.name = "c2meyer"
+        return [p]
     if name == "c3":
         return [wl.config_c3()]
     if name == "c4":
@@ -237,8 +261,15 @@ def main():
     counts = {"flops_per_step": 0.0, "bytes_per_step": 0.0, "kernel_flops": {}, "kernel_bytes": {}}
     for p in probs:
         wins = (p.w_rows, p.w_cols) if p.separable else p.w
-        plan = pcm.Plan(wins, p.h, batch=p.batch, product_convolution=args.workload in PRODUCT_CONVOLUTION,
-                        full_grid=args.workload in FULL_GRID)
+        if args.workload == "c2meyer":
+            t0 = time.perf_counter()
+            lam, mu, c = p.extra["meyer"]
+            plan = pcm.Plan.from_meyer(p.shape[0], MEYER_LEVELS, p.extra["lowpass"], lam, mu, c, batch=p.batch)
+            torch.cuda.synchronize()
+            log(f"[bench] Meyer plan: {plan.m} terms synthesised and planned in {time.perf_counter() - t0:.2f} s")
+        else:
+            plan = pcm.Plan(wins, p.h, batch=p.batch, product_convolution=args.workload in PRODUCT_CONVOLUTION,
+                            full_grid=args.workload in FULL_GRID)
         u = torch.from_numpy(p.u).to(dev)
         jobs.append((p, plan, u, torch.empty_like(u), torch.empty_like(u)))
         c = algorithmic_counts(p, plan.info())
@@ -363,8 +394,14 @@ def main():
         for q, _, _, yq, xq in jobs:
             if tc >= args.cpu_seconds and n_sig > 0:
                 break
-            w64 = q.dense_windows()
-            h64 = q.h.astype(np.float64)
+            if args.workload == "c2meyer":
+                from oracle import wavelets as wv
+                lam, mu, c = q.extra["meyer"]
+                _, w64, h64 = wv.meyer_expansion(lam, mu, c.astype(np.float64), q.shape[0],
+                                                 wv.daubechies(2), MEYER_LEVELS)
+            else:
+                w64 = q.dense_windows()
+                h64 = q.h.astype(np.float64)
             y_gpu = yq.cpu().numpy()
             x_gpu = xq.cpu().numpy()
             for b in range(q.batch):

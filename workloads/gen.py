@@ -404,3 +404,16 @@ def tvir_band_torch(n: int, sigma_fn, device, cutoff_sigmas: float = 15.0):
         lam = torch.from_numpy(lam_all[s0:s0 + 1024]).to(device)[:, None]
         out[s0:s0 + 1024] = (torch.exp(-0.5 * (lam / sig_t[None, :]) ** 2) * norm[None, :]).float()
     return out, lags
+
+
+def meyer_coefficients_random(n: int = 65536, n_mu: int = 32, n_lam: int = 4096, count: int = 20000,
+                              seed: int = 6):
+    """A seeded set of kept wavelet coefficients c_{lam, mu} for Meyer's
+    representation: ``mu`` among the first ``n_mu`` basis vectors (the
+    coarsest scaling functions), ``lam`` among the first ``n_lam`` (coarse
+    scales), values N(0, 1) decaying like 1 / (1 + lam / 64)."""
+    rng = np.random.default_rng(seed)
+    lam = rng.integers(0, n_lam, count)
+    mu = rng.integers(0, n_mu, count)
+    c = rng.standard_normal(count) / (1.0 + lam / 64.0)
+    return lam.astype(np.int64), mu.astype(np.int64), c.astype(np.float32)
