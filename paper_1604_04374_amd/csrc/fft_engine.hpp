@@ -216,20 +216,24 @@ constexpr bool sched_ok(int L, int P) {
 
 // LDS word (float2) index with one pad slot per PAD entries: keeps the
 // stride-R writes of the first passes free of bank conflicts.
+// The default period suits the 2D kernels; the four-step 1D kernels use 32
+// (fewer bank conflicts in their 512-thread exchanges, measured).
 #ifndef PC_LDS_PAD
 #define PC_LDS_PAD 16
 #endif
 constexpr int PAD = PC_LDS_PAD;
-constexpr int PAD_SHIFT = PAD == 16 ? 4 : PAD == 32 ? 5 : PAD == 64 ? 6 : 0;
-static_assert(PAD_SHIFT != 0, "PAD is 16, 32 or 64");
-__device__ __forceinline__ int lpad(int i) { return i + (i >> PAD_SHIFT); }
-template <int L>
-constexpr int lds_len() { return L + L / PAD; }
+static_assert(PAD == 16 || PAD == 32, "pad period 16 or 32");
+template <int PW = PAD>
+__device__ __forceinline__ int lpad(int i) {
+  return i + i / PW;  // PW is a power of two: a shift
+}
+template <int L, int PW = PAD>
+constexpr int lds_len() { return L + L / PW; }
 
 // ---------------------------------------------------------------------------
 // the engine
 // ---------------------------------------------------------------------------
-template <int L, int P, bool INV, int S, int Ns, int TW>
+template <int L, int P, bool INV, int S, int Ns, int TW, int PW>
 struct FftPass {
   static constexpr Sched sch = make_sched(L, P);
   static constexpr int R = sch.r[S];
@@ -262,34 +266,34 @@ struct FftPass {
         if (b == 0) __syncthreads();  // previous readers of this LDS region are done
         const int base = (j / Ns) * Ns * R + k;
         // The padded index is base + constant whenever the R outputs stay
-        // inside one PAD-entry row (Ns R divides PAD; base is then a multiple
-        // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of PAD).
-        if constexpr (Ns % PAD == 0) {
-          float2* dst = lds + lpad(base);
+        // inside one PW-entry row (Ns R divides PW; base is then a multiple
+        // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of PW).
+        if constexpr (Ns % PW == 0) {
+          float2* dst = lds + lpad<PW>(base);
 #pragma unroll
-          for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / PAD)] = x[q];
-        } else if constexpr (PAD % (Ns * R) == 0) {
-          float2* dst = lds + lpad(base);
+          for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / PW)] = x[q];
+        } else if constexpr (PW % (Ns * R) == 0) {
+          float2* dst = lds + lpad<PW>(base);
 #pragma unroll
           for (int q = 0; q < R; ++q) dst[q * Ns] = x[q];
         } else {
 #pragma unroll
-          for (int q = 0; q < R; ++q) lds[lpad(base + q * Ns)] = x[q];
+          for (int q = 0; q < R; ++q) lds[lpad<PW>(base + q * Ns)] = x[q];
         }
       }
     }
     if constexpr (!LAST) {
       __syncthreads();
-      if constexpr (T % PAD == 0) {
-        // (t + T e) / PAD = t / PAD + e T / PAD
-        const float2* src = lds + lpad(t);
+      if constexpr (T % PW == 0) {
+        // (t + T e) / PW = t / PW + e T / PW
+        const float2* src = lds + lpad<PW>(t);
 #pragma unroll
-        for (int e = 0; e < P; ++e) v[e] = src[e * (T + T / PAD)];
+        for (int e = 0; e < P; ++e) v[e] = src[e * (T + T / PW)];
       } else {
 #pragma unroll
-        for (int e = 0; e < P; ++e) v[e] = lds[lpad(t + T * e)];
+        for (int e = 0; e < P; ++e) v[e] = lds[lpad<PW>(t + T * e)];
       }
-      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1)>::run(v, lds, tw, t);
+      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW>::run(v, lds, tw, t);
     }
   }
 };
@@ -306,10 +310,10 @@ __device__ __forceinline__ void stage_twiddles(float2* tw_lds, const float2* __r
 // In-place transform of the register array v (see the header comment).
 // Every thread of the workgroup must call it (it contains barriers), even
 // threads whose FFT slot is unused.
-template <int L, int P, bool INV>
+template <int L, int P, bool INV, int PW = PAD>
 __device__ __forceinline__ void fft_wg(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
   static_assert(sched_ok(L, P), "unsupported (L, P)");
-  FftPass<L, P, INV, 0, 1, 0>::run(v, lds, tw, t);
+  FftPass<L, P, INV, 0, 1, 0, PW>::run(v, lds, tw, t);
 }
 
 }  // namespace pc

@@ -235,6 +235,9 @@ LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int6
 // W_R^{j} = twN[j * L].
 // ===========================================================================
 
+// LDS pad period of the four-step kernels' exchanges
+constexpr int FPAD = 32;
+
 template <int L, int R>
 __device__ __forceinline__ float2 unit_root_R(const float2* __restrict__ twN, int j) {
   return twN[(j % R) * L];
@@ -345,9 +348,10 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
                                                              const float2* __restrict__ twC,
                                                              const float2* __restrict__ twN) {
   constexpr int T = L / P, N = L * R;
-  __shared__ float2 lds[lds_len<L>()];
-  __shared__ float2 twl[L];
-  stage_twiddles<L>(twl, tw);
+  // one transform per workgroup: the twiddles are read from the (cached)
+  // global table rather than staged, which also leaves room for two
+  // workgroups per CU
+  __shared__ float2 lds[lds_len<L, FPAD>()];
   const int t = threadIdx.x;
   const int f1 = blockIdx.x % R;
   const int64_t idx = blockIdx.x / R;
@@ -381,7 +385,7 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
     }
     v[e] = cmul(a, tc[n2]);
   }
-  fft_wg<L, P, false>(v, lds, twl, t);
+  fft_wg<L, P, false, FPAD>(v, lds, tw, t);
   store_blk<L, P>(out + (idx * R + f1) * L, v, t);
 }
 
@@ -390,7 +394,7 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
 template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__ u, int64_t batch, Large1D p) {
   constexpr int N = L * R;
-  __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 lds[lds_len<L, FPAD>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
@@ -418,11 +422,11 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     // latency overlaps it
     float2 hv[P];
     load_blk<L, P>(p.Hd + ((int64_t)k * R + f1) * L, hv, t);
-    fft_wg<L, P, false>(v, lds, twl, t);
+    fft_wg<L, P, false, FPAD>(v, lds, twl, t);
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
   }
-  fft_wg<L, P, true>(acc, lds, twl, t);
+  fft_wg<L, P, true, FPAD>(acc, lds, twl, t);
   store_blk<L, P>(p.Bws + (pair * R + f1) * L, acc, t);
 }
 
@@ -459,7 +463,7 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
 template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   constexpr int T = L / P;
-  __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 lds[lds_len<L, FPAD>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
@@ -485,7 +489,7 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   // class f1: inverse FFT_L of conj(Hd) . V, back-modulated by W_N^{-f1 d}
   // (chunks after the first also carry W_R^{-f1 chunk}) and summed
   auto step = [&](float2(&vv)[P], int f1) {
-    fft_wg<L, P, true>(vv, lds, twl, t);
+    fft_wg<L, P, true, FPAD>(vv, lds, twl, t);
     float2 rt[P];
     if constexpr (SHORT) {
       load_blk<L, P>(p.cw + ((int64_t)k * R + f1) * L, rt, t);
@@ -537,16 +541,15 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
 // that can cover a sample are listed per tile of 256 samples.
 template <int L, int R>
 __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x, int64_t batch) {
-  constexpr int N = L * R;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t pairs = (batch + 1) / 2;
-  if (gid >= pairs * N) return;
-  const int64_t pair = gid / N;
-  const int n = (int)(gid % N);
+  constexpr int N = L * R, TILES = N / 256;
+  // one workgroup per (pair, tile): the tile's item list is uniform
+  const int64_t pair = blockIdx.x / TILES;
+  const int tile = (int)(blockIdx.x % TILES);
+  const int n = tile * 256 + (int)threadIdx.x;
   const float2* base = p.Pws + pair * p.p_stride;
-  const int tile = n >> 8;
   float2 acc = make_float2(0.f, 0.f);
-  for (int j = p.tile_off[tile]; j < p.tile_off[tile + 1]; ++j) {
+  const int j0 = p.tile_off[tile], j1 = p.tile_off[tile + 1];
+  for (int j = j0; j < j1; ++j) {
     const int it = p.tile_items[j];
     int dd = n - p.item_oc[it];
     if (dd < 0) dd += N;
@@ -620,9 +623,8 @@ static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, in
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int64_t nthr = pairs * (int64_t)L * R;
   TraceScope ts(tr, "ola1d", s);
-  hipLaunchKernelGGL((k_ola1d<L, R>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p, x, batch);
+  hipLaunchKernelGGL((k_ola1d<L, R>), dim3((unsigned)(pairs * (L * R / 256))), dim3(256), 0, s, p, x, batch);
   return hipGetLastError();
 }
 
@@ -832,7 +834,7 @@ template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict__ u, int64_t batch, Large1D p,
                                                         float2* __restrict__ E) {
   constexpr int N = L * R;
-  __shared__ float2 lds[lds_len<L>()];
+  __shared__ float2 lds[lds_len<L, FPAD>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
@@ -859,7 +861,7 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
         fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
       float2 gv[P];
       load_blk<L, P>(p.Vws + (pr * R + f1) * L, gv, t);
-      fft_wg<L, P, false>(v, lds, twl, t);
+      fft_wg<L, P, false, FPAD>(v, lds, twl, t);
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
     }
