@@ -298,6 +298,118 @@ struct FftPass {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Register-resident twiddles.  Every thread's twiddles depend only on its
+// index, so a kernel that runs many transforms of the same length can load
+// them once (tw_reg_count values per thread) and keep them in registers; the
+// passes then read no twiddles from memory.  Same passes, same order, same
+// values as fft_wg.
+// ---------------------------------------------------------------------------
+template <int L, int P>
+constexpr int tw_reg_count() {
+  Sched s = make_sched(L, P);
+  int n = 0, Ns = 1;
+  for (int i = 0; i < s.n; ++i) {
+    if (Ns > 1) n += (P / s.r[i]) * (s.r[i] - 1);
+    Ns *= s.r[i];
+  }
+  return n;
+}
+
+template <int L, int P, int S, int Ns, int TW, int RO>
+struct TwRegLoad {
+  static constexpr Sched sch = make_sched(L, P);
+  static constexpr int R = sch.r[S];
+  static constexpr int B = P / R;
+  static constexpr int T = L / P;
+  __device__ __forceinline__ static void run(float2* twr, const float2* __restrict__ tw, int t) {
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int k = (t + T * b) % Ns;
+#pragma unroll
+        for (int q = 1; q < R; ++q) twr[RO + b * (R - 1) + q - 1] = tw[TW + k * (R - 1) + q - 1];
+      }
+    }
+    if constexpr (S + 1 < sch.n)
+      TwRegLoad<L, P, S + 1, Ns * R, TW + Ns * (R - 1), RO + (Ns > 1 ? B * (R - 1) : 0)>::run(twr, tw, t);
+  }
+};
+
+template <int L, int P, int NT>
+__device__ __forceinline__ void load_tw_reg(float2 (&twr)[NT], const float2* __restrict__ tw, int t) {
+  static_assert(NT == tw_reg_count<L, P>(), "register twiddle count");
+  TwRegLoad<L, P, 0, 1, 0, 0>::run(twr, tw, t);
+}
+
+template <int L, int P, bool INV, int S, int Ns, int RO, int PW>
+struct FftPassReg {
+  static constexpr Sched sch = make_sched(L, P);
+  static constexpr int R = sch.r[S];
+  static constexpr int B = P / R;
+  static constexpr int T = L / P;
+  static constexpr bool LAST = (S == sch.n - 1);
+
+  template <int NTW>
+  __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds, const float2 (&twr)[NTW], int t) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + T * b;
+      const int k = j % Ns;
+      float2 x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = v[b + q * B];
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          float2 ww = twr[RO + b * (R - 1) + q - 1];
+          if (INV) ww.y = -ww.y;
+          x[q] = cmul(x[q], ww);
+        }
+      }
+      dftR<R, INV>(x);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[b + q * B] = x[q];
+      } else {
+        if (b == 0) __syncthreads();  // previous readers of this LDS region are done
+        const int base = (j / Ns) * Ns * R + k;
+        if constexpr (Ns % PW == 0) {
+          float2* dst = lds + lpad<PW>(base);
+#pragma unroll
+          for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / PW)] = x[q];
+        } else if constexpr (PW % (Ns * R) == 0) {
+          float2* dst = lds + lpad<PW>(base);
+#pragma unroll
+          for (int q = 0; q < R; ++q) dst[q * Ns] = x[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < R; ++q) lds[lpad<PW>(base + q * Ns)] = x[q];
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+      if constexpr (T % PW == 0) {
+        const float2* src = lds + lpad<PW>(t);
+#pragma unroll
+        for (int e = 0; e < P; ++e) v[e] = src[e * (T + T / PW)];
+      } else {
+#pragma unroll
+        for (int e = 0; e < P; ++e) v[e] = lds[lpad<PW>(t + T * e)];
+      }
+      FftPassReg<L, P, INV, S + 1, Ns * R, RO + (Ns > 1 ? B * (R - 1) : 0), PW>::run(v, lds, twr, t);
+    }
+  }
+};
+
+template <int L, int P, bool INV, int PW = PAD, int NT>
+__device__ __forceinline__ void fft_wg_reg(float2 (&v)[P], float2* lds, const float2 (&twr)[NT], int t) {
+  static_assert(sched_ok(L, P), "unsupported (L, P)");
+  static_assert(NT == tw_reg_count<L, P>(), "register twiddle count");
+  FftPassReg<L, P, INV, 0, 1, 0, PW>::run(v, lds, twr, t);
+}
+
 // Copy an engine twiddle table (L entries) into LDS.  Every thread of the
 // workgroup calls it; it ends with a barrier.  Reading twiddles from LDS
 // keeps the per-pass global-memory round trips off the transform.

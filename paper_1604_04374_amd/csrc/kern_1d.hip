@@ -395,9 +395,10 @@ template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__ u, int64_t batch, Large1D p) {
   constexpr int N = L * R;
   __shared__ float2 lds[lds_len<L, FPAD>()];
-  __shared__ float2 twl[L];
-  stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
+  // the thread's twiddles stay in registers for all m + 1 transforms
+  float2 twr[tw_reg_count<L, P>()];
+  load_tw_reg<L, P>(twr, p.tw, t);
   const int f1 = blockIdx.x % R;
   const int64_t pair = blockIdx.x / R;
   const float* xa = u + 2 * pair * N;
@@ -422,11 +423,11 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     // latency overlaps it
     float2 hv[P];
     load_blk<L, P>(p.Hd + ((int64_t)k * R + f1) * L, hv, t);
-    fft_wg<L, P, false, FPAD>(v, lds, twl, t);
+    fft_wg_reg<L, P, false, FPAD>(v, lds, twr, t);
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
   }
-  fft_wg<L, P, true, FPAD>(acc, lds, twl, t);
+  fft_wg_reg<L, P, true, FPAD>(acc, lds, twr, t);
   store_blk<L, P>(p.Bws + (pair * R + f1) * L, acc, t);
 }
 
