@@ -465,9 +465,10 @@ template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   constexpr int T = L / P;
   __shared__ float2 lds[lds_len<L, FPAD>()];
-  __shared__ float2 twl[L];
-  stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
+  // the thread's twiddles stay in registers for all R transforms
+  float2 twr[tw_reg_count<L, P>()];
+  load_tw_reg<L, P>(twr, p.tw, t);
   const int item = blockIdx.x % p.n_items;
   const int64_t pair = blockIdx.x / p.n_items;
   const int k = p.item_k[item];
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   // class f1: inverse FFT_L of conj(Hd) . V, back-modulated by W_N^{-f1 d}
   // (chunks after the first also carry W_R^{-f1 chunk}) and summed
   auto step = [&](float2(&vv)[P], int f1) {
-    fft_wg<L, P, true, FPAD>(vv, lds, twl, t);
+    fft_wg_reg<L, P, true, FPAD>(vv, lds, twr, t);
     float2 rt[P];
     if constexpr (SHORT) {
       load_blk<L, P>(p.cw + ((int64_t)k * R + f1) * L, rt, t);
@@ -508,17 +509,13 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], cmulc(vv[e], rt[e]));
   };
-  // two register sets: the next class's inputs load during the current
-  // class's transform (R is even)
-  float2 va[P], ha[P], vb[P], hb[P];
-  load(va, ha, 0);
-  for (int f1 = 0; f1 < R; f1 += 2) {
+  // (prefetching the next class into a second register set measured slower
+  // than register-resident twiddles, which need those registers)
+  for (int f1 = 0; f1 < R; ++f1) {
+    float2 va[P], ha[P];
+    load(va, ha, f1);
     prod(va, ha);
-    load(vb, hb, f1 + 1);
     step(va, f1);
-    prod(vb, hb);
-    if (f1 + 2 < R) load(va, ha, f1 + 2);
-    step(vb, f1 + 1);
   }
   float2* out = p.Pws + pair * p.p_stride + p.item_out[item];
   const float sc = 1.0f / (float)(L * R);
@@ -836,9 +833,9 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
                                                         float2* __restrict__ E) {
   constexpr int N = L * R;
   __shared__ float2 lds[lds_len<L, FPAD>()];
-  __shared__ float2 twl[L];
-  stage_twiddles<L>(twl, p.tw);
   const int t = threadIdx.x;
+  float2 twr[tw_reg_count<L, P>()];
+  load_tw_reg<L, P>(twr, p.tw, t);
   const int f1 = blockIdx.x % R;
   const int k = blockIdx.x / R;
   const int S = p.w_len[k];
@@ -862,7 +859,7 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
         fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
       float2 gv[P];
       load_blk<L, P>(p.Vws + (pr * R + f1) * L, gv, t);
-      fft_wg<L, P, false, FPAD>(v, lds, twl, t);
+      fft_wg_reg<L, P, false, FPAD>(v, lds, twr, t);
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
     }
