@@ -48,7 +48,7 @@ def test_c1_forward_adjoint_vs_direct_sums():
 @pytest.mark.parametrize("n,m,deg,batch", [
     (64, 3, 1, 5), (96, 4, 3, 2), (128, 8, 1, 1), (192, 2, 1, 3), (256, 16, 3, 4),
     (384, 5, 3, 1), (512, 8, 1, 7), (768, 4, 1, 2), (1536, 6, 3, 3), (2048, 12, 3, 2),
-    (3072, 3, 1, 1), (4096, 16, 3, 2), (6144, 6, 3, 3), (8192, 8, 3, 2),
+    (3072, 3, 1, 1), (4096, 16, 3, 2), (6144, 6, 3, 3), (8192, 8, 3, 2), (256, 1, 1, 3),
 ])
 def test_1d_small_sizes(n, m, deg, batch):
     p = wl.small_1d(n, m, deg, batch, seed=100 + n, sigma_fn=lambda y: 0.01 + 0.03 * y)
@@ -98,6 +98,8 @@ def test_c2_full_size():
 @pytest.mark.parametrize("n1,n2,m1,m2,kind,batch", [
     (64, 64, 2, 2, "hat", 1), (64, 96, 3, 2, "hat", 2), (192, 128, 3, 2, "tile", 3),
     (128, 384, 2, 4, "hat", 1), (256, 256, 4, 4, "hat", 2), (512, 192, 4, 3, "tile", 1),
+    # the longest transforms along each axis, and a single term
+    (8192, 64, 2, 1, "hat", 1), (64, 8192, 1, 4, "tile", 2), (128, 128, 1, 1, "hat", 2),
 ])
 def test_2d_separable(n1, n2, m1, m2, kind, batch):
     p = wl.small_2d(n1, n2, m1, m2, batch, seed=300 + n1 + n2, kind=kind)
