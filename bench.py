@@ -98,7 +98,7 @@ def algorithmic_counts(p, info):
         kb = {"cols_fwd": B * s_n * 2 * pl_s + spec_bytes, "cols_adj": B * s_n * 2 * pl_s + spec_bytes,
               "cols_fft": B * s_n * 2 * pl_s,
               "rows_fwd": 2 * B * s_n * (img_s + pl_s), "rows_inv": 2 * B * s_n * (img_s + pl_s),
-              "sec_gather": 2 * B * (ntot * 4 + s_n * img_s), "sec_scatter": 2 * B * (s_n * img_s + ntot * 4)}
+              "sec_scatter": 2 * B * (s_n * img_s + ntot * 4)}
         bytes_dir = B * ntot * 4 * 2 + spec_bytes + support_sum * 4
         return {"flops_per_step": 2 * B * per_sig, "bytes_per_step": 2 * bytes_dir, "kernel_flops": kf,
                 "kernel_bytes": kb}

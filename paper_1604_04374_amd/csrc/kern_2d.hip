@@ -72,13 +72,14 @@ constexpr int row_pairs_per_block(int L2) {
 template <int L2>
 __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_rows_fwd(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
-    const float2* __restrict__ tw) {
+    const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L2), T = L2 / P, G = row_pairs_per_block(L2), H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
-  stage_twiddles<L2>(twl, tw);
   const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L2>(twl, tw);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
   const float* x = jb.x ? jb.x : x_arg;
@@ -87,14 +88,28 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
   const int r0 = bm.blk * 2 * G;
   const int r = r0 + 2 * c;
   const int q = bm.q;
-  const float* ra = x + (img * N1 + r) * L2;
+  // rows r and r + 1 of the job's image; columns n2 >= wrap read at n2 - gN2
+  const float *ra, *rb;
+  int wrap = L2;
+  if (jb.gN2 > 0) {
+    int ia = jb.g1 + r;  // g1 < gN1 and r + 1 < N1 <= gN1: one wrap at most
+    if (ia >= jb.gN1) ia -= jb.gN1;
+    const int ib = ia + 1 == jb.gN1 ? 0 : ia + 1;
+    ra = x + (img * jb.gN1 + ia) * jb.gN2 + jb.g2;
+    rb = x + (img * jb.gN1 + ib) * jb.gN2 + jb.g2;
+    wrap = jb.gN2 - jb.g2;
+  } else {
+    ra = x + (img * N1 + r) * L2;
+    rb = ra + L2;
+  }
   float2 v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
+    const int o = n2 < wrap ? n2 : n2 - jb.gN2;
     float wa, wb;
     row_weights(jb.wsrc, jb.mode, q, N1, L2, r, n2, wa, wb);
-    v[e] = make_float2(wa * ra[n2], wb * ra[n2 + L2]);
+    v[e] = make_float2(wa * ra[o], wb * rb[o]);
   }
   float2* my = lds + c * lds_len<L2>();
   fft_wg<L2, P, false>(v, my, twl, t);
@@ -402,7 +417,7 @@ int col_groups_for(int H2, int64_t batch, int nq) {
 }
 
 LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg, float* y_arg, hipStream_t s,
-                        Tracer* tr) {
+                        Tracer* tr, int64_t img_limit) {
   if (nblocks <= 0) return hipSuccess;
   TraceScope ts(tr, kernel_kind_name(ls.kind), s);
   const dim3 grid((unsigned)nblocks), block((unsigned)ls.threads);
@@ -413,7 +428,7 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_rows_fwd<LL>, grid, block, 0, s, rj, ls.bmap, x_arg, ls.tw); \
+    hipLaunchKernelGGL(k_rows_fwd<LL>, grid, block, 0, s, rj, ls.bmap, x_arg, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE

@@ -687,9 +687,10 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   return PC_SUCCESS;
 }
 
-hipError_t launch_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s, pc::Tracer* tr) {
+hipError_t launch_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s, pc::Tracer* tr,
+                      const float* x_arg = nullptr, int64_t img_limit = INT64_MAX) {
   for (const pc::LaunchSet& ls : seq) {
-    hipError_t e = pc::launch_set(ls, ls.blocks, nullptr, nullptr, s, tr);
+    hipError_t e = pc::launch_set(ls, ls.blocks, x_arg, nullptr, s, tr, img_limit);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -729,7 +730,16 @@ struct BatchLists {
   std::vector<pc::LaunchSet> f_rows_in, f_cols, f_rows_out, a_rows_in, a_fft, a_cols, a_rows_out;
 };
 
-pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa) {
+// Section evaluation: the row-forward jobs read the boxes of the call's
+// input in place (origins per instance: window box for apply, output box for
+// the adjoint).
+struct GatherSpec {
+  int N1, N2;
+  const std::vector<pc::SecTerm>* terms;
+};
+
+pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa,
+                      const GatherSpec* gather = nullptr) {
   // group instances by row length (N2) and by column length (N1)
   std::vector<int> n2s, n1s;
   for (pc_plan p : b->plans) {
@@ -755,14 +765,25 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
         const int nq = q.dense ? q.m : q.m2, mode = q.dense ? 2 : 1;
         const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
+        auto gathered = [&](pc::RowJob j) {
+          if (gather) {
+            const pc::SecTerm& t = (*gather->terms)[i];
+            j.x = nullptr;
+            j.gN1 = gather->N1;
+            j.gN2 = gather->N2;
+            j.g1 = c == 0 ? t.gf1 : t.ga1;
+            j.g2 = c == 0 ? t.gf2 : t.ga2;
+          }
+          return j;
+        };
         if (fwd_type(i, c)) {
           pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq);
-          jf.push_back(pc::RowJob{in[i], nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap});
+          jf.push_back(gathered(pc::RowJob{in[i], nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap}));
           pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1);
           jfo.push_back(pc::RowJob{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0});
         } else {
           pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
-          ja.push_back(pc::RowJob{in[i], nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap});
+          ja.push_back(gathered(pc::RowJob{in[i], nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
           pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1);
           jao.push_back(pc::RowJob{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap});
         }
@@ -935,11 +956,12 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
     t.sa2 = t.gf2;
     t.ea1 = (int)sc.p1;
     t.ea2 = (int)sc.p2;
+    // the row-forward pass reads the boxes in place with one wrap per axis
+    if (t.M1 > N1 || t.M2 > N2 || t.gf1 >= N1 || t.gf2 >= N2)
+      return fail(PC_ERROR_UNSUPPORTED, "section larger than the image");
     terms.push_back(t);
-    q.max_m1 = std::max(q.max_m1, t.M1);
     off += cap * sc.M1 * sc.M2;
   }
-  if ((st = p->alloc(&q.Sin, (size_t)off, &p->workspace_bytes))) return st;
   if ((st = p->alloc(&q.Sout, (size_t)off, &p->workspace_bytes))) return st;
   pc::SecTerm* dterms = nullptr;
   if ((st = p->upload(&dterms, terms, s))) return st;
@@ -980,30 +1002,20 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
   b->device = p->device;
   b->plans.assign(p->sec_sub.begin(), p->sec_sub.end());
   b->has_fwd = b->has_adj = true;
-  std::vector<const float*> in;
+  std::vector<const float*> in(terms.size(), nullptr);
   std::vector<float*> outs;
-  for (const pc::SecTerm& t : terms) {
-    in.push_back(q.Sin + t.off);
-    outs.push_back(q.Sout + t.off);
-  }
-  if ((st = build_batch(b, in.data(), outs.data(), outs.data()))) return st;
-  hipStream_t cs = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
-  st = capture(b->fwd_seq, cs, &b->gf, &b->ef);
-  if (!st) st = capture(b->adj_seq, cs, &b->ga, &b->ea);
-  (void)hipStreamDestroy(cs);
-  return st;
+  for (const pc::SecTerm& t : terms) outs.push_back(q.Sout + t.off);
+  const GatherSpec gs{(int)N1, (int)N2, &terms};
+  // the launches take the call's input pointer, so they are not captured
+  b->use_graph = false;
+  return build_batch(b, in.data(), outs.data(), outs.data(), &gs);
 }
 
 hipError_t run_sections(pc_plan p, const float* in, float* out, int64_t batch, bool adjoint, hipStream_t s) {
-  hipError_t e = pc::launch_sec_gather(p->sec, in, adjoint, batch, s, p->tr());
-  if (e != hipSuccess) return e;
   const pc_batch_s* b = p->sec_batch;
-  if (p->tracing)  // kernel by kernel, so that each is timed
-    e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr());
-  else
-    e = hipGraphLaunch(adjoint ? b->ea : b->ef, s);
+  // blocks of images >= batch skip their row pass; the later passes compute
+  // on stale spectra for them, which the overlap-add never reads
+  hipError_t e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr(), in, batch);
   if (e != hipSuccess) return e;
   return pc::launch_sec_scatter(p->sec, out, adjoint, batch, s, p->tr());
 }

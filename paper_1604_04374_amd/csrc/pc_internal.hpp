@@ -130,6 +130,11 @@ struct RowJob {
   const float2* sin;   // row-inverse: input planes [q][img][f2][n1]
   float2* sout;        // row-forward: output planes [q][img][f2][n1]
   int64_t q_stride;    // elements between factor planes
+  // row-forward, section evaluation (gN2 > 0): the job's image img is the
+  // box of image img of the launch's input (gN1 x gN2 samples) whose origin
+  // is (g1, g2), both axes wrapped; needs N1 <= gN1, L2 <= gN2, g1 < gN1,
+  // g2 < gN2
+  int gN1 = 0, gN2 = 0, g1 = 0, g2 = 0;
 };
 
 // One instance of a column pass (column transforms of length N1).
@@ -191,8 +196,10 @@ int col_threads(int L1);
 void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq);
 void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H2, int L1, int nsub);
 const char* kernel_kind_name(int kind);
+// img_limit: row-forward blocks of images >= img_limit return at once (their
+// input need not exist)
 LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg, float* y_arg, hipStream_t s,
-                        Tracer* tr);
+                        Tracer* tr, int64_t img_limit = INT64_MAX);
 // h (m x N1 x N2, lag layout) -> Hs, through the plan's spectra launch sets
 LaunchStatus launch_spec2d(const Plan2D& p, const float* h, hipStream_t s);
 LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s,
@@ -231,9 +238,7 @@ struct SecTerm {
 struct Sec2D {
   int N1, N2, n_sec;
   int64_t cap;
-  int max_m1;                 // largest M1 over the sections
   const SecTerm* terms;       // n_sec entries (device)
-  float* Sin;                 // section inputs (staging)
   float* Sout;                // section outputs (staging)
   // output tiles of SEC_TILE_R x SEC_TILE_C pixels: sections whose output
   // box meets each tile (CSR, section order), forward and adjoint
@@ -244,9 +249,6 @@ struct Sec2D {
   const int* ta_items;
 };
 constexpr int SEC_TILE_R = 8, SEC_TILE_C = 32;
-// staging <- input boxes of the first `batch` images
-LaunchStatus launch_sec_gather(const Sec2D& q, const float* x, bool adjoint, int64_t batch, hipStream_t s,
-                               Tracer* tr);
 // every output pixel of the first `batch` images <- sum of the sections covering it
 LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr);
 
