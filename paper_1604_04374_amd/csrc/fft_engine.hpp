@@ -342,7 +342,7 @@ __device__ __forceinline__ void load_tw_reg(float2 (&twr)[NT], const float2* __r
   TwRegLoad<L, P, 0, 1, 0, 0>::run(twr, tw, t);
 }
 
-template <int L, int P, bool INV, int S, int Ns, int RO, int PW>
+template <int L, int P, bool INV, int S, int Ns, int RO, int PW, bool PP>
 struct FftPassReg {
   static constexpr Sched sch = make_sched(L, P);
   static constexpr int R = sch.r[S];
@@ -351,7 +351,10 @@ struct FftPassReg {
   static constexpr bool LAST = (S == sch.n - 1);
 
   template <int NTW>
-  __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds, const float2 (&twr)[NTW], int t) {
+  __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds0, float2* lds1, const float2 (&twr)[NTW],
+                                             int t) {
+    // exchange S goes through lds0 (S even) or lds1 (S odd, ping-pong only)
+    float2* lds = (PP && (S & 1)) ? lds1 : lds0;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + T * b;
@@ -372,7 +375,9 @@ struct FftPassReg {
 #pragma unroll
         for (int q = 0; q < R; ++q) v[b + q * B] = x[q];
       } else {
-        if (b == 0) __syncthreads();  // previous readers of this LDS region are done
+        // previous readers of this LDS region are done (ping-pong: they
+        // read before the barrier that ended the previous exchange)
+        if (b == 0 && !PP) __syncthreads();
         const int base = (j / Ns) * Ns * R + k;
         if constexpr (Ns % PW == 0) {
           float2* dst = lds + lpad<PW>(base);
@@ -398,7 +403,7 @@ struct FftPassReg {
 #pragma unroll
         for (int e = 0; e < P; ++e) v[e] = lds[lpad<PW>(t + T * e)];
       }
-      FftPassReg<L, P, INV, S + 1, Ns * R, RO + (Ns > 1 ? B * (R - 1) : 0), PW>::run(v, lds, twr, t);
+      FftPassReg<L, P, INV, S + 1, Ns * R, RO + (Ns > 1 ? B * (R - 1) : 0), PW, PP>::run(v, lds0, lds1, twr, t);
     }
   }
 };
@@ -407,7 +412,28 @@ template <int L, int P, bool INV, int PW = PAD, int NT>
 __device__ __forceinline__ void fft_wg_reg(float2 (&v)[P], float2* lds, const float2 (&twr)[NT], int t) {
   static_assert(sched_ok(L, P), "unsupported (L, P)");
   static_assert(NT == tw_reg_count<L, P>(), "register twiddle count");
-  FftPassReg<L, P, INV, 0, 1, 0, PW>::run(v, lds, twr, t);
+  FftPassReg<L, P, INV, 0, 1, 0, PW, false>::run(v, lds, lds, twr, t);
+}
+
+// LDS exchanges of one transform (passes - 1).
+template <int L, int P>
+constexpr int fft_exchanges() {
+  return make_sched(L, P).n - 1;
+}
+
+// Ping-pong form: consecutive exchanges alternate between two LDS buffers,
+// so a pass writes without first waiting for the readers of the exchange
+// before: every thread read that one before it wrote the previous exchange,
+// hence before the barrier that ended it.  The alternation must continue
+// across calls: the caller swaps buf[0] and buf[1] after every call when
+// fft_exchanges<L, P>() is odd.  Costs a second buffer of lds_len entries;
+// pays where the workgroup is the only one on its compute unit.
+template <int L, int P, bool INV, int PW, int NT>
+__device__ __forceinline__ void fft_wg_reg_pp(float2 (&v)[P], float2* const (&buf)[2], const float2 (&twr)[NT],
+                                              int t) {
+  static_assert(sched_ok(L, P), "unsupported (L, P)");
+  static_assert(NT == tw_reg_count<L, P>(), "register twiddle count");
+  FftPassReg<L, P, INV, 0, 1, 0, PW, true>::run(v, buf[0], buf[1], twr, t);
 }
 
 // Copy an engine twiddle table (L entries) into LDS.  Every thread of the

@@ -238,6 +238,38 @@ LaunchStatus launch_adj1d_small(const Small1D& p, const float* v, float* x, int6
 // LDS pad period of the four-step kernels' exchanges
 constexpr int FPAD = 32;
 
+// LDS exchange buffers of the four-step transform kernels.  Workgroups of 512
+// or more threads use two, with ping-pong exchanges (at the register counts of
+// these kernels such a workgroup is alone on its compute unit, so the second
+// buffer costs no occupancy); smaller workgroups use one.
+template <int L, int P>
+constexpr bool fs_pingpong() {
+  return L / P >= 512;
+}
+template <int L, int P>
+constexpr int fs_lds_len() {
+  return (fs_pingpong<L, P>() ? 2 : 1) * lds_len<L, FPAD>();
+}
+template <int L, int P>
+struct FsLds {
+  float2* buf[2];
+  __device__ explicit FsLds(float2* lds) : buf{lds, fs_pingpong<L, P>() ? lds + lds_len<L, FPAD>() : lds} {}
+  // one transform with the thread's register twiddles
+  template <bool INV, int NT>
+  __device__ __forceinline__ void fft(float2 (&v)[P], const float2 (&twr)[NT], int t) {
+    if constexpr (fs_pingpong<L, P>()) {
+      fft_wg_reg_pp<L, P, INV, FPAD>(v, buf, twr, t);
+      if constexpr (fft_exchanges<L, P>() % 2 == 1) {
+        float2* x = buf[0];
+        buf[0] = buf[1];
+        buf[1] = x;
+      }
+    } else {
+      fft_wg_reg<L, P, INV, FPAD>(v, buf[0], twr, t);
+    }
+  }
+};
+
 template <int L, int R>
 __device__ __forceinline__ float2 unit_root_R(const float2* __restrict__ twN, int j) {
   return twN[(j % R) * L];
@@ -394,7 +426,8 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
 template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__ u, int64_t batch, Large1D p) {
   constexpr int N = L * R;
-  __shared__ float2 lds[lds_len<L, FPAD>()];
+  __shared__ float2 lds[fs_lds_len<L, P>()];
+  FsLds<L, P> xl(lds);
   const int t = threadIdx.x;
   // the thread's twiddles stay in registers for all m + 1 transforms
   float2 twr[tw_reg_count<L, P>()];
@@ -423,11 +456,11 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     // latency overlaps it
     float2 hv[P];
     load_blk<L, P>(p.Hd + ((int64_t)k * R + f1) * L, hv, t);
-    fft_wg_reg<L, P, false, FPAD>(v, lds, twr, t);
+    xl.template fft<false>(v, twr, t);
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
   }
-  fft_wg_reg<L, P, true, FPAD>(acc, lds, twr, t);
+  xl.template fft<true>(acc, twr, t);
   store_blk<L, P>(p.Bws + (pair * R + f1) * L, acc, t);
 }
 
@@ -464,7 +497,8 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
 template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   constexpr int T = L / P;
-  __shared__ float2 lds[lds_len<L, FPAD>()];
+  __shared__ float2 lds[fs_lds_len<L, P>()];
+  FsLds<L, P> xl(lds);
   const int t = threadIdx.x;
   // the thread's twiddles stay in registers for all R transforms
   float2 twr[tw_reg_count<L, P>()];
@@ -491,7 +525,7 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   // class f1: inverse FFT_L of conj(Hd) . V, back-modulated by W_N^{-f1 d}
   // (chunks after the first also carry W_R^{-f1 chunk}) and summed
   auto step = [&](float2(&vv)[P], int f1) {
-    fft_wg_reg<L, P, true, FPAD>(vv, lds, twr, t);
+    xl.template fft<true>(vv, twr, t);
     float2 rt[P];
     if constexpr (SHORT) {
       load_blk<L, P>(p.cw + ((int64_t)k * R + f1) * L, rt, t);
@@ -832,7 +866,8 @@ template <int L, int R, int P, bool SHORT>
 __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict__ u, int64_t batch, Large1D p,
                                                         float2* __restrict__ E) {
   constexpr int N = L * R;
-  __shared__ float2 lds[lds_len<L, FPAD>()];
+  __shared__ float2 lds[fs_lds_len<L, P>()];
+  FsLds<L, P> xl(lds);
   const int t = threadIdx.x;
   float2 twr[tw_reg_count<L, P>()];
   load_tw_reg<L, P>(twr, p.tw, t);
@@ -859,7 +894,7 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
         fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
       float2 gv[P];
       load_blk<L, P>(p.Vws + (pr * R + f1) * L, gv, t);
-      fft_wg_reg<L, P, false, FPAD>(v, lds, twr, t);
+      xl.template fft<false>(v, twr, t);
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
     }
