@@ -385,8 +385,11 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
   // workgroups per CU
   __shared__ float2 lds[lds_len<L, FPAD>()];
   const int t = threadIdx.x;
-  const int f1 = blockIdx.x % R;
-  const int64_t idx = blockIdx.x / R;
+  // the R class workgroups of a signal (pair) each read the whole signal:
+  // numbered so that they run on one XCD and the signal is fetched once
+  const int64_t b = xcd_major(blockIdx.x, gridDim.x);
+  const int f1 = (int)(b % R);
+  const int64_t idx = b / R;
   const float* xa;
   const float* xb;
   float sb = 0.f;

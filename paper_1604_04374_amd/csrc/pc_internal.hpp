@@ -27,6 +27,17 @@ constexpr int ffts_per_block(int L) {
 
 bool fft_size_supported(int64_t L);  // 64..8192, 2^a or 3*2^a
 
+// The chip deals workgroups to its 8 XCDs round-robin (workgroup b to XCD
+// b % 8), each XCD with its own L2.  xcd_major renumbers a launch so that
+// every XCD receives one contiguous range of the returned indices (identity
+// when the launch is not a multiple of 8 workgroups): workgroups that read
+// the same data, given neighbouring indices, then share one L2.
+constexpr int XCDS = 8;
+__device__ __forceinline__ int64_t xcd_major(int64_t b, int64_t nblocks) {
+  if (nblocks % XCDS) return b;
+  return (b % XCDS) * (nblocks / XCDS) + b / XCDS;
+}
+
 // Optional per-kernel timing: the launchers bracket every kernel with
 // begin/end (HIP events recorded on the launch stream).
 struct Tracer {
