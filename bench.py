@@ -141,7 +141,7 @@ WORKLOADS = {
               "(no sections)",
     "c2proj": "construction: L2 projection (section 4.2) of the C2 TVIR band (all lags within 15 widths, "
               "65536 positions) onto the 32 cubic B-spline windows, on the device",
-    "c2meyer": "Meyer representation (section 4.6): 1D batch 64 x N=65536, 20000 kept coefficients, 4-tap "
+    "c2meyer": "Meyer representation (section 4.5): 1D batch 64 x N=65536, 20000 kept coefficients, 4-tap "
                "Daubechies wavelets at 11 levels, windows = the 32 coarsest scaling functions, responses "
                "synthesised on the device; step = H_m u + H_m^* u",
 }

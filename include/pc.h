@@ -292,7 +292,7 @@ pc_status pc_construct_interpolate(int64_t n, int32_t m, int64_t rows, const flo
                                    const int64_t* nodes, const float* windows, float* h, void* stream);
 
 /*
- * Meyer's operator representation (section 4.6).  The TVIR is expanded in a
+ * Meyer's operator representation (section 4.5).  The TVIR is expanded in a
  * tensor basis of periodic orthonormal wavelets,
  *   T(x, y) = sum c_{lambda,mu} psi_lambda(x) psi_mu(y),
  * of which a few coefficients are kept; regrouped by mu (the paper's trick

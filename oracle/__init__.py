@@ -17,6 +17,6 @@ Modules
 ``grads``      gradients of ``0.5 ||H_m u - f||^2`` with respect to ``u`` and
                to the half-spectra of the ``h_k``.
 ``wavelets``   periodic orthonormal Daubechies wavelets and Meyer's operator
-               representation (section 4.6).
+               representation (section 4.5).
 """
 from . import expansion, dense, construct, grads, wavelets  # noqa: F401

@@ -1,7 +1,7 @@
 """Periodic orthonormal wavelets and Meyer's operator representation
 (TEST INFRASTRUCTURE; imported only by tests and the bench's CPU baseline).
 
-Section 4.6 ("On Meyer's operator representation") expands the TVIR in the
+Section 4.5 ("On Meyer's operator representation") expands the TVIR in the
 tensor basis psi_lambda (x) psi_mu and keeps m coefficients
 c_{lambda,mu} = <T, psi_lambda (x) psi_mu>; regrouping the sum by mu (the
 paper's trick equation) gives a convolution-product expansion with windows

@@ -288,7 +288,7 @@ class Plan:
     @classmethod
     def from_meyer(cls, n, levels, lowpass, lam, mu, c, batch=1, stream=None, gradients=False,
                    product_convolution=False):
-        """Plan of Meyer's representation (section 4.6) from kept wavelet
+        """Plan of Meyer's representation (section 4.5) from kept wavelet
         coefficients c[i] = c_{lam[i], mu[i]}; terms are the distinct mu in
         increasing order (see pc_plan_create_meyer)."""
         self = cls.__new__(cls)

@@ -1,5 +1,5 @@
 // Periodic orthonormal discrete wavelet transforms for Meyer's operator
-// representation (section 4.6): the TVIR is expanded in a tensor wavelet
+// representation (section 4.5): the TVIR is expanded in a tensor wavelet
 // basis and the expansion is regrouped into windows psi_mu and responses
 // c~_mu = sum_lambda c_{lambda,mu} psi_lambda, which are syntheses (inverse
 // transforms) of coefficient vectors.

@@ -285,7 +285,7 @@ LaunchStatus launch_to_double(const float* x, int64_t n, double* y, hipStream_t 
 LaunchStatus launch_flip(const float* in, float* out, int64_t count, int64_t n0, int64_t n1, hipStream_t s);
 
 // --------------------------------------------------------------------------
-// Periodic orthonormal wavelet transforms (section 4.6)
+// Periodic orthonormal wavelet transforms (section 4.5)
 // --------------------------------------------------------------------------
 constexpr int WAVELET_MAX_TAPS = 20;
 struct WaveletFilter {

@@ -1,5 +1,5 @@
 """Periodic wavelet transforms and Meyer's operator representation (section
-4.6) on the GPU against the FP64 oracle (`oracle.wavelets`, pinned in
+4.5) on the GPU against the FP64 oracle (`oracle.wavelets`, pinned in
 test_oracle_wavelets.py).  Tolerance: rel-L2 <= 1e-5 (FP32 transforms of a
 few taps per level; orthogonal, so nothing amplifies the rounding)."""
 import numpy as np

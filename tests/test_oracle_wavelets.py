@@ -1,5 +1,5 @@
 """Pins of the wavelet oracle and of Meyer's operator representation
-(section 4.6): the published closed form of the 4-tap Daubechies filter, the
+(section 4.5): the published closed form of the 4-tap Daubechies filter, the
 filter identities (sum, orthogonality to even shifts, vanishing moments),
 orthogonality of the DWT matrix, the explicit Haar matrix, perfect
 reconstruction of the TVIR from all its coefficients, Parseval for
