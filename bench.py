@@ -93,10 +93,9 @@ def algorithmic_counts(p, info):
         img_s, pl_s = m1s * m2s * 4, m1s * h2s * 8    # one section image / half-spectrum plane, bytes
         kf = {"rows_fwd": B * s_n * 2 * rowfft, "rows_inv": B * s_n * 2 * rowfft,
               "cols_fwd": B * s_n * (2 * colfft + 8.0 * m1s * h2s),
-              "cols_adj": B * s_n * (colfft + 8.0 * m1s * h2s), "cols_fft": B * s_n * colfft}
+              "cols_adj": B * s_n * (2 * colfft + 8.0 * m1s * h2s)}  # one term: the column pass transforms V itself
         # per step (forward + adjoint); each family runs once or twice per step
         kb = {"cols_fwd": B * s_n * 2 * pl_s + spec_bytes, "cols_adj": B * s_n * 2 * pl_s + spec_bytes,
-              "cols_fft": B * s_n * 2 * pl_s,
               "rows_fwd": 2 * B * s_n * (img_s + pl_s), "rows_inv": 2 * B * s_n * (img_s + pl_s),
               "sec_scatter": 2 * B * (s_n * img_s + ntot * 4)}
         bytes_dir = B * ntot * 4 * 2 + spec_bytes + support_sum * 4

@@ -309,7 +309,8 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
 }
 
 // Adjoint column pass, one (column, q = bm.q) per FFT slot:
-// dst_q[img][f2][:] = sum_k1 a_k1 . colIFFT(conj(H_k) . src[img][f2][:]).
+// dst_q[img][f2][:] = sum_k1 a_k1 . colIFFT(conj(H_k) . src[img][f2][:]),
+// src column-transformed beforehand by k_cols_fft, or here when fft_src.
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
@@ -333,6 +334,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   for (int e = 0; e < P; ++e) vh[e] = jb.src[coff + t + T * e];
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
+  if (jb.fft_src) fft_wg<L1, P, false>(vh, my, twl, t);  // uniform over the workgroup
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
@@ -522,7 +524,7 @@ LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t bat
 
 LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s, Tracer* tr) {
   LaunchStatus e = run(p.adj_rows, batch, v, nullptr, s, tr);
-  if (e == hipSuccess) e = run(p.adj_fft, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess && !p.adj_fused) e = run(p.adj_fft, batch, nullptr, nullptr, s, tr);
   if (e == hipSuccess) e = run(p.adj_cols, batch, nullptr, nullptr, s, tr);
   if (e == hipSuccess) e = run(p.adj_rows_out, batch, nullptr, x, s, tr);
   return e;

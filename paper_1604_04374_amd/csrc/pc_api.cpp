@@ -571,7 +571,11 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
     pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
     if ((st = make_set(p, q.adj_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s))) return st;
   }
+  // a single term needs one column transform of V per column: the adjoint
+  // column pass does it itself
+  q.adj_fused = m == 1;
   pc::ColJob ca{q.Tws, q.RA, nullptr, Hs, q.wrows, plane * cap, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+  ca.fft_src = q.adj_fused ? 1 : 0;
   pc::ColJob cfft{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
   bm.clear();
   pc::append_col_blocks(bm, 0, cap, H2, N1, 1);
@@ -807,10 +811,14 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
           jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
         } else {
-          pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
-          jt.push_back(pc::ColJob{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, q.H2, q.m1, q.m2, dense, 1});
+          if (!q.adj_fused) {
+            pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
+            jt.push_back(pc::ColJob{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, q.H2, q.m1, q.m2, dense, 1});
+          }
           pc::append_col_blocks(ba, (int)ja.size(), cap, q.H2, L1, nq);
-          ja.push_back(pc::ColJob{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+          pc::ColJob j{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1};
+          j.fft_src = q.adj_fused ? 1 : 0;
+          ja.push_back(j);
         }
       }
       if ((st = batch_set(b, bl.f_cols, pc::KK_COLS_FWD, L1, jf, bf, tw))) return st;

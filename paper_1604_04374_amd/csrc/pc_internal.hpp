@@ -158,6 +158,9 @@ struct ColJob {
   int64_t q_stride;    // between factor planes of src (forward) / dst (adjoint)
   int64_t part_stride;
   int H2, m1, m2, dense, ngroups;
+  // adjoint pass of a single-term job: transform src's columns first, in
+  // registers (no separate k_cols_fft pass and plane round trip)
+  int fft_src = 0;
 };
 
 // Block of a table-driven launch: job, image, block within the image,
@@ -193,6 +196,7 @@ struct Plan2D {
   float2* RA;                // nq x batch_cap planes (nq = m2 or m), column-major [f2][n1]
   float2* Tws;               // batch_cap planes
   int col_groups;            // term groups of the forward column pass
+  bool adj_fused;            // single term: adj_cols transforms its input itself (adj_fft unused by the adjoint)
   float2* Part;              // col_groups x batch_cap planes of partial spectra (col_groups > 1)
   LaunchSet fwd_rows, fwd_cols, fwd_sum, fwd_rows_out;
   LaunchSet adj_rows, adj_fft, adj_cols, adj_rows_out;
