@@ -49,6 +49,17 @@ __device__ __forceinline__ void row_weights(const float* __restrict__ wsrc, int 
   }
 }
 
+// The thread index, opaque to the compiler (an empty asm statement that
+// claims to modify it).  Passed to a transform inside a runtime loop, it keeps
+// the transform's per-element LDS addresses from being hoisted out of the
+// loop, where they held up to 64 extra VGPRs for the whole loop and halved
+// the waves per SIMD of these memory-bound passes; recomputing them costs a
+// few integer instructions per iteration.
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // Launches are table-driven: every block reads a BlockRef (job, image,
 // block, factor) and its job's descriptor, so one launch serves every
@@ -194,7 +205,7 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
       }
       v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
     }
-    fft_wg<L2, P, true>(v, my, twl, t);
+    fft_wg<L2, P, true>(v, my, twl, opaque(t));
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       float wa, wb;
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
       for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
 #pragma unroll
       for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], jb.wrows[(int64_t)k1 * L1 + t + T * e]);
-      fft_wg<L1, P, false>(v, my, twl, t);
+      fft_wg<L1, P, false>(v, my, twl, opaque(t));
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
     }
@@ -344,7 +355,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
     float2 g[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], Hk[t + T * e]);
-    fft_wg<L1, P, true>(g, my, twl, t);
+    fft_wg<L1, P, true>(g, my, twl, opaque(t));
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       const float wv = dense ? 1.0f : jb.wrows[(int64_t)k1 * L1 + t + T * e];
