@@ -31,6 +31,26 @@ bool fft_size_supported(int64_t L) {
 // N <= 8192: one workgroup (or one slice of it) per signal pair
 // ===========================================================================
 
+// Small batches (fewer workgroups than compute units) run split: the NF
+// transform slots of a workgroup share one pair and take its terms in turn,
+// and their spectral sums are added in LDS before the slot-0 result is kept.
+// Sum of the slots' acc into slot 0's acc (every thread calls it).
+template <int L, int P, int NF>
+__device__ __forceinline__ void sum_slots(float2 (&acc)[P], float2* lds, int c, int t) {
+  constexpr int T = L / P;
+  __syncthreads();  // every slot's transforms are done with LDS
+#pragma unroll
+  for (int e = 0; e < P; ++e) lds[c * lds_len<L>() + lpad(t + T * e)] = acc[e];
+  __syncthreads();
+  if (c == 0) {
+    for (int sl = 1; sl < NF; ++sl) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], lds[sl * lds_len<L>() + lpad(t + T * e)]);
+    }
+  }
+  // the next transform's first LDS write follows a barrier of its own
+}
+
 // Plan-time spectra H_k = F^* h_k (full complex, natural order).
 template <int L>
 __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_spec1d_full(
@@ -56,14 +76,15 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_spec1d_f
 template <int L>
 __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_small(
     const float* __restrict__ u, float* __restrict__ y, int64_t batch, int m, const float* __restrict__ w,
-    const float2* __restrict__ H, const float2* __restrict__ tw) {
+    const float2* __restrict__ H, const float2* __restrict__ tw, int split) {
   constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);
   __shared__ float2 lds[NF * lds_len<L>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int64_t pair = (int64_t)blockIdx.x * NF + c;
+  const int64_t pair = split ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * NF + c;
   const int64_t sa = 2 * pair, sb = sa + 1;
+  const bool keep = !split || c == 0;
   const bool va = sa < batch, vb = sb < batch;
   float ua[P], ub[P];
 #pragma unroll
@@ -76,12 +97,18 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_sm
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
   float2* my = lds + c * lds_len<L>();
-  for (int k = 0; k < m; ++k) {
+  // every slot makes the same number of transform calls (they hold barriers):
+  // a slot past the last term transforms a valid term with zero weight
+  const int nk = split ? (m + NF - 1) / NF : m;
+  for (int i = 0; i < nk; ++i) {
+    const int kt = split ? c + NF * i : i;
+    const int k = kt < m ? kt : m - 1;
+    const float live = kt < m ? 1.f : 0.f;
     float2 v[P];
     const float* wk = w + (int64_t)k * L;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      const float ww = wk[t + T * e];
+      const float ww = live * wk[t + T * e];
       v[e] = make_float2(ww * ua[e], ww * ub[e]);
     }
     fft_wg<L, P, false>(v, my, twl, t);
@@ -89,13 +116,16 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_sm
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], Hk[t + T * e], v[e]);
   }
+  if (split && NF > 1) sum_slots<L, P, NF>(acc, lds, c, t);
   fft_wg<L, P, true>(acc, my, twl, t);
   const float sc = 1.0f / (float)L;
+  if (keep) {
 #pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int n = t + T * e;
-    if (va) y[sa * L + n] = acc[e].x * sc;
-    if (vb) y[sb * L + n] = acc[e].y * sc;
+    for (int e = 0; e < P; ++e) {
+      const int n = t + T * e;
+      if (va) y[sa * L + n] = acc[e].x * sc;
+      if (vb) y[sb * L + n] = acc[e].y * sc;
+    }
   }
 }
 
@@ -103,14 +133,16 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_sm
 template <int L>
 __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_small(
     const float* __restrict__ vin, float* __restrict__ x, int64_t batch, int m, const float* __restrict__ w,
-    const float2* __restrict__ H, const float2* __restrict__ tw) {
+    const float2* __restrict__ H, const float2* __restrict__ tw, int split) {
   constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);
   __shared__ float2 lds[NF * lds_len<L>()];
   __shared__ float2 twl[L];
   stage_twiddles<L>(twl, tw);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int64_t pair = (int64_t)blockIdx.x * NF + c;
+  // split: every slot transforms the pair's input, then takes its terms in turn
+  const int64_t pair = split ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * NF + c;
   const int64_t sa = 2 * pair, sb = sa + 1;
+  const bool keep = !split || c == 0;
   const bool va = sa < batch, vb = sb < batch;
   float2 V[P];
 #pragma unroll
@@ -123,7 +155,11 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_sm
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  for (int k = 0; k < m; ++k) {
+  const int nk = split ? (m + NF - 1) / NF : m;  // same count in every slot (see the forward)
+  for (int i = 0; i < nk; ++i) {
+    const int kt = split ? c + NF * i : i;
+    const int k = kt < m ? kt : m - 1;
+    const float live = kt < m ? 1.f : 0.f;
     const float2* Hk = H + (int64_t)k * L;
     float2 g[P];
 #pragma unroll
@@ -132,17 +168,20 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_sm
     const float* wk = w + (int64_t)k * L;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      const float ww = wk[t + T * e];
+      const float ww = live * wk[t + T * e];
       acc[e].x = fmaf(ww, g[e].x, acc[e].x);
       acc[e].y = fmaf(ww, g[e].y, acc[e].y);
     }
   }
+  if (split && NF > 1) sum_slots<L, P, NF>(acc, lds, c, t);
   const float sc = 1.0f / (float)L;
+  if (keep) {
 #pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int n = t + T * e;
-    if (va) x[sa * L + n] = acc[e].x * sc;
-    if (vb) x[sb * L + n] = acc[e].y * sc;
+    for (int e = 0; e < P; ++e) {
+      const int n = t + T * e;
+      if (va) x[sa * L + n] = acc[e].x * sc;
+      if (vb) x[sb * L + n] = acc[e].y * sc;
+    }
   }
 }
 
@@ -154,15 +193,20 @@ static LaunchStatus spec1d_full_t(const float* h, float2* H, int m, const float2
   return hipGetLastError();
 }
 
+// split the terms over a workgroup's slots when one pair per slot leaves
+// compute units idle
+static inline bool split_small(int64_t pairs, int NF) { return NF > 1 && (pairs + NF - 1) / NF < 256; }
+
 template <int L>
 static LaunchStatus fwd1d_small_t(const Small1D& p, const float* u, float* y, int64_t batch, hipStream_t s,
                                   Tracer* tr) {
   constexpr int NF = ffts_per_block(L), T = fft_threads(L);
   const int64_t pairs = (batch + 1) / 2;
-  const int64_t blocks = (pairs + NF - 1) / NF;
+  const bool split = split_small(pairs, NF);
+  const int64_t blocks = split ? pairs : (pairs + NF - 1) / NF;
   TraceScope ts(tr, "fwd1d_small", s);
   hipLaunchKernelGGL(k_fwd1d_small<L>, dim3((unsigned)blocks), dim3(NF * T), 0, s, u, y, batch, p.m, p.w, p.H,
-                     p.tw);
+                     p.tw, split ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -171,10 +215,11 @@ static LaunchStatus adj1d_small_t(const Small1D& p, const float* v, float* x, in
                                   Tracer* tr) {
   constexpr int NF = ffts_per_block(L), T = fft_threads(L);
   const int64_t pairs = (batch + 1) / 2;
-  const int64_t blocks = (pairs + NF - 1) / NF;
+  const bool split = split_small(pairs, NF);
+  const int64_t blocks = split ? pairs : (pairs + NF - 1) / NF;
   TraceScope ts(tr, "adj1d_small", s);
   hipLaunchKernelGGL(k_adj1d_small<L>, dim3((unsigned)blocks), dim3(NF * T), 0, s, v, x, batch, p.m, p.w, p.H,
-                     p.tw);
+                     p.tw, split ? 1 : 0);
   return hipGetLastError();
 }
 

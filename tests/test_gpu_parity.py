@@ -49,10 +49,13 @@ def test_c1_forward_adjoint_vs_direct_sums():
     (64, 3, 1, 5), (96, 4, 3, 2), (128, 8, 1, 1), (192, 2, 1, 3), (256, 16, 3, 4),
     (384, 5, 3, 1), (512, 8, 1, 7), (768, 4, 1, 2), (1536, 6, 3, 3), (2048, 12, 3, 2),
     (3072, 3, 1, 1), (4096, 16, 3, 2), (6144, 6, 3, 3), (8192, 8, 3, 2), (256, 1, 1, 3),
+    # enough pairs to fill the chip one pair per transform slot (the small
+    # batches above split each pair's terms over a workgroup's slots)
+    (256, 5, 1, 8200),
 ])
 def test_1d_small_sizes(n, m, deg, batch):
     p = wl.small_1d(n, m, deg, batch, seed=100 + n, sigma_fn=lambda y: 0.01 + 0.03 * y)
-    _check(p, direct=n <= 2048)
+    _check(p, direct=n <= 2048 and batch <= 64)
 
 
 # ---------------------------------------------------------------------------
