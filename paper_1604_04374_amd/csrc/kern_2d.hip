@@ -79,12 +79,15 @@ constexpr int row_pairs_per_block(int L2) {
   return g;
 }
 
+// Row pairs per workgroup of the small-tile variant.
+constexpr int row_pairs_small(int L2) { return row_pairs_per_block(L2) < 2 ? row_pairs_per_block(L2) : 2; }
+
 // Half-spectra of windowed rows, transposed: sout[q][img][f2][n1], f2 < H2.
-template <int L2>
-__global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_rows_fwd(
+template <int L2, int G = row_pairs_per_block(L2)>
+__global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
     const float2* __restrict__ tw, int64_t img_limit) {
-  constexpr int P = points_per_thread(L2), T = L2 / P, G = row_pairs_per_block(L2), H2 = L2 / 2 + 1;
+  constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
@@ -158,11 +161,11 @@ __global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_r
 
 // Real rows from transposed half-spectra:
 // y[img][n1][n2] = scale * sum_{q < nq} w_q . rowIFFT(sin[q][img][:, n1]).
-template <int L2>
-__global__ __launch_bounds__(row_pairs_per_block(L2) * fft_threads(L2)) void k_rows_inv(
+template <int L2, int G = row_pairs_per_block(L2)>
+__global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
     const float2* __restrict__ tw) {
-  constexpr int P = points_per_thread(L2), T = L2 / P, G = row_pairs_per_block(L2), H2 = L2 / 2 + 1;
+  constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
@@ -400,13 +403,15 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
 // ---------------------------------------------------------------------------
 // host side: block maps and launches
 // ---------------------------------------------------------------------------
-int row_block_rows(int L2) { return 2 * row_pairs_per_block(L2); }
+int row_block_rows(int L2, bool small) { return 2 * (small ? row_pairs_small(L2) : row_pairs_per_block(L2)); }
 int col_block_cols(int L1) { return ffts_per_block(L1); }
-int row_threads(int L2) { return row_pairs_per_block(L2) * fft_threads(L2); }
+int row_threads(int L2, bool small) {
+  return (small ? row_pairs_small(L2) : row_pairs_per_block(L2)) * fft_threads(L2);
+}
 int col_threads(int L1) { return ffts_per_block(L1) * fft_threads(L1); }
 
-void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq) {
-  const int nb = N1 / row_block_rows(L2);
+void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq, bool small) {
+  const int nb = N1 / row_block_rows(L2, small);
   for (int64_t img = 0; img < n_img; ++img)
     for (int b = 0; b < nb; ++b)
       for (int q = 0; q < nq; ++q) out.push_back(BlockRef{job, (int)img, b, q});
@@ -441,7 +446,10 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_rows_fwd<LL>, grid, block, 0, s, rj, ls.bmap, x_arg, ls.tw, img_limit); \
+    if (ls.small_rows)  \
+      hipLaunchKernelGGL((k_rows_fwd<LL, row_pairs_small(LL)>), grid, block, 0, s, rj, ls.bmap, x_arg, ls.tw, img_limit); \
+    else  \
+      hipLaunchKernelGGL(k_rows_fwd<LL>, grid, block, 0, s, rj, ls.bmap, x_arg, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -451,7 +459,10 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_rows_inv<LL>, grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+    if (ls.small_rows)  \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL)>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+    else  \
+      hipLaunchKernelGGL(k_rows_inv<LL>, grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE

@@ -467,7 +467,8 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
 
 template <class J>
 pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vector<J>& jobs,
-                   const std::vector<pc::BlockRef>& bm, int64_t per_img, const float2* tw, hipStream_t s) {
+                   const std::vector<pc::BlockRef>& bm, int64_t per_img, const float2* tw, hipStream_t s,
+                   bool small_rows = false) {
   J* dj = nullptr;
   pc::BlockRef* db = nullptr;
   pc_status st = p->upload(&dj, jobs, s);
@@ -476,7 +477,8 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   const bool rows = kind == pc::KK_ROWS_FWD || kind == pc::KK_ROWS_INV;
   ls.kind = kind;
   ls.L = L;
-  ls.threads = rows ? pc::row_threads(L) : pc::col_threads(L);
+  ls.threads = rows ? pc::row_threads(L, small_rows) : pc::col_threads(L);
+  ls.small_rows = rows && small_rows;
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();
@@ -538,14 +540,17 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   // launch tables
   const int mode = dense ? 2 : 1;
   const float scale = 1.0f / ((float)N1 * (float)N2);
-  const int rpi = N1 / pc::row_block_rows(N2);                    // row blocks per image
+  // images too small to fill the chip with the default row tiles (one row
+  // block per compute unit at least) take the small tiles
+  const bool sr = (int64_t)(N1 / pc::row_block_rows(N2)) * cap < 256;
+  const int rpi = N1 / pc::row_block_rows(N2, sr);                 // row blocks per image
   const int cpi = (H2 + pc::col_block_cols(N1) - 1) / pc::col_block_cols(N1);  // column blocks per image
   std::vector<pc::BlockRef> bm;
   {  // forward: rows of b_q . u -> RA
     pc::RowJob j{nullptr, nullptr, q.wcols, mode, N1, 0, 0.f, nullptr, q.RA, plane * cap};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, nq);
-    if ((st = make_set(p, q.fwd_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, (int64_t)rpi * nq, tw2, s)))
+    pc::append_row_blocks(bm, 0, cap, N1, N2, nq, sr);
+    if ((st = make_set(p, q.fwd_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, (int64_t)rpi * nq, tw2, s, sr)))
       return st;
   }
   pc::ColJob cf{q.RA, q.Tws, q.Part, Hs, q.wrows, plane * cap, plane * cap, H2, q.m1, q.m2, dense ? 1 : 0,
@@ -561,15 +566,15 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   {  // forward: rows of T -> y
     pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 1, scale, q.Tws, nullptr, 0};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
-    if ((st = make_set(p, q.fwd_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s)))
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr);
+    if ((st = make_set(p, q.fwd_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr)))
       return st;
   }
   {  // adjoint: rows of v -> Tws
     pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 0, 0.f, nullptr, q.Tws, plane * cap};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
-    if ((st = make_set(p, q.adj_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s))) return st;
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr);
+    if ((st = make_set(p, q.adj_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr))) return st;
   }
   // a single term needs one column transform of V per column: the adjoint
   // column pass does it itself
@@ -587,15 +592,15 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   {  // adjoint: sum_q b_q . rows of Q_q -> x
     pc::RowJob j{nullptr, nullptr, q.wcols, mode, N1, nq, scale, q.RA, nullptr, plane * cap};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, 1);
-    if ((st = make_set(p, q.adj_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s)))
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr);
+    if ((st = make_set(p, q.adj_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr)))
       return st;
   }
   {  // spectra: rows of h_k -> Hs, then columns in place
     pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 0, 0.f, nullptr, Hs, plane * m};
     bm.clear();
-    pc::append_row_blocks(bm, 0, m, N1, N2, 1);
-    if ((st = make_set(p, q.spec_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s))) return st;
+    pc::append_row_blocks(bm, 0, m, N1, N2, 1, sr);
+    if ((st = make_set(p, q.spec_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr))) return st;
     pc::ColJob c{nullptr, Hs, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
     bm.clear();
     pc::append_col_blocks(bm, 0, m, H2, N1, 1);

@@ -181,6 +181,7 @@ struct LaunchSet {
   int64_t blocks = 0;              // blocks of the whole table
   int64_t blocks_per_img = 0;      // single plans: blocks per image (prefix launches)
   const float2* tw = nullptr;      // engine twiddles for L
+  bool small_rows = false;         // row kernels: the small-tile variant (row_block_rows(L, true) rows)
 };
 
 struct Plan2D {
@@ -204,11 +205,14 @@ struct Plan2D {
 };
 
 int col_groups_for(int H2, int64_t batch, int nq);
-int row_block_rows(int L2);
+// Row kernels take 2 G rows per workgroup; the small-tile variant (fewer
+// rows, more workgroups) serves single images too small to fill the chip.
+int row_block_rows(int L2, bool small = false);
 int col_block_cols(int L1);
-int row_threads(int L2);
+int row_threads(int L2, bool small = false);
 int col_threads(int L1);
-void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq);
+void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq,
+                       bool small = false);
 void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H2, int L1, int nsub);
 const char* kernel_kind_name(int kind);
 // img_limit: row-forward blocks of images >= img_limit return at once (their
