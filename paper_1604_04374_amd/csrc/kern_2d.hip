@@ -22,6 +22,9 @@
 //           rows:  x = sum_q b_q . rowIFFT(Q_q) / (N1 N2)
 // With dense (non-separable) windows q runs over the m terms, a = 1 and
 // b_q = w_q.
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "fft_engine.hpp"
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 // src_q is loaded once and reused for all of them).  ngroups == 1: the
 // inverse column transform of the sum is written to dst; otherwise the
 // partial spectrum goes to part[group] for k_cols_sum_inv.
-template <int L1>
+template <int L1, bool LATE>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
@@ -267,14 +270,19 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
     for (int k1 = 0; k1 < nk1; ++k1) {
       const int k = dense ? q : k1 * m2 + q;
       const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
+      // the spectrum is loaded before the transform (its latency hides
+      // behind it) or, LATE, after it (P fewer complex registers live across
+      // the transform, which can buy another wave per SIMD)
       float2 hv[P], v[P];
+      if constexpr (!LATE) {
 #pragma unroll
-      for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
+        for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
+      }
 #pragma unroll
       for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], jb.wrows[(int64_t)k1 * L1 + t + T * e]);
       fft_wg<L1, P, false>(v, my, twl, opaque(t));
 #pragma unroll
-      for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], hv[e], v[e]);
+      for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], LATE ? Hk[t + T * e] : hv[e], v[e]);
     }
   }
   if (ngroups == 1) {
@@ -424,6 +432,45 @@ void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H
       for (int q = 0; q < nsub; ++q) out.push_back(BlockRef{job, (int)img, b, q});
 }
 
+// Late loads pay where the early variant is down to two waves per SIMD and
+// the late one has more (measured: the 1024 and 2048 column passes of single
+// images, 1.6x faster); with three or more waves the early loads' latency
+// hiding is worth more (measured on 256 instances of 128 to 512 columns).
+template <int L1>
+static bool late_pays() {
+  const int threads = col_threads(L1);
+  const int waves = (threads + 63) / 64;
+  int early = 0, late = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&early, k_cols_fwd<L1, false>, threads, 0) != hipSuccess) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&late, k_cols_fwd<L1, true>, threads, 0) != hipSuccess) return false;
+  const int early_per_simd = early * waves / 4, late_per_simd = late * waves / 4;
+  return early_per_simd <= 2 && late_per_simd > early_per_simd;
+}
+
+bool cols_fwd_late(int L1) {
+  static std::mutex mu;
+  static std::map<int, bool> known;
+  std::lock_guard<std::mutex> g(mu);
+  const auto it = known.find(L1);
+  if (it != known.end()) return it->second;
+  bool r = false;
+  if (const char* env = std::getenv("PC_COLS_FWD_LATE")) {  // tuning override: 0 early, 1 late
+    r = std::atoi(env) != 0;
+    known[L1] = r;
+    return r;
+  }
+  switch (L1) {
+#define PC_CASE(LL) \
+  case LL:          \
+    r = late_pays<LL>(); \
+    break;
+    PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+  }
+  known[L1] = r;
+  return r;
+}
+
 int col_groups_for(int H2, int64_t batch, int nq) {
   // split the forward column pass over groups of column factors until about
   // eight column transforms per compute unit are in flight
@@ -472,7 +519,10 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_cols_fwd<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    if (ls.late)    \
+      hipLaunchKernelGGL((k_cols_fwd<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    else            \
+      hipLaunchKernelGGL((k_cols_fwd<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE

@@ -182,6 +182,7 @@ struct LaunchSet {
   int64_t blocks_per_img = 0;      // single plans: blocks per image (prefix launches)
   const float2* tw = nullptr;      // engine twiddles for L
   bool small_rows = false;         // row kernels: the small-tile variant (row_block_rows(L, true) rows)
+  bool late = false;               // forward column kernel: the late-spectrum variant (cols_fwd_late)
 };
 
 struct Plan2D {
@@ -205,6 +206,11 @@ struct Plan2D {
 };
 
 int col_groups_for(int H2, int64_t batch, int nq);
+// Whether the forward column kernel of length L1 runs its late-spectrum
+// variant (spectrum loaded after the transform: fewer registers, no latency
+// hiding): decided once per length from the runtime's occupancy figures for
+// both variants; PC_COLS_FWD_LATE=0/1 overrides it.
+bool cols_fwd_late(int L1);
 // Row kernels take 2 G rows per workgroup; the small-tile variant (fewer
 // rows, more workgroups) serves single images too small to fill the chip.
 int row_block_rows(int L2, bool small = false);
