@@ -15,7 +15,12 @@ The JSON line also carries
     stream) against the chip's vector peak;
   * ``hbm``: algorithmic bytes per step over the step time against 8 TB/s;
   * ``cpu_baseline``: the FP64 oracle (FFT form) timed on the host cores on
-    a bounded sample of the same workload, and its agreement with the GPU.
+    a bounded sample of the same workload, and its agreement with the GPU;
+  * ``cold_ms_per_step``: the median of steps timed one by one, each after a
+    1 GiB write that leaves none of the step's data in L2 or the Infinity
+    Cache (``ms_per_step`` is the warm rate of back-to-back steps);
+  * ``hbm.copy_GBps``: a plain device copy's measured rate, with the HBM
+    fractions also quoted against it (``frac_of_copy``).
 """
 import argparse
 import hashlib
@@ -213,6 +218,26 @@ def read_traffic(kernel, workload, ndim):
     return float(m_b.group(1))
 
 
+def measure_copy_gbps(torch, dev, mib=512, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of
+    a plain torch copy of ``mib`` MiB, best of ``reps``: the attainable HBM
+    rate the fractions are also quoted against."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +248,9 @@ def main():
     ap.add_argument("--no-trace", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS),
                     help="c2 (default) is the reported configuration; the others are extra reports")
+    ap.add_argument("--cold-steps", type=int, default=10,
+                    help="extra steps timed one by one after a 1 GiB write that evicts L2 and the "
+                         "Infinity Cache (reported as cold_ms_per_step; 0 disables)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 5 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -334,6 +362,24 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = samples_per_step / (ms_per_step * 1e-3)
 
+    cold_ms = None
+    if args.cold_steps > 0:
+        # every step starts with caches holding none of its data: a 1 GiB
+        # write (4x the Infinity Cache) on the same stream just before it
+        log(f"[bench] {args.cold_steps} cold steps")
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.cold_steps)]
+        for i, (e0, e1) in enumerate(ev):
+            flush.fill_(float(i))
+            e0.record()
+            step()
+            e1.record()
+        torch.cuda.synchronize()
+        cold_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        del flush
+    copy_gbps = measure_copy_gbps(torch, dev)
+
     roofline = None
     kernels = {}
     if not args.no_trace and step is step_plans:
@@ -370,6 +416,7 @@ def main():
                         "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                         "traffic": read_traffic(name, args.workload, probs[0].ndim),
                         "avg_launch_ms": round(st["avg_ms"], 5), "bytes_per_launch": nbytes,
+                        "frac_of_copy": round(achieved / copy_gbps, 4),
                         "alu_tflops": round(flops / t_s / 1e12, 3)}
     hbm_gbps = counts["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
     if roofline is None and step is not step_plans:
@@ -442,7 +489,9 @@ def main():
                    "batch": B, "shape": list(p.shape), "m": p.m},
         "roofline": roofline,
         "hbm": {"alg_bytes_per_step": counts["bytes_per_step"], "achieved_GBps": round(hbm_gbps, 1),
-                "peak_GBps": HBM_PEAK_GBPS, "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4)},
+                "peak_GBps": HBM_PEAK_GBPS, "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4),
+                "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(hbm_gbps / copy_gbps, 4)},
+        "cold_ms_per_step": None if cold_ms is None else round(cold_ms, 5),
         "alg_tflops": round(counts["flops_per_step"] / (ms_per_step * 1e-3) / 1e12, 3),
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kernels.items()},
         "max_rel_l2_vs_oracle": err,
