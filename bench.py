@@ -436,39 +436,49 @@ def main():
         tc = 0.0
         n_sig = 0
         done_samples = 0
+        passes = 0
         total_sig = sum(q.batch for q in probs)
-        for q, _, _, yq, xq in jobs:
-            if tc >= args.cpu_seconds and n_sig > 0:
-                break
-            if args.workload == "c2meyer":
-                from oracle import wavelets as wv
-                lam, mu, c = q.extra["meyer"]
-                _, w64, h64 = wv.meyer_expansion(lam, mu, c.astype(np.float64), q.shape[0],
-                                                 wv.daubechies(2), MEYER_LEVELS)
-            else:
-                w64 = q.dense_windows()
-                h64 = q.h.astype(np.float64)
-            y_gpu = yq.cpu().numpy()
-            x_gpu = xq.cpu().numpy()
-            for b in range(q.batch):
+        refs = {}
+        # whole passes over the workload until the budget is spent (the first
+        # pass also checks the GPU outputs); a budget shorter than one pass
+        # stops inside it
+        while tc < args.cpu_seconds:
+            for qi, (q, _, _, yq, xq) in enumerate(jobs):
                 if tc >= args.cpu_seconds and n_sig > 0:
                     break
-                uu = q.u[b:b + 1].astype(np.float64)
-                c0 = time.perf_counter()
-                if args.workload in PRODUCT_CONVOLUTION:
-                    ry = ex.apply_pc_fft(uu, w64, h64)
-                    rx = ex.adjoint_pc_fft(uu, w64, h64)
-                else:
-                    ry = ex.apply_fft(uu, w64, h64)
-                    rx = ex.adjoint_fft(uu, w64, h64)
-                tc += time.perf_counter() - c0
-                errs.append(float(np.linalg.norm(y_gpu[b] - ry[0]) / np.linalg.norm(ry[0])))
-                errs.append(float(np.linalg.norm(x_gpu[b] - rx[0]) / np.linalg.norm(rx[0])))
-                n_sig += 1
-                done_samples += 2 * q.n_total
+                if qi not in refs:
+                    if args.workload == "c2meyer":
+                        from oracle import wavelets as wv
+                        lam, mu, c = q.extra["meyer"]
+                        _, w64, h64 = wv.meyer_expansion(lam, mu, c.astype(np.float64), q.shape[0],
+                                                         wv.daubechies(2), MEYER_LEVELS)
+                    else:
+                        w64 = q.dense_windows()
+                        h64 = q.h.astype(np.float64)
+                    refs[qi] = (w64, h64, yq.cpu().numpy(), xq.cpu().numpy())
+                w64, h64, y_gpu, x_gpu = refs[qi]
+                for b in range(q.batch):
+                    if tc >= args.cpu_seconds and n_sig > 0:
+                        break
+                    uu = q.u[b:b + 1].astype(np.float64)
+                    c0 = time.perf_counter()
+                    if args.workload in PRODUCT_CONVOLUTION:
+                        ry = ex.apply_pc_fft(uu, w64, h64)
+                        rx = ex.adjoint_pc_fft(uu, w64, h64)
+                    else:
+                        ry = ex.apply_fft(uu, w64, h64)
+                        rx = ex.adjoint_fft(uu, w64, h64)
+                    tc += time.perf_counter() - c0
+                    if passes == 0:
+                        errs.append(float(np.linalg.norm(y_gpu[b] - ry[0]) / np.linalg.norm(ry[0])))
+                        errs.append(float(np.linalg.norm(x_gpu[b] - rx[0]) / np.linalg.norm(rx[0])))
+                    n_sig += 1
+                    done_samples += 2 * q.n_total
+            passes += 1
         cpu = {"value": round(done_samples / tc, 1), "unit": "samples/s", "cores": ex.workers(),
                "kind": "oracle",
-               "sample": f"{n_sig} of {total_sig} signals, forward + adjoint, float64 FFT form (scipy.fft, "
+               "sample": f"{n_sig} signal evaluations over the workload's {total_sig} signals "
+                         f"({n_sig / total_sig:.2f} passes), forward + adjoint, float64 FFT form (scipy.fft, "
                          f"{ex.workers()} workers), {tc:.1f} s"}
         err = max(errs)
 
