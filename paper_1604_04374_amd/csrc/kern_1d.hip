@@ -289,7 +289,7 @@ constexpr int FPAD = 32;
 // buffer costs no occupancy); smaller workgroups use one.
 template <int L, int P>
 constexpr bool fs_pingpong() {
-  return L / P >= 512;
+  return L / P >= 512 || 2 * lds_len<L, FPAD>() * 8 <= 80 * 1024;
 }
 template <int L, int P>
 constexpr int fs_lds_len() {
@@ -371,27 +371,38 @@ __device__ __forceinline__ uint32_t wrapN(uint32_t n) {
     return min(n, n - N);  // n - N wraps above n when n < N
 }
 
-// a^{f1}[d] = cw_k^{f1}[d] z[o + d] with cw_k^{f1}[d] = w_k[o + d] W_N^{f1 d},
-// for a windowed term whose support [o, o + S) is at most L long (every slot
-// d receives at most one sample; cw is zero beyond S).  All loads are issued
-// before any is used.
-template <int L, int R, int P>
+// a^{f1}[d] = sum_{c < C} cw_k^{f1,c}[d] z[o + c L + d] with
+// cw_k^{f1,c}[d] = w_k[o + c L + d] W_N^{f1 (c L + d)}, for a windowed term
+// whose support [o, o + S) is at most C L long (cw is zero beyond S; C is 1
+// or 2, and C L <= N).  The chunk c of cw starts at cwb + c L.  All loads are
+// issued before any is used.
+template <int L, int R, int P, int C>
 __device__ __forceinline__ void fold_short(float2 (&v)[P], int t, const float* __restrict__ xa,
                                            const float* __restrict__ xb, float sb, int o,
                                            const float2* __restrict__ cwb) {
+  static_assert(C == 1 || C == 2, "one or two chunks");
   constexpr int T = L / P;
   constexpr uint32_t N = (uint32_t)L * R;
-  float ra[P], rb[P];
-  float2 rc[P];
+  float ra[C][P], rb[C][P];
+  float2 rc[C][P];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const uint32_t n = wrapN<N>((uint32_t)o + (uint32_t)(c * L + t + T * e));  // o < N, c L + d < N
+      ra[c][e] = ldu(xa, n);
+      rb[c][e] = ldu(xb, n);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) load_blk<L, P>(cwb + c * L, rc[c], t);
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    const uint32_t n = wrapN<N>((uint32_t)o + (uint32_t)(t + T * e));
-    ra[e] = ldu(xa, n);
-    rb[e] = ldu(xb, n);
-  }
-  load_blk<L, P>(cwb, rc, t);
+    float2 a = cmul(make_float2(ra[0][e], sb * rb[0][e]), rc[0][e]);
 #pragma unroll
-  for (int e = 0; e < P; ++e) v[e] = cmul(make_float2(ra[e], sb * rb[e]), rc[e]);
+    for (int c = 1; c < C; ++c) a = cfma(a, make_float2(ra[c][e], sb * rb[c][e]), rc[c][e]);
+    v[e] = a;
+  }
 }
 
 // Same for supports longer than L: a^{f1}[d] = W_N^{f1 d} sum_c z[o + d + c L] W_R^{f1 c}.
@@ -471,7 +482,9 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
 
 // Forward, class f1 of one signal pair: sum_k Hd_k^{f1} . FFT_L(fold(w_k u)),
 // then the class's inverse FFT_L, stored for the combine step.
-template <int L, int R, int P, bool SHORT>
+// C: chunks of the short-support path (1 or 2; the plan's cw table), 0 for
+// the long-support path.
+template <int L, int R, int P, int C>
 __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__ u, int64_t batch, Large1D p) {
   constexpr int N = L * R;
   __shared__ float2 lds[fs_lds_len<L, P>()];
@@ -496,8 +509,8 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     const float* wc = p.wc + p.w_base[k];
     (void)wc;
     float2 v[P];
-    if constexpr (SHORT)
-      fold_short<L, R, P>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * L);
+    if constexpr (C > 0)
+      fold_short<L, R, P, C>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * C * L);
     else
       fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
     // the spectrum loads are issued before the transform so that their
@@ -537,12 +550,14 @@ __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bw
   }
 }
 
-// Adjoint, one (term, support chunk of at most L samples) item of one signal
-// pair: g = F(conj(H_k) . V) on the chunk, assembled class by class, times
-// the window; stored for the overlap-add.  Short-support plans take the
-// window and the class modulation together from cw (one item per term,
-// chunk 0).
-template <int L, int R, int P, bool SHORT>
+// Adjoint, one item of one signal pair: g = F(conj(H_k) . V) on the item's
+// samples, assembled class by class, times the window; stored for the
+// overlap-add.  Long-support plans (C = 0) have one item per chunk of at most
+// L samples of a term's support.  Short-support plans (C = 1 or 2) have one
+// item per term, whose support is at most C L long: the R class transforms
+// serve all its chunks, and each chunk takes its window and class modulation
+// together from cw.
+template <int L, int R, int P, int C>
 __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   constexpr int T = L / P;
   __shared__ float2 lds[fs_lds_len<L, P>()];
@@ -556,10 +571,13 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   const int k = p.item_k[item];
   const int c0 = p.item_d0[item];
   const int Sc = p.item_len[item];
-  const int chunk = c0 / L;  // chunks start at multiples of L inside the support
-  float2 acc[P];
+  const int chunk = c0 / L;  // long path: chunks start at multiples of L inside the support
+  constexpr int NC = C > 0 ? C : 1;  // accumulators (chunks) per item
+  float2 acc[NC][P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < P; ++e) acc[c][e] = make_float2(0.f, 0.f);
   const float2* Hk = p.Hd + (int64_t)k * R * L;
   const float2* Vp = p.Vws + pair * R * L;
   auto load = [&](float2(&vv)[P], float2(&hh)[P], int f1) {
@@ -574,10 +592,18 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   // (chunks after the first also carry W_R^{-f1 chunk}) and summed
   auto step = [&](float2(&vv)[P], int f1) {
     xl.template fft<true>(vv, twr, t);
-    float2 rt[P];
-    if constexpr (SHORT) {
-      load_blk<L, P>(p.cw + ((int64_t)k * R + f1) * L, rt, t);
+    if constexpr (C > 0) {
+      // chunk c: conj(cw_k^{f1,c}) carries W_N^{-f1 (c L + d)} and the window
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        float2 rt[P];
+        load_blk<L, P>(p.cw + (((int64_t)k * R + f1) * C + c) * L, rt, t);
+        // slots at or beyond Sc accumulate values that are never stored
+#pragma unroll
+        for (int e = 0; e < P; ++e) acc[c][e] = cadd(acc[c][e], cmulc(vv[e], rt[e]));
+      }
     } else {
+      float2 rt[P];
       const float2* tc = p.twC + f1 * L;
 #pragma unroll
       for (int e = 0; e < P; ++e) rt[e] = ldu(tc, (uint32_t)(t + T * e));
@@ -586,10 +612,9 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
 #pragma unroll
         for (int e = 0; e < P; ++e) rt[e] = cmul(rt[e], u);
       }
-    }
-    // slots at or beyond Sc accumulate values that are never stored
 #pragma unroll
-    for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], cmulc(vv[e], rt[e]));
+      for (int e = 0; e < P; ++e) acc[0][e] = cadd(acc[0][e], cmulc(vv[e], rt[e]));
+    }
   };
   // (prefetching the next class into a second register set measured slower
   // than register-resident twiddles, which need those registers)
@@ -601,18 +626,20 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
   }
   float2* out = p.Pws + pair * p.p_stride + p.item_out[item];
   const float sc = 1.0f / (float)(L * R);
-  if constexpr (SHORT) {
+  if constexpr (C > 0) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      const int d = t + T * e;
-      if (d < Sc) out[d] = cscale(acc[e], sc);
-    }
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const int d = c * L + t + T * e;
+        if (d < Sc) out[d] = cscale(acc[c][e], sc);
+      }
   } else {
     const float* wc = p.wc + p.w_base[k] + c0;
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       const int d = t + T * e;
-      if (d < Sc) out[d] = cscale(acc[e], wc[d] * sc);
+      if (d < Sc) out[d] = cscale(acc[0][e], wc[d] * sc);
     }
   }
 }
@@ -643,10 +670,9 @@ __global__ __launch_bounds__(256) void k_ola1d(Large1D p, float* __restrict__ x,
 // (L, R, P) instantiations of the four-step kernels; P (points per thread)
 // is a plan-time choice.
 #define PC_FOR_EACH_LRP(X)                                                          \
-  X(8192, 2, 16) X(8192, 4, 16) X(8192, 8, 16) X(8192, 16, 16) X(8192, 2, 8)      \
-  X(8192, 4, 8) X(8192, 8, 8) X(8192, 16, 8) X(6144, 2, 24) X(6144, 4, 24)        \
-  X(6144, 8, 24) X(6144, 16, 24) X(6144, 2, 12) X(6144, 4, 12) X(6144, 8, 12)     \
-  X(6144, 16, 12)
+  X(8192, 2, 16) X(8192, 4, 16) X(8192, 8, 16) X(8192, 16, 16)                     \
+  X(6144, 2, 24) X(6144, 4, 24) X(6144, 8, 24) X(6144, 16, 24)                     \
+  X(4096, 2, 16) X(4096, 4, 16) X(4096, 8, 16) X(4096, 16, 16)
 
 bool fourstep_variant_supported(int L, int R, int P) {
 #define PC_CASE(LL, RR, PP) \
@@ -672,12 +698,13 @@ static LaunchStatus fwd1d_large_t(const Large1D& p, const float* u, float* y, in
   const int64_t pairs = (batch + 1) / 2;
   {
     TraceScope ts(tr, "fwd1d_large", s);
-    if (p.short_support)
-      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, true>), dim3((unsigned)(pairs * R)), dim3(L / P), 0, s, u, batch,
-                         p);
+    const dim3 grid((unsigned)(pairs * R)), block(L / P);
+    if (p.chunks == 2)
+      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, 2>), grid, block, 0, s, u, batch, p);
+    else if (p.chunks == 1)
+      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, 1>), grid, block, 0, s, u, batch, p);
     else
-      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, false>), dim3((unsigned)(pairs * R)), dim3(L / P), 0, s, u, batch,
-                         p);
+      hipLaunchKernelGGL((k_fwd1d_large<L, R, P, 0>), grid, block, 0, s, u, batch, p);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -696,10 +723,13 @@ static LaunchStatus adj1d_large_t(const Large1D& p, const float* v, float* x, in
   if (e != hipSuccess) return e;
   if (p.n_items > 0) {
     TraceScope ts(tr, "adj1d_large", s);
-    if (p.short_support)
-      hipLaunchKernelGGL((k_adj1d_large<L, R, P, true>), dim3((unsigned)(pairs * p.n_items)), dim3(L / P), 0, s, p);
+    const dim3 grid((unsigned)(pairs * p.n_items)), block(L / P);
+    if (p.chunks == 2)
+      hipLaunchKernelGGL((k_adj1d_large<L, R, P, 2>), grid, block, 0, s, p);
+    else if (p.chunks == 1)
+      hipLaunchKernelGGL((k_adj1d_large<L, R, P, 1>), grid, block, 0, s, p);
     else
-      hipLaunchKernelGGL((k_adj1d_large<L, R, P, false>), dim3((unsigned)(pairs * p.n_items)), dim3(L / P), 0, s, p);
+      hipLaunchKernelGGL((k_adj1d_large<L, R, P, 0>), grid, block, 0, s, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -910,7 +940,7 @@ __global__ __launch_bounds__(256) void k_origin_phase1d(float2* __restrict__ Hd,
 
 // E_k^{f1} = sum over pairs of conj(FFT_L(fold(w_k u))) . Gdec^{f1}, one
 // (term, class) per workgroup.
-template <int L, int R, int P, bool SHORT>
+template <int L, int R, int P, int C>
 __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict__ u, int64_t batch, Large1D p,
                                                         float2* __restrict__ E) {
   constexpr int N = L * R;
@@ -936,8 +966,8 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
       const float* xb = hasb ? xa + N : xa;
       const float sb = hasb ? 1.f : 0.f;
       float2 v[P];
-      if constexpr (SHORT)
-        fold_short<L, R, P>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * L);
+      if constexpr (C > 0)
+        fold_short<L, R, P, C>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * C * L);
       else
         fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
       float2 gv[P];
@@ -1067,12 +1097,13 @@ static LaunchStatus grad1d_large_t(const Large1D& p, const float* u, const float
   if (e != hipSuccess) return e;
   {
     TraceScope ts(tr, "grad1d_large", s);
-    if (p.short_support)
-      hipLaunchKernelGGL((k_grad1d_large<L, R, P, true>), dim3((unsigned)(p.m * R)), dim3(L / P), 0, s, u, batch, p,
-                         E);
+    const dim3 grid((unsigned)(p.m * R)), block(L / P);
+    if (p.chunks == 2)
+      hipLaunchKernelGGL((k_grad1d_large<L, R, P, 2>), grid, block, 0, s, u, batch, p, E);
+    else if (p.chunks == 1)
+      hipLaunchKernelGGL((k_grad1d_large<L, R, P, 1>), grid, block, 0, s, u, batch, p, E);
     else
-      hipLaunchKernelGGL((k_grad1d_large<L, R, P, false>), dim3((unsigned)(p.m * R)), dim3(L / P), 0, s, u, batch, p,
-                         E);
+      hipLaunchKernelGGL((k_grad1d_large<L, R, P, 0>), grid, block, 0, s, u, batch, p, E);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

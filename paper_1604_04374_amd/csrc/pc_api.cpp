@@ -76,14 +76,28 @@ std::vector<float2> unit_roots(int64_t N) {
   return w;
 }
 
-bool large_split(int64_t N, int& L, int& R) {
-  for (int l : {8192, 6144})
+// Inner length L and class count R (N = R L, R in {2, 4, 8, 16}) of a
+// four-step plan whose longest window support is max_support: the shortest L
+// whose windows fit in two chunks of L samples (the short-support kernels;
+// shorter transforms have fewer LDS exchanges, and at L = 4096 two
+// workgroups share a compute unit), else the longest L (long-support path).
+// PC_FOURSTEP_L overrides the choice (tuning).
+bool large_split(int64_t N, int64_t max_support, int& L, int& R) {
+  auto fits = [&](int l) {
     for (int r : {2, 4, 8, 16})
       if ((int64_t)l * r == N) {
         L = l;
         R = r;
         return true;
       }
+    return false;
+  };
+  if (const char* env = std::getenv("PC_FOURSTEP_L"))
+    if (fits(std::atoi(env))) return true;
+  for (int l : {4096, 6144, 8192})
+    if (max_support <= 2 * (int64_t)l && fits(l)) return true;
+  for (int l : {8192, 6144, 4096})
+    if (fits(l)) return true;
   return false;
 }
 
@@ -333,27 +347,31 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   std::vector<int> it_k, it_d0, it_oc, it_len;
   std::vector<int64_t> it_out;
   int64_t pstride = 0;
-  bool short_support = true;
+  int64_t max_support = 0;
   for (int k = 0; k < m; ++k) {
     int64_t o, S;
     circular_support(windows + (size_t)k * N, N, o, S);
     off[k] = (int)o;
     len[k] = (int)S;
-    if (S > L) short_support = false;
+    max_support = std::max(max_support, S);
   }
+  // short supports: windows within one or two chunks of L samples
+  const int chunks = max_support <= L ? 1 : max_support <= 2 * (int64_t)L ? 2 : 0;
   for (int k = 0; k < m; ++k) {
     const float* wk = windows + (size_t)k * N;
     const int64_t o = off[k], S = len[k];
     base[k] = (int64_t)wc.size();
     for (int64_t d = 0; d < S; ++d) wc.push_back(wk[(o + d) % N]);
-    // short-support plans keep every window on L samples (zeros beyond its
-    // support) so that the fold loads every slot unconditionally
-    if (short_support) wc.resize((size_t)base[k] + L, 0.f);
-    for (int64_t c0 = 0; c0 < S; c0 += L) {
+    // short-support plans keep every window on chunks x L samples (zeros
+    // beyond its support) so that the fold loads every slot unconditionally
+    if (chunks > 0) wc.resize((size_t)base[k] + (size_t)chunks * L, 0.f);
+    // adjoint items: the whole support (short), or chunks of L samples (long)
+    const int64_t step = chunks > 0 ? std::max<int64_t>(S, 1) : L;
+    for (int64_t c0 = 0; c0 < S; c0 += step) {
       it_k.push_back(k);
       it_d0.push_back((int)c0);
       it_oc.push_back((int)((o + c0) % N));
-      const int64_t cl = std::min<int64_t>(L, S - c0);
+      const int64_t cl = std::min<int64_t>(step, S - c0);
       it_len.push_back((int)cl);
       it_out.push_back(pstride);
       pstride += cl;
@@ -395,7 +413,7 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
     if (pc::fourstep_variant_supported(L, R, want)) q.P = want;
   }
   q.m = m;
-  q.short_support = short_support;
+  q.chunks = chunks;
   float* dwc = nullptr;
   if ((st = p->upload(&dwc, wc, s, &p->window_bytes))) return st;
   int *doff = nullptr, *dlen = nullptr, *dik = nullptr, *did0 = nullptr, *dioc = nullptr, *dilen = nullptr;
@@ -415,20 +433,23 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   if ((st = p->upload(&tw, engine_twiddles(L, q.P), s))) return st;
   if ((st = p->upload(&twN, unit_roots(N), s))) return st;
   if ((st = p->upload(&dtwC, twC, s))) return st;
-  // short supports: window times class modulation, in the block layout
+  // short supports: window times class modulation per chunk, in the block
+  // layout
   q.cw = nullptr;
-  if (short_support) {
+  if (chunks > 0) {
     const int T = L / q.P;
-    std::vector<float2> cw((size_t)m * N);
+    std::vector<float2> cw((size_t)m * N * chunks);
     for (int k = 0; k < m; ++k)
-      for (int f1 = 0; f1 < R; ++f1) {
-        float2* dst = cw.data() + ((size_t)k * R + f1) * L;
-        for (int d = 0; d < L; ++d) {
-          const double wv = wc[(size_t)base[k] + d];
-          const double a = -2.0 * M_PI * (double)(((int64_t)f1 * d) % N) / (double)N;
-          dst[pc::block_pos(d, T)] = make_float2((float)(wv * std::cos(a)), (float)(wv * std::sin(a)));
+      for (int f1 = 0; f1 < R; ++f1)
+        for (int c = 0; c < chunks; ++c) {
+          float2* dst = cw.data() + (((size_t)k * R + f1) * chunks + c) * L;
+          for (int d = 0; d < L; ++d) {
+            const int64_t dd = (int64_t)c * L + d;
+            const double wv = wc[(size_t)base[k] + dd];
+            const double a = -2.0 * M_PI * (double)(((int64_t)f1 * dd) % N) / (double)N;
+            dst[pc::block_pos(d, T)] = make_float2((float)(wv * std::cos(a)), (float)(wv * std::sin(a)));
+          }
         }
-      }
     float2* dcw = nullptr;
     if ((st = p->upload(&dcw, cw, s, &p->window_bytes))) return st;
     q.cw = dcw;
@@ -1069,9 +1090,17 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
   if (d.ndim == 1) {
     if (d.n1 != 1) return fail(PC_ERROR_INVALID_VALUE, "1D plans need n1 == 1");
     if (d.w_format != PC_W_DENSE) return fail(PC_ERROR_INVALID_VALUE, "1D plans take dense windows");
+    int64_t max_support = 0;
+    if (!pc::fft_size_supported(d.n0) && windows) {
+      for (int64_t k = 0; k < d.m; ++k) {
+        int64_t o = 0, S = 0;
+        circular_support(windows + (size_t)k * d.n0, d.n0, o, S);
+        max_support = std::max(max_support, S);
+      }
+    }
     if (pc::fft_size_supported(d.n0)) {
       path = 0;
-    } else if (large_split(d.n0, L, R)) {
+    } else if (large_split(d.n0, max_support, L, R)) {
       path = 1;
     } else {
       return fail(PC_ERROR_UNSUPPORTED, "1D size " + std::to_string(d.n0) + " is not supported");

@@ -92,17 +92,20 @@ struct Large1D {
   const int* w_len;          // m: support length (0 = empty window)
   const int64_t* w_base;     // m: start of window k inside wc
   const float2* Hd;          // m x R x L, Hd[k][f1][block_pos(f2)] = H_k[f] W_N^{f o_k}, f = f1 + R f2
-  const float2* cw;          // short supports: m x R x L, cw[k][f1][block_pos(d)] = w_k[o_k + d] W_N^{f1 d}
+  const float2* cw;          // short supports: m x R x chunks x L,
+                             // cw[k][f1][c][block_pos(d)] = w_k[o_k + c L + d] W_N^{f1 (c L + d)}
   const float2* tw;          // engine twiddles for L
   const float2* twN;         // exp(-2 i pi j / N), j < N
   const float2* twC;         // class table: twC[f1 * L + n2] = exp(-2 i pi f1 n2 / N)
-  bool short_support;        // every window support is at most L long
-  // adjoint work items: (term, chunk of at most L samples of its support)
+  int chunks;                // short supports: every window support is at most chunks x L long
+                             // (1 or 2); 0: long-support path
+  // adjoint work items: long path, (term, chunk of at most L samples of its
+  // support); short supports, one per term (chunk 0, the whole support)
   int n_items;
   const int* item_k;
   const int* item_d0;        // chunk start inside the term's support
   const int* item_oc;        // chunk origin on the circle
-  const int* item_len;       // chunk length (<= L)
+  const int* item_len;       // item length (<= L, or <= chunks x L on the short-support path)
   const int64_t* item_out;   // offset of the item's samples in a pair's P block
   int64_t p_stride;          // float2 per pair in the P block
   // overlap-add: items that can cover each tile of 256 samples (CSR)
