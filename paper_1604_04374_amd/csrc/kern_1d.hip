@@ -378,7 +378,7 @@ __device__ __forceinline__ uint32_t wrapN(uint32_t n) {
 // issued before any is used.
 template <int L, int R, int P, int C>
 __device__ __forceinline__ void fold_short(float2 (&v)[P], int t, const float* __restrict__ xa,
-                                           const float* __restrict__ xb, float sb, int o,
+                                           const float* __restrict__ xb, int o,
                                            const float2* __restrict__ cwb) {
   static_assert(C == 1 || C == 2, "one or two chunks");
   constexpr int T = L / P;
@@ -398,9 +398,9 @@ __device__ __forceinline__ void fold_short(float2 (&v)[P], int t, const float* _
   for (int c = 0; c < C; ++c) load_blk<L, P>(cwb + c * L, rc[c], t);
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    float2 a = cmul(make_float2(ra[0][e], sb * rb[0][e]), rc[0][e]);
+    float2 a = cmul(make_float2(ra[0][e], rb[0][e]), rc[0][e]);
 #pragma unroll
-    for (int c = 1; c < C; ++c) a = cfma(a, make_float2(ra[c][e], sb * rb[c][e]), rc[c][e]);
+    for (int c = 1; c < C; ++c) a = cfma(a, make_float2(ra[c][e], rb[c][e]), rc[c][e]);
     v[e] = a;
   }
 }
@@ -408,7 +408,7 @@ __device__ __forceinline__ void fold_short(float2 (&v)[P], int t, const float* _
 // Same for supports longer than L: a^{f1}[d] = W_N^{f1 d} sum_c z[o + d + c L] W_R^{f1 c}.
 template <int L, int R, int P>
 __device__ __forceinline__ void fold_long(float2 (&v)[P], int t, int f1, const float* __restrict__ xa,
-                                          const float* __restrict__ xb, float sb, const float* __restrict__ wc,
+                                          const float* __restrict__ xb, const float* __restrict__ wc,
                                           int o, int S, const float2* __restrict__ twC,
                                           const float2* __restrict__ twN) {
   constexpr int T = L / P;
@@ -421,7 +421,7 @@ __device__ __forceinline__ void fold_long(float2 (&v)[P], int t, int f1, const f
     for (int d = d0; d < S; d += L, ++c) {
       const uint32_t n = wrapN<N>((uint32_t)(o + d));
       const float ww = ldu(wc, (uint32_t)d);
-      const float2 z = make_float2(ww * ldu(xa, n), ww * sb * ldu(xb, n));
+      const float2 z = make_float2(ww * ldu(xa, n), ww * ldu(xb, n));
       a = cfma(a, z, unit_root_R<L, R>(twN, f1 * c));
     }
     v[e] = cmul(a, ldu(twC, (uint32_t)(f1 * L + d0)));
@@ -434,7 +434,8 @@ template <int L, int R, int P>
 __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x, int64_t n_sig, bool pairs,
                                                              float2* __restrict__ out, const float2* __restrict__ tw,
                                                              const float2* __restrict__ twC,
-                                                             const float2* __restrict__ twN) {
+                                                             const float2* __restrict__ twN,
+                                                             const float* __restrict__ zeros) {
   constexpr int T = L / P, N = L * R;
   // one transform per workgroup: the twiddles are read from the (cached)
   // global table rather than staged, which also leaves room for two
@@ -446,19 +447,14 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
   const int64_t b = xcd_major(blockIdx.x, gridDim.x);
   const int f1 = (int)(b % R);
   const int64_t idx = b / R;
+  // the imaginary part: the pair's second signal, or N zeros (no pair)
   const float* xa;
-  const float* xb;
-  float sb = 0.f;
+  const float* xb = zeros;
   if (pairs) {
     xa = x + 2 * idx * N;
-    xb = xa;
-    if (2 * idx + 1 < n_sig) {
-      xb = xa + N;
-      sb = 1.f;
-    }
+    if (2 * idx + 1 < n_sig) xb = xa + N;
   } else {
     xa = x + idx * N;
-    xb = xa;
   }
   float2 wr[R];
 #pragma unroll
@@ -471,7 +467,7 @@ __global__ __launch_bounds__(L / P) void k_fold_fft(const float* __restrict__ x,
     float2 a = make_float2(0.f, 0.f);
 #pragma unroll
     for (int n1 = 0; n1 < R; ++n1) {
-      const float2 z = make_float2(xa[n2 + L * n1], sb * xb[n2 + L * n1]);
+      const float2 z = make_float2(xa[n2 + L * n1], xb[n2 + L * n1]);
       a = cfma(a, z, wr[n1]);
     }
     v[e] = cmul(a, tc[n2]);
@@ -496,9 +492,7 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
   const int f1 = blockIdx.x % R;
   const int64_t pair = blockIdx.x / R;
   const float* xa = u + 2 * pair * N;
-  const bool hasb = 2 * pair + 1 < batch;
-  const float* xb = hasb ? xa + N : xa;
-  const float sb = hasb ? 1.f : 0.f;
+  const float* xb = 2 * pair + 1 < batch ? xa + N : p.zeros;  // odd batch: a zero second signal
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
@@ -510,9 +504,9 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
     (void)wc;
     float2 v[P];
     if constexpr (C > 0)
-      fold_short<L, R, P, C>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * C * L);
+      fold_short<L, R, P, C>(v, t, xa, xb, o, p.cw + ((int64_t)k * R + f1) * C * L);
     else
-      fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+      fold_long<L, R, P>(v, t, f1, xa, xb, wc, o, S, p.twC, p.twN);
     // the spectrum loads are issued before the transform so that their
     // latency overlaps it
     float2 hv[P];
@@ -688,7 +682,7 @@ static LaunchStatus fold_fft_t(const Large1D& p, const float* x, int64_t n_sig, 
   const int64_t nb = pairs ? (n_sig + 1) / 2 : n_sig;
   TraceScope ts(tr, "fold_fft", s);
   hipLaunchKernelGGL((k_fold_fft<L, R, P>), dim3((unsigned)(nb * R)), dim3(L / P), 0, s, x, n_sig, pairs, out, p.tw,
-                     p.twC, p.twN);
+                     p.twC, p.twN, p.zeros);
   return hipGetLastError();
 }
 
@@ -962,14 +956,12 @@ __global__ __launch_bounds__(L / P) void k_grad1d_large(const float* __restrict_
   if (S > 0) {
     for (int64_t pr = 0; pr < pairs; ++pr) {
       const float* xa = u + 2 * pr * N;
-      const bool hasb = 2 * pr + 1 < batch;
-      const float* xb = hasb ? xa + N : xa;
-      const float sb = hasb ? 1.f : 0.f;
+      const float* xb = 2 * pr + 1 < batch ? xa + N : p.zeros;
       float2 v[P];
       if constexpr (C > 0)
-        fold_short<L, R, P, C>(v, t, xa, xb, sb, o, p.cw + ((int64_t)k * R + f1) * C * L);
+        fold_short<L, R, P, C>(v, t, xa, xb, o, p.cw + ((int64_t)k * R + f1) * C * L);
       else
-        fold_long<L, R, P>(v, t, f1, xa, xb, sb, wc, o, S, p.twC, p.twN);
+        fold_long<L, R, P>(v, t, f1, xa, xb, wc, o, S, p.twC, p.twN);
       float2 gv[P];
       load_blk<L, P>(p.Vws + (pr * R + f1) * L, gv, t);
       xl.template fft<false>(v, twr, t);

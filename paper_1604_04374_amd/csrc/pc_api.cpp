@@ -461,6 +461,9 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   q.tw = tw;
   q.twN = twN;
   q.twC = dtwC;
+  float* zeros = nullptr;
+  if ((st = p->upload(&zeros, std::vector<float>((size_t)N, 0.f), s, &p->workspace_bytes))) return st;
+  q.zeros = zeros;
   q.n_items = (int)it_k.size();
   q.item_k = dik;
   q.item_d0 = did0;

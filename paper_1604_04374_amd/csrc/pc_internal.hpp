@@ -97,6 +97,7 @@ struct Large1D {
   const float2* tw;          // engine twiddles for L
   const float2* twN;         // exp(-2 i pi j / N), j < N
   const float2* twC;         // class table: twC[f1 * L + n2] = exp(-2 i pi f1 n2 / N)
+  const float* zeros;        // N zeros: the second signal of a pair when there is none
   int chunks;                // short supports: every window support is at most chunks x L long
                              // (1 or 2); 0: long-support path
   // adjoint work items: long path, (term, chunk of at most L samples of its
