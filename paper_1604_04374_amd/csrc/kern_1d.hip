@@ -520,27 +520,38 @@ __global__ __launch_bounds__(L / P) void k_fwd1d_large(const float* __restrict__
 }
 
 // y[n2 + L n1] = (1/N) sum_f1 W_R^{-f1 n1} (W_N^{-f1 n2} b^{f1}[n2]).
+// One thread per 16-byte pair of a block (block_pos: elements n2 = t + T e
+// and n2 + T, e even), so every class block is read with coalesced 16-byte
+// loads.
 template <int L, int R, int P>
 __global__ __launch_bounds__(256) void k_combine1d(const float2* __restrict__ Bws, float* __restrict__ y, int64_t batch,
                                                    const float2* __restrict__ twC) {
-  constexpr int N = L * R;
+  constexpr int N = L * R, T = L / P;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t pairs = (batch + 1) / 2;
-  if (gid >= pairs * L) return;
-  const int64_t pair = gid / L;
-  const int n2 = (int)(gid % L);
-  float2 b[R];
-  const int bp = block_pos(n2, L / P);
+  if (gid >= pairs * (L / 2)) return;
+  const int64_t pair = gid / (L / 2);
+  const int q = (int)(gid % (L / 2));  // float4 index inside a block: h T + t
+  const int h = q / T, t = q % T;
+  const int n2[2] = {t + T * 2 * h, t + T * (2 * h + 1)};
+  float2 b[2][R];
 #pragma unroll
-  for (int f1 = 0; f1 < R; ++f1) b[f1] = cmulc(Bws[(pair * R + f1) * L + bp], twC[f1 * L + n2]);
-  dftR<R, true>(b);
+  for (int f1 = 0; f1 < R; ++f1) {
+    const float4 v = reinterpret_cast<const float4*>(Bws + (pair * R + f1) * L)[q];
+    b[0][f1] = cmulc(make_float2(v.x, v.y), twC[f1 * L + n2[0]]);
+    b[1][f1] = cmulc(make_float2(v.z, v.w), twC[f1 * L + n2[1]]);
+  }
   const float sc = 1.0f / (float)N;
   const int64_t sa = 2 * pair, sb = sa + 1;
 #pragma unroll
-  for (int n1 = 0; n1 < R; ++n1) y[sa * N + n2 + L * n1] = b[n1].x * sc;
-  if (sb < batch) {
+  for (int j = 0; j < 2; ++j) {
+    dftR<R, true>(b[j]);
 #pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) y[sb * N + n2 + L * n1] = b[n1].y * sc;
+    for (int n1 = 0; n1 < R; ++n1) y[sa * N + n2[j] + L * n1] = b[j][n1].x * sc;
+    if (sb < batch) {
+#pragma unroll
+      for (int n1 = 0; n1 < R; ++n1) y[sb * N + n2[j] + L * n1] = b[j][n1].y * sc;
+    }
   }
 }
 
@@ -702,7 +713,7 @@ static LaunchStatus fwd1d_large_t(const Large1D& p, const float* u, float* y, in
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t nthr = pairs * L;
+  const int64_t nthr = pairs * (L / 2);
   TraceScope ts(tr, "combine1d", s);
   hipLaunchKernelGGL((k_combine1d<L, R, P>), dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, p.Bws, y, batch,
                      p.twC);
