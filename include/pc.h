@@ -104,8 +104,11 @@ typedef struct {
 
 /* Supported sizes.
  *   1D:  N in {2^a, 3*2^a : 64 <= N <= 8192} (one workgroup per transform)
- *        or N = R*L with L in {8192, 6144} and R in {2, 4, 8, 16}
- *        (16384 ... 131072; four-step split).
+ *        or N = R*L with L in {4096, 6144, 8192} and R in {2, 4, 8, 16}
+ *        (12288 ... 131072; four-step split).  The plan takes the shortest
+ *        L whose windows' circular supports all fit in 2 L samples (the
+ *        short-support kernels), else the longest L; sizes that are also
+ *        a single-transform length take the one-workgroup path.
  *   2D:  N1, N2 in {2^a, 3*2^a : 64 <= N <= 8192}.
  * Other sizes return PC_ERROR_UNSUPPORTED. */
 
@@ -170,7 +173,8 @@ typedef struct {
                             3: 2D sectioned */
   int32_t fft_inner;     /* 1D: inner transform length L (N for path 0); 2D: N1 (largest M1 if sectioned) */
   int32_t fft_outer;     /* 1D four-step: R = N / L; otherwise 1 (2D: N2, largest M2 if sectioned) */
-  int32_t n_items;       /* 1D four-step: adjoint work items (term, support chunk); sectioned: sections */
+  int32_t n_items;       /* 1D four-step: adjoint work items (one per non-empty term when every support
+                            fits in 2 L, else one per L-sample chunk of each support); sectioned: sections */
   int64_t spectra_bytes; /* device bytes of the stored spectra */
   int64_t window_bytes;  /* device bytes of the stored (compacted) windows */
   int64_t workspace_bytes;

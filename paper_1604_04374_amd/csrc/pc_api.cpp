@@ -1093,17 +1093,16 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
   if (d.ndim == 1) {
     if (d.n1 != 1) return fail(PC_ERROR_INVALID_VALUE, "1D plans need n1 == 1");
     if (d.w_format != PC_W_DENSE) return fail(PC_ERROR_INVALID_VALUE, "1D plans take dense windows");
-    int64_t max_support = 0;
-    if (!pc::fft_size_supported(d.n0) && windows) {
+    if (pc::fft_size_supported(d.n0)) {
+      path = 0;
+    } else if (large_split(d.n0, d.n0, L, R)) {  // a four-step size: now read the supports
+      int64_t max_support = 0;
       for (int64_t k = 0; k < d.m; ++k) {
         int64_t o = 0, S = 0;
         circular_support(windows + (size_t)k * d.n0, d.n0, o, S);
         max_support = std::max(max_support, S);
       }
-    }
-    if (pc::fft_size_supported(d.n0)) {
-      path = 0;
-    } else if (large_split(d.n0, max_support, L, R)) {
+      large_split(d.n0, max_support, L, R);
       path = 1;
     } else {
       return fail(PC_ERROR_UNSUPPORTED, "1D size " + std::to_string(d.n0) + " is not supported");

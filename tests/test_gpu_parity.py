@@ -204,3 +204,22 @@ def test_destroyed_plan_is_rejected():
     lib = pcm.load_library()
     assert lib.pc_destroy(h) == 5
     assert lib.pc_apply(h, None, None, 1, None) == 5
+
+
+@pytest.mark.parametrize("n,m,deg,expect", [
+    # C2: cubic supports of 8192 = 2 x 4096 -> L = 4096, R = 16, one item per term
+    (65536, 32, 3, (4096, 16, 32)),
+    # hat supports of 2 N / m = 4915 <= 6144 -> L = 6144 (the only split), one item per term
+    (12288, 5, 1, (6144, 2, 5)),
+    # cubic supports of 24576 > 2 x 6144 -> long-support path, chunks of L samples
+    (98304, 16, 3, (6144, 16, 16 * 4)),
+])
+def test_fourstep_split_choice(n, m, deg, expect):
+    # the plan takes the shortest inner length whose windows fit in two
+    # chunks (short-support kernels), else the long-support path
+    import paper_1604_04374_amd as pcm
+    p = wl.small_1d(n, m, deg, 1, seed=5, sigma_fn=wl.gen.c2_sigma)
+    with pcm.Plan(plan_args(p), p.h, batch=1) as plan:
+        info = plan.info()
+    assert info["path"] == 1
+    assert (info["fft_inner"], info["fft_outer"], info["n_items"]) == expect
