@@ -65,6 +65,9 @@ def test_1d_small_sizes(n, m, deg, batch):
 @pytest.mark.parametrize("n,m,deg,batch", [
     (16384, 4, 3, 3), (12288, 5, 1, 2), (32768, 16, 3, 2), (24576, 8, 3, 1),
     (49152, 12, 1, 2), (98304, 16, 3, 1), (131072, 32, 3, 1),
+    # C2's split (L = 4096, R = 16, two-chunk windows) with an odd batch: the
+    # last pair's second signal is the plan's zero vector
+    (65536, 32, 3, 3),
 ])
 def test_1d_fourstep_sizes(n, m, deg, batch):
     p = wl.small_1d(n, m, deg, batch, seed=200 + m, sigma_fn=wl.gen.c2_sigma)
