@@ -18,59 +18,88 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // part[split][r][c] = sum over the split's chunk of j of A[r][j] B[c][j].
 // A: rows x K, B: cols x K, both row-major with K contiguous, K % 16 == 0,
-// 16-byte aligned rows.  Workgroup: 4 waves x 16 rows, 32 columns (two
-// 16 x 16 output blocks per wave).  Each lane loads 4 consecutive k of its
-// row (and of its two columns) and feeds them to 4 consecutive MFMA steps,
-// so one 16-k step of the loop covers k0 + 4g + s for lane group g < 4 and
-// step s < 4 on both operands alike.
+// 16-byte aligned rows.  Workgroup: 4 waves x GEMM_WAVE_ROWS rows, 32
+// columns; a wave holds GEMM_WAVE_ROWS / 16 row blocks x 2 column blocks of
+// 16 x 16 outputs, so each 16-byte load of B serves that many row blocks
+// (B, the windows, is re-read by every workgroup; A, the TVIR band, is
+// streamed once).  Each lane loads 4 consecutive k of its rows (and of its
+// two columns) and feeds them to 4 consecutive MFMA steps, so one 16-k step
+// of the loop covers k0 + 4g + s for lane group g < 4 and step s < 4 on both
+// operands alike.
 __global__ __launch_bounds__(256) void k_gemm_nt_f32(const float* __restrict__ A, int64_t rows,
                                                      const float* __restrict__ B, int cols, int64_t K,
                                                      float* __restrict__ part) {
+  constexpr int RT = GEMM_WAVE_ROWS / 16;  // row blocks per wave
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int64_t r = (int64_t)blockIdx.x * GEMM_ROWS + wave * 16 + li;
+  const int64_t r0 = (int64_t)blockIdx.x * GEMM_ROWS + (int64_t)wave * GEMM_WAVE_ROWS;
   const int ca = blockIdx.y * GEMM_COLS + li, cb = ca + 16;
-  const bool rok = r < rows, aok = ca < cols, bok = cb < cols;
+  const bool aok = ca < cols, bok = cb < cols;
   const int64_t k_begin = (int64_t)blockIdx.z * GEMM_CHUNK;
   const int64_t k_end = k_begin + GEMM_CHUNK < K ? k_begin + GEMM_CHUNK : K;
-  const float4* Ar = reinterpret_cast<const float4*>(A + (rok ? r : 0) * K);
-  const float4* Ba = reinterpret_cast<const float4*>(B + (int64_t)(aok ? ca : 0) * K);
-  const float4* Bb = reinterpret_cast<const float4*>(B + (int64_t)(bok ? cb : 0) * K);
   // out-of-range rows and columns read row 0 (valid memory) and are zeroed
   // by a factor, so that every load is one unconditional 16-byte access
-  const float fa = rok ? 1.f : 0.f, fx = aok ? 1.f : 0.f, fy = bok ? 1.f : 0.f;
+  const float4* Ar[RT];
+  float fa[RT];
+#pragma unroll
+  for (int b = 0; b < RT; ++b) {
+    const int64_t r = r0 + 16 * b + li;
+    const bool rok = r < rows;
+    Ar[b] = reinterpret_cast<const float4*>(A + (rok ? r : 0) * K);
+    fa[b] = rok ? 1.f : 0.f;
+  }
+  const float4* Ba = reinterpret_cast<const float4*>(B + (int64_t)(aok ? ca : 0) * K);
+  const float4* Bb = reinterpret_cast<const float4*>(B + (int64_t)(bok ? cb : 0) * K);
+  const float fx = aok ? 1.f : 0.f, fy = bok ? 1.f : 0.f;
   auto scale = [](float4 v, float f) { return make_float4(v.x * f, v.y * f, v.z * f, v.w * f); };
-  floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  floatx4 acc0[RT], acc1[RT];
+#pragma unroll
+  for (int b = 0; b < RT; ++b) {
+    acc0[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    acc1[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
   // operands of step k0 + 16 load while the MFMAs of step k0 issue
   int64_t q = (k_begin >> 2) + g;  // float4 index of k0 + 4g
-  float4 an = Ar[q], xn = Ba[q], yn = Bb[q];
+  float4 an[RT];
+#pragma unroll
+  for (int b = 0; b < RT; ++b) an[b] = Ar[b][q];
+  float4 xn = Ba[q], yn = Bb[q];
   for (int64_t k0 = k_begin; k0 < k_end; k0 += 16) {
-    const float4 a = scale(an, fa), x = scale(xn, fx), y = scale(yn, fy);
+    float4 a[RT];
+#pragma unroll
+    for (int b = 0; b < RT; ++b) a[b] = scale(an[b], fa[b]);
+    const float4 x = scale(xn, fx), y = scale(yn, fy);
     q += 4;
     if (k0 + 16 < k_end) {
-      an = Ar[q];
+#pragma unroll
+      for (int b = 0; b < RT; ++b) an[b] = Ar[b][q];
       xn = Ba[q];
       yn = Bb[q];
     }
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x.x, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, y.x, acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x.y, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, y.y, acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, x.z, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, y.z, acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, x.w, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, y.w, acc1, 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      acc0[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].x, x.x, acc0[b], 0, 0, 0);
+      acc1[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].x, y.x, acc1[b], 0, 0, 0);
+      acc0[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].y, x.y, acc0[b], 0, 0, 0);
+      acc1[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].y, y.y, acc1[b], 0, 0, 0);
+      acc0[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].z, x.z, acc0[b], 0, 0, 0);
+      acc1[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].z, y.z, acc1[b], 0, 0, 0);
+      acc0[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].w, x.w, acc0[b], 0, 0, 0);
+      acc1[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].w, y.w, acc1[b], 0, 0, 0);
+    }
   }
   // output block element (i, j) sits in lane j + 16 (i / 4), item i % 4
   float* P = part + (int64_t)blockIdx.z * rows * cols;
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int64_t row = (int64_t)blockIdx.x * GEMM_ROWS + wave * 16 + 4 * g + it;
-    if (row < rows) {
-      if (aok) P[row * cols + ca] = acc0[it];
-      if (bok) P[row * cols + cb] = acc1[it];
+  for (int b = 0; b < RT; ++b)
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int64_t row = r0 + 16 * b + 4 * g + it;
+      if (row < rows) {
+        if (aok) P[row * cols + ca] = acc0[b][it];
+        if (bok) P[row * cols + cb] = acc1[b][it];
+      }
     }
-  }
 }
 
 // out[i] = sum_s part[s][i] in float64

@@ -285,7 +285,7 @@ LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t 
 // Construction of h_k from a TVIR (section 4.2 projection, section 4.4
 // interpolation)
 // --------------------------------------------------------------------------
-constexpr int GEMM_ROWS = 64, GEMM_COLS = 32, GEMM_CHUNK = 2048;
+constexpr int GEMM_WAVE_ROWS = 64, GEMM_ROWS = 4 * GEMM_WAVE_ROWS, GEMM_COLS = 32, GEMM_CHUNK = 2048;
 constexpr int CONSTRUCT_MAX_M = 128;
 inline int gemm_splits(int64_t K) { return (int)((K + GEMM_CHUNK - 1) / GEMM_CHUNK); }
 // part[split][r][c] = sum over the split's chunk of A[r][j] B[c][j] (FP32 MFMA);
