@@ -286,7 +286,12 @@ pc_status pc_plan_set_responses(pc_plan plan, const float* h, void* stream);
  * chunks of 2048 positions added in float64); the m x m factorisations
  * (Cholesky of the Gram matrix, LU with partial pivoting of the node matrix)
  * and the per-lag solves are float64.  Both calls are synchronous: they
- * return once h is written (they allocate and free their workspace).
+ * return once h is written.  Their workspace (and that of
+ * pc_wavelet_transform and pc_plan_create_meyer) comes from a device scratch
+ * buffer that the library keeps between calls, one per device, grown when a
+ * call needs more (the projection of rows lags needs about
+ * 4 rows m (n / 2048 + 4) bytes) and held until the process ends; calls on
+ * one device that use it run one after another.
  * Errors: INVALID_VALUE (null pointers, sizes or indices out of range,
  * misaligned buffers, a singular Gram or node matrix), OUT_OF_MEMORY, HIP.
  */

@@ -1171,28 +1171,79 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
   return PC_SUCCESS;
 }
 
-// Temporary device buffers of one construction call, freed at return (the
-// call waits for its stream first).
+// Device scratch of the construction and wavelet calls, kept between calls:
+// one grow-only buffer per device (allocating and freeing ~100 MB per call
+// cost more than the solves).  A call holds its device's lock from commit()
+// until it has waited for its stream, so calls on one device run one at a
+// time and never share live scratch.
+struct DeviceScratch {
+  std::mutex mu;
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+DeviceScratch& device_scratch(int device) {
+  static DeviceScratch per_device[64];
+  return per_device[device & 63];
+}
+
+// Temporary device buffers of one call: alloc() and upload() record the
+// requests, commit() carves them out of the device scratch (256-byte
+// aligned) and performs the uploads; the pointers are valid after commit().
 struct CallTemps {
-  std::vector<void*> ptrs;
+  struct Req {
+    void** out;
+    size_t bytes;
+    const void* host;  // upload source, or null
+  };
+  std::vector<Req> reqs;
+  DeviceScratch* sc = nullptr;
+  hipStream_t stream = nullptr;
   ~CallTemps() {
-    for (void* q : ptrs) (void)hipFree(q);
+    if (sc) {
+      (void)hipStreamSynchronize(stream);  // nothing in flight uses the scratch
+      sc->mu.unlock();
+    }
   }
   template <class T>
   pc_status alloc(T** out, size_t count) {
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 256));
-    if (e != hipSuccess) return fail_hip(e, "hipMalloc");
-    ptrs.push_back(q);
-    *out = static_cast<T*>(q);
+    reqs.push_back(Req{reinterpret_cast<void**>(out), count * sizeof(T), nullptr});
     return PC_SUCCESS;
   }
   template <class T>
   pc_status upload(T** out, const T* host, size_t count) {
-    pc_status st = alloc(out, count);
-    if (st) return st;
-    hipError_t e = hipMemcpy(*out, host, count * sizeof(T), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    reqs.push_back(Req{reinterpret_cast<void**>(out), count * sizeof(T), host});
+    return PC_SUCCESS;
+  }
+  pc_status commit(hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(PC_ERROR_UNSUPPORTED, "device index above 63");
+    size_t total = 0;
+    for (const Req& r : reqs) total += (std::max<size_t>(r.bytes, 1) + 255) / 256 * 256;
+    sc = &device_scratch(dev);
+    sc->mu.lock();
+    stream = s;
+    if (total > sc->bytes) {  // the previous holder waited for its stream
+      if (sc->p) (void)hipFree(sc->p);
+      sc->p = nullptr;
+      sc->bytes = 0;
+      e = hipMalloc(&sc->p, total);
+      if (e != hipSuccess) {
+        sc->p = nullptr;
+        return fail_hip(e, "hipMalloc");
+      }
+      sc->bytes = total;
+    }
+    char* base = static_cast<char*>(sc->p);
+    for (const Req& r : reqs) {
+      *r.out = base;
+      if (r.host && r.bytes) {
+        e = hipMemcpy(base, r.host, r.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+      }
+      base += (std::max<size_t>(r.bytes, 1) + 255) / 256 * 256;
+    }
     return PC_SUCCESS;
   }
 };
@@ -1542,7 +1593,8 @@ pc_status pc_construct_project(int64_t n, int32_t m, int64_t rows, const float* 
   int* dfail = nullptr;
   if ((st = t.alloc(&part, (size_t)splits * rows * m)) || (st = t.alloc(&gpart, (size_t)splits * m * m)) ||
       (st = t.alloc(&rhs, (size_t)rows * m)) || (st = t.alloc(&work, (size_t)rows * m)) ||
-      (st = t.alloc(&G, (size_t)m * m)) || (st = t.alloc(&dfail, 1)) || (st = t.upload(&dl, lags, (size_t)rows)))
+      (st = t.alloc(&G, (size_t)m * m)) || (st = t.alloc(&dfail, 1)) || (st = t.upload(&dl, lags, (size_t)rows)) ||
+      (st = t.commit(s)))
     return st;
   hipError_t e = pc::launch_fill_zero(h, (int64_t)m * n, s);
   // right-hand sides W T(x, .)^T for every row, and the Gram matrix W W^T
@@ -1576,7 +1628,7 @@ pc_status pc_construct_interpolate(int64_t n, int32_t m, int64_t rows, const flo
   int *perm = nullptr, *dfail = nullptr;
   if ((st = t.alloc(&src, (size_t)rows * m)) || (st = t.alloc(&work, (size_t)rows * m)) ||
       (st = t.alloc(&E, (size_t)m * m)) || (st = t.alloc(&perm, (size_t)m)) || (st = t.alloc(&dfail, 1)) ||
-      (st = t.upload(&dl, lags, (size_t)rows)) || (st = t.upload(&dn, nodes, (size_t)m)))
+      (st = t.upload(&dl, lags, (size_t)rows)) || (st = t.upload(&dn, nodes, (size_t)m)) || (st = t.commit(s)))
     return st;
   hipError_t e = pc::launch_fill_zero(h, (int64_t)m * n, s);
   if (e == hipSuccess) e = pc::launch_node_matrix(windows, m, n, dn, E, s);
@@ -1600,7 +1652,8 @@ pc_status pc_wavelet_transform(int32_t inverse, int64_t n, int32_t levels, int32
   hipStream_t s = static_cast<hipStream_t>(stream);
   CallTemps t;
   float *s1 = nullptr, *s2 = nullptr;
-  if ((st = t.alloc(&s1, (size_t)(count * (n / 2 + 1)))) || (st = t.alloc(&s2, (size_t)(count * (n / 2 + 1)))))
+  if ((st = t.alloc(&s1, (size_t)(count * (n / 2 + 1)))) || (st = t.alloc(&s2, (size_t)(count * (n / 2 + 1)))) ||
+      (st = t.commit(s)))
     return st;
   hipError_t e = pc::launch_wavelet(inverse != 0, n, levels, f, count, stride, dist, in, out, s1, s2, s);
   if (e != hipSuccess) return fail_hip(e, "pc_wavelet_transform launch");
@@ -1642,7 +1695,8 @@ pc_status pc_plan_create_meyer(pc_plan* out, int64_t n, int32_t levels, int32_t 
     CallTemps t;
     float *din = nullptr, *dout = nullptr, *s1 = nullptr, *s2 = nullptr;
     if ((st = t.upload(&din, coef.data(), coef.size())) || (st = t.alloc(&dout, coef.size())) ||
-        (st = t.alloc(&s1, (size_t)(2 * m2 * (n / 2 + 1)))) || (st = t.alloc(&s2, (size_t)(2 * m2 * (n / 2 + 1)))))
+        (st = t.alloc(&s1, (size_t)(2 * m2 * (n / 2 + 1)))) || (st = t.alloc(&s2, (size_t)(2 * m2 * (n / 2 + 1)))) ||
+        (st = t.commit(s)))
       return st;
     hipError_t e = pc::launch_wavelet(true, n, levels, f, 2 * m2, 1, n, din, dout, s1, s2, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
