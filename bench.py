@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU work budget for the oracle baseline (0 disables it)")
     ap.add_argument("--no-trace", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison runs of c4 (single-plan calls) and c5ad (plain step)")
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS),
                     help="c2 (default) is the reported configuration; the others are extra reports")
     ap.add_argument("--cold-steps", type=int, default=10,
@@ -332,7 +334,8 @@ def main():
         def step_batch():
             batch.apply()
             batch.apply_adjoint()
-        extra["single_plans_ms_per_step"] = round(timed(step_plans, max(args.steps // 4, 2)), 5)
+        if not args.no_compare:
+            extra["single_plans_ms_per_step"] = round(timed(step_plans, max(args.steps // 4, 2)), 5)
         step = step_batch
     elif args.workload == "c5ad":
         from paper_1604_04374_amd.autograd import ExpansionOperator
@@ -346,7 +349,8 @@ def main():
             op.spec.grad = None
             loss = 0.5 * torch.sum((op(u_ad) - f_ad) ** 2)
             loss.backward()
-        extra["plain_ms_per_step"] = round(timed(step_plans, args.steps), 5)
+        if not args.no_compare:
+            extra["plain_ms_per_step"] = round(timed(step_plans, args.steps), 5)
         step = step_autograd
 
     log(f"[bench] warmup {args.warmup} steps")

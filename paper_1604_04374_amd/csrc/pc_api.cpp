@@ -782,6 +782,14 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
     if (std::find(n1s.begin(), n1s.end(), p->p2.N1) == n1s.end()) n1s.push_back(p->p2.N1);
   }
   BatchLists lists[2];  // [0]: pc_batch_apply, [1]: pc_batch_apply_adjoint
+  // Blocks are listed instance by instance, the instances with the most
+  // terms first: a block's work grows with its instance's terms, and the
+  // chip takes blocks roughly in list order, so the short blocks fill the
+  // last, partly occupied round instead of the long ones.
+  std::vector<size_t> order(b->plans.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return b->plans[x]->p2.m > b->plans[y]->p2.m; });
   // instance i, call c: output buffer and whether it takes the forward-type chain
   auto out_of = [&](size_t i, int c) -> float* { return c == 0 ? fo[i] : fa[i]; };
   auto fwd_type = [&](size_t i, int c) { return (c == 0) != b->plans[i]->pconv; };
@@ -792,7 +800,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
       std::vector<pc::RowJob> jf, jfo, ja, jao;
       std::vector<pc::BlockRef> bf, bfo, ba, bao;
       const float2* tw = nullptr;
-      for (size_t i = 0; i < b->plans.size(); ++i) {
+      for (size_t i : order) {
         const pc::Plan2D& q = b->plans[i]->p2;
         float* out = out_of(i, c);
         if (q.N2 != L2 || !out) continue;
@@ -832,7 +840,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
       std::vector<pc::ColJob> jf, jt, ja;
       std::vector<pc::BlockRef> bf, bt, ba;
       const float2* tw = nullptr;
-      for (size_t i = 0; i < b->plans.size(); ++i) {
+      for (size_t i : order) {
         const pc::Plan2D& q = b->plans[i]->p2;
         if (q.N1 != L1 || !out_of(i, c)) continue;
         tw = q.tw1;
