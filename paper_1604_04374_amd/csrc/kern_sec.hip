@@ -13,33 +13,44 @@
 
 namespace pc {
 
-// One thread per output pixel, one workgroup per (tile, image): the sum, in
-// section order, of the sections whose output box covers the pixel.
-__global__ __launch_bounds__(SEC_TILE_R * SEC_TILE_C) void k_sec_scatter(
+// One workgroup per (tile, image) of SEC_TILE_R x SEC_TILE_C pixels, each
+// thread SEC_ROWS_PER_THREAD rows of one column: every pixel is the sum, in
+// section order, of the sections whose output box covers it.
+constexpr int SEC_THREADS = 256, SEC_ROWS_PER_THREAD = SEC_TILE_R * SEC_TILE_C / SEC_THREADS,
+              SEC_ROW_STEP = SEC_THREADS / SEC_TILE_C;
+__global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
     const SecTerm* __restrict__ terms, const float* __restrict__ S, float* __restrict__ y, int N1, int N2,
     int tiles2, const int* __restrict__ toff, const int* __restrict__ titems, int adjoint) {
   const int tile = blockIdx.x;
   const int64_t b = blockIdx.y;
-  const int i1 = (tile / tiles2) * SEC_TILE_R + (int)threadIdx.x / SEC_TILE_C;
+  const int i10 = (tile / tiles2) * SEC_TILE_R + (int)threadIdx.x / SEC_TILE_C;  // rows i10 + SEC_ROW_STEP r
   const int i2 = (tile % tiles2) * SEC_TILE_C + (int)threadIdx.x % SEC_TILE_C;
-  float acc = 0.f;
+  float acc[SEC_ROWS_PER_THREAD];
+#pragma unroll
+  for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) acc[r] = 0.f;
   for (int j = toff[tile]; j < toff[tile + 1]; ++j) {
     const SecTerm tm = terms[titems[j]];
     const int s1 = adjoint ? tm.sa1 : tm.sf1, s2 = adjoint ? tm.sa2 : tm.sf2;
     const int e1 = adjoint ? tm.ea1 : tm.ef1, e2 = adjoint ? tm.ea2 : tm.ef2;
-    int d1 = i1 - s1;
-    if (d1 < 0) d1 += N1;
     int d2 = i2 - s2;
     if (d2 < 0) d2 += N2;
-    if (d1 < e1 && d2 < e2) acc += S[tm.off + (b * tm.M1 + d1) * tm.M2 + d2];
+    if (d2 >= e2) continue;
+    const float* Sb = S + tm.off + b * tm.M1 * tm.M2 + d2;
+#pragma unroll
+    for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) {
+      int d1 = i10 + SEC_ROW_STEP * r - s1;
+      if (d1 < 0) d1 += N1;
+      if (d1 < e1) acc[r] += Sb[(int64_t)d1 * tm.M2];
+    }
   }
-  y[(b * N1 + i1) * N2 + i2] = acc;
+#pragma unroll
+  for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) y[(b * N1 + i10 + SEC_ROW_STEP * r) * N2 + i2] = acc[r];
 }
 
 LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr) {
   TraceScope ts(tr, "sec_scatter", s);
   const int tiles = (q.N1 / SEC_TILE_R) * q.tiles2;
-  hipLaunchKernelGGL(k_sec_scatter, dim3((unsigned)tiles, (unsigned)batch), dim3(SEC_TILE_R * SEC_TILE_C), 0, s,
+  hipLaunchKernelGGL(k_sec_scatter, dim3((unsigned)tiles, (unsigned)batch), dim3(SEC_THREADS), 0, s,
                      q.terms, q.Sout, y, q.N1, q.N2, q.tiles2, adjoint ? q.ta_off : q.tf_off,
                      adjoint ? q.ta_items : q.tf_items, adjoint ? 1 : 0);
   return hipGetLastError();

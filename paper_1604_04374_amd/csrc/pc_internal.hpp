@@ -277,7 +277,7 @@ struct Sec2D {
   const int* ta_off;
   const int* ta_items;
 };
-constexpr int SEC_TILE_R = 8, SEC_TILE_C = 32;
+constexpr int SEC_TILE_R = 32, SEC_TILE_C = 32;  // tile sides divide every supported size (>= 64, 2^a or 3 x 2^a)
 // every output pixel of the first `batch` images <- sum of the sections covering it
 LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr);
 
