@@ -408,10 +408,7 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   q.L = L;
   q.R = R;
   q.P = pc::points_per_thread(L);
-  if (const char* env = std::getenv("PC_FOURSTEP_P")) {  // tuning override
-    const int want = std::atoi(env);
-    if (pc::fourstep_variant_supported(L, R, want)) q.P = want;
-  }
+  if (!pc::fourstep_variant_supported(L, R, q.P)) return fail(PC_ERROR_UNSUPPORTED, "four-step variant not built");
   q.m = m;
   q.chunks = chunks;
   float* dwc = nullptr;
