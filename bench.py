@@ -20,7 +20,10 @@ The JSON line also carries
     1 GiB write that leaves none of the step's data in L2 or the Infinity
     Cache (``ms_per_step`` is the warm rate of back-to-back steps);
   * ``hbm.copy_GBps``: a plain device copy's measured rate, with the HBM
-    fractions also quoted against it (``frac_of_copy``).
+    fractions also quoted against it (``frac_of_copy``);
+  * ``roofline.traffic_ratio``: the counter-measured bytes of the dominant
+    kernel over its algorithmic bytes (``traffic_above_1_5x`` flags re-read
+    intermediates).
 """
 import argparse
 import hashlib
@@ -413,7 +416,8 @@ def main():
                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                         "traffic": read_traffic(name, args.workload, probs[0].ndim),
-                        "avg_launch_ms": round(st["avg_ms"], 5), "flops_per_launch": flops}
+                        "avg_launch_ms": round(st["avg_ms"], 5), "flops_per_launch": flops,
+                        "bytes_per_launch": nbytes}
         else:
             achieved = nbytes / t_s / 1e9
             roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
@@ -422,6 +426,12 @@ def main():
                         "avg_launch_ms": round(st["avg_ms"], 5), "bytes_per_launch": nbytes,
                         "frac_of_copy": round(achieved / copy_gbps, 4),
                         "alu_tflops": round(flops / t_s / 1e12, 3)}
+        # counter bytes against algorithmic bytes of the same launch; above
+        # 1.5 the kernel moves intermediates (re-reads, spills) beyond what
+        # the method must move
+        if roofline["traffic"] and nbytes > 0:
+            roofline["traffic_ratio"] = round(roofline["traffic"] / nbytes, 2)
+            roofline["traffic_above_1_5x"] = roofline["traffic_ratio"] > 1.5
     hbm_gbps = counts["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
     if roofline is None and step is not step_plans:
         roofline = {"bound": "hbm", "kernel": "whole step (graph or autograd launches)",
