@@ -605,7 +605,7 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
         load_blk<L, P>(p.cw + (((int64_t)k * R + f1) * C + c) * L, rt, t);
         // slots at or beyond Sc accumulate values that are never stored
 #pragma unroll
-        for (int e = 0; e < P; ++e) acc[c][e] = cadd(acc[c][e], cmulc(vv[e], rt[e]));
+        for (int e = 0; e < P; ++e) acc[c][e] = cfma_conj(acc[c][e], rt[e], vv[e]);  // + vv conj(rt), 4 FMAs
       }
     } else {
       float2 rt[P];
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(L / P) void k_adj1d_large(Large1D p) {
         for (int e = 0; e < P; ++e) rt[e] = cmul(rt[e], u);
       }
 #pragma unroll
-      for (int e = 0; e < P; ++e) acc[0][e] = cadd(acc[0][e], cmulc(vv[e], rt[e]));
+      for (int e = 0; e < P; ++e) acc[0][e] = cfma_conj(acc[0][e], rt[e], vv[e]);
     }
   };
   // (prefetching the next class into a second register set measured slower
