@@ -85,8 +85,10 @@ enum {
    * result.  The plan takes this route only when it is estimated to be at
    * least twice as cheap; pc_plan_query reports it as path 3.  Sectioned
    * plans keep only per-section spectra: the spectra calls return
-   * PC_ERROR_UNSUPPORTED for them, and they cannot join a batch; they
-   * always transform their full batch capacity. */
+   * PC_ERROR_UNSUPPORTED for them, and they cannot join a batch.  They read
+   * only the call's batch of input images, but their later passes run over
+   * the full batch capacity, so a smaller batch costs about as much as a
+   * full one. */
   PC_PLAN_FULL_GRID = 4u
 };
 
