@@ -648,8 +648,11 @@ __global__ __launch_bounds__(256) void k_transpose_spec(const float2* __restrict
   }
 }
 
-// E_k[f2][:] = sum_b conj(colFFT(a_k1 . RA_k2[b][f2][:])) . Gh[b][f2][:], one
-// (column, term) per FFT slot.
+// E_k[f2][:] = sum_b conj(colFFT(a_k1 . RA_k2[b][f2][:])) . Gh[b][f2][:].
+// One (column, column factor k2) per FFT slot, looping over the row factors
+// k1 (dense windows: one term per slot): the terms of one k2 share the
+// columns of RA_k2 and Gh, which then come from the caches instead of being
+// fetched by a separate workgroup per term.
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d_cols(
     const float2* __restrict__ RA, int64_t q_stride, const float2* __restrict__ Gh, int64_t batch, int H2, int m1,
@@ -663,33 +666,35 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d
   const int f2raw = blockIdx.x * NF + c;
   const bool valid = f2raw < H2;
   const int f2 = valid ? f2raw : H2 - 1;
-  const int k = blockIdx.y;
+  const int q = blockIdx.y;  // column factor (dense: the term)
   (void)nblk;
-  const int k1 = dense ? 0 : k / m2, q = dense ? k : k % m2;
-  (void)m1;
+  const int nk1 = dense ? 1 : m1;
   const int64_t plane = (int64_t)L1 * H2;
   float2* my = lds + c * lds_len<L1>();
-  float2 acc[P];
+  for (int k1 = 0; k1 < nk1; ++k1) {
+    const int k = dense ? q : k1 * m2 + q;
+    float2 acc[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  for (int64_t b = 0; b < batch; ++b) {
-    const float2* col = RA + q * q_stride + b * plane + (int64_t)f2 * L1;
-    const float2* gcol = Gh + b * plane + (int64_t)f2 * L1;
-    float2 v[P], gv[P];
+    for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
+    for (int64_t b = 0; b < batch; ++b) {
+      const float2* col = RA + q * q_stride + b * plane + (int64_t)f2 * L1;
+      const float2* gcol = Gh + b * plane + (int64_t)f2 * L1;
+      float2 v[P], gv[P];
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      v[e] = col[t + T * e];
-      gv[e] = gcol[t + T * e];
-      if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+      for (int e = 0; e < P; ++e) {
+        v[e] = col[t + T * e];
+        gv[e] = gcol[t + T * e];
+        if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+      }
+      fft_wg<L1, P, false>(v, my, twl, opaque(t));
+#pragma unroll
+      for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
     }
-    fft_wg<L1, P, false>(v, my, twl, t);
+    if (valid) {
+      float2* dst = E + (int64_t)k * plane + (int64_t)f2 * L1;
 #pragma unroll
-    for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gv[e]);
-  }
-  if (valid) {
-    float2* dst = E + (int64_t)k * plane + (int64_t)f2 * L1;
-#pragma unroll
-    for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
+      for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
+    }
   }
 }
 
@@ -697,7 +702,8 @@ template <int L1>
 static LaunchStatus grad2d_cols_t(const Plan2D& p, int64_t batch, int64_t q_stride, float2* E, hipStream_t s) {
   constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
   const int nblk = (p.H2 + NF - 1) / NF;
-  hipLaunchKernelGGL(k_grad2d_cols<L1>, dim3((unsigned)nblk, (unsigned)p.m), dim3(NF * T), 0, s, p.RA, q_stride,
+  hipLaunchKernelGGL(k_grad2d_cols<L1>, dim3((unsigned)nblk, (unsigned)(p.dense ? p.m : p.m2)), dim3(NF * T), 0, s,
+                     p.RA, q_stride,
                      p.Tws, batch, p.H2, p.m1, p.m2, p.dense ? 1 : 0, p.wrows, E, p.tw1);
   return hipGetLastError();
 }
