@@ -22,6 +22,7 @@
 //           rows:  x = sum_q b_q . rowIFFT(Q_q) / (N1 N2)
 // With dense (non-separable) windows q runs over the m terms, a = 1 and
 // b_q = w_q.
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -612,40 +613,73 @@ LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t bat
 // ===========================================================================
 
 // Tiled transpose between natural [k][f1][f2] (f2 contiguous) and internal
-// [k][f2][f1] (f1 contiguous), with a scale per f2 column.
+// [k][f2][f1] (f1 contiguous), with a scale per f2 column.  A tile is TA
+// frequencies f1 by TB frequencies f2; the natural rows (N2/2+1 entries) start
+// at any 8-byte offset, so the cache lines at a tile's two f2 edges are shared
+// with its neighbours.  The tiles of one f1 strip take consecutive indices and
+// xcd_major keeps consecutive indices on one XCD, so those shared lines meet
+// in one L2 instead of reaching HBM as partial writes from two.
+constexpr int SPEC_TA = 32, SPEC_TB = 32, SPEC_THREADS = 256;
 template <bool TO_INTERNAL>
-__global__ __launch_bounds__(256) void k_transpose_spec(const float2* __restrict__ src, float2* __restrict__ dst,
-                                                        int N1, int H2, int scale_mode, float inv_n) {
-  __shared__ float2 tile[32][33];
-  const int k = blockIdx.z;
+__global__ __launch_bounds__(SPEC_THREADS) void k_transpose_spec(const float2* __restrict__ src,
+                                                                float2* __restrict__ dst, int N1, int H2,
+                                                                int scale_mode, float inv_n, int64_t nblocks) {
+  constexpr int TA = SPEC_TA, TB = SPEC_TB;
+  __shared__ float2 tile[TA][TB + 1];
+  const int nbB = (H2 + TB - 1) / TB, nbA = (N1 + TA - 1) / TA;
+  const int64_t b = xcd_major(blockIdx.x, nblocks);
+  const int jb = (int)(b % nbB);
+  const int64_t rest = b / nbB;
+  const int ib = (int)(rest % nbA);
+  const int64_t k = rest / nbA;
   const int64_t plane = (int64_t)N1 * H2;
-  // tile origin: a = f1 block, b = f2 block
-  const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
-  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
-  for (int i = ty; i < 32; i += 8) {
-    const int f1 = a0 + i, f2 = b0 + tx;       // natural: read/write along f2
-    const int g1 = a0 + tx, g2 = b0 + i;       // internal: read/write along f1
+  const int a0 = ib * TA, b0 = jb * TB;
+  src += k * plane;
+  dst += k * plane;
+  // natural side: lanes run along f2; internal side: lanes run along f1
+  for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
     if (TO_INTERNAL) {
-      if (f1 < N1 && f2 < H2) tile[i][tx] = src[k * plane + (int64_t)f1 * H2 + f2];
+      const int i = idx / TB, j = idx % TB;
+      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = src[(int64_t)(a0 + i) * H2 + b0 + j];
     } else {
-      if (g1 < N1 && g2 < H2) tile[tx][i] = src[k * plane + (int64_t)g2 * N1 + g1];
+      const int i = idx % TA, j = idx / TA;
+      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = src[(int64_t)(b0 + j) * N1 + a0 + i];
     }
   }
   __syncthreads();
-  for (int i = ty; i < 32; i += 8) {
-    const int f1 = a0 + i, f2 = b0 + tx;
-    const int g1 = a0 + tx, g2 = b0 + i;
+  for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
     if (TO_INTERNAL) {
-      if (g1 < N1 && g2 < H2) dst[k * plane + (int64_t)g2 * N1 + g1] = tile[tx][i];
-    } else if (f1 < N1 && f2 < H2) {
-      float2 v = tile[i][tx];
-      if (scale_mode) {
-        const float c = (f2 == 0 || f2 == H2 - 1) ? inv_n : 2.f * inv_n;  // DC and Nyquist columns
-        v = cscale(v, c);
+      const int i = idx % TA, j = idx / TA;
+      if (a0 + i < N1 && b0 + j < H2) dst[(int64_t)(b0 + j) * N1 + a0 + i] = tile[i][j];
+    } else {
+      const int i = idx / TB, j = idx % TB;
+      const int f2 = b0 + j;
+      if (a0 + i < N1 && f2 < H2) {
+        float2 v = tile[i][j];
+        if (scale_mode) {
+          const float c = (f2 == 0 || f2 == H2 - 1) ? inv_n : 2.f * inv_n;  // DC and Nyquist columns
+          v = cscale(v, c);
+        }
+        dst[(int64_t)(a0 + i) * H2 + f2] = v;
       }
-      dst[k * plane + (int64_t)f1 * H2 + f2] = v;
     }
   }
+}
+
+// Launches the transpose over all m terms, in groups of terms small enough
+// for one grid (at most 2^22 workgroups per launch).
+template <bool TO_INTERNAL>
+static LaunchStatus transpose_spec(const Plan2D& p, const float2* src, float2* dst, int scale_mode, float inv_n,
+                                   hipStream_t s) {
+  const int64_t per_term = (int64_t)((p.N1 + SPEC_TA - 1) / SPEC_TA) * ((p.H2 + SPEC_TB - 1) / SPEC_TB);
+  const int64_t group = std::max<int64_t>(1, ((int64_t)1 << 22) / per_term);
+  const int64_t plane = (int64_t)p.N1 * p.H2;
+  for (int64_t k0 = 0; k0 < p.m; k0 += group) {
+    const int64_t nb = std::min<int64_t>(group, p.m - k0) * per_term;
+    hipLaunchKernelGGL(k_transpose_spec<TO_INTERNAL>, dim3((unsigned)nb), dim3(SPEC_THREADS), 0, s,
+                       src + k0 * plane, dst + k0 * plane, p.N1, p.H2, scale_mode, inv_n, nb);
+  }
+  return hipGetLastError();
 }
 
 // E_k[f2][:] = sum_b conj(colFFT(a_k1 . RA_k2[b][f2][:])) . Gh[b][f2][:].
@@ -709,13 +743,8 @@ static LaunchStatus grad2d_cols_t(const Plan2D& p, int64_t batch, int64_t q_stri
 }
 
 LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bool import, hipStream_t s) {
-  const dim3 grid((unsigned)((p.H2 + 31) / 32), (unsigned)((p.N1 + 31) / 32), (unsigned)p.m);
-  if (import)
-    hipLaunchKernelGGL(k_transpose_spec<true>, grid, dim3(256), 0, s, in, const_cast<float2*>(p.Hs), p.N1, p.H2, 0,
-                       1.f);
-  else
-    hipLaunchKernelGGL(k_transpose_spec<false>, grid, dim3(256), 0, s, p.Hs, out, p.N1, p.H2, 0, 1.f);
-  return hipGetLastError();
+  if (import) return transpose_spec<true>(p, in, const_cast<float2*>(p.Hs), 0, 1.f, s);
+  return transpose_spec<false>(p, p.Hs, out, 0, 1.f, s);
 }
 
 LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
@@ -742,10 +771,7 @@ LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, flo
     }
     if (e != hipSuccess) return e;
   }
-  const dim3 grid((unsigned)((p.H2 + 31) / 32), (unsigned)((p.N1 + 31) / 32), (unsigned)p.m);
-  hipLaunchKernelGGL(k_transpose_spec<false>, grid, dim3(256), 0, s, E, gspec, p.N1, p.H2, 1,
-                     1.0f / ((float)p.N1 * (float)p.N2));
-  return hipGetLastError();
+  return transpose_spec<false>(p, E, gspec, 1, 1.0f / ((float)p.N1 * (float)p.N2), s);
 }
 
 }  // namespace pc
