@@ -334,7 +334,9 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
 // Adjoint column pass, one (column, q = bm.q) per FFT slot:
 // dst_q[img][f2][:] = sum_k1 a_k1 . colIFFT(conj(H_k) . src[img][f2][:]),
 // src column-transformed beforehand by k_cols_fft, or here when fft_src.
-template <int L1>
+// PF: the next term's spectrum column is loaded before the current transform
+// (its latency hides behind it, for P more complex registers).
+template <int L1, bool PF>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
@@ -361,12 +363,29 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  for (int k1 = 0; k1 < nk1; ++k1) {
-    const int k = dense ? q : k1 * m2 + q;
-    const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
-    float2 g[P];
+  // term k = k1 m2 + q (dense windows: k = q, one pass)
+  const float2* Hq = jb.Hs + (int64_t)q * plane + (int64_t)f2 * L1;
+  const int64_t k1_stride = (int64_t)m2 * plane;
+  float2 hn[PF ? P : 1];
+  if constexpr (PF) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], Hk[t + T * e]);
+    for (int e = 0; e < P; ++e) hn[e] = Hq[t + T * e];
+  }
+  for (int k1 = 0; k1 < nk1; ++k1) {
+    float2 g[P];
+    if constexpr (PF) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], hn[e]);
+      if (k1 + 1 < nk1) {
+        const float2* Hn = Hq + (int64_t)(k1 + 1) * k1_stride;
+#pragma unroll
+        for (int e = 0; e < P; ++e) hn[e] = Hn[t + T * e];
+      }
+    } else {
+      const float2* Hk = Hq + (int64_t)k1 * k1_stride;
+#pragma unroll
+      for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], Hk[t + T * e]);
+    }
     fft_wg<L1, P, true>(g, my, twl, opaque(t));
 #pragma unroll
     for (int e = 0; e < P; ++e) {
@@ -448,35 +467,70 @@ static bool late_pays() {
   return early_per_simd <= 2 && late_per_simd > early_per_simd;
 }
 
-bool cols_fwd_late(int L1) {
-  static std::mutex mu;
-  static std::map<int, bool> known;
+// The adjoint's prefetch pays wherever it costs no resident workgroup
+// (measured: 2048^2, 64 terms, 2% faster; 128 to 512 columns, where it costs
+// a wave per SIMD, 2% slower).
+template <int L1>
+static bool prefetch_pays() {
+  const int threads = col_threads(L1);
+  int plain = 0, pf = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&plain, k_cols_adj<L1, false>, threads, 0) != hipSuccess)
+    return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pf, k_cols_adj<L1, true>, threads, 0) != hipSuccess) return false;
+  return pf >= plain;
+}
+
+// One decision per length, cached; the environment variable (0 or 1), when
+// set, overrides it for tuning.
+template <class Decide>
+static bool decide_once(std::map<int, bool>& known, std::mutex& mu, const char* env, int L1, Decide decide) {
   std::lock_guard<std::mutex> g(mu);
   const auto it = known.find(L1);
   if (it != known.end()) return it->second;
-  bool r = false;
-  if (const char* env = std::getenv("PC_COLS_FWD_LATE")) {  // tuning override: 0 early, 1 late
-    r = std::atoi(env) != 0;
-    known[L1] = r;
-    return r;
-  }
-  switch (L1) {
-#define PC_CASE(LL) \
-  case LL:          \
-    r = late_pays<LL>(); \
-    break;
-    PC_FOR_EACH_L2(PC_CASE)
-#undef PC_CASE
-  }
+  const char* e = std::getenv(env);
+  const bool r = e ? std::atoi(e) != 0 : decide(L1);
   known[L1] = r;
   return r;
 }
 
+bool cols_fwd_late(int L1) {
+  static std::mutex mu;
+  static std::map<int, bool> known;
+  return decide_once(known, mu, "PC_COLS_FWD_LATE", L1, [](int L) {
+    switch (L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return late_pays<LL>();
+      PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+    }
+    return false;
+  });
+}
+
+bool cols_adj_prefetch(int L1) {
+  static std::mutex mu;
+  static std::map<int, bool> known;
+  return decide_once(known, mu, "PC_COLS_ADJ_PREFETCH", L1, [](int L) {
+    switch (L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return prefetch_pays<LL>();
+      PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+    }
+    return false;
+  });
+}
+
 int col_groups_for(int H2, int64_t batch, int nq) {
   // split the forward column pass over groups of column factors until about
-  // eight column transforms per compute unit are in flight
+  // sixteen column transforms per compute unit are launched: with two or
+  // three resident workgroups per CU, fewer leave the last round of
+  // workgroups mostly empty (measured: 2048^2, 64 terms, 8 -> 16 per CU cut
+  // the pass by ~15%; 32 per CU was slower again from the partial sums)
   const int64_t cols = (int64_t)H2 * batch;
-  const int64_t target = 256 * 8;
+  const int64_t target = 256 * 16;
   int g = 1;
   while (g < nq && cols * g < target) g *= 2;
   return g < nq ? g : nq;
@@ -543,7 +597,10 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_cols_adj<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    if (ls.prefetch) \
+      hipLaunchKernelGGL((k_cols_adj<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    else \
+      hipLaunchKernelGGL((k_cols_adj<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE

@@ -187,6 +187,7 @@ struct LaunchSet {
   const float2* tw = nullptr;      // engine twiddles for L
   bool small_rows = false;         // row kernels: the small-tile variant (row_block_rows(L, true) rows)
   bool late = false;               // forward column kernel: the late-spectrum variant (cols_fwd_late)
+  bool prefetch = false;           // adjoint column kernel: the prefetching variant (cols_adj_prefetch)
 };
 
 struct Plan2D {
@@ -215,6 +216,11 @@ int col_groups_for(int H2, int64_t batch, int nq);
 // hiding): decided once per length from the runtime's occupancy figures for
 // both variants; PC_COLS_FWD_LATE=0/1 overrides it.
 bool cols_fwd_late(int L1);
+// Whether the adjoint column kernel of length L1 loads the next spectrum
+// column while it transforms the current one: decided once per length, true
+// where the runtime's occupancy figures show it costs no resident workgroup;
+// PC_COLS_ADJ_PREFETCH=0/1 overrides it.
+bool cols_adj_prefetch(int L1);
 // Row kernels take 2 G rows per workgroup; the small-tile variant (fewer
 // rows, more workgroups) serves single images too small to fill the chip.
 int row_block_rows(int L2, bool small = false);
