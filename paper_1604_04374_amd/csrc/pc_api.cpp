@@ -563,17 +563,21 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   // launch tables
   const int mode = dense ? 2 : 1;
   const float scale = 1.0f / ((float)N1 * (float)N2);
-  // images too small to fill the chip with the default row tiles (one row
-  // block per compute unit at least) take the small tiles
+  // launches too small to fill the chip with the default row tiles (one row
+  // block per compute unit at least) take the small tiles; the forward row
+  // pass launches its blocks once per column factor
   const bool sr = (int64_t)(N1 / pc::row_block_rows(N2)) * cap < 256;
   const int rpi = N1 / pc::row_block_rows(N2, sr);                 // row blocks per image
+  const bool sr_q = (int64_t)(N1 / pc::row_block_rows(N2)) * cap * nq < 256;
+  const int rpi_q = N1 / pc::row_block_rows(N2, sr_q);
   const int cpi = (H2 + pc::col_block_cols(N1) - 1) / pc::col_block_cols(N1);  // column blocks per image
   std::vector<pc::BlockRef> bm;
   {  // forward: rows of b_q . u -> RA
     pc::RowJob j{nullptr, nullptr, q.wcols, mode, N1, 0, 0.f, nullptr, q.RA, plane * cap};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, nq, sr);
-    if ((st = make_set(p, q.fwd_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, (int64_t)rpi * nq, tw2, s, sr)))
+    pc::append_row_blocks(bm, 0, cap, N1, N2, nq, sr_q);
+    if ((st = make_set(p, q.fwd_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, (int64_t)rpi_q * nq, tw2, s,
+                       sr_q)))
       return st;
   }
   pc::ColJob cf{q.RA, q.Tws, q.Part, Hs, q.wrows, plane * cap, plane * cap, H2, q.m1, q.m2, dense ? 1 : 0,
