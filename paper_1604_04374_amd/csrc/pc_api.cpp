@@ -502,6 +502,7 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   ls.small_rows = rows && small_rows;
   ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L);
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::cols_adj_prefetch(L);
+  ls.pipe = kind == pc::KK_ROWS_INV && pc::rows_inv_pipe(L, ls.small_rows);
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();
@@ -717,6 +718,7 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   ls.threads = rows ? pc::row_threads(L) : pc::col_threads(L);
   ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L);
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::cols_adj_prefetch(L);
+  ls.pipe = kind == pc::KK_ROWS_INV && pc::rows_inv_pipe(L, false);
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();

@@ -188,6 +188,7 @@ struct LaunchSet {
   bool small_rows = false;         // row kernels: the small-tile variant (row_block_rows(L, true) rows)
   bool late = false;               // forward column kernel: the late-spectrum variant (cols_fwd_late)
   bool prefetch = false;           // adjoint column kernel: the prefetching variant (cols_adj_prefetch)
+  bool pipe = false;               // row-inverse kernel: the pipelined variant (rows_inv_pipe)
 };
 
 struct Plan2D {
@@ -221,6 +222,11 @@ bool cols_fwd_late(int L1);
 // where the runtime's occupancy figures show it costs no resident workgroup;
 // PC_COLS_ADJ_PREFETCH=0/1 overrides it.
 bool cols_adj_prefetch(int L1);
+// Whether the row-inverse kernel of length L2 (small: the small-tile variant)
+// loads the next plane's tile while it transforms the current one: decided
+// once per variant, true where the runtime's figures show at least two waves
+// per SIMD and no spilled registers; PC_ROWS_INV_PIPE=0/1 overrides it.
+bool rows_inv_pipe(int L2, bool small);
 // Row kernels take 2 G rows per workgroup; the small-tile variant (fewer
 // rows, more workgroups) serves single images too small to fill the chip.
 int row_block_rows(int L2, bool small = false);
