@@ -262,7 +262,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the expansion shards with no communication across signals: see DESIGN.md)", file=sys.stderr)
+              "(the expansion shards over signals, terms or image bands with no per-step communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch
