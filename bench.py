@@ -262,7 +262,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the expansion shards over signals, terms or image bands with no per-step communication)", file=sys.stderr)
+              "(signals shard across GPUs with no communication; terms and image bands need one sum or halo exchange per step)", file=sys.stderr)
         sys.exit(2)
 
     import torch
