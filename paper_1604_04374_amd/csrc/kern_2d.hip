@@ -507,15 +507,16 @@ static bool prefetch_pays() {
   return pf >= plain;
 }
 
-// One decision per length, cached; the environment variable (0 or 1), when
-// set, overrides it for tuning.
+// One decision per length, cached.  The environment variable (0 or 1), when
+// set, overrides it for tuning; it is read at every plan creation, so a
+// process can build plans of both variants.
 template <class Decide>
 static bool decide_once(std::map<int, bool>& known, std::mutex& mu, const char* env, int L1, Decide decide) {
+  if (const char* e = std::getenv(env)) return std::atoi(e) != 0;
   std::lock_guard<std::mutex> g(mu);
   const auto it = known.find(L1);
   if (it != known.end()) return it->second;
-  const char* e = std::getenv(env);
-  const bool r = e ? std::atoi(e) != 0 : decide(L1);
+  const bool r = decide(L1);
   known[L1] = r;
   return r;
 }
