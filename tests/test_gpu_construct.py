@@ -34,7 +34,10 @@ def _tvir(n, sigma_fn):
     return TT, lags
 
 
-@pytest.mark.parametrize("n,m,deg", [(1024, 8, 1), (4096, 16, 3), (6144, 12, 3), (16384, 32, 3)])
+# n = 1040 and 3088 (n % 32 == 16): the contraction's chunks end on a
+# lone 16-sample step
+@pytest.mark.parametrize("n,m,deg", [(1024, 8, 1), (1040, 8, 1), (3088, 12, 3), (4096, 16, 3), (6144, 12, 3),
+                                     (16384, 32, 3)])
 def test_projection_matches_oracle(n, m, deg):
     import torch
     import paper_1604_04374_amd as pcm
