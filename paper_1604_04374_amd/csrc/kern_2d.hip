@@ -40,14 +40,30 @@ namespace pc {
 // Window applied by the row kernels.
 enum RowWin { RW_NONE = 0, RW_FACTOR = 1, RW_DENSE = 2 };
 
+// Device-memory access through the job tables' pointers.  The compiler
+// cannot tell that a pointer read from a table addresses global memory and
+// emits flat instructions for it, whose completion the hardware tracks on
+// the same counter as LDS reads: every LDS wait of a transform then also
+// waits for them.  These helpers read and write through global-address-space
+// views (every table pointer addresses device memory).
+typedef float pc_f2 __attribute__((ext_vector_type(2)));
+#define PC_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ float2 gld(const float2* p, int64_t i) {
+  const pc_f2 v = ((const PC_GLOBAL pc_f2*)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(float2* p, int64_t i, float2 v) { ((PC_GLOBAL pc_f2*)p)[i] = pc_f2{v.x, v.y}; }
+__device__ __forceinline__ float gldf(const float* p, int64_t i) { return ((const PC_GLOBAL float*)p)[i]; }
+__device__ __forceinline__ void gstf(float* p, int64_t i, float v) { ((PC_GLOBAL float*)p)[i] = v; }
+
 __device__ __forceinline__ void row_weights(const float* __restrict__ wsrc, int mode, int q, int N1, int L2, int r,
                                             int n2, float& wa, float& wb) {
   if (mode == RW_FACTOR) {
-    wa = wb = wsrc[(int64_t)q * L2 + n2];
+    wa = wb = gldf(wsrc, (int64_t)q * L2 + n2);
   } else if (mode == RW_DENSE) {
     const float* base = wsrc + ((int64_t)q * N1 + r) * L2 + n2;
-    wa = base[0];
-    wb = base[L2];
+    wa = gldf(base, 0);
+    wb = gldf(base, L2);
   } else {
     wa = wb = 1.0f;
   }
@@ -127,7 +143,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
     const int o = n2 < wrap ? n2 : n2 - jb.gN2;
     float wa, wb;
     row_weights(jb.wsrc, jb.mode, q, N1, L2, r, n2, wa, wb);
-    v[e] = make_float2(wa * ra[o], wb * rb[o]);
+    v[e] = make_float2(wa * gldf(ra, o), wb * gldf(rb, o));
   }
   float2* my = lds + c * lds_len<L2>();
   fft_wg<L2, P, false>(v, my, twl, t);
@@ -159,7 +175,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
   float2* o = jb.sout + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
   for (int idx = threadIdx.x; idx < H2 * 2 * G; idx += NT) {
     const int f = idx / (2 * G), ri = idx % (2 * G);
-    o[(int64_t)f * N1 + ri] = lds[idx];
+    gst(o, (int64_t)f * N1 + ri, lds[idx]);
   }
 }
 
@@ -196,7 +212,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int idx = threadIdx.x + i * NT;
-      if (idx < TILE) nxt[i] = src0[(int64_t)(idx / (2 * G)) * N1 + idx % (2 * G)];
+      if (idx < TILE) nxt[i] = gld(src0, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
     }
   }
   for (int q = 0; q < jb.nq; ++q) {
@@ -213,12 +229,12 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
           const int idx = threadIdx.x + i * NT;
-          if (idx < TILE) nxt[i] = src[(int64_t)(idx / (2 * G)) * N1 + idx % (2 * G)];
+          if (idx < TILE) nxt[i] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
         }
       }
     } else {
       const float2* src = src0 + (int64_t)q * jb.q_stride;
-      for (int idx = threadIdx.x; idx < TILE; idx += NT) lds[idx] = src[(int64_t)(idx / (2 * G)) * N1 + idx % (2 * G)];
+      for (int idx = threadIdx.x; idx < TILE; idx += NT) lds[idx] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
       __syncthreads();
     }
     float2 v[P];
@@ -252,8 +268,8 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
-    oa[n2] = acc[e].x * jb.scale;
-    oa[n2 + L2] = acc[e].y * jb.scale;
+    gstf(oa, n2, acc[e].x * jb.scale);
+    gstf(oa, n2 + L2, acc[e].y * jb.scale);
   }
 }
 
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
     const float2* col = jb.src + q * jb.q_stride + img * plane + (int64_t)f2 * L1;
     float2 cv[P];
 #pragma unroll
-    for (int e = 0; e < P; ++e) cv[e] = col[t + T * e];
+    for (int e = 0; e < P; ++e) cv[e] = gld(col, t + T * e);
     for (int k1 = 0; k1 < nk1; ++k1) {
       const int k = dense ? q : k1 * m2 + q;
       const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
@@ -304,13 +320,13 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
       float2 hv[P], v[P];
       if constexpr (!LATE) {
 #pragma unroll
-        for (int e = 0; e < P; ++e) hv[e] = Hk[t + T * e];
+        for (int e = 0; e < P; ++e) hv[e] = gld(Hk, t + T * e);
       }
 #pragma unroll
-      for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], jb.wrows[(int64_t)k1 * L1 + t + T * e]);
+      for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e));
       fft_wg<L1, P, false>(v, my, twl, opaque(t));
 #pragma unroll
-      for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], LATE ? Hk[t + T * e] : hv[e], v[e]);
+      for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], LATE ? gld(Hk, t + T * e) : hv[e], v[e]);
     }
   }
   if (ngroups == 1) {
@@ -318,12 +334,12 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
     if (valid) {
       float2* dst = jb.dst + img * plane + (int64_t)f2 * L1;
 #pragma unroll
-      for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
+      for (int e = 0; e < P; ++e) gst(dst, t + T * e, acc[e]);
     }
   } else if (valid) {
     float2* dst = jb.part + g * jb.part_stride + img * plane + (int64_t)f2 * L1;
 #pragma unroll
-    for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
+    for (int e = 0; e < P; ++e) gst(dst, t + T * e, acc[e]);
   }
 }
 
@@ -346,15 +362,15 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
   const int64_t off = img * ((int64_t)L1 * H2) + (int64_t)f2 * L1;
   float2 acc[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) acc[e] = jb.part[off + t + T * e];
+  for (int e = 0; e < P; ++e) acc[e] = gld(jb.part, off + t + T * e);
   for (int g = 1; g < jb.ngroups; ++g) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], jb.part[g * jb.part_stride + off + t + T * e]);
+    for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], gld(jb.part, g * jb.part_stride + off + t + T * e));
   }
   fft_wg<L1, P, true>(acc, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) jb.dst[off + t + T * e] = acc[e];
+    for (int e = 0; e < P; ++e) gst(jb.dst, off + t + T * e, acc[e]);
   }
 }
 
@@ -383,7 +399,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   const int64_t coff = img * plane + (int64_t)f2 * L1;
   float2 vh[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) vh[e] = jb.src[coff + t + T * e];
+  for (int e = 0; e < P; ++e) vh[e] = gld(jb.src, coff + t + T * e);
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
   if (jb.fft_src) fft_wg<L1, P, false>(vh, my, twl, t);  // uniform over the workgroup
@@ -396,7 +412,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   float2 hn[PF ? P : 1];
   if constexpr (PF) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) hn[e] = Hq[t + T * e];
+    for (int e = 0; e < P; ++e) hn[e] = gld(Hq, t + T * e);
   }
   for (int k1 = 0; k1 < nk1; ++k1) {
     float2 g[P];
@@ -406,17 +422,17 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
       if (k1 + 1 < nk1) {
         const float2* Hn = Hq + (int64_t)(k1 + 1) * k1_stride;
 #pragma unroll
-        for (int e = 0; e < P; ++e) hn[e] = Hn[t + T * e];
+        for (int e = 0; e < P; ++e) hn[e] = gld(Hn, t + T * e);
       }
     } else {
       const float2* Hk = Hq + (int64_t)k1 * k1_stride;
 #pragma unroll
-      for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], Hk[t + T * e]);
+      for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], gld(Hk, t + T * e));
     }
     fft_wg<L1, P, true>(g, my, twl, opaque(t));
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      const float wv = dense ? 1.0f : jb.wrows[(int64_t)k1 * L1 + t + T * e];
+      const float wv = dense ? 1.0f : gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e);
       acc[e].x = fmaf(wv, g[e].x, acc[e].x);
       acc[e].y = fmaf(wv, g[e].y, acc[e].y);
     }
@@ -424,7 +440,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   if (valid) {
     float2* dst = jb.dst + q * jb.q_stride + coff;
 #pragma unroll
-    for (int e = 0; e < P; ++e) dst[t + T * e] = acc[e];
+    for (int e = 0; e < P; ++e) gst(dst, t + T * e, acc[e]);
   }
 }
 
@@ -447,11 +463,11 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   const int64_t off = img * ((int64_t)L1 * H2) + (int64_t)f2 * L1;
   float2 v[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) v[e] = jb.dst[off + t + T * e];
+  for (int e = 0; e < P; ++e) v[e] = gld(jb.dst, off + t + T * e);
   fft_wg<L1, P, false>(v, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) jb.dst[off + t + T * e] = v[e];
+    for (int e = 0; e < P; ++e) gst(jb.dst, off + t + T * e, v[e]);
   }
 }
 
