@@ -497,17 +497,22 @@ void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H
 
 // Late loads pay where the early variant is down to two waves per SIMD and
 // the late one has more (measured: the 1024 and 2048 column passes of single
-// images, 1.6x faster); with three or more waves the early loads' latency
-// hiding is worth more (measured on 256 instances of 128 to 512 columns).
+// images, 1.6x faster).  With three or more waves, early loads are worth
+// more when a launch's instances loop over several terms (each term's
+// spectrum loads during the previous term's transform; measured on 256
+// instances of 4 to 16 terms and 128 to 512 columns: late loads at 192, 256
+// and 384 points cost 12%), and less when every instance has a single term,
+// where there is no previous transform to hide behind (the 384-point
+// single-term sections of C5: late loads 2% faster).
 template <int L1>
-static bool late_pays() {
+static bool late_pays(bool multi_term) {
   const int threads = col_threads(L1);
   const int waves = (threads + 63) / 64;
   int early = 0, late = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&early, k_cols_fwd<L1, false>, threads, 0) != hipSuccess) return false;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&late, k_cols_fwd<L1, true>, threads, 0) != hipSuccess) return false;
   const int early_per_simd = early * waves / 4, late_per_simd = late * waves / 4;
-  return early_per_simd <= 2 && late_per_simd > early_per_simd;
+  return late_per_simd > early_per_simd && (!multi_term || early_per_simd <= 2);
 }
 
 // The adjoint's prefetch pays wherever it costs no resident workgroup
@@ -537,14 +542,15 @@ static bool decide_once(std::map<int, bool>& known, std::mutex& mu, const char* 
   return r;
 }
 
-bool cols_fwd_late(int L1) {
+bool cols_fwd_late(int L1, bool multi_term) {
   static std::mutex mu;
   static std::map<int, bool> known;
-  return decide_once(known, mu, "PC_COLS_FWD_LATE", L1, [](int L) {
-    switch (L) {
+  return decide_once(known, mu, "PC_COLS_FWD_LATE", multi_term ? -L1 : L1, [](int key) {
+    const bool b = key < 0;
+    switch (b ? -key : key) {
 #define PC_CASE(LL) \
   case LL:          \
-    return late_pays<LL>();
+    return late_pays<LL>(b);
       PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
     }

@@ -489,7 +489,7 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
 template <class J>
 pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vector<J>& jobs,
                    const std::vector<pc::BlockRef>& bm, int64_t per_img, const float2* tw, hipStream_t s,
-                   bool small_rows = false) {
+                   bool small_rows = false, bool multi_term = true) {
   J* dj = nullptr;
   pc::BlockRef* db = nullptr;
   pc_status st = p->upload(&dj, jobs, s);
@@ -500,7 +500,7 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   ls.L = L;
   ls.threads = rows ? pc::row_threads(L, small_rows) : pc::col_threads(L);
   ls.small_rows = rows && small_rows;
-  ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L);
+  ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L, multi_term);
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::cols_adj_prefetch(L);
   ls.pipe = kind == pc::KK_ROWS_INV && pc::rows_inv_pipe(L, ls.small_rows);
   ls.jobs = dj;
@@ -586,7 +586,7 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   bm.clear();
   pc::append_col_blocks(bm, 0, cap, H2, N1, q.col_groups);
   if ((st = make_set(p, q.fwd_cols, pc::KK_COLS_FWD, N1, std::vector<pc::ColJob>{cf}, bm,
-                     (int64_t)cpi * q.col_groups, tw1, s)))
+                     (int64_t)cpi * q.col_groups, tw1, s, false, m > 1)))
     return st;
   bm.clear();
   pc::append_col_blocks(bm, 0, cap, H2, N1, 1);
@@ -704,7 +704,7 @@ std::set<const void*> g_batches;  // live batches (guarded by g_registry_mu)
 
 template <class J>
 pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L, const std::vector<J>& jobs,
-                    const std::vector<pc::BlockRef>& bm, const float2* tw) {
+                    const std::vector<pc::BlockRef>& bm, const float2* tw, bool multi_term = true) {
   if (jobs.empty()) return PC_SUCCESS;
   J* dj = nullptr;
   pc::BlockRef* db = nullptr;
@@ -716,7 +716,7 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   ls.kind = kind;
   ls.L = L;
   ls.threads = rows ? pc::row_threads(L) : pc::col_threads(L);
-  ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L);
+  ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L, multi_term);
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::cols_adj_prefetch(L);
   ls.pipe = kind == pc::KK_ROWS_INV && pc::rows_inv_pipe(L, false);
   ls.jobs = dj;
@@ -845,6 +845,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
       std::vector<pc::ColJob> jf, jt, ja;
       std::vector<pc::BlockRef> bf, bt, ba;
       const float2* tw = nullptr;
+      bool f_multi = false;  // some forward-type instance loops over several terms
       for (size_t i : order) {
         const pc::Plan2D& q = b->plans[i]->p2;
         if (q.N1 != L1 || !out_of(i, c)) continue;
@@ -853,6 +854,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         const int nq = q.dense ? q.m : q.m2, dense = q.dense ? 1 : 0;
         if (fwd_type(i, c)) {  // one term group: the many instances already fill the device
           pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
+          f_multi = f_multi || q.m > 1;
           jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
         } else {
           if (!q.adj_fused) {
@@ -865,7 +867,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           ja.push_back(j);
         }
       }
-      if ((st = batch_set(b, bl.f_cols, pc::KK_COLS_FWD, L1, jf, bf, tw))) return st;
+      if ((st = batch_set(b, bl.f_cols, pc::KK_COLS_FWD, L1, jf, bf, tw, f_multi))) return st;
       if ((st = batch_set(b, bl.a_fft, pc::KK_COLS_FFT, L1, jt, bt, tw))) return st;
       if ((st = batch_set(b, bl.a_cols, pc::KK_COLS_ADJ, L1, ja, ba, tw))) return st;
     }

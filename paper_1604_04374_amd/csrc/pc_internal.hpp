@@ -214,9 +214,10 @@ struct Plan2D {
 int col_groups_for(int H2, int64_t batch, int nq);
 // Whether the forward column kernel of length L1 runs its late-spectrum
 // variant (spectrum loaded after the transform: fewer registers, no latency
-// hiding): decided once per length from the runtime's occupancy figures for
-// both variants; PC_COLS_FWD_LATE=0/1 overrides it.
-bool cols_fwd_late(int L1);
+// hiding), for a launch whose instances loop over several terms or have one
+// term each: decided once per length and kind from the runtime's occupancy
+// figures for both variants; PC_COLS_FWD_LATE=0/1 overrides it.
+bool cols_fwd_late(int L1, bool multi_term);
 // Whether the adjoint column kernel of length L1 loads the next spectrum
 // column while it transforms the current one: decided once per length, true
 // where the runtime's occupancy figures show it costs no resident workgroup;
