@@ -35,7 +35,7 @@ import scipy.fft as sfft
 __all__ = [
     "apply_direct", "adjoint_direct", "apply_direct_at", "adjoint_direct_at",
     "apply_dft", "adjoint_dft", "apply_fft", "adjoint_fft", "workers",
-    "dft_matrix", "circular_conv_direct",
+    "dft_matrix",
     "apply_pc_direct", "adjoint_pc_direct", "apply_pc_direct_at", "adjoint_pc_direct_at",
     "apply_pc_fft", "adjoint_pc_fft",
 ]
@@ -73,13 +73,6 @@ def _circulant(h: np.ndarray) -> np.ndarray:
     d2 = (i2[:, None] - i2[None, :]) % n2           # [i2, j2]
     c = h[d1[:, None, :, None], d2[None, :, None, :]]  # [i1, i2, j1, j2]
     return c.reshape(n1 * n2, n1 * n2)
-
-
-def circular_conv_direct(h: np.ndarray, z: np.ndarray) -> np.ndarray:
-    """``(h * z)[i] = sum_j h[i - j] z[j]`` by the direct sum (section 3.5)."""
-    h = np.asarray(h, np.float64)
-    z = np.asarray(z, np.float64)
-    return (_circulant(h) @ z.reshape(-1)).reshape(z.shape)
 
 
 def apply_direct(u, w, h):

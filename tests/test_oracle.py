@@ -242,6 +242,67 @@ def test_example3_two_terms_are_exact():
                                rtol=1e-12, atol=1e-14)
 
 
+def _shifted_two_tile_tvir(n):
+    # A TVIR that is not symmetric in the lag: two Gaussians centred at
+    # opposite nonzero lags, switched by the indicator of |y| <= 1/4 as in
+    # Example 3.3.  Each column of the kernel is then a bump displaced from
+    # the diagonal, in a direction fixed by the introduction's
+    # K(x, y) = T(x - y, y).
+    d1, d2 = 0.1, -0.07
+    def T(x, y):
+        yc = y - np.floor(np.asarray(y, np.float64) + 0.5)
+        ind = (np.abs(yc) <= 0.25).astype(np.float64)
+        return wl.gaussian(x - d1, 0.05) * ind + wl.gaussian(x - d2, 0.08) * (1.0 - ind)
+    y = np.arange(n) / n
+    yc = y - np.floor(y + 0.5)
+    w1 = (np.abs(yc) <= 0.25).astype(float)
+    lam = wl.lag_unit(n)
+    h = np.stack([wl.gaussian(lam - d1, 0.05), wl.gaussian(lam - d2, 0.08)]) / n
+    return T, np.stack([w1, 1 - w1]), h, (d1, d2)
+
+
+def test_dense_quadrature_lag_direction():
+    # The dense quadrature must put the response of the source y_j at
+    # x_i = y_j + lag, i.e. K[i, j] = T(lam(i - j), y_j) / n.  With a TVIR
+    # that is asymmetric in the lag and exactly two tensor products, the
+    # two-term expansion with the centre-sampled shifted responses equals the
+    # dense operator column by column (Lemma 3.1 with exact windows); a lag
+    # taken as j - i would move every bump to the other side of the diagonal.
+    n = 256
+    T, w, h, (d1, d2) = _shifted_two_tile_tvir(n)
+    K = dense.kernel_matrix_1d(T, n)
+    for j in (0, 17, 64, 100, 128, 191, 255):
+        e = np.zeros(n)
+        e[j] = 1.0
+        col = ex.apply_direct(e, w, h)
+        np.testing.assert_allclose(col, K[:, j], rtol=1e-12, atol=1e-15)
+        # the peak of column j sits at the index of y_j + d (mod 1)
+        d = d1 if abs(j / n - np.floor(j / n + 0.5)) <= 0.25 else d2
+        assert int(np.argmax(K[:, j])) == int(round((j / n + d) * n)) % n
+    u = np.random.default_rng(31).standard_normal(n)
+    np.testing.assert_allclose(ex.apply_direct(u, w, h), dense.apply_dense(K, u), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(ex.adjoint_direct(u, w, h), dense.adjoint_dense(K, u), rtol=1e-12, atol=1e-14)
+    # the test separates the two lag directions: the mirrored quadrature
+    # differs from the expansion by the size of the operator itself
+    i = np.arange(n)
+    K_mirror = T(dense.lag_of(i[None, :] - i[:, None], n), np.broadcast_to((i / n)[None, :], (n, n))) / n
+    assert _rel(K_mirror, K) > 0.5
+
+
+def test_tvir_matrix_rows_are_lags():
+    # tvir_matrix_1d's row l is the lag lam(l): with the shifted TVIR the
+    # largest entry of each column sits at the row of the shift.
+    n = 256
+    T, _, _, (d1, d2) = _shifted_two_tile_tvir(n)
+    TT = dense.tvir_matrix_1d(T, n)
+    assert int(np.argmax(TT[:, 0])) == int(round(d1 * n)) % n
+    assert int(np.argmax(TT[:, n // 2])) == int(round(d2 * n)) % n
+    # and the kernel matrix is the TVIR read along the circulant diagonals
+    K = dense.kernel_matrix_1d(T, n)
+    for j in (0, 40, 128, 200):
+        np.testing.assert_allclose(np.roll(K[:, j], -j), TT[:, j] / n, rtol=1e-13, atol=1e-16)
+
+
 def test_hat_windows_interpolate_columns_at_centres():
     # Lemma 3.1 with interpolating hat windows: at a window centre y_j = c_k
     # only w_k is nonzero (and equals 1), so column j of H_m is column j of H.
