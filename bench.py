@@ -1,29 +1,35 @@
 #!/usr/bin/env python3
 """Throughput of the convolution-product expansion on one MI355X.
 
-Workload (default): 64 real signals of N = 65536 samples sharing one
-operator with m = 32 cubic B-spline windows and Gaussian impulse responses
-(sigma(y) = 0.002 + 0.01 sin^2(pi y)), float32, seeded synthetic data.  One
-step is the whole hot path over the batch: y = H_m u (pc_apply) and
-x = H_m^* u (pc_apply_adjoint).  ``value`` counts the output samples of both
-(2 x 64 x 65536 per step) per second, with the inputs already resident in
-device memory.
+Workload (default, ``--workload c5``): one 2048 x 2048 float32 image and the
+operator with m = 64 terms of 8 x 8 tile windows (256 x 256 indicators) and
+anisotropic Gaussian PSFs sampled at the tile centres, seeded synthetic data,
+evaluated section by section (the compact-support lemma, Lemma 3.2).  One
+step is the whole hot path: y = H_m u (pc_apply) and x = H_m^* u
+(pc_apply_adjoint).  ``value`` counts the output samples of both
+(2 x 2048 x 2048 per step) per second, with the inputs already resident in
+device memory.  The other workloads (``--workload``) are the 1D and uneven
+batch configurations and the autograd step.
 
 The JSON line also carries
-  * ``roofline``: the dominant kernel's algorithmic FP32 rate (flops per
-    launch / average launch duration from HIP events recorded on the launch
-    stream) against the chip's vector peak;
-  * ``hbm``: algorithmic bytes per step over the step time against 8 TB/s;
+  * ``roofline``: for the 2D workloads the whole step, HBM-bound: the
+    method's algorithmic bytes per step (inputs read, outputs written, the
+    plan's spectra and windows, each once per direction) over the step time
+    from HIP events recorded on the launch stream around the timed region,
+    against 8 TB/s; ``traffic`` is the counter-measured bytes of the step's
+    kernels (committed summary under profiles/, when it matches the current
+    kernel sources).  For the 1D batch (VALU-bound) the dominant kernel's
+    algorithmic FP32 rate against the vector peak;
+  * ``kernels``: every kernel family's average launch time (HIP events on
+    the launch stream), its bytes as a separate pass (intermediate planes
+    included) and its share of the step;
   * ``cpu_baseline``: the FP64 oracle (FFT form) timed on the host cores on
     a bounded sample of the same workload, and its agreement with the GPU;
   * ``cold_ms_per_step``: the median of steps timed one by one, each after a
     1 GiB write that leaves none of the step's data in L2 or the Infinity
     Cache (``ms_per_step`` is the warm rate of back-to-back steps);
   * ``hbm.copy_GBps``: a plain device copy's measured rate, with the HBM
-    fractions also quoted against it (``frac_of_copy``);
-  * ``roofline.traffic_ratio``: the counter-measured bytes of the dominant
-    kernel over its algorithmic bytes (``traffic_above_1_5x`` flags re-read
-    intermediates).
+    fractions also quoted against it (``frac_of_copy``).
 """
 import argparse
 import hashlib
@@ -65,8 +71,10 @@ def algorithmic_counts(p, info):
     flops and bytes for one plan of workload ``p`` (batch ``p.batch``)."""
     B, m = p.batch, p.m
     ntot = p.n_total
+    # nonzero window samples over all terms (the compacted windows); a
+    # separable grid's term (k1, k2) has nnz(a_k1) nnz(b_k2) of them
     support_sum = int(np.count_nonzero(p.dense_windows())) if p.ndim == 1 else (
-        int(np.count_nonzero(p.w_rows)) * p.shape[1] + int(np.count_nonzero(p.w_cols)) * p.shape[0]
+        int(np.count_nonzero(p.w_rows)) * int(np.count_nonzero(p.w_cols))
         if p.separable else int(np.count_nonzero(p.w)))
     if p.ndim == 1:
         n = p.shape[0]
@@ -204,7 +212,8 @@ def source_digest(files):
 
 
 KERNEL_SOURCES = {1: ["paper_1604_04374_amd/csrc/kern_1d.hip", "paper_1604_04374_amd/csrc/fft_engine.hpp"],
-                  2: ["paper_1604_04374_amd/csrc/kern_2d.hip", "paper_1604_04374_amd/csrc/fft_engine.hpp"]}
+                  2: ["paper_1604_04374_amd/csrc/kern_2d.hip", "paper_1604_04374_amd/csrc/kern_sec.hip",
+                      "paper_1604_04374_amd/csrc/fft_engine.hpp"]}
 
 
 def read_traffic(kernel, workload, ndim):
@@ -215,7 +224,7 @@ def read_traffic(kernel, workload, ndim):
         return None
     text = open(path).read()
     m_src = re.search(r"source_digest:\s*([0-9a-f]+)", text)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_b = re.search(r"hbm_bytes_per_(?:launch|step):\s*([0-9.eE+]+)", text)
     if not (m_src and m_b) or m_src.group(1) != source_digest(KERNEL_SOURCES[ndim]):
         return None
     return float(m_b.group(1))
@@ -251,8 +260,8 @@ def main():
     ap.add_argument("--no-trace", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison runs of c4 (single-plan calls) and c5ad (plain step)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS),
-                    help="c2 (default) is the reported configuration; the others are extra reports")
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS),
+                    help="c5 (default) is the reported configuration; the others are extra reports")
     ap.add_argument("--cold-steps", type=int, default=10,
                     help="extra steps timed one by one after a 1 GiB write that evicts L2 and the "
                          "Infinity Cache (reported as cold_ms_per_step; 0 disables)")
@@ -329,14 +338,15 @@ def main():
 
     extra = {}
     step = step_plans
+    batch = None
     if args.workload == "c4":
         # all instances in one graph launch per direction, against the loop of single plans
-        batch = pcm.Batch([j[1] for j in jobs], [j[2] for j in jobs],
-                          fwd_outputs=[j[3] for j in jobs], adj_outputs=[j[4] for j in jobs])
+        batch = pcm.Batch([j[1] for j in jobs])
+        b_in, b_y, b_x = [j[2] for j in jobs], [j[3] for j in jobs], [j[4] for j in jobs]
 
         def step_batch():
-            batch.apply()
-            batch.apply_adjoint()
+            batch.apply(b_in, outputs=b_y)
+            batch.apply_adjoint(b_in, outputs=b_x)
         if not args.no_compare:
             extra["single_plans_ms_per_step"] = round(timed(step_plans, max(args.steps // 4, 2)), 5)
         step = step_batch
@@ -361,12 +371,17 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
+    # HIP events on torch's current stream, the stream the library launches on
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     for _ in range(args.steps):
         step()
+    ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    event_ms_per_step = ev0.elapsed_time(ev1) / args.steps
     value = samples_per_step / (ms_per_step * 1e-3)
 
     cold_ms = None
@@ -402,41 +417,45 @@ def main():
                 agg["launches"] += v["launches"]
                 agg["total_ms"] += v["total_ms"]
             plan.set_tracing(False)
-        for v in kernels.values():
+        traced_total = sum(v["total_ms"] for v in kernels.values())
+        for k, v in kernels.items():
             v["avg_ms"] = v["total_ms"] / max(v["launches"], 1)
-        name, st = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
-        # per-launch algorithmic work: totals per step / launches per step
-        launches_per_step = st["launches"] / args.steps
-        flops = counts["kernel_flops"].get(name, 0.0) / launches_per_step
-        nbytes = counts["kernel_bytes"].get(name, 0.0) / launches_per_step
-        t_s = st["avg_ms"] * 1e-3
-        if probs[0].ndim == 1:
-            achieved = flops / t_s / 1e12
-            roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
-                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                        "traffic": read_traffic(name, args.workload, probs[0].ndim),
-                        "avg_launch_ms": round(st["avg_ms"], 5), "flops_per_launch": flops,
-                        "bytes_per_launch": nbytes}
-        else:
-            achieved = nbytes / t_s / 1e9
-            roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
-                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                        "traffic": read_traffic(name, args.workload, probs[0].ndim),
-                        "avg_launch_ms": round(st["avg_ms"], 5), "bytes_per_launch": nbytes,
-                        "frac_of_copy": round(achieved / copy_gbps, 4),
-                        "alu_tflops": round(flops / t_s / 1e12, 3)}
-        # counter bytes against algorithmic bytes of the same launch; above
-        # 1.5 the kernel moves intermediates (re-reads, spills) beyond what
-        # the method must move
-        if roofline["traffic"] and nbytes > 0:
-            roofline["traffic_ratio"] = round(roofline["traffic"] / nbytes, 2)
-            roofline["traffic_above_1_5x"] = roofline["traffic_ratio"] > 1.5
+            v["launches_per_step"] = v["launches"] / args.steps
+            v["share"] = v["total_ms"] / traced_total if traced_total > 0 else None
+            per_launch = v["launches"] / args.steps
+            v["pass_bytes_per_launch"] = counts["kernel_bytes"].get(k, 0.0) / per_launch if per_launch else 0.0
+            v["alg_flops_per_launch"] = counts["kernel_flops"].get(k, 0.0) / per_launch if per_launch else 0.0
+            v["traffic_per_launch"] = read_traffic(k, args.workload, probs[0].ndim)
     hbm_gbps = counts["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
-    if roofline is None and step is not step_plans:
-        roofline = {"bound": "hbm", "kernel": "whole step (graph or autograd launches)",
-                    "achieved": round(hbm_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                    "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4), "traffic": None}
+    if probs[0].ndim == 1 and kernels:
+        # VALU-bound: the dominant kernel's algorithmic FP32 rate
+        name, st = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
+        t_s = st["avg_ms"] * 1e-3
+        flops = st["alg_flops_per_launch"]
+        achieved = flops / t_s / 1e12
+        roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": st["traffic_per_launch"],
+                    "avg_launch_ms": round(st["avg_ms"], 5), "flops_per_launch": flops,
+                    "bytes_per_launch": st["pass_bytes_per_launch"]}
+        if roofline["traffic"] and roofline["bytes_per_launch"] > 0:
+            roofline["traffic_ratio"] = round(roofline["traffic"] / roofline["bytes_per_launch"], 2)
+    elif probs[0].ndim == 2:
+        # HBM-bound: the whole step (every launch of both directions) moving
+        # the method's algorithmic bytes, timed with HIP events on the launch
+        # stream around the timed region
+        achieved = counts["bytes_per_step"] / (event_ms_per_step * 1e-3) / 1e9
+        roofline = {"bound": "hbm",
+                    "kernel": "whole step (every launch of H_m u and H_m^* u)" if step is step_plans
+                    else "whole step (graph or autograd launches)",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": read_traffic("step", args.workload, 2),
+                    "bytes_per_step": counts["bytes_per_step"], "event_ms_per_step": round(event_ms_per_step, 5),
+                    "frac_of_copy": round(achieved / copy_gbps, 4)}
+        if roofline["traffic"]:
+            roofline["traffic_ratio"] = round(roofline["traffic"] / counts["bytes_per_step"], 2)
     p = probs[0]
     B = p.batch
     _, _, _, y, x = jobs[0]
@@ -517,12 +536,17 @@ def main():
                 "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(hbm_gbps / copy_gbps, 4)},
         "cold_ms_per_step": None if cold_ms is None else round(cold_ms, 5),
         "alg_tflops": round(counts["flops_per_step"] / (ms_per_step * 1e-3) / 1e12, 3),
-        "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kernels.items()},
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "launches_per_step": v["launches_per_step"],
+                        "share": None if v["share"] is None else round(v["share"], 3),
+                        "pass_bytes_per_launch": v["pass_bytes_per_launch"],
+                        "traffic_per_launch": v["traffic_per_launch"]} for k, v in kernels.items()},
         "max_rel_l2_vs_oracle": err,
         "cpu_baseline": cpu,
         **extra,
     }
     print(json.dumps(line), flush=True)
+    if batch is not None:
+        batch.destroy()
     for _, plan, _, _, _ in jobs:
         plan.destroy()
 

@@ -165,7 +165,8 @@ pc_status pc_apply_adjoint(pc_plan plan, const float* v, float* x, int64_t batch
  * pc_destroy - release the plan and its device memory.  Waits for the
  * device to finish work that may still use the plan.  Destroying a NULL or
  * already destroyed handle returns INVALID_PLAN (a handle that was
- * destroyed must not be used again: its memory is freed).
+ * destroyed must not be used again: its memory is freed).  A plan held by a
+ * live batch returns INVALID_VALUE and stays alive.
  */
 pc_status pc_destroy(pc_plan plan);
 
@@ -350,37 +351,48 @@ pc_status pc_plan_create_meyer(pc_plan* out, int64_t n, int32_t levels, int32_t 
  * transform length (the work of all instances with that row or column
  * length shares the launch), and the sequence of launches of each direction
  * is captured once into a HIP graph, so that one pc_batch_apply call is one
- * graph launch.
+ * graph launch.  The kernels read each instance's input and output pointers
+ * from a device table, so every call may name new buffers.
  *
- *   plans        (host array of count handles) 2D plans; they must outlive
- *                the batch and must not be used by other calls while the
- *                batch runs (the batch uses their workspaces).
- *   inputs       (host array of count device pointers) each instance's input,
- *                plan batch x N1 x N2 floats (the plan's full batch).
- *   fwd_outputs  (host array) where pc_batch_apply writes H_i inputs[i]
- *                (G_i inputs[i] for a product-convolution plan).
- *   adj_outputs  (host array) where pc_batch_apply_adjoint writes
- *                H_i^* inputs[i] (G_i^* inputs[i]).  Either array may be
- *                NULL if that direction is never used; the entries of a
- *                given array must not be NULL, and outputs must not overlap
- *                inputs.  Convolution-product and product-convolution
- *                plans may share a batch.
- *   flags        PC_BATCH_NO_GRAPH: launch the passes directly instead of
- *                through the captured graphs.
- *   stream       used to build the graphs; creation is synchronous.
- * Errors: INVALID_VALUE (count < 1, null arrays or entries, a plan that is
- * not 2D, overlapping buffers), INVALID_PLAN, OUT_OF_MEMORY, HIP.
+ *   plans   (host array of count handles) distinct 2D full-grid plans (a
+ *           handle listed twice is rejected: its instances would share the
+ *           plan's workspace).  While the batch lives, pc_destroy refuses its
+ *           plans, and the plans must not be used by other calls while a
+ *           batch call runs (the batch uses their workspaces).
+ *           Convolution-product and product-convolution plans may share a
+ *           batch.
+ *   flags   PC_BATCH_NO_GRAPH: launch the passes directly instead of
+ *           through the captured graphs.
+ *   stream  unused (creation is synchronous).
+ * Errors: INVALID_VALUE (count < 1, null array, a repeated plan, a plan that
+ * is not 2D or is sectioned, plans on different devices, unknown flags),
+ * INVALID_PLAN, OUT_OF_MEMORY, HIP.
  */
 typedef struct pc_batch_s* pc_batch;
 enum { PC_BATCH_NO_GRAPH = 1u };
-pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, const float* const* inputs,
-                          float* const* fwd_outputs, float* const* adj_outputs, uint32_t flags, void* stream);
-/* Enqueue the whole batch on `stream`; returns without waiting.  Errors:
- * INVALID_VALUE (null or destroyed batch, or a direction whose outputs were
- * not given), HIP. */
-pc_status pc_batch_apply(pc_batch batch, void* stream);
-pc_status pc_batch_apply_adjoint(pc_batch batch, void* stream);
-/* Release the batch (waits for the device first). */
+pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, uint32_t flags, void* stream);
+/*
+ * pc_batch_apply - outputs[i] = H_i inputs[i] for every instance i (G_i for a
+ * product-convolution plan); pc_batch_apply_adjoint - outputs[i] =
+ * H_i^* inputs[i] (G_i^*).
+ *
+ *   inputs, outputs  (host arrays of count device pointers) each instance's
+ *                    plan batch x N1 x N2 floats (the plan's full batch).  No
+ *                    output may overlap another output or any input.
+ *   stream           the work is enqueued on this stream; the call returns
+ *                    without waiting.
+ * When the pointers differ from the previous call's in the same direction,
+ * the call first uploads them (a copy of 16 bytes per instance enqueued on
+ * `stream`; the host waits only if the previous upload of that direction
+ * has not run yet).  Calls on one batch must be ordered (one stream, or
+ * synchronised streams): they share the table and the plans' workspaces.
+ * Errors: INVALID_VALUE (null or destroyed batch, null arrays or entries,
+ * overlapping buffers), HIP.
+ */
+pc_status pc_batch_apply(pc_batch batch, const float* const* inputs, float* const* outputs, void* stream);
+pc_status pc_batch_apply_adjoint(pc_batch batch, const float* const* inputs, float* const* outputs, void* stream);
+/* Release the batch (waits for the device first); its plans may then be
+ * destroyed.  Errors: INVALID_VALUE (null or destroyed batch), HIP. */
 pc_status pc_batch_destroy(pc_batch batch);
 
 /* Static text for a status code (never NULL). */

@@ -116,12 +116,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_plan_trace_stats.restype = ctypes.c_int
     lib.pc_plan_trace_reset.argtypes = [vp]
     lib.pc_plan_trace_reset.restype = ctypes.c_int
-    lib.pc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
-                                    ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_uint32, vp]
+    lib.pc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp), ctypes.c_uint32, vp]
     lib.pc_batch_create.restype = ctypes.c_int
     for name in ("pc_batch_apply", "pc_batch_apply_adjoint"):
         f = getattr(lib, name)
-        f.argtypes = [vp, vp]
+        f.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         f.restype = ctypes.c_int
     lib.pc_batch_destroy.argtypes = [vp]
     lib.pc_batch_destroy.restype = ctypes.c_int
@@ -468,39 +467,41 @@ def wavelet_transform(x, lowpass, levels, inverse=False, axis=-1, stream=None):
 class Batch:
     """Many 2D operators of uneven sizes run together (see pc_batch_create).
 
-    ``plans``: list of 2D :class:`Plan`; ``inputs``: list of CUDA tensors
-    (each the plan's full batch); outputs are allocated here unless given.
-    ``apply()`` enqueues H_i inputs[i] for every instance with one graph
-    launch; ``apply_adjoint()`` the adjoints.  The tensors are kept alive by
-    the batch object and must not be reallocated.
+    ``plans``: distinct 2D full-grid :class:`Plan` objects.  ``apply(inputs)``
+    enqueues ``H_i inputs[i]`` for every instance with one graph launch and
+    returns the outputs (allocated here unless ``outputs`` is given);
+    ``apply_adjoint`` the adjoints.  Each call may pass new tensors.  While
+    the batch lives its plans cannot be destroyed.
     """
 
-    def __init__(self, plans, inputs, fwd_outputs=None, adj_outputs=None, graph: bool = True, stream=None):
-        import torch
+    def __init__(self, plans, graph: bool = True, stream=None):
         self._lib = load_library()
         self.plans = list(plans)
-        self.inputs = [x.contiguous() for x in inputs]
-        self.fwd = list(fwd_outputs) if fwd_outputs is not None else [torch.empty_like(x) for x in self.inputs]
-        self.adj = list(adj_outputs) if adj_outputs is not None else [torch.empty_like(x) for x in self.inputs]
         n = len(self.plans)
-        arr = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(x.data_ptr() if hasattr(x, "data_ptr") else x)  # noqa: E731
-                                                  for x in xs])
         self._handle = ctypes.c_void_p()
         hp = (ctypes.c_void_p * n)(*[p._handle.value for p in self.plans])
-        st = self._lib.pc_batch_create(ctypes.byref(self._handle), n, hp, arr(self.inputs), arr(self.fwd),
-                                       arr(self.adj), 0 if graph else PC_BATCH_NO_GRAPH,
+        st = self._lib.pc_batch_create(ctypes.byref(self._handle), n, hp, 0 if graph else PC_BATCH_NO_GRAPH,
                                        ctypes.c_void_p(_stream_ptr(stream)))
         _check(self._lib, st, "pc_batch_create")
 
-    def apply(self, stream=None):
-        _check(self._lib, self._lib.pc_batch_apply(self._handle, ctypes.c_void_p(_stream_ptr(stream))),
-               "pc_batch_apply")
-        return self.fwd
+    def _call(self, fn, name, inputs, outputs, stream):
+        import torch
+        n = len(self.plans)
+        inputs = [x.contiguous() for x in inputs]
+        if len(inputs) != n:
+            raise ValueError(f"{name}: {len(inputs)} inputs for {n} instances")
+        outputs = [torch.empty_like(x) for x in inputs] if outputs is None else list(outputs)
+        if len(outputs) != n or any(not y.is_contiguous() for y in outputs):
+            raise ValueError(f"{name}: need {n} contiguous outputs")
+        arr = lambda xs: (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])  # noqa: E731
+        _check(self._lib, fn(self._handle, arr(inputs), arr(outputs), ctypes.c_void_p(_stream_ptr(stream))), name)
+        return outputs
 
-    def apply_adjoint(self, stream=None):
-        _check(self._lib, self._lib.pc_batch_apply_adjoint(self._handle, ctypes.c_void_p(_stream_ptr(stream))),
-               "pc_batch_apply_adjoint")
-        return self.adj
+    def apply(self, inputs, outputs=None, stream=None):
+        return self._call(self._lib.pc_batch_apply, "pc_batch_apply", inputs, outputs, stream)
+
+    def apply_adjoint(self, inputs, outputs=None, stream=None):
+        return self._call(self._lib.pc_batch_apply_adjoint, "pc_batch_apply_adjoint", inputs, outputs, stream)
 
     def destroy(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:

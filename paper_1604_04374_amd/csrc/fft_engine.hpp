@@ -231,9 +231,42 @@ template <int L, int PW = PAD>
 constexpr int lds_len() { return L + L / PW; }
 
 // ---------------------------------------------------------------------------
+// Synchronisation of the LDS exchanges.  A transform carried by T threads
+// with T dividing the wavefront size (64) lives inside one wavefront, whose
+// LDS operations the hardware performs in program order: its exchanges then
+// need only a compiler-level barrier, not a workgroup barrier, and the other
+// wavefronts of the workgroup run on.  SYNC_WG: every exchange waits on the
+// workgroup (always correct); SYNC_WAVE_ENTRY: wave-local exchanges, but the
+// first write still waits on the workgroup (the caller's LDS region was read
+// by other wavefronts just before the transform); SYNC_WAVE: wave-local
+// throughout (the region was last used by this transform's own threads).
+// The wave-local modes fall back to SYNC_WG when T does not divide 64.
+// ---------------------------------------------------------------------------
+enum { SYNC_WG = 0, SYNC_WAVE_ENTRY = 1, SYNC_WAVE = 2 };
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int T, int SYNC>
+constexpr int eff_sync() {
+  return (T <= 64 && 64 % T == 0) ? SYNC : SYNC_WG;
+}
+
+template <int SYNC, bool ENTRY>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (SYNC == SYNC_WG || (ENTRY && SYNC == SYNC_WAVE_ENTRY))
+    __syncthreads();
+  else
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
 // the engine
 // ---------------------------------------------------------------------------
-template <int L, int P, bool INV, int S, int Ns, int TW, int PW>
+template <int L, int P, bool INV, int S, int Ns, int TW, int PW, int SYNC = SYNC_WG>
 struct FftPass {
   static constexpr Sched sch = make_sched(L, P);
   static constexpr int R = sch.r[S];
@@ -263,7 +296,7 @@ struct FftPass {
 #pragma unroll
         for (int q = 0; q < R; ++q) v[b + q * B] = x[q];
       } else {
-        if (b == 0) __syncthreads();  // previous readers of this LDS region are done
+        if (b == 0) exchange_sync<SYNC, S == 0>();  // previous readers of this LDS region are done
         const int base = (j / Ns) * Ns * R + k;
         // The padded index is base + constant whenever the R outputs stay
         // inside one PW-entry row (Ns R divides PW; base is then a multiple
@@ -283,7 +316,7 @@ struct FftPass {
       }
     }
     if constexpr (!LAST) {
-      __syncthreads();
+      exchange_sync<SYNC, false>();
       if constexpr (T % PW == 0) {
         // (t + T e) / PW = t / PW + e T / PW
         const float2* src = lds + lpad<PW>(t);
@@ -293,7 +326,7 @@ struct FftPass {
 #pragma unroll
         for (int e = 0; e < P; ++e) v[e] = lds[lpad<PW>(t + T * e)];
       }
-      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW>::run(v, lds, tw, t);
+      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW, SYNC>::run(v, lds, tw, t);
     }
   }
 };
@@ -452,6 +485,16 @@ template <int L, int P, bool INV, int PW = PAD>
 __device__ __forceinline__ void fft_wg(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
   static_assert(sched_ok(L, P), "unsupported (L, P)");
   FftPass<L, P, INV, 0, 1, 0, PW>::run(v, lds, tw, t);
+}
+
+// The same transform with the exchange synchronisation SYNC (see SYNC_WG):
+// wave-local exchanges where the T = L/P threads of a transform share one
+// wavefront.  Threads of one transform must be consecutive and T-aligned
+// (transform slot c = threadIdx.x / T), as in every caller.
+template <int L, int P, bool INV, int SYNC, int PW = PAD>
+__device__ __forceinline__ void fft_wv(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
+  static_assert(sched_ok(L, P), "unsupported (L, P)");
+  FftPass<L, P, INV, 0, 1, 0, PW, eff_sync<L / P, SYNC>()>::run(v, lds, tw, t);
 }
 
 }  // namespace pc

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
   stage_twiddles<L2>(twl, tw);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
-  const float* x = jb.x ? jb.x : x_arg;
+  const float* x = jb.xp ? *jb.xp : (jb.x ? jb.x : x_arg);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t img = bm.img;
   const int r0 = bm.blk * 2 * G;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
     v[e] = make_float2(wa * gldf(ra, o), wb * gldf(rb, o));
   }
   float2* my = lds + c * lds_len<L2>();
-  fft_wg<L2, P, false>(v, my, twl, t);
+  fft_wv<L2, P, false, SYNC_WAVE>(v, my, twl, t);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < P; ++e) my[lpad(t + T * e)] = v[e];
@@ -187,16 +187,17 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
 template <int L2, int G, bool PIPE>
 __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
-    const float2* __restrict__ tw) {
+    const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
-  stage_twiddles<L2>(twl, tw);
   const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L2>(twl, tw);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
-  float* yout = jb.y ? jb.y : y_arg;
+  float* yout = jb.yp ? *jb.yp : (jb.y ? jb.y : y_arg);
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t img = bm.img;
   const int r0 = bm.blk * 2 * G;
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
       }
       v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
     }
-    fft_wg<L2, P, true>(v, my, twl, opaque(t));
+    fft_wv<L2, P, true, SYNC_WAVE_ENTRY>(v, my, twl, opaque(t));
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       float wa, wb;
@@ -263,6 +264,27 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
       acc[e].x = fmaf(wa, v[e].x, acc[e].x);
       acc[e].y = fmaf(wb, v[e].y, acc[e].y);
     }
+  }
+  if (jb.oN2 > 0) {
+    // section evaluation: the leading orows x ocols block goes straight to
+    // its place in the output image (both axes wrapped)
+    int ia = jb.o1 + r;
+    if (ia >= jb.oN1) ia -= jb.oN1;
+    const int ib = ia + 1 == jb.oN1 ? 0 : ia + 1;
+    float* oa = yout + (img * jb.oN1 + ia) * jb.oN2;
+    float* ob = yout + (img * jb.oN1 + ib) * jb.oN2;
+    const bool wa = r < jb.orows, wb = r + 1 < jb.orows;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n2 = t + T * e;
+      int o = jb.o2 + n2;
+      if (o >= jb.oN2) o -= jb.oN2;
+      if (n2 < jb.ocols) {
+        if (wa) gstf(oa, o, acc[e].x * jb.scale);
+        if (wb) gstf(ob, o, acc[e].y * jb.scale);
+      }
+    }
+    return;
   }
   float* oa = yout + (img * N1 + r) * L2;
 #pragma unroll
@@ -284,12 +306,13 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 // partial spectrum goes to part[group] for k_cols_sum_inv.
 template <int L1, bool LATE>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
-    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
-  stage_twiddles<L1>(twl, tw);
   const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L1>(twl, tw);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense, ngroups = jb.ngroups;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
@@ -309,8 +332,12 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   for (int q = q0; q < q1; ++q) {
     const float2* col = jb.src + q * jb.q_stride + img * plane + (int64_t)f2 * L1;
     float2 cv[P];
+    // elements e < ne of this thread are loaded (t + T e < nvalid_in), the
+    // rest are zero
+    const int nv = jb.nvalid_in == 0 ? L1 : jb.nvalid_in;
+    const int ne = nv > t ? (nv - t + T - 1) / T : 0;
 #pragma unroll
-    for (int e = 0; e < P; ++e) cv[e] = gld(col, t + T * e);
+    for (int e = 0; e < P; ++e) cv[e] = e < ne ? gld(col, t + T * e) : make_float2(0.f, 0.f);
     for (int k1 = 0; k1 < nk1; ++k1) {
       const int k = dense ? q : k1 * m2 + q;
       const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
@@ -324,13 +351,13 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
       }
 #pragma unroll
       for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e));
-      fft_wg<L1, P, false>(v, my, twl, opaque(t));
+      fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], LATE ? gld(Hk, t + T * e) : hv[e], v[e]);
     }
   }
   if (ngroups == 1) {
-    fft_wg<L1, P, true>(acc, my, twl, t);
+    fft_wv<L1, P, true, SYNC_WAVE>(acc, my, twl, t);
     if (valid) {
       float2* dst = jb.dst + img * plane + (int64_t)f2 * L1;
 #pragma unroll
@@ -346,12 +373,13 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
 // dst[img][f2][:] = colIFFT(sum_g part[g][img][f2][:]).
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_sum_inv(
-    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
-  stage_twiddles<L1>(twl, tw);
   const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L1>(twl, tw);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
@@ -367,7 +395,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
 #pragma unroll
     for (int e = 0; e < P; ++e) acc[e] = cadd(acc[e], gld(jb.part, g * jb.part_stride + off + t + T * e));
   }
-  fft_wg<L1, P, true>(acc, lds + c * lds_len<L1>(), twl, t);
+  fft_wv<L1, P, true, SYNC_WAVE>(acc, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < P; ++e) gst(jb.dst, off + t + T * e, acc[e]);
@@ -381,12 +409,13 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
 // (its latency hides behind it, for P more complex registers).
 template <int L1, bool PF>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
-    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
-  stage_twiddles<L1>(twl, tw);
   const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L1>(twl, tw);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
@@ -402,7 +431,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   for (int e = 0; e < P; ++e) vh[e] = gld(jb.src, coff + t + T * e);
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
-  if (jb.fft_src) fft_wg<L1, P, false>(vh, my, twl, t);  // uniform over the workgroup
+  if (jb.fft_src) fft_wv<L1, P, false, SYNC_WAVE>(vh, my, twl, t);  // uniform over the workgroup
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
@@ -429,7 +458,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
 #pragma unroll
       for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], gld(Hk, t + T * e));
     }
-    fft_wg<L1, P, true>(g, my, twl, opaque(t));
+    fft_wv<L1, P, true, SYNC_WAVE>(g, my, twl, opaque(t));
 #pragma unroll
     for (int e = 0; e < P; ++e) {
       const float wv = dense ? 1.0f : gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e);
@@ -439,20 +468,25 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   }
   if (valid) {
     float2* dst = jb.dst + q * jb.q_stride + coff;
+    // elements e < ne of this thread are stored (t + T e < nvalid_out)
+    const int nv = jb.nvalid_out == 0 ? L1 : jb.nvalid_out;
+    const int ne = nv > t ? (nv - t + T - 1) / T : 0;
 #pragma unroll
-    for (int e = 0; e < P; ++e) gst(dst, t + T * e, acc[e]);
+    for (int e = 0; e < P; ++e)
+      if (e < ne) gst(dst, t + T * e, acc[e]);
   }
 }
 
 // In-place column FFTs of dst: dst[img][f2][:] = colFFT(dst[img][f2][:]).
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fft(
-    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw) {
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
-  stage_twiddles<L1>(twl, tw);
   const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L1>(twl, tw);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2;
   const int c = threadIdx.x / T, t = threadIdx.x % T;
@@ -464,7 +498,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   float2 v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) v[e] = gld(jb.dst, off + t + T * e);
-  fft_wg<L1, P, false>(v, lds + c * lds_len<L1>(), twl, t);
+  fft_wv<L1, P, false, SYNC_WAVE>(v, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < P; ++e) gst(jb.dst, off + t + T * e, v[e]);
@@ -481,8 +515,10 @@ int row_threads(int L2, bool small) {
 }
 int col_threads(int L1) { return ffts_per_block(L1) * fft_threads(L1); }
 
-void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq, bool small) {
-  const int nb = N1 / row_block_rows(L2, small);
+void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq, bool small,
+                       int rows) {
+  const int br = row_block_rows(L2, small);
+  const int nb = rows > 0 && rows < N1 ? (rows + br - 1) / br : N1 / br;
   for (int64_t img = 0; img < n_img; ++img)
     for (int b = 0; b < nb; ++b)
       for (int q = 0; q < nq; ++q) out.push_back(BlockRef{job, (int)img, b, q});
@@ -644,13 +680,13 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
 #define PC_CASE(LL) \
   case LL:          \
     if (ls.small_rows && ls.pipe)  \
-      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     else if (ls.small_rows)  \
-      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), false>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), false>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     else if (ls.pipe)  \
-      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     else  \
-      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), false>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw); \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), false>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -661,9 +697,9 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
 #define PC_CASE(LL) \
   case LL:          \
     if (ls.late)    \
-      hipLaunchKernelGGL((k_cols_fwd<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
+      hipLaunchKernelGGL((k_cols_fwd<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     else            \
-      hipLaunchKernelGGL((k_cols_fwd<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
+      hipLaunchKernelGGL((k_cols_fwd<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -673,7 +709,7 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_cols_sum_inv<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    hipLaunchKernelGGL(k_cols_sum_inv<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -684,9 +720,9 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
 #define PC_CASE(LL) \
   case LL:          \
     if (ls.prefetch) \
-      hipLaunchKernelGGL((k_cols_adj<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
+      hipLaunchKernelGGL((k_cols_adj<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     else \
-      hipLaunchKernelGGL((k_cols_adj<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw); \
+      hipLaunchKernelGGL((k_cols_adj<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -696,7 +732,7 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_cols_fft<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw); \
+    hipLaunchKernelGGL(k_cols_fft<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -864,7 +900,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d
         v[e] = col[t + T * e];
         if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
       }
-      fft_wg<L1, P, false>(v, my, twl, opaque(t));
+      fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gcol[t + T * e]);
     }

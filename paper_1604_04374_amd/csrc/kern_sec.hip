@@ -1,4 +1,4 @@
-// Gather and overlap-add kernels of the sectioned 2D evaluation (the
+// Overlap-add kernel of the sectioned 2D evaluation (the
 // compact-support complexity lemma of section 3.5, Lemma 3.2).
 //
 // A term whose window has the box [o, o + p) (per axis, on the torus) and

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <mutex>
 #include <new>
 #include <set>
@@ -207,6 +208,7 @@ struct pc_plan_s {
   pc::Sec2D sec{};
   std::vector<pc_plan_s*> sec_sub;
   pc_batch_s* sec_batch = nullptr;
+  int batch_refs = 0;  // live batches holding the plan (guarded by g_registry_mu)
   pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
   ~pc_plan_s();
@@ -672,11 +674,22 @@ struct pc_batch_s {
   bool has_fwd = false, has_adj = false, use_graph = true;
   hipGraph_t gf = nullptr, ga = nullptr;
   hipGraphExec_t ef = nullptr, ea = nullptr;
+  // Buffers of the calls: the jobs read each instance's input and output
+  // pointers from a device table, [direction][instance][in, out], refreshed
+  // from pinned host staging before a call whose pointers differ from the
+  // previous call's in that direction.
+  float** dtab = nullptr;
+  float** htab = nullptr;  // pinned host staging, same layout
+  std::vector<float*> last[2];
+  hipEvent_t ev[2] = {nullptr, nullptr};  // the last upload of each direction
   ~pc_batch_s() {
     if (ef) (void)hipGraphExecDestroy(ef);
     if (ea) (void)hipGraphExecDestroy(ea);
     if (gf) (void)hipGraphDestroy(gf);
     if (ga) (void)hipGraphDestroy(ga);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (htab) (void)hipHostFree(htab);
     for (void* p : allocs) (void)hipFree(p);
   }
   template <class T>
@@ -728,9 +741,9 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
 }
 
 hipError_t launch_seq(const std::vector<pc::LaunchSet>& seq, hipStream_t s, pc::Tracer* tr,
-                      const float* x_arg = nullptr, int64_t img_limit = INT64_MAX) {
+                      const float* x_arg = nullptr, int64_t img_limit = INT64_MAX, float* y_arg = nullptr) {
   for (const pc::LaunchSet& ls : seq) {
-    hipError_t e = pc::launch_set(ls, ls.blocks, x_arg, nullptr, s, tr, img_limit);
+    hipError_t e = pc::launch_set(ls, ls.blocks, x_arg, y_arg, s, tr, img_limit);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -776,10 +789,17 @@ struct BatchLists {
 struct GatherSpec {
   int N1, N2;
   const std::vector<pc::SecTerm>* terms;
+  // the window boxes partition the image: the adjoint's row-inverse pass
+  // writes each section's window box straight into the call's output
+  bool direct_adj = false;
 };
 
+// Fixed pointers (in, fo, fa: the sections of a sectioned plan) or, with
+// in == nullptr, the entries of the batch's device table b->dtab.
 pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa,
                       const GatherSpec* gather = nullptr) {
+  const bool table = in == nullptr;
+  const size_t nb = b->plans.size();
   // group instances by row length (N2) and by column length (N1)
   std::vector<int> n2s, n1s;
   for (pc_plan p : b->plans) {
@@ -796,7 +816,15 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
   std::stable_sort(order.begin(), order.end(),
                    [&](size_t x, size_t y) { return b->plans[x]->p2.m > b->plans[y]->p2.m; });
   // instance i, call c: output buffer and whether it takes the forward-type chain
-  auto out_of = [&](size_t i, int c) -> float* { return c == 0 ? fo[i] : fa[i]; };
+  auto out_of = [&](size_t i, int c) -> float* {
+    if (table) return reinterpret_cast<float*>(1);  // every instance has both directions
+    return c == 0 ? fo[i] : fa[i];
+  };
+  // the device table entries of instance i, call c
+  auto in_slot = [&](size_t i, int c) -> const float* const* {
+    return table ? const_cast<const float* const*>(b->dtab + (c * nb + i) * 2) : nullptr;
+  };
+  auto out_slot = [&](size_t i, int c) -> float* const* { return table ? b->dtab + (c * nb + i) * 2 + 1 : nullptr; };
   auto fwd_type = [&](size_t i, int c) { return (c == 0) != b->plans[i]->pconv; };
   pc_status st;
   for (int c = 0; c < 2; ++c) {
@@ -807,13 +835,15 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
       const float2* tw = nullptr;
       for (size_t i : order) {
         const pc::Plan2D& q = b->plans[i]->p2;
-        float* out = out_of(i, c);
-        if (q.N2 != L2 || !out) continue;
+        float* out = table ? nullptr : out_of(i, c);
+        if (q.N2 != L2 || !out_of(i, c)) continue;
+        const float* inp = table ? nullptr : in[i];
         tw = q.tw2;
         const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
         const int nq = q.dense ? q.m : q.m2, mode = q.dense ? 2 : 1;
         const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
         auto gathered = [&](pc::RowJob j) {
+          j.xp = in_slot(i, c);
           if (gather) {
             const pc::SecTerm& t = (*gather->terms)[i];
             j.x = nullptr;
@@ -824,16 +854,33 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           }
           return j;
         };
+        // sections: rows that matter (the window box leads the section in
+        // both directions; the forward output box is p + q - 1 rows)
+        const pc::SecTerm* st = gather ? &(*gather->terms)[i] : nullptr;
+        const int win_rows = st ? st->ea1 : 0, out_rows = st ? st->ef1 : 0;
         if (fwd_type(i, c)) {
-          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq);
-          jf.push_back(gathered(pc::RowJob{in[i], nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap}));
-          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1);
-          jfo.push_back(pc::RowJob{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0});
+          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, false, win_rows);
+          jf.push_back(gathered(pc::RowJob{inp, nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap}));
+          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, false, out_rows);
+          pc::RowJob jo{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0};
+          jo.yp = out_slot(i, c);
+          jfo.push_back(jo);
         } else {
           pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
-          ja.push_back(gathered(pc::RowJob{in[i], nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
-          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1);
-          jao.push_back(pc::RowJob{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap});
+          ja.push_back(gathered(pc::RowJob{inp, nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
+          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, false, win_rows);
+          pc::RowJob jo{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap};
+          jo.yp = out_slot(i, c);
+          if (st && gather->direct_adj) {
+            jo.y = nullptr;  // the launch's output argument: the call's output image
+            jo.oN1 = gather->N1;
+            jo.oN2 = gather->N2;
+            jo.o1 = st->sa1;
+            jo.o2 = st->sa2;
+            jo.orows = st->ea1;
+            jo.ocols = st->ea2;
+          }
+          jao.push_back(jo);
         }
       }
       if ((st = batch_set(b, bl.f_rows_in, pc::KK_ROWS_FWD, L2, jf, bf, tw))) return st;
@@ -852,10 +899,12 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         tw = q.tw1;
         const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
         const int nq = q.dense ? q.m : q.m2, dense = q.dense ? 1 : 0;
+        const pc::SecTerm* st = gather ? &(*gather->terms)[i] : nullptr;
         if (fwd_type(i, c)) {  // one term group: the many instances already fill the device
           pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
           f_multi = f_multi || q.m > 1;
           jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
+          if (st) jf.back().nvalid_in = st->ea1;  // the row pass transformed the window box rows only
         } else {
           if (!q.adj_fused) {
             pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
@@ -864,6 +913,10 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           pc::append_col_blocks(ba, (int)ja.size(), cap, q.H2, L1, nq);
           pc::ColJob j{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1};
           j.fft_src = q.adj_fused ? 1 : 0;
+          if (st) {  // the row-inverse pass reads whole row blocks of the window box rows
+            const int br = pc::row_block_rows(q.N2);
+            j.nvalid_out = std::min(q.N1, (st->ea1 + br - 1) / br * br);
+          }
           ja.push_back(j);
         }
       }
@@ -948,6 +1001,26 @@ bool plan_sections(const pc_plan_desc& d, const float* windows, const float* h, 
 }
 
 pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out);
+
+// Whether the sections' window boxes (the adjoint's output boxes) cover
+// every pixel of the N1 x N2 torus exactly once: their areas add up to the
+// image and no two of them meet.
+bool boxes_partition(const std::vector<pc::SecTerm>& t, int64_t N1, int64_t N2) {
+  int64_t area = 0;
+  for (const pc::SecTerm& a : t) area += (int64_t)a.ea1 * a.ea2;
+  if (area != N1 * N2) return false;
+  // circular intervals [s, s + e) and [s', s' + e') meet iff one starts
+  // inside the other
+  auto meet = [](int64_t s1, int64_t e1, int64_t s2, int64_t e2, int64_t n) {
+    const int64_t d12 = ((s2 - s1) % n + n) % n, d21 = ((s1 - s2) % n + n) % n;
+    return d12 < e1 || d21 < e2;
+  };
+  for (size_t i = 0; i < t.size(); ++i)
+    for (size_t j = i + 1; j < t.size(); ++j)
+      if (meet(t[i].sa1, t[i].ea1, t[j].sa1, t[j].ea1, N1) && meet(t[i].sa2, t[i].ea2, t[j].sa2, t[j].ea2, N2))
+        return false;
+  return true;
+}
 
 pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std::vector<Section>& secs,
                       hipStream_t s) {
@@ -1059,7 +1132,8 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
   std::vector<const float*> in(terms.size(), nullptr);
   std::vector<float*> outs;
   for (const pc::SecTerm& t : terms) outs.push_back(q.Sout + t.off);
-  const GatherSpec gs{(int)N1, (int)N2, &terms};
+  GatherSpec gs{(int)N1, (int)N2, &terms};
+  gs.direct_adj = q.direct_adj = boxes_partition(terms, N1, N2);
   // the launches take the call's input pointer, so they are not captured
   b->use_graph = false;
   return build_batch(b, in.data(), outs.data(), outs.data(), &gs);
@@ -1067,10 +1141,10 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
 
 hipError_t run_sections(pc_plan p, const float* in, float* out, int64_t batch, bool adjoint, hipStream_t s) {
   const pc_batch_s* b = p->sec_batch;
-  // blocks of images >= batch skip their row pass; the later passes compute
-  // on stale spectra for them, which the overlap-add never reads
-  hipError_t e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr(), in, batch);
+  // blocks of images >= batch return at once in every pass
+  hipError_t e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr(), in, batch, out);
   if (e != hipSuccess) return e;
+  if (adjoint && p->sec.direct_adj) return hipSuccess;  // the row pass wrote the output
   return pc::launch_sec_scatter(p->sec, out, adjoint, batch, s, p->tr());
 }
 
@@ -1307,50 +1381,61 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 extern "C" {
 
-pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, const float* const* inputs,
-                          float* const* fwd_outputs, float* const* adj_outputs, uint32_t flags, void* stream) {
+pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, uint32_t flags, void* stream) {
   if (!out) return fail(PC_ERROR_INVALID_VALUE, "out is NULL");
   *out = nullptr;
-  if (count < 1 || !plans || !inputs || (!fwd_outputs && !adj_outputs))
-    return fail(PC_ERROR_INVALID_VALUE, "count < 1 or null arrays");
+  if (count < 1 || !plans) return fail(PC_ERROR_INVALID_VALUE, "count < 1 or null plan array");
   if (flags & ~(uint32_t)PC_BATCH_NO_GRAPH) return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
-  std::vector<const float*> in(count);
-  std::vector<float*> fo(count, nullptr), fa(count, nullptr);
   int device = -1;
+  std::set<pc_plan> seen;
   for (int i = 0; i < count; ++i) {
     pc_status st = check_plan(plans[i]);
     if (st) return st;
     const pc_plan p = plans[i];
+    if (!seen.insert(p).second)
+      return fail(PC_ERROR_INVALID_VALUE, "plan of instance " + std::to_string(i) +
+                                              " appears twice (instances share a plan's workspace)");
     if (p->path != 2)
       return fail(PC_ERROR_INVALID_VALUE, "batches take 2D full-grid plans (sectioned plans: use PC_PLAN_FULL_GRID)");
     if (device < 0) device = p->device;
     if (p->device != device) return fail(PC_ERROR_INVALID_VALUE, "plans of a batch must share a device");
-    in[i] = inputs[i];
-    if (fwd_outputs) fo[i] = fwd_outputs[i];
-    if (adj_outputs) fa[i] = adj_outputs[i];
-    if (!in[i] || (fwd_outputs && !fo[i]) || (adj_outputs && !fa[i]))
-      return fail(PC_ERROR_INVALID_VALUE, "null buffer for instance " + std::to_string(i));
-    const size_t bytes = (size_t)(p->d.batch * p->n_total) * sizeof(float);
-    if ((fo[i] && overlaps(in[i], fo[i], bytes)) || (fa[i] && overlaps(in[i], fa[i], bytes)))
-      return fail(PC_ERROR_INVALID_VALUE, "input and output buffers overlap for instance " + std::to_string(i));
   }
   pc_batch_s* b = new (std::nothrow) pc_batch_s();
   if (!b) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
   b->device = device;
   b->plans.assign(plans, plans + count);
-  b->has_fwd = fwd_outputs != nullptr;
-  b->has_adj = adj_outputs != nullptr;
+  b->has_fwd = b->has_adj = true;
   b->use_graph = !(flags & PC_BATCH_NO_GRAPH);
   DeviceGuard g(device);
-  pc_status st = build_batch(b, in.data(), fo.data(), fa.data());
+  const size_t tab_bytes = (size_t)4 * count * sizeof(float*);
+  pc_status st = PC_SUCCESS;
+  {
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, tab_bytes);
+    if (e != hipSuccess) {
+      st = fail_hip(e, "hipMalloc");
+    } else {
+      b->allocs.push_back(d);
+      b->dtab = static_cast<float**>(d);
+      void* h = nullptr;
+      e = hipHostMalloc(&h, tab_bytes, hipHostMallocDefault);
+      if (e != hipSuccess) st = fail_hip(e, "hipHostMalloc");
+      b->htab = static_cast<float**>(h);
+      for (int c = 0; c < 2 && !st; ++c) {
+        e = hipEventCreateWithFlags(&b->ev[c], hipEventDisableTiming);
+        if (e != hipSuccess) st = fail_hip(e, "hipEventCreate");
+      }
+    }
+  }
+  if (!st) st = build_batch(b, nullptr, nullptr, nullptr);
   if (!st && b->use_graph) {
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) {
       st = fail_hip(e, "hipStreamCreate");
     } else {
-      if (b->has_fwd) st = capture(b->fwd_seq, cs, &b->gf, &b->ef);
-      if (!st && b->has_adj) st = capture(b->adj_seq, cs, &b->ga, &b->ea);
+      st = capture(b->fwd_seq, cs, &b->gf, &b->ef);
+      if (!st) st = capture(b->adj_seq, cs, &b->ga, &b->ea);
       (void)hipStreamDestroy(cs);
     }
   }
@@ -1362,32 +1447,92 @@ pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, co
   {
     std::lock_guard<std::mutex> lk(g_registry_mu);
     g_batches.insert(b);
+    for (pc_plan p : b->plans) ++p->batch_refs;
   }
   *out = b;
   return PC_SUCCESS;
 }
 
-static pc_status batch_run(pc_batch b, bool adjoint, void* stream) {
+namespace {
+
+// Every input and output of a batch call non-null; an instance's output
+// overlaps neither another output nor any input (inputs may overlap each
+// other: they are only read).
+pc_status check_batch_buffers(pc_batch b, const float* const* inputs, float* const* outputs) {
+  if (!inputs || !outputs) return fail(PC_ERROR_INVALID_VALUE, "null input or output array");
+  struct Span {
+    uintptr_t a, e;
+    size_t i;
+  };
+  std::vector<Span> outs, ins;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    if (!inputs[i] || !outputs[i]) return fail(PC_ERROR_INVALID_VALUE, "null buffer for instance " + std::to_string(i));
+    const size_t bytes = (size_t)(b->plans[i]->d.batch * b->plans[i]->n_total) * sizeof(float);
+    outs.push_back({reinterpret_cast<uintptr_t>(outputs[i]), reinterpret_cast<uintptr_t>(outputs[i]) + bytes, i});
+    ins.push_back({reinterpret_cast<uintptr_t>(inputs[i]), reinterpret_cast<uintptr_t>(inputs[i]) + bytes, i});
+  }
+  std::sort(outs.begin(), outs.end(), [](const Span& x, const Span& y) { return x.a < y.a; });
+  for (size_t k = 1; k < outs.size(); ++k)
+    if (outs[k].a < outs[k - 1].e)
+      return fail(PC_ERROR_INVALID_VALUE, "outputs of instances " + std::to_string(outs[k - 1].i) + " and " +
+                                              std::to_string(outs[k].i) + " overlap");
+  for (const Span& x : ins) {
+    // the first output starting at or after x.a, and the one before it
+    auto it = std::lower_bound(outs.begin(), outs.end(), x.a, [](const Span& o, uintptr_t v) { return o.a < v; });
+    if ((it != outs.end() && it->a < x.e) || (it != outs.begin() && std::prev(it)->e > x.a))
+      return fail(PC_ERROR_INVALID_VALUE, "input of instance " + std::to_string(x.i) + " overlaps an output");
+  }
+  return PC_SUCCESS;
+}
+
+}  // namespace
+
+static pc_status batch_run(pc_batch b, bool adjoint, const float* const* inputs, float* const* outputs,
+                           void* stream) {
   pc_status st = check_batch(b);
   if (st) return st;
-  if (adjoint ? !b->has_adj : !b->has_fwd)
-    return fail(PC_ERROR_INVALID_VALUE, "the batch was created without outputs for this direction");
+  if ((st = check_batch_buffers(b, inputs, outputs))) return st;
   DeviceGuard g(b->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const int c = adjoint ? 1 : 0;
+  const size_t n = b->plans.size();
+  std::vector<float*> cur(2 * n);
+  for (size_t i = 0; i < n; ++i) {
+    cur[2 * i] = const_cast<float*>(inputs[i]);  // read only: the kernels take it as const
+    cur[2 * i + 1] = outputs[i];
+  }
+  if (cur != b->last[c]) {
+    // the staging slot is rewritten only once its previous upload has run
+    hipError_t e = hipEventSynchronize(b->ev[c]);
+    if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    std::copy(cur.begin(), cur.end(), b->htab + c * 2 * n);
+    e = hipMemcpyAsync(b->dtab + c * 2 * n, b->htab + c * 2 * n, 2 * n * sizeof(float*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[c], s);
+    if (e != hipSuccess) {
+      b->last[c].clear();
+      return fail_hip(e, "batch pointer upload");
+    }
+    b->last[c] = cur;
+  }
   if (!b->use_graph) return run_seq(adjoint ? b->adj_seq : b->fwd_seq, s);
   hipError_t e = hipGraphLaunch(adjoint ? b->ea : b->ef, s);
   if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
   return PC_SUCCESS;
 }
 
-pc_status pc_batch_apply(pc_batch b, void* stream) { return batch_run(b, false, stream); }
-pc_status pc_batch_apply_adjoint(pc_batch b, void* stream) { return batch_run(b, true, stream); }
+pc_status pc_batch_apply(pc_batch b, const float* const* inputs, float* const* outputs, void* stream) {
+  return batch_run(b, false, inputs, outputs, stream);
+}
+pc_status pc_batch_apply_adjoint(pc_batch b, const float* const* inputs, float* const* outputs, void* stream) {
+  return batch_run(b, true, inputs, outputs, stream);
+}
 
 pc_status pc_batch_destroy(pc_batch b) {
   {
     std::lock_guard<std::mutex> lk(g_registry_mu);
     if (!b || !g_batches.count(b)) return fail(PC_ERROR_INVALID_VALUE, "batch handle is not a live batch");
     g_batches.erase(b);
+    for (pc_plan p : b->plans) --p->batch_refs;
   }
   DeviceGuard g(b->device);
   hipError_t e = hipDeviceSynchronize();
@@ -1451,6 +1596,9 @@ pc_status pc_destroy(pc_plan p) {
   {
     std::lock_guard<std::mutex> g(g_registry_mu);
     if (!p || !g_registry.count(p)) return fail(PC_ERROR_INVALID_PLAN, "plan handle is not a live plan");
+    if (p->batch_refs > 0)
+      return fail(PC_ERROR_INVALID_VALUE, "the plan is held by " + std::to_string(p->batch_refs) +
+                                              " live batch(es); destroy them first");
     g_registry.erase(p);
   }
   DeviceGuard g(p->device);
@@ -1661,7 +1809,7 @@ pc_status pc_wavelet_transform(int32_t inverse, int64_t n, int32_t levels, int32
   pc_status st = make_filter(taps, lowpass, f);
   if (st) return st;
   if (!is_pow2(n) || n < 2) return fail(PC_ERROR_INVALID_VALUE, "n must be a power of two >= 2");
-  if (levels < 0 || (n >> levels) < 1 || levels > 62) return fail(PC_ERROR_INVALID_VALUE, "levels out of range");
+  if (levels < 0 || levels > 62 || (n >> levels) < 1) return fail(PC_ERROR_INVALID_VALUE, "levels out of range");
   if (count < 1 || stride < 1 || dist < 1) return fail(PC_ERROR_INVALID_VALUE, "count, stride, dist must be >= 1");
   if (!in || !out || in == out) return fail(PC_ERROR_INVALID_VALUE, "null or identical in/out");
   hipStream_t s = static_cast<hipStream_t>(stream);

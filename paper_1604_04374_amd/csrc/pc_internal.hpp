@@ -150,6 +150,15 @@ struct RowJob {
   // is (g1, g2), both axes wrapped; needs N1 <= gN1, L2 <= gN2, g1 < gN1,
   // g2 < gN2
   int gN1 = 0, gN2 = 0, g1 = 0, g2 = 0;
+  // batches: the input (row-forward) or output (row-inverse) pointer is read
+  // from this device table entry at run time, so that each call can name
+  // new buffers; null: x / y / the launch's pointer argument
+  const float* const* xp = nullptr;
+  float* const* yp = nullptr;
+  // row-inverse, section evaluation (oN2 > 0): row r < orows of the job's
+  // image img is written, columns n2 < ocols only, to image img of the output
+  // (oN1 x oN2 samples) at ((o1 + r) mod oN1, (o2 + n2) mod oN2)
+  int oN1 = 0, oN2 = 0, o1 = 0, o2 = 0, orows = 0, ocols = 0;
 };
 
 // One instance of a column pass (column transforms of length N1).
@@ -165,6 +174,11 @@ struct ColJob {
   // adjoint pass of a single-term job: transform src's columns first, in
   // registers (no separate k_cols_fft pass and plane round trip)
   int fft_src = 0;
+  // rows of the columns known to matter (0: all N1): the forward pass reads
+  // src entries n1 < nvalid_in only (the rest are zero: rows the row pass
+  // skipped), the adjoint pass writes dst entries n1 < nvalid_out only (the
+  // rest are never read)
+  int nvalid_in = 0, nvalid_out = 0;
 };
 
 // Block of a table-driven launch: job, image, block within the image,
@@ -234,12 +248,14 @@ int row_block_rows(int L2, bool small = false);
 int col_block_cols(int L1);
 int row_threads(int L2, bool small = false);
 int col_threads(int L1);
+// rows: the leading rows of each image the blocks cover (0: all N1; rounded
+// up to whole row blocks)
 void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq,
-                       bool small = false);
+                       bool small = false, int rows = 0);
 void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H2, int L1, int nsub);
 const char* kernel_kind_name(int kind);
-// img_limit: row-forward blocks of images >= img_limit return at once (their
-// input need not exist)
+// img_limit: blocks of images >= img_limit return at once (their input and
+// output need not exist)
 LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg, float* y_arg, hipStream_t s,
                         Tracer* tr, int64_t img_limit = INT64_MAX);
 // h (m x N1 x N2, lag layout) -> Hs, through the plan's spectra launch sets
@@ -289,6 +305,9 @@ struct Sec2D {
   const int* tf_items;
   const int* ta_off;
   const int* ta_items;
+  // the window boxes partition the image: the adjoint's row-inverse pass
+  // writes the output itself (no staging, no overlap-add)
+  bool direct_adj = false;
 };
 constexpr int SEC_TILE_R = 32, SEC_TILE_C = 32;  // tile sides divide every supported size (>= 64, 2^a or 3 x 2^a)
 // every output pixel of the first `batch` images <- sum of the sections covering it

@@ -131,7 +131,7 @@ def test_set_responses_on_invalid_plan(lib):
     assert lib.pc_plan_set_responses(None, ctypes.c_void_p(4096), None) == 5
 
 
-@pytest.mark.parametrize("kw", [dict(n=96), dict(n=1), dict(levels=11), dict(levels=-1), dict(taps=3),
+@pytest.mark.parametrize("kw", [dict(n=96), dict(n=1), dict(levels=11), dict(levels=-1), dict(levels=64), dict(levels=100), dict(taps=3),
                                 dict(taps=22), dict(count=0), dict(stride=0), dict(same=True)])
 def test_wavelet_transform_rejects_bad_arguments(lib, kw):
     lp = np.ones(kw.get("taps", 4), dtype=np.float32)

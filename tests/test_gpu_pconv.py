@@ -165,9 +165,9 @@ def test_batch_mixing_both_kinds(graph):
     plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch, product_convolution=k, full_grid=True)
              for p, k in zip(probs, kinds)]
     inputs = [torch.from_numpy(p.u).cuda() for p in probs]
-    b = pcm.Batch(plans, inputs, graph=graph)
-    y = [t.clone() for t in b.apply()]
-    x = [t.clone() for t in b.apply_adjoint()]
+    b = pcm.Batch(plans, graph=graph)
+    y = [t.clone() for t in b.apply(inputs)]
+    x = [t.clone() for t in b.apply_adjoint(inputs)]
     torch.cuda.synchronize()
     for i, (p, k) in enumerate(zip(probs, kinds)):
         w, h, u = p.dense_windows(), p.h.astype(np.float64), p.u.astype(np.float64)

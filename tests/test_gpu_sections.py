@@ -135,7 +135,7 @@ def test_spectra_and_batches_need_full_grid_plans():
             plan.get_spectra()
         assert ei.value.status == 2
         with pytest.raises(pcm.PCError) as ei:
-            pcm.Batch([plan], [u])
+            pcm.Batch([plan])
         assert ei.value.status == 1
 
 
