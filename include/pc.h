@@ -346,6 +346,23 @@ pc_status pc_plan_create_meyer(pc_plan* out, int64_t n, int32_t levels, int32_t 
                                uint32_t flags, void* stream);
 
 /*
+ * pc_wavelet_transform_noalloc - pc_wavelet_transform for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments,
+ * results and errors; it calls no allocation routine and does not wait:
+ * the work is enqueued on `stream` and the call returns.  Its scratch is a
+ * fixed device array of 16 MiB per device (4194304 floats), kept until the
+ * process ends and shared by every call of this function on that device, so
+ * such calls that overlap on one device (several streams, several host
+ * threads) race; calls ordered on one stream do not.  Limit: count * n <=
+ * 4194304; larger requests return PC_ERROR_INVALID_VALUE before anything is
+ * launched.
+ */
+pc_status pc_wavelet_transform_noalloc(int32_t inverse, int64_t n, int32_t levels, int32_t taps,
+                                       const float* lowpass, int64_t count, int64_t stride, int64_t dist,
+                                       const float* in, float* out, void* stream);
+
+/*
  * Uneven batches.  A batch runs many 2D operators of different sizes and
  * term counts together: every pass of the evaluation is one launch per
  * transform length (the work of all instances with that row or column

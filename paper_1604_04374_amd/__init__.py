@@ -43,7 +43,7 @@ EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_p
            "pc_plan_set_spectra", "pc_plan_get_spectra", "pc_grad_spectra",
            "pc_plan_set_tracing", "pc_plan_trace_stats", "pc_plan_trace_reset",
            "pc_plan_set_responses", "pc_construct_project", "pc_construct_interpolate",
-           "pc_wavelet_transform", "pc_plan_create_meyer",
+           "pc_wavelet_transform", "pc_wavelet_transform_noalloc", "pc_plan_create_meyer",
            "pc_batch_create", "pc_batch_apply", "pc_batch_apply_adjoint", "pc_batch_destroy",
            "pc_status_string", "pc_last_error")
 
@@ -133,6 +133,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_wavelet_transform.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_int32, vp, i64, i64, i64,
                                          vp, vp, vp]
     lib.pc_wavelet_transform.restype = ctypes.c_int
+    lib.pc_wavelet_transform_noalloc.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_int32, vp, i64, i64, i64,
+                                         vp, vp, vp]
+    lib.pc_wavelet_transform_noalloc.restype = ctypes.c_int
     lib.pc_plan_create_meyer.argtypes = [ctypes.POINTER(vp), i64, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp,
                                          vp, i64, ctypes.c_uint32, vp]
     lib.pc_plan_create_meyer.restype = ctypes.c_int
@@ -441,9 +444,13 @@ def construct_interpolate(samples, lags, nodes, windows, stream=None):
     return h
 
 
-def wavelet_transform(x, lowpass, levels, inverse=False, axis=-1, stream=None):
+def wavelet_transform(x, lowpass, levels, inverse=False, axis=-1, stream=None, out=None, no_alloc=False):
     """Periodic orthonormal DWT (or its inverse) of a float32 CUDA tensor
-    along ``axis`` (``x`` 1D, or 2D with axis 0 or 1), pyramid order."""
+    along ``axis`` (``x`` 1D, or 2D with axis 0 or 1), pyramid order.
+
+    ``no_alloc=True`` calls ``pc_wavelet_transform_noalloc`` (fixed scratch,
+    no device allocation, asynchronous; pass ``out`` to keep torch from
+    allocating too)."""
     import torch
     lib = load_library()
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32) or x.dim() not in (1, 2):
@@ -456,11 +463,15 @@ def wavelet_transform(x, lowpass, levels, inverse=False, axis=-1, stream=None):
         count, n, stride, dist = x.shape[0], x.shape[1], 1, x.shape[1]
     else:
         count, n, stride, dist = x.shape[1], x.shape[0], x.shape[1], 1
-    out = torch.empty_like(x)
-    st = lib.pc_wavelet_transform(1 if inverse else 0, n, int(levels), lp.shape[0], lp.ctypes.data_as(ctypes.c_void_p),
-                                  count, stride, dist, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                  ctypes.c_void_p(_stream_ptr(stream, x.device)))
-    _check(lib, st, "pc_wavelet_transform")
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor shaped like x")
+    fn = lib.pc_wavelet_transform_noalloc if no_alloc else lib.pc_wavelet_transform
+    st = fn(1 if inverse else 0, n, int(levels), lp.shape[0], lp.ctypes.data_as(ctypes.c_void_p),
+            count, stride, dist, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(_stream_ptr(stream, x.device)))
+    _check(lib, st, "pc_wavelet_transform_noalloc" if no_alloc else "pc_wavelet_transform")
     return out
 
 

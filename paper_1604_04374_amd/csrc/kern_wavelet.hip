@@ -12,6 +12,8 @@
 //   i = ((p - k) / 2) mod (len / 2).
 // Vector b's element i lives at base + b * dist + i * stride, so a 2D
 // transform is a pass over rows (stride 1) and one over columns (dist 1).
+#include <mutex>
+
 #include "pc_internal.hpp"
 
 namespace pc {
@@ -142,6 +144,45 @@ LaunchStatus launch_wavelet(bool synthesis, int64_t n, int levels, const Wavelet
     e = hipGetLastError();
   }
   return e;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free transforms: the two ping-pong buffers live in a fixed
+// device array instead of the library's grow-only scratch.  Each device
+// holds its own copy of the array; its address is looked up once per device
+// (with that device current) and kept.  The array is shared by every such
+// call on a device, so calls that overlap on one device race; every entry a
+// level reads was written by the level before it in the same call, so
+// nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[WAVELET_STATIC_FLOATS];
+
+namespace {
+std::mutex g_static_mu;
+float* g_static_ptr[64] = {};  // per device
+}  // namespace
+
+LaunchStatus launch_wavelet_static(bool synthesis, int64_t n, int levels, const WaveletFilter& f, int64_t count,
+                                   int64_t stride, int64_t dist, const float* in, float* out, hipStream_t s) {
+  if (count * (n / 2) > WAVELET_STATIC_FLOATS / 2) return hipErrorInvalidValue;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  float* base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (!g_static_ptr[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      g_static_ptr[dev] = static_cast<float*>(ptr);
+    }
+    base = g_static_ptr[dev];
+  }
+  float* s1 = base;
+  float* s2 = base + WAVELET_STATIC_FLOATS / 2;
+  return launch_wavelet(synthesis, n, levels, f, count, stride, dist, in, out, s1, s2, s);
 }
 
 }  // namespace pc

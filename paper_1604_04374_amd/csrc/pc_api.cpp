@@ -1825,6 +1825,26 @@ pc_status pc_wavelet_transform(int32_t inverse, int64_t n, int32_t levels, int32
   return PC_SUCCESS;
 }
 
+pc_status pc_wavelet_transform_noalloc(int32_t inverse, int64_t n, int32_t levels, int32_t taps,
+                                       const float* lowpass, int64_t count, int64_t stride, int64_t dist,
+                                       const float* in, float* out, void* stream) {
+  pc::WaveletFilter f;
+  pc_status st = make_filter(taps, lowpass, f);
+  if (st) return st;
+  if (!is_pow2(n) || n < 2) return fail(PC_ERROR_INVALID_VALUE, "n must be a power of two >= 2");
+  if (levels < 0 || levels > 62 || (n >> levels) < 1) return fail(PC_ERROR_INVALID_VALUE, "levels out of range");
+  if (count < 1 || stride < 1 || dist < 1) return fail(PC_ERROR_INVALID_VALUE, "count, stride, dist must be >= 1");
+  if (!in || !out || in == out) return fail(PC_ERROR_INVALID_VALUE, "null or identical in/out");
+  if (count > pc::WAVELET_STATIC_FLOATS / n)
+    return fail(PC_ERROR_INVALID_VALUE, "count * n = " + std::to_string(count) + " * " + std::to_string(n) +
+                                            " exceeds the fixed scratch (" +
+                                            std::to_string(pc::WAVELET_STATIC_FLOATS) + " samples per call)");
+  hipError_t e = pc::launch_wavelet_static(inverse != 0, n, levels, f, count, stride, dist, in, out,
+                                           static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail_hip(e, "pc_wavelet_transform_noalloc launch");
+  return PC_SUCCESS;
+}
+
 pc_status pc_plan_create_meyer(pc_plan* out, int64_t n, int32_t levels, int32_t taps, const float* lowpass,
                                int64_t count, const int64_t* lam, const int64_t* mu, const float* c, int64_t batch,
                                uint32_t flags, void* stream) {

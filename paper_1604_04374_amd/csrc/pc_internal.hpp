@@ -349,5 +349,12 @@ struct WaveletFilter {
 LaunchStatus launch_wavelet(bool synthesis, int64_t n, int levels, const WaveletFilter& f, int64_t count,
                             int64_t stride, int64_t dist, const float* in, float* out, float* s1, float* s2,
                             hipStream_t s);
+// The same transform with its two scratch buffers in a fixed device array
+// of WAVELET_STATIC_FLOATS floats per device (no allocation): needs
+// count * (n / 2) <= WAVELET_STATIC_FLOATS / 2 (hipErrorInvalidValue
+// otherwise, nothing launched).  Calls that overlap on one device race.
+constexpr int64_t WAVELET_STATIC_FLOATS = (int64_t)1 << 22;  // 16 MiB per device
+LaunchStatus launch_wavelet_static(bool synthesis, int64_t n, int levels, const WaveletFilter& f, int64_t count,
+                                   int64_t stride, int64_t dist, const float* in, float* out, hipStream_t s);
 
 }  // namespace pc

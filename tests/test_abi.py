@@ -154,3 +154,14 @@ def test_meyer_plan_rejects_bad_coefficients(lib):
                                       la.ctypes.data_as(ctypes.c_void_p), mu_.ctypes.data_as(ctypes.c_void_p),
                                       c.ctypes.data_as(ctypes.c_void_p), 1, 0, None)
         assert st == 1 and out.value is None
+
+
+def test_noalloc_wavelet_transform_rejects_oversize_requests(lib):
+    # host-side check: nothing is launched for a request beyond the fixed scratch
+    lp = np.ones(4, dtype=np.float32)
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    st = lib.pc_wavelet_transform_noalloc(0, 1 << 20, 3, 4, lp.ctypes.data_as(ctypes.c_void_p), 5, 1, 1 << 20, a, b,
+                                          None)
+    assert st == 1 and b"exceeds the fixed scratch" in lib.pc_last_error()
+    st = lib.pc_wavelet_transform_noalloc(0, 96, 3, 4, lp.ctypes.data_as(ctypes.c_void_p), 1, 1, 96, a, b, None)
+    assert st == 1
