@@ -148,8 +148,8 @@ WORKLOADS = {
     "c3": "2D 1024x1024, m=16 (4x4 separable hat grid), anisotropic Gaussian PSF 1->4 px, batch 1",
     "c4": "256 uneven 2D instances, sides in {128,192,256,384,512}, m in {4,9,16}, one plan each",
     "c5": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1",
-    "c5ad": "2D 2048x2048, m=64 tiles: autograd step of 0.5||H_m u - f||^2 (forward, adjoint for du, "
-            "spectra gradient), against the plain forward + adjoint",
+    "c5ad": "2D 2048x2048, m=64 tiles, sectioned: autograd step of 0.5||H_m u - f||^2 (forward, du and the "
+            "sections' spectra gradient from one backward call), against the plain forward + adjoint",
     "c2pc": "1D batch 64 x N=65536, m=32 cubic B-spline windows, Gaussian h_k, product-convolution form "
             "G_m u = sum_k w_k . (h_k * u); step = G_m u + G_m^* u",
     "c5full": "2D 2048x2048, m=64 (8x8 tile windows), Gaussian PSFs, batch 1, evaluated on the full grid "
@@ -163,9 +163,8 @@ WORKLOADS = {
 MEYER_LEVELS = 11
 MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PRODUCT_CONVOLUTION = {"c2pc"}
-# batched instances must be full-grid plans; c5full measures C5 without sections;
-# the autograd step (gradients) runs on the full grid, and so do its counts
-FULL_GRID = {"c4", "c5full", "c5ad"}
+# batched instances must be full-grid plans; c5full measures C5 without sections
+FULL_GRID = {"c4", "c5full"}
 
 
 def make_problems(name):

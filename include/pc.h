@@ -62,8 +62,10 @@ enum {
 
 /* Plan flags. */
 enum {
-  /* Allocate, at plan creation, the workspace pc_grad_spectra needs (one
-   * spectrum-sized buffer); without it pc_grad_spectra returns
+  /* Allocate, at plan creation, the workspace pc_grad_spectra and
+   * pc_backward need (one spectrum-sized buffer), and keep the windowed
+   * spectra of pc_apply_save calls within the plan's budget (default 1 GiB,
+   * pc_plan_set_budget); without it the spectra gradients return
    * PC_ERROR_INVALID_VALUE. */
   PC_PLAN_GRADIENTS = 1u,
   /* The plan represents the product-convolution expansion of the
@@ -76,19 +78,18 @@ enum {
    * flipped responses h~_k, such a plan runs the same kernels with the two
    * directions exchanged. */
   PC_PLAN_PRODUCT_CONVOLUTION = 2u,
-  /* 2D: always evaluate on the full N1 x N2 grid.  Without this flag (and
-   * without PC_PLAN_GRADIENTS), a 2D plan whose windows and impulse
-   * responses have small supports is evaluated section by section (the
-   * compact-support complexity lemma of section 3.5, Lemma 3.2): term k
-   * runs on an M1 x M2 section with M >= p + q - 1 per axis (p, q: the
-   * circular supports of w_k and h_k), and the sections are added into the
-   * result.  The plan takes this route only when it is estimated to be at
-   * least twice as cheap; pc_plan_query reports it as path 3.  Sectioned
-   * plans keep only per-section spectra: the spectra calls return
-   * PC_ERROR_UNSUPPORTED for them, and they cannot join a batch.  They read
-   * only the call's batch of input images, but their later passes run over
-   * the full batch capacity, so a smaller batch costs about as much as a
-   * full one. */
+  /* 2D: always evaluate on the full N1 x N2 grid.  Without this flag, a 2D
+   * plan whose windows and impulse responses have small supports is
+   * evaluated section by section (the compact-support complexity lemma of
+   * section 3.5, Lemma 3.2): term k runs on an M1 x M2 section with
+   * M >= p + q - 1 per axis (p, q: the circular supports of w_k and h_k),
+   * and the sections are added into the result.  The plan takes this route
+   * only when it is estimated to be at least twice as cheap (never for a
+   * product-convolution plan with gradients); pc_plan_query reports it as
+   * path 3 and pc_plan_sections lists the sections.  A sectioned plan's
+   * parameters are its sections' spectra (see the spectra calls); it cannot
+   * join a batch, and pc_plan_set_responses returns PC_ERROR_UNSUPPORTED for
+   * it.  Every pass skips images beyond the call's batch. */
   PC_PLAN_FULL_GRID = 4u
 };
 
@@ -181,6 +182,8 @@ typedef struct {
   int64_t spectra_bytes; /* device bytes of the stored spectra */
   int64_t window_bytes;  /* device bytes of the stored (compacted) windows */
   int64_t workspace_bytes;
+  int64_t keep_bytes;    /* device bytes held for the windowed spectra of pc_apply_save (0: recomputed) */
+  int64_t spectra_count; /* complex entries of the spectra layout of pc_plan_get_spectra */
 } pc_plan_info;
 
 /* pc_plan_query - fill *info.  Errors: INVALID_PLAN, INVALID_VALUE. */
@@ -209,11 +212,41 @@ pc_status pc_plan_trace_stats(pc_plan plan, pc_kernel_stat* stats, int32_t capac
 pc_status pc_plan_trace_reset(pc_plan plan);
 
 /*
+ * Sections of a sectioned plan (path 3), in the plan's order: term k, the
+ * section's size, the window box and the impulse response's lag box (origin
+ * and extent per axis, origins modulo the image size), and the offset of the
+ * section's spectrum in the spectra layout.  Section s evaluates
+ * h_k * (w_k . u) restricted to the window box, on an M1 x M2 grid whose
+ * origin is the window box origin, with the response shifted by its lag box
+ * origin; its output box (p + q - 1 samples per axis) is added into the
+ * result at window origin + lag origin.
+ */
+typedef struct {
+  int32_t term;
+  int32_t m1, m2;
+  int32_t win_o1, win_p1, win_o2, win_p2;
+  int32_t lag_o1, lag_q1, lag_o2, lag_q2;
+  int64_t spec_offset;
+} pc_section_info;
+/* pc_plan_sections - *count receives the number of sections (0 unless
+ * sectioned); up to `capacity` entries are copied into `info` (host).
+ * Errors: INVALID_PLAN, INVALID_VALUE (null count, or null info with
+ * capacity > 0). */
+pc_status pc_plan_sections(pc_plan plan, pc_section_info* info, int32_t capacity, int32_t* count);
+
+/*
  * Spectra as parameters.  The operator's spectra F^* h_k (section 3.5) can be
  * read and replaced, in the natural layout of a real FFT:
  *   1D: m x (N/2 + 1) complex64 (interleaved re, im), spec[k][f];
  *   2D: m x N1 x (N2/2 + 1) complex64, spec[k][f1][f2] (the layout of a 2D
- *       real FFT over the last axis, then a complex FFT over the first).
+ *       real FFT over the last axis, then a complex FFT over the first);
+ *   sectioned 2D: the sections' spectra one after another, section s an
+ *       M1 x (M2/2 + 1) array at spec_offset (pc_plan_sections): the real
+ *       FFT of its shifted response on the section grid.  The operator a
+ *       sectioned plan applies is the sum of its sections, so these spectra
+ *       are its parameters (a section whose spectrum no longer comes from a
+ *       response within its lag box is evaluated circularly on its grid).
+ *       Product-convolution sectioned plans only export them.
  * The represented h_k are real: on import, the imaginary parts of the 1D DC
  * and Nyquist bins are ignored, as an inverse real transform ignores them;
  * in 2D the imaginary parts discarded after the column transforms (DC and
@@ -233,7 +266,10 @@ pc_status pc_plan_get_spectra(pc_plan plan, void* spec, void* stream);
  * N the number of samples per signal, c_f = 1 on the bins of the last axis
  * that stand alone (DC, Nyquist), 2 on those that stand for a conjugate
  * pair; complex convention dL/dRe + i dL/dIm, summed over the batch.  Layout
- * of gspec as for pc_plan_set_spectra.  The windowed spectra F^*(w_k . u_b)
+ * of gspec as for pc_plan_set_spectra.  For a sectioned plan the same
+ * formula holds per section on its M1 x M2 grid (N = M1 M2), with u_b the
+ * section's window box of u and gy_b its output box of gy (zero elsewhere
+ * on the section grid).  The windowed spectra F^*(w_k . u_b)
  * are recomputed from u rather than stored.  The plan must have been
  * created with PC_PLAN_GRADIENTS.  u, gy: device, batch x N floats; gspec:
  * device.  Enqueued on `stream`, returns without waiting; uses the plan's
@@ -243,6 +279,42 @@ pc_status pc_plan_get_spectra(pc_plan plan, void* spec, void* stream);
  */
 pc_status pc_grad_spectra(pc_plan plan, const float* u, const float* gy, void* gspec, int64_t batch,
                           void* stream);
+
+/*
+ * The differentiable form of pc_apply (the torch.autograd binding uses it).
+ *
+ * pc_apply_save - pc_apply that also leaves, in the plan, what pc_backward
+ *   needs about u: the row transforms of the windowed inputs (2D paths, as
+ *   pc_apply does) and, for a plan with gradients whose windowed spectra
+ *   U_k = F^*(w_k . u_b) fit in its budget, U_k themselves.  Same arguments
+ *   and errors as pc_apply.
+ *
+ * pc_backward - for y = H_m u (G_m u) and gy = dL/dy, computes
+ *   gu = dL/du = H_m^* gy (G_m^* gy) when gu is not NULL, and the spectra
+ *   gradient of pc_grad_spectra into gspec when gspec is not NULL (at least
+ *   one of them).  Both come from one transform of gy on the sectioned and
+ *   2D paths.  With use_saved != 0 the caller states that u holds the values
+ *   it held at the plan's last pc_apply / pc_apply_save call; the plan then
+ *   reuses what that call left, if the call had the same u pointer and batch
+ *   and no other call on the plan has reused its workspace since (otherwise,
+ *   or with use_saved == 0, U_k are recomputed from u).
+ *   u, gy: device, batch x N floats; gu: device, must not overlap u or gy;
+ *   gspec: device, spectra layout.  Enqueued on `stream`, returns without
+ *   waiting.  Errors: INVALID_PLAN, INVALID_VALUE (null u or gy, both
+ *   outputs NULL, gspec without PC_PLAN_GRADIENTS, batch out of range,
+ *   overlapping buffers), HIP.
+ *
+ * pc_plan_set_budget - the device bytes the plan may hold to keep U_k
+ *   between pc_apply_save and pc_backward (they are recomputed when they do
+ *   not fit; 0: always recomputed).  A plan with PC_PLAN_GRADIENTS starts with
+ *   1 GiB; pc_plan_query reports the bytes held (keep_bytes).  Synchronous
+ *   (allocates or frees; waits for the device before freeing).  Errors:
+ *   INVALID_PLAN, INVALID_VALUE (bytes < 0), OUT_OF_MEMORY, HIP.
+ */
+pc_status pc_apply_save(pc_plan plan, const float* u, float* y, int64_t batch, void* stream);
+pc_status pc_backward(pc_plan plan, const float* u, const float* gy, float* gu, void* gspec, int64_t batch,
+                      int32_t use_saved, void* stream);
+pc_status pc_plan_set_budget(pc_plan plan, int64_t bytes);
 
 /*
  * pc_plan_set_responses - replace the impulse responses h_k of a plan by

@@ -18,5 +18,7 @@ Modules
                to the half-spectra of the ``h_k``.
 ``wavelets``   periodic orthonormal Daubechies wavelets and Meyer's operator
                representation (section 4.5).
+``sections``   the sectioned evaluation of Lemma 3.2 as a function of
+               per-section spectra, its adjoint and its spectra gradient.
 """
-from . import expansion, dense, construct, grads, wavelets  # noqa: F401
+from . import expansion, dense, construct, grads, wavelets, sections  # noqa: F401

@@ -45,6 +45,7 @@ EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_p
            "pc_plan_set_responses", "pc_construct_project", "pc_construct_interpolate",
            "pc_wavelet_transform", "pc_wavelet_transform_noalloc", "pc_plan_create_meyer",
            "pc_batch_create", "pc_batch_apply", "pc_batch_apply_adjoint", "pc_batch_destroy",
+           "pc_plan_sections", "pc_apply_save", "pc_backward", "pc_plan_set_budget",
            "pc_status_string", "pc_last_error")
 
 PC_BATCH_NO_GRAPH = 1
@@ -63,7 +64,15 @@ class PlanDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("fft_inner", ctypes.c_int32), ("fft_outer", ctypes.c_int32),
                 ("n_items", ctypes.c_int32), ("spectra_bytes", ctypes.c_int64),
-                ("window_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("window_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("keep_bytes", ctypes.c_int64), ("spectra_count", ctypes.c_int64)]
+
+
+class SectionInfo(ctypes.Structure):
+    _fields_ = [("term", ctypes.c_int32), ("m1", ctypes.c_int32), ("m2", ctypes.c_int32),
+                ("win_o1", ctypes.c_int32), ("win_p1", ctypes.c_int32), ("win_o2", ctypes.c_int32),
+                ("win_p2", ctypes.c_int32), ("lag_o1", ctypes.c_int32), ("lag_q1", ctypes.c_int32),
+                ("lag_o2", ctypes.c_int32), ("lag_q2", ctypes.c_int32), ("spec_offset", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -116,6 +125,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_plan_trace_stats.restype = ctypes.c_int
     lib.pc_plan_trace_reset.argtypes = [vp]
     lib.pc_plan_trace_reset.restype = ctypes.c_int
+    lib.pc_plan_sections.argtypes = [vp, ctypes.POINTER(SectionInfo), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.pc_plan_sections.restype = ctypes.c_int
+    lib.pc_apply_save.argtypes = [vp, vp, vp, i64, vp]
+    lib.pc_apply_save.restype = ctypes.c_int
+    lib.pc_backward.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_int32, vp]
+    lib.pc_backward.restype = ctypes.c_int
+    lib.pc_plan_set_budget.argtypes = [vp, i64]
+    lib.pc_plan_set_budget.restype = ctypes.c_int
     lib.pc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp), ctypes.c_uint32, vp]
     lib.pc_batch_create.restype = ctypes.c_int
     for name in ("pc_batch_apply", "pc_batch_apply_adjoint"):
@@ -179,10 +196,12 @@ class Plan:
         ``w_{k1*m2+k2} = a_k1 (x) b_k2``.
     h : array ``m x N`` / ``m x N1 x N2``, impulse responses in lag layout.
     batch : largest number of signals per call.
-    gradients : allocate the workspace of :meth:`grad_spectra`.
+    gradients : allocate the workspace of :meth:`grad_spectra` and
+        :meth:`backward` (and keep windowed spectra within the budget).
     product_convolution : build ``G_m`` (eq. 1.3) instead of ``H_m``.
     full_grid : 2D: never evaluate section by section (sectioned plans,
-        ``info()["path"] == 3``, cannot read or replace their spectra).
+        ``info()["path"] == 3``, take their sections' spectra as parameters;
+        see :meth:`sections`).
     """
 
     def __init__(self, windows: Union[np.ndarray, Tuple[np.ndarray, np.ndarray]], h: np.ndarray,
@@ -249,6 +268,46 @@ class Plan:
         _check(self._lib, st, "pc_apply")
         return out
 
+    def apply_save(self, u, out=None, stream=None):
+        """:meth:`apply` that leaves in the plan what :meth:`backward` needs
+        (pc_apply_save)."""
+        u, out, batch = self._prep(u, out)
+        st = self._lib.pc_apply_save(self._handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     batch, ctypes.c_void_p(_stream_ptr(stream, u.device)))
+        _check(self._lib, st, "pc_apply_save")
+        return out
+
+    def backward(self, u, gy, want_u=True, want_spectra=True, use_saved=False, stream=None):
+        """(dL/du, dL/dspec) for y = H_m u and gy = dL/dy (pc_backward); either
+        may be skipped (None).  ``use_saved``: u is unchanged since the last
+        :meth:`apply` / :meth:`apply_save` on this plan."""
+        import torch
+        u, _, batch = self._prep(u, None)
+        gy = gy.contiguous()
+        if gy.shape != u.shape or gy.dtype != torch.float32 or not gy.is_cuda:
+            raise ValueError("gy must be a float32 CUDA tensor shaped like u")
+        gu = torch.empty_like(u) if want_u else None
+        gs = torch.empty(self.spectra_shape, dtype=torch.complex64, device=u.device) if want_spectra else None
+        st = self._lib.pc_backward(self._handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                   ctypes.c_void_p(gu.data_ptr() if gu is not None else None),
+                                   ctypes.c_void_p(gs.data_ptr() if gs is not None else None), batch,
+                                   1 if use_saved else 0, ctypes.c_void_p(_stream_ptr(stream, u.device)))
+        _check(self._lib, st, "pc_backward")
+        return gu, gs
+
+    def set_budget(self, nbytes: int):
+        """Device bytes the plan may hold to keep the windowed spectra for
+        :meth:`backward` (pc_plan_set_budget)."""
+        _check(self._lib, self._lib.pc_plan_set_budget(self._handle, int(nbytes)), "pc_plan_set_budget")
+
+    def sections(self) -> list:
+        """The sections of a sectioned plan (pc_plan_sections), as dicts."""
+        n = ctypes.c_int32()
+        _check(self._lib, self._lib.pc_plan_sections(self._handle, None, 0, ctypes.byref(n)), "pc_plan_sections")
+        arr = (SectionInfo * max(n.value, 1))()
+        _check(self._lib, self._lib.pc_plan_sections(self._handle, arr, n.value, ctypes.byref(n)), "pc_plan_sections")
+        return [{f: getattr(arr[i], f) for f, _ in SectionInfo._fields_} for i in range(n.value)]
+
     def apply_adjoint(self, v, out=None, stream=None):
         """``x = H_m^* v``."""
         v, out, batch = self._prep(v, out)
@@ -265,8 +324,15 @@ class Plan:
 
     @property
     def spectra_shape(self):
-        """Shape of the natural-layout spectra: (m, N/2+1) or (m, N1, N2/2+1)."""
-        return (self.m,) + tuple(self.shape[:-1]) + (self.shape[-1] // 2 + 1,)
+        """Shape of the natural-layout spectra: (m, N/2+1) or (m, N1, N2/2+1);
+        for a sectioned plan the flat concatenation of its sections' spectra."""
+        if getattr(self, "_spec_shape", None) is None:
+            inf = self.info()
+            if inf["path"] == 3:
+                self._spec_shape = (int(inf["spectra_count"]),)
+            else:
+                self._spec_shape = (self.m,) + tuple(self.shape[:-1]) + (self.shape[-1] // 2 + 1,)
+        return self._spec_shape
 
     def get_spectra(self, out=None, stream=None):
         """The operator's spectra as a complex64 CUDA tensor (real-FFT layout)."""

@@ -1,10 +1,12 @@
 """torch.autograd support: the expansion as a differentiable function of the
 signal and of the spectra of its impulse responses.
 
-Forward runs ``pc_apply``; backward runs the hand-written adjoint
-(``pc_apply_adjoint``) for the signal and ``pc_grad_spectra`` for the
-spectra.  Spectra use the natural layout of a real FFT (``torch.fft.rfft`` /
-``rfft2``), complex64.
+Forward runs ``pc_apply_save`` (which leaves in the plan what the backward
+pass reuses); backward runs ``pc_backward``: the hand-written adjoint for the
+signal and the spectra gradient, from one transform of the output gradient.
+Spectra use the natural layout of a real FFT (``torch.fft.rfft`` /
+``rfft2``), complex64; a sectioned plan's parameters are its sections'
+spectra, concatenated (``Plan.sections``).
 """
 from __future__ import annotations
 
@@ -31,19 +33,21 @@ class ExpansionFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u, spec, plan):
         _load(plan, spec)
-        y = plan.apply(u.contiguous())
+        u = u.contiguous()
+        y = plan.apply_save(u)
         ctx.plan = plan
         ctx.save_for_backward(u, spec)
         return y
 
     @staticmethod
     def backward(ctx, gy):
+        # autograd raises before this point if u was modified in place since
+        # the forward, so the plan may reuse what the forward left
         u, spec = ctx.saved_tensors
         plan = ctx.plan
         _load(plan, spec)
-        gy = gy.contiguous()
-        gu = plan.apply_adjoint(gy) if ctx.needs_input_grad[0] else None
-        gs = plan.grad_spectra(u.contiguous(), gy) if ctx.needs_input_grad[1] else None
+        gu, gs = plan.backward(u, gy.contiguous(), want_u=ctx.needs_input_grad[0],
+                               want_spectra=ctx.needs_input_grad[1], use_saved=True)
         return gu, gs, None
 
 
@@ -56,12 +60,17 @@ class ExpansionOperator(torch.nn.Module):
     a product-convolution operator, eq. 1.3) whose spectra are trainable.
 
     ``windows``/``h`` as for :class:`Plan`; the initial spectra are the plan's
-    transform of ``h``.
+    transform of ``h`` (for a sectioned plan, its sections' spectra).
+    ``full_grid`` keeps a 2D operator on the full grid; ``budget`` (bytes)
+    bounds the windowed spectra the plan keeps from forward to backward.
     """
 
-    def __init__(self, windows, h, batch=1, product_convolution=False):
+    def __init__(self, windows, h, batch=1, product_convolution=False, full_grid=False, budget=None):
         super().__init__()
-        self.plan = Plan(windows, h, batch=batch, gradients=True, product_convolution=product_convolution)
+        self.plan = Plan(windows, h, batch=batch, gradients=True, product_convolution=product_convolution,
+                         full_grid=full_grid)
+        if budget is not None:
+            self.plan.set_budget(budget)
         self.spec = torch.nn.Parameter(self.plan.get_spectra())
         torch.cuda.synchronize()
 

@@ -137,13 +137,19 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
     rb = ra + L2;
   }
   float2 v[P];
+  // masked rows and columns count as zero (the gradient's box of the output
+  // gradient); the samples are read anyway (they lie inside the image)
+  const float ma = (jb.mrows > 0 && r >= jb.mrows) ? 0.f : 1.f;
+  const float mb = (jb.mrows > 0 && r + 1 >= jb.mrows) ? 0.f : 1.f;
+  const int mc = jb.mcols > 0 ? jb.mcols : L2;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
     const int o = n2 < wrap ? n2 : n2 - jb.gN2;
     float wa, wb;
     row_weights(jb.wsrc, jb.mode, q, N1, L2, r, n2, wa, wb);
-    v[e] = make_float2(wa * gldf(ra, o), wb * gldf(rb, o));
+    const float mcol = n2 < mc ? 1.f : 0.f;
+    v[e] = make_float2(wa * ma * mcol * gldf(ra, o), wb * mb * mcol * gldf(rb, o));
   }
   float2* my = lds + c * lds_len<L2>();
   fft_wv<L2, P, false, SYNC_WAVE>(v, my, twl, t);
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 // src_q is loaded once and reused for all of them).  ngroups == 1: the
 // inverse column transform of the sum is written to dst; otherwise the
 // partial spectrum goes to part[group] for k_cols_sum_inv.
-template <int L1, bool LATE>
+template <int L1, bool LATE, bool KEEP>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
@@ -352,6 +358,11 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
 #pragma unroll
       for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e));
       fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
+      if (KEEP && valid) {
+        float2* kp = jb.keep + (int64_t)k * jb.keep_stride + img * plane + (int64_t)f2 * L1;
+#pragma unroll
+        for (int e = 0; e < P; ++e) gst(kp, t + T * e, v[e]);
+      }
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma(acc[e], LATE ? gld(Hk, t + T * e) : hv[e], v[e]);
     }
@@ -505,6 +516,75 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   }
 }
 
+// Backward column pass of a single-term job (the sections of Lemma 3.2):
+// one column per FFT slot, all images in turn.  From one transform of the
+// output gradient's column, V = colFFT(src), it forms the adjoint's plane
+// colIFFT(conj(H) . V) (into dst, when want_gu) and the spectra gradient's
+// column sum_b conj(U) . V, with U = colFFT(dst) (the row transforms of the
+// windowed input left by the forward pass) or U read from keep.  dst is read
+// before it is overwritten, column by column, by the same threads.
+template <int L1>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_bwd1(
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw,
+    int64_t img_limit) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  const BlockRef bm = bmap[blockIdx.x];
+  stage_twiddles<L1>(twl, tw);
+  const ColJob& jb = jobs[bm.job];
+  const int H2 = jb.H2;
+  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int f2raw = bm.blk * NF + c;
+  const bool valid = f2raw < H2;
+  const int f2 = valid ? f2raw : H2 - 1;
+  const int64_t plane = (int64_t)L1 * H2;
+  float2* my = lds + c * lds_len<L1>();
+  const float2* Hc = jb.Hs + (int64_t)f2 * L1;
+  // per-thread element counts of the row ranges that matter
+  auto count = [&](int nv) { return nv == 0 ? P : (nv > t ? (nv - t + T - 1) / T : 0); };
+  const int ne_src = count(jb.nv_src), ne_in = count(jb.nvalid_in), ne_out = count(jb.nvalid_out);
+  const int64_t nimg = jb.nimg < img_limit ? jb.nimg : img_limit;
+  float2 ga[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) ga[e] = make_float2(0.f, 0.f);
+  for (int64_t b = 0; b < nimg; ++b) {
+    const int64_t coff = b * plane + (int64_t)f2 * L1;
+    float2 v[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) v[e] = e < ne_src ? gld(jb.src, coff + t + T * e) : make_float2(0.f, 0.f);
+    fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
+    if (jb.grad) {
+      float2 z[P];
+      if (jb.keep) {
+#pragma unroll
+        for (int e = 0; e < P; ++e) z[e] = gld(jb.keep, coff + t + T * e);
+      } else {
+#pragma unroll
+        for (int e = 0; e < P; ++e) z[e] = e < ne_in ? gld(jb.dst, coff + t + T * e) : make_float2(0.f, 0.f);
+        fft_wv<L1, P, false, SYNC_WAVE>(z, my, twl, opaque(t));
+      }
+#pragma unroll
+      for (int e = 0; e < P; ++e) ga[e] = cfma_conj(ga[e], z[e], v[e]);
+    }
+    if (jb.want_gu) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) v[e] = cmulc(v[e], gld(Hc, t + T * e));
+      fft_wv<L1, P, true, SYNC_WAVE>(v, my, twl, opaque(t));
+      if (valid) {
+#pragma unroll
+        for (int e = 0; e < P; ++e)
+          if (e < ne_out) gst(jb.dst, coff + t + T * e, v[e]);
+      }
+    }
+  }
+  if (jb.grad && valid) {
+    float2* gp = jb.grad + (int64_t)f2 * L1;
+#pragma unroll
+    for (int e = 0; e < P; ++e) gst(gp, t + T * e, ga[e]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side: block maps and launches
 // ---------------------------------------------------------------------------
@@ -545,8 +625,8 @@ static bool late_pays(bool multi_term) {
   const int threads = col_threads(L1);
   const int waves = (threads + 63) / 64;
   int early = 0, late = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&early, k_cols_fwd<L1, false>, threads, 0) != hipSuccess) return false;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&late, k_cols_fwd<L1, true>, threads, 0) != hipSuccess) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&early, k_cols_fwd<L1, false, false>, threads, 0) != hipSuccess) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&late, k_cols_fwd<L1, true, false>, threads, 0) != hipSuccess) return false;
   const int early_per_simd = early * waves / 4, late_per_simd = late * waves / 4;
   return late_per_simd > early_per_simd && (!multi_term || early_per_simd <= 2);
 }
@@ -696,10 +776,14 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    if (ls.late)    \
-      hipLaunchKernelGGL((k_cols_fwd<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
-    else            \
-      hipLaunchKernelGGL((k_cols_fwd<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    if (ls.keep && ls.late)    \
+      hipLaunchKernelGGL((k_cols_fwd<LL, true, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    else if (ls.keep)          \
+      hipLaunchKernelGGL((k_cols_fwd<LL, false, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    else if (ls.late)          \
+      hipLaunchKernelGGL((k_cols_fwd<LL, true, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    else                       \
+      hipLaunchKernelGGL((k_cols_fwd<LL, false, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE
@@ -728,6 +812,16 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
 #undef PC_CASE
       }
       break;
+    case KK_COLS_BWD1:
+      switch (ls.L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    hipLaunchKernelGGL(k_cols_bwd1<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    return hipGetLastError();
+        PC_FOR_EACH_L2(PC_CASE)
+#undef PC_CASE
+      }
+      break;
     case KK_COLS_FFT:
       switch (ls.L) {
 #define PC_CASE(LL) \
@@ -750,6 +844,7 @@ const char* kernel_kind_name(int kind) {
     case KK_COLS_SUM: return "cols_sum";
     case KK_COLS_ADJ: return "cols_adj";
     case KK_COLS_FFT: return "cols_fft";
+    case KK_COLS_BWD1: return "cols_bwd";
   }
   return "unknown";
 }
@@ -766,11 +861,20 @@ LaunchStatus launch_spec2d(const Plan2D& p, const float* h, hipStream_t s) {
   return launch_set(p.spec_cols, p.spec_cols.blocks, nullptr, nullptr, s, nullptr);
 }
 
-LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s, Tracer* tr) {
+LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s, Tracer* tr,
+                          bool keep) {
   LaunchStatus e = run(p.fwd_rows, batch, u, nullptr, s, tr);
-  if (e == hipSuccess) e = run(p.fwd_cols, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess) e = run(keep && p.keep ? p.fwd_cols_keep : p.fwd_cols, batch, nullptr, nullptr, s, tr);
   if (e == hipSuccess && p.col_groups > 1) e = run(p.fwd_sum, batch, nullptr, nullptr, s, tr);
   if (e == hipSuccess) e = run(p.fwd_rows_out, batch, nullptr, y, s, tr);
+  return e;
+}
+
+// The adjoint's tail after launch_grad2d left V = colFFT(rowFFT(v)) in Tws
+// (plans with more than one term, whose adjoint column pass takes V).
+LaunchStatus launch_adj2d_tail(const Plan2D& p, float* x, int64_t batch, hipStream_t s, Tracer* tr) {
+  LaunchStatus e = run(p.adj_cols, batch, nullptr, nullptr, s, tr);
+  if (e == hipSuccess) e = run(p.adj_rows_out, batch, nullptr, x, s, tr);
   return e;
 }
 
@@ -871,7 +975,8 @@ static LaunchStatus transpose_spec(const Plan2D& p, const float2* src, float2* d
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d_cols(
     const float2* __restrict__ RA, int64_t q_stride, const float2* __restrict__ Gh, int64_t batch, int H2, int m1,
-    int m2, int dense, const float* __restrict__ wrows, float2* __restrict__ E, const float2* __restrict__ tw) {
+    int m2, int dense, const float* __restrict__ wrows, float2* __restrict__ E, const float2* __restrict__ tw,
+    const float2* __restrict__ keep, int64_t keep_stride) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
@@ -895,12 +1000,18 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d
       const float2* col = RA + q * q_stride + b * plane + (int64_t)f2 * L1;
       const float2* gcol = Gh + b * plane + (int64_t)f2 * L1;
       float2 v[P];
+      if (keep) {  // U_k kept by the forward pass (uniform over the workgroup)
+        const float2* kp = keep + (int64_t)k * keep_stride + b * plane + (int64_t)f2 * L1;
 #pragma unroll
-      for (int e = 0; e < P; ++e) {
-        v[e] = col[t + T * e];
-        if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+        for (int e = 0; e < P; ++e) v[e] = kp[t + T * e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+          v[e] = col[t + T * e];
+          if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+        }
+        fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
       }
-      fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
 #pragma unroll
       for (int e = 0; e < P; ++e) acc[e] = cfma_conj(acc[e], v[e], gcol[t + T * e]);
     }
@@ -913,12 +1024,69 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d
 }
 
 template <int L1>
-static LaunchStatus grad2d_cols_t(const Plan2D& p, int64_t batch, int64_t q_stride, float2* E, hipStream_t s) {
+static LaunchStatus grad2d_cols_t(const Plan2D& p, int64_t batch, int64_t q_stride, float2* E, const float2* keep,
+                                  hipStream_t s) {
   constexpr int NF = ffts_per_block(L1), T = fft_threads(L1);
   const int nblk = (p.H2 + NF - 1) / NF;
   hipLaunchKernelGGL(k_grad2d_cols<L1>, dim3((unsigned)nblk, (unsigned)(p.dense ? p.m : p.m2)), dim3(NF * T), 0, s,
                      p.RA, q_stride,
-                     p.Tws, batch, p.H2, p.m1, p.m2, p.dense ? 1 : 0, p.wrows, E, p.tw1);
+                     p.Tws, batch, p.H2, p.m1, p.m2, p.dense ? 1 : 0, p.wrows, E, p.tw1, keep,
+                     q_stride);
+  return hipGetLastError();
+}
+
+int64_t transpose_blocks(int N1, int H2) {
+  return (int64_t)((N1 + SPEC_TA - 1) / SPEC_TA) * ((H2 + SPEC_TB - 1) / SPEC_TB);
+}
+
+// One workgroup per tile of one job's plane (the job found by a binary
+// search over the jobs' first workgroups); tiles as in k_transpose_spec.
+__global__ __launch_bounds__(SPEC_THREADS) void k_transpose_tab(const TransposeJob* __restrict__ jobs, int njobs,
+                                                               float2* __restrict__ ext, int to_internal) {
+  constexpr int TA = SPEC_TA, TB = SPEC_TB;
+  __shared__ float2 tile[TA][TB + 1];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].block0 <= blk) lo = mid; else hi = mid - 1;
+  }
+  const TransposeJob jb = jobs[lo];
+  const int N1 = jb.N1, H2 = jb.H2;
+  const int nbB = (H2 + TB - 1) / TB;
+  const int64_t b = blk - jb.block0;
+  const int a0 = (int)(b / nbB) * TA, b0 = (int)(b % nbB) * TB;
+  float2* nat = ext + jb.ext_off;
+  for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
+    if (to_internal) {
+      const int i = idx / TB, j = idx % TB;
+      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = nat[(int64_t)(a0 + i) * H2 + b0 + j];
+    } else {
+      const int i = idx % TA, j = idx / TA;
+      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = jb.internal[(int64_t)(b0 + j) * N1 + a0 + i];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
+    if (to_internal) {
+      const int i = idx % TA, j = idx / TA;
+      if (a0 + i < N1 && b0 + j < H2) jb.internal[(int64_t)(b0 + j) * N1 + a0 + i] = tile[i][j];
+    } else {
+      const int i = idx / TB, j = idx % TB;
+      const int f2 = b0 + j;
+      if (a0 + i < N1 && f2 < H2) {
+        float2 v = tile[i][j];
+        if (jb.scale_mode) v = cscale(v, (f2 == 0 || f2 == H2 - 1) ? jb.inv_n : 2.f * jb.inv_n);
+        nat[(int64_t)(a0 + i) * H2 + f2] = v;
+      }
+    }
+  }
+}
+
+LaunchStatus launch_transpose_set(const TransposeSet& ts, float2* ext, bool to_internal, hipStream_t s) {
+  if (ts.blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_tab, dim3((unsigned)ts.blocks), dim3(SPEC_THREADS), 0, s, ts.jobs, ts.njobs, ext,
+                     to_internal ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -928,10 +1096,11 @@ LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bo
 }
 
 LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
-                           float2* E, hipStream_t s, Tracer* tr) {
+                           float2* E, hipStream_t s, Tracer* tr, bool rows_u, const float2* keep) {
   const int64_t plane = (int64_t)p.N1 * p.H2;
   const int64_t q_stride = plane * p.batch_cap;
-  LaunchStatus e = run(p.fwd_rows, batch, u, nullptr, s, tr);  // RA_q = rowFFT(b_q . u)
+  LaunchStatus e = hipSuccess;
+  if (rows_u && !keep) e = run(p.fwd_rows, batch, u, nullptr, s, tr);  // RA_q = rowFFT(b_q . u)
   if (e != hipSuccess) return e;
   e = run(p.adj_rows, batch, gy, nullptr, s, tr);              // Tws = rowFFT(gy)
   if (e != hipSuccess) return e;
@@ -942,7 +1111,7 @@ LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, flo
     switch (p.N1) {
 #define PC_CASE(LL)                                      \
   case LL:                                               \
-    e = grad2d_cols_t<LL>(p, batch, q_stride, E, s);     \
+    e = grad2d_cols_t<LL>(p, batch, q_stride, E, keep, s); \
     break;
       PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -31,6 +32,9 @@
 namespace {
 
 thread_local std::string g_last_error;
+
+// Default budget of the kept windowed spectra of a plan with gradients.
+constexpr int64_t PC_DEFAULT_KEEP_BUDGET = (int64_t)1 << 30;
 
 pc_status fail(pc_status st, const std::string& msg) {
   g_last_error = msg;
@@ -209,6 +213,27 @@ struct pc_plan_s {
   std::vector<pc_plan_s*> sec_sub;
   pc_batch_s* sec_batch = nullptr;
   int batch_refs = 0;  // live batches holding the plan (guarded by g_registry_mu)
+  // What the last forward left for pc_backward: saved_state 1, the row
+  // transforms of the windowed input saved_u (batch saved_batch) are still
+  // in the workspace; 2, the windowed spectra U_k are also in keep.  Any
+  // call that reuses the workspace resets it to 0.
+  const float* saved_u = nullptr;
+  int64_t saved_batch = 0;
+  int saved_state = 0;
+  // Kept windowed spectra U_k (PC_PLAN_GRADIENTS plans): held while they fit
+  // in `budget` bytes (pc_plan_set_budget)
+  int64_t budget = 0;
+  int64_t keep_bytes = 0;
+  void* keep_alloc = nullptr;
+  // sectioned plans: section geometry (plan order), spectra transposes
+  // (natural <-> each sub-plan's internal layout), and with gradients the
+  // gradient export and the backward column launches [want_gu][kept U_k]
+  std::vector<int> sec_k;
+  std::vector<std::array<int64_t, 10>> sec_geom;  // o1 p1 o2 p2 a1 q1 a2 q2 M1 M2
+  pc::TransposeSet tr_spec{}, tr_grad{};
+  std::vector<pc::LaunchSet> sec_bwd[2][2];
+  pc_batch_s* sec_batch_keep = nullptr;  // the forward launches storing U_k into keep
+  std::vector<pc::SecTerm> sec_terms;
   pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
   ~pc_plan_s();
@@ -707,6 +732,8 @@ struct pc_batch_s {
 
 pc_plan_s::~pc_plan_s() {
   delete sec_batch;
+  delete sec_batch_keep;
+  if (keep_alloc) (void)hipFree(keep_alloc);
   for (pc_plan_s* q : sec_sub) delete q;
   for (void* p : allocs) (void)hipFree(p);
 }
@@ -797,7 +824,7 @@ struct GatherSpec {
 // Fixed pointers (in, fo, fa: the sections of a sectioned plan) or, with
 // in == nullptr, the entries of the batch's device table b->dtab.
 pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa,
-                      const GatherSpec* gather = nullptr) {
+                      const GatherSpec* gather = nullptr, const std::vector<float2*>* keep = nullptr) {
   const bool table = in == nullptr;
   const size_t nb = b->plans.size();
   // group instances by row length (N2) and by column length (N1)
@@ -868,6 +895,10 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         } else {
           pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
           ja.push_back(gathered(pc::RowJob{inp, nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
+          if (st) {  // only the output box of the forward section is read (the gradient needs the mask)
+            ja.back().mrows = st->ef1;
+            ja.back().mcols = st->ef2;
+          }
           pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, false, win_rows);
           pc::RowJob jo{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap};
           jo.yp = out_slot(i, c);
@@ -905,6 +936,10 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           f_multi = f_multi || q.m > 1;
           jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
           if (st) jf.back().nvalid_in = st->ea1;  // the row pass transformed the window box rows only
+          if (keep) {
+            jf.back().keep = (*keep)[i];
+            jf.back().keep_stride = plane * cap;
+          }
         } else {
           if (!q.adj_fused) {
             pc::append_col_blocks(bt, (int)jt.size(), cap, q.H2, L1, 1);
@@ -1002,6 +1037,70 @@ bool plan_sections(const pc_plan_desc& d, const float* windows, const float* h, 
 
 pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out);
 
+pc_status make_transpose_set(pc_plan p, pc::TransposeSet& ts, std::vector<pc::TransposeJob> jobs) {
+  int64_t b0 = 0;
+  for (pc::TransposeJob& j : jobs) {
+    j.block0 = b0;
+    b0 += pc::transpose_blocks(j.N1, j.H2);
+  }
+  pc::TransposeJob* dj = nullptr;
+  pc_status st = p->upload(&dj, jobs, nullptr);
+  if (st) return st;
+  ts.jobs = dj;
+  ts.njobs = (int)jobs.size();
+  ts.blocks = b0;
+  return PC_SUCCESS;
+}
+
+// The backward column launches of a sectioned plan with gradients (one
+// single-term job per section, grouped by column length), for the adjoint
+// and spectra gradient together or the gradient alone; with kept U_k
+// (kept = true, the sections' keep planes consecutive in keep_alloc) or
+// recomputing them from the row transforms left in the workspace.
+pc_status build_sec_bwd(pc_plan p, const std::vector<pc::SecTerm>& terms, bool kept) {
+  const int64_t cap = p->d.batch;
+  std::vector<int> lens;
+  for (pc_plan_s* sub : p->sec_sub)
+    if (std::find(lens.begin(), lens.end(), sub->p2.N1) == lens.end()) lens.push_back(sub->p2.N1);
+  for (int gu = 0; gu < 2; ++gu) {
+    std::vector<pc::LaunchSet>& seq = p->sec_bwd[gu][kept ? 1 : 0];
+    seq.clear();
+    for (int L1 : lens) {
+      std::vector<pc::ColJob> jobs;
+      std::vector<pc::BlockRef> bm;
+      const float2* tw = nullptr;
+      int64_t koff = 0;
+      for (size_t i = 0; i < p->sec_sub.size(); ++i) {
+        const pc::Plan2D& q = p->sec_sub[i]->p2;
+        const int64_t plane = (int64_t)q.N1 * q.H2;
+        float2* kp = kept ? static_cast<float2*>(p->keep_alloc) + koff : nullptr;
+        koff += cap * plane;
+        if (q.N1 != L1) continue;
+        tw = q.tw1;
+        pc::ColJob j{q.Tws, q.RA, nullptr, q.Hs, nullptr, plane * cap, 0, q.H2, 1, 1, 1, 1};
+        const pc::SecTerm& t = terms[i];
+        const int br = pc::row_block_rows(q.N2);
+        j.nvalid_in = t.ea1;
+        j.nvalid_out = std::min(q.N1, (t.ea1 + br - 1) / br * br);
+        j.nv_src = t.ef1;
+        j.keep = kp;
+        j.grad = p->sec_sub[i]->grad_ws;
+        j.want_gu = gu;
+        j.nimg = cap;
+        pc::append_col_blocks(bm, (int)jobs.size(), 1, q.H2, L1, 1);
+        jobs.push_back(j);
+      }
+      if (jobs.empty()) continue;
+      pc::LaunchSet ls;
+      pc_status st = make_set(p, ls, pc::KK_COLS_BWD1, L1, jobs, bm, 0, tw, nullptr);
+      if (st) return st;
+      ls.blocks_per_img = 0;
+      seq.push_back(ls);
+    }
+  }
+  return PC_SUCCESS;
+}
+
 // Whether the sections' window boxes (the adjoint's output boxes) cover
 // every pixel of the N1 x N2 torus exactly once: their areas add up to the
 // image and no two of them meet.
@@ -1060,13 +1159,15 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
     sd.n1 = sc.M2;
     sd.batch = cap;
     sd.w_format = PC_W_DENSE;
-    sd.flags = PC_PLAN_FULL_GRID;
+    sd.flags = PC_PLAN_FULL_GRID | (d.flags & PC_PLAN_GRADIENTS);
     pc_plan_s* sub = nullptr;
     if ((st = create_plan(sd, wsub.data(), hsub.data(), s, &sub))) return st;
     p->sec_sub.push_back(sub);
     p->spectra_bytes += sub->spectra_bytes;
     p->window_bytes += sub->window_bytes;
     p->workspace_bytes += sub->workspace_bytes;
+    p->sec_k.push_back(sc.k);
+    p->sec_geom.push_back({sc.o1, sc.p1, sc.o2, sc.p2, sc.a1, sc.q1, sc.a2, sc.q2, sc.M1, sc.M2});
     pc::SecTerm t{};
     t.off = off;
     t.M1 = (int)sc.M1;
@@ -1136,7 +1237,143 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
   gs.direct_adj = q.direct_adj = boxes_partition(terms, N1, N2);
   // the launches take the call's input pointer, so they are not captured
   b->use_graph = false;
-  return build_batch(b, in.data(), outs.data(), outs.data(), &gs);
+  if ((st = build_batch(b, in.data(), outs.data(), outs.data(), &gs))) return st;
+  // spectra as parameters: the sections' spectra, one after another, each in
+  // the natural layout of its M1 x M2 grid
+  {
+    std::vector<pc::TransposeJob> jobs, gjobs;
+    int64_t off_c = 0;
+    for (pc_plan_s* sub : p->sec_sub) {
+      const pc::Plan2D& q2 = sub->p2;
+      jobs.push_back({const_cast<float2*>(q2.Hs), off_c, q2.N1, q2.H2, 0, 1.f, 0});
+      if (sub->grad_ws)
+        gjobs.push_back({sub->grad_ws, off_c, q2.N1, q2.H2, 1, 1.0f / ((float)q2.N1 * (float)q2.N2), 0});
+      off_c += (int64_t)q2.N1 * q2.H2;
+    }
+    p->spec_count = off_c;
+    if ((st = make_transpose_set(p, p->tr_spec, jobs))) return st;
+    if (!gjobs.empty() && (st = make_transpose_set(p, p->tr_grad, gjobs))) return st;
+  }
+  p->sec_terms = terms;
+  if (d.flags & PC_PLAN_GRADIENTS) return build_sec_bwd(p, terms, false);
+  return PC_SUCCESS;
+}
+
+// Bytes of the windowed spectra U_k a plan with gradients can keep: every
+// term's spectrum for the plan's batch capacity (2D full grid: m x batch
+// planes; sectioned: one plane per section and image).  0: the path keeps
+// nothing (1D, product-convolution).
+int64_t keep_size(pc_plan p) {
+  if (!(p->d.flags & PC_PLAN_GRADIENTS) || p->pconv) return 0;
+  if (p->path == 2) return (int64_t)p->d.m * p->d.batch * p->p2.N1 * p->p2.H2 * (int64_t)sizeof(float2);
+  if (p->path == 3) {
+    int64_t n = 0;
+    for (pc_plan_s* sub : p->sec_sub) n += p->d.batch * sub->p2.N1 * (int64_t)sub->p2.H2;
+    return n * (int64_t)sizeof(float2);
+  }
+  return 0;
+}
+
+// Hold the kept U_k when they fit in the budget, release them otherwise.
+pc_status set_keep(pc_plan p, int64_t budget) {
+  p->budget = budget;
+  const int64_t need = keep_size(p);
+  const bool want = need > 0 && need <= budget;
+  if (p->saved_state > 1) p->saved_state = 1;
+  if (want == (p->keep_alloc != nullptr)) return PC_SUCCESS;
+  if (!want) {
+    hipError_t e = hipDeviceSynchronize();  // kernels of earlier calls may still use it
+    (void)hipFree(p->keep_alloc);
+    p->keep_alloc = nullptr;
+    p->keep_bytes = 0;
+    p->p2.keep = nullptr;
+    delete p->sec_batch_keep;
+    p->sec_batch_keep = nullptr;
+    if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize");
+    return PC_SUCCESS;
+  }
+  hipError_t e = hipMalloc(&p->keep_alloc, (size_t)need);
+  if (e != hipSuccess) {
+    p->keep_alloc = nullptr;
+    return fail(PC_ERROR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(need) + " bytes for the kept spectra");
+  }
+  p->keep_bytes = need;
+  float2* kp = static_cast<float2*>(p->keep_alloc);
+  pc_status st = PC_SUCCESS;
+  if (p->path == 2) {
+    pc::Plan2D& q = p->p2;
+    const int64_t plane = (int64_t)q.N1 * q.H2;
+    pc::ColJob cf{q.RA, q.Tws, q.Part, q.Hs, q.wrows, plane * q.batch_cap, plane * q.batch_cap, q.H2, q.m1, q.m2,
+                  q.dense ? 1 : 0, q.col_groups};
+    cf.keep = kp;
+    cf.keep_stride = plane * q.batch_cap;
+    std::vector<pc::BlockRef> bm;
+    pc::append_col_blocks(bm, 0, q.batch_cap, q.H2, q.N1, q.col_groups);
+    const int cpi = (q.H2 + pc::col_block_cols(q.N1) - 1) / pc::col_block_cols(q.N1);
+    st = make_set(p, q.fwd_cols_keep, pc::KK_COLS_FWD, q.N1, std::vector<pc::ColJob>{cf}, bm,
+                  (int64_t)cpi * q.col_groups, q.tw1, nullptr, false, q.m > 1);
+    q.fwd_cols_keep.keep = true;
+    if (!st) q.keep = kp;
+  } else {
+    std::vector<float2*> keeps;
+    int64_t off = 0;
+    for (pc_plan_s* sub : p->sec_sub) {
+      keeps.push_back(kp + off);
+      off += p->d.batch * sub->p2.N1 * (int64_t)sub->p2.H2;
+    }
+    pc_batch_s* b = new (std::nothrow) pc_batch_s();
+    if (!b) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    p->sec_batch_keep = b;
+    b->device = p->device;
+    b->plans.assign(p->sec_sub.begin(), p->sec_sub.end());
+    b->has_fwd = b->has_adj = true;
+    b->use_graph = false;
+    std::vector<const float*> in(p->sec_terms.size(), nullptr);
+    std::vector<float*> outs;
+    for (const pc::SecTerm& t : p->sec_terms) outs.push_back(p->sec.Sout + t.off);
+    GatherSpec gs{p->sec.N1, p->sec.N2, &p->sec_terms};
+    gs.direct_adj = p->sec.direct_adj;
+    st = build_batch(b, in.data(), outs.data(), outs.data(), &gs, &keeps);
+    for (pc::LaunchSet& ls : b->fwd_seq)
+      if (ls.kind == pc::KK_COLS_FWD) ls.keep = true;  // its jobs carry the keep pointers
+    if (!st) st = build_sec_bwd(p, p->sec_terms, true);
+  }
+  if (st) {
+    (void)hipFree(p->keep_alloc);
+    p->keep_alloc = nullptr;
+    p->keep_bytes = 0;
+    p->p2.keep = nullptr;
+    delete p->sec_batch_keep;
+    p->sec_batch_keep = nullptr;
+  }
+  return st;
+}
+
+// The launch sets of a sequence with the given kind.
+std::vector<pc::LaunchSet> of_kind(const std::vector<pc::LaunchSet>& seq, int kind) {
+  std::vector<pc::LaunchSet> out;
+  for (const pc::LaunchSet& ls : seq)
+    if (ls.kind == kind) out.push_back(ls);
+  return out;
+}
+
+// Sectioned backward pass: gu = H_m^* gy (if gu) and the sections' spectra
+// gradient (if gspec) from one transform of each section's box of gy.
+// state: what the forward left (see pc_plan_s::saved_state).
+hipError_t run_sec_backward(pc_plan p, const float* u, const float* gy, float* gu, float2* gspec, int64_t batch,
+                            int state, hipStream_t s) {
+  const pc_batch_s* b = p->sec_batch;
+  hipError_t e = hipSuccess;
+  if (gspec && state == 0) e = launch_seq(of_kind(b->fwd_seq, pc::KK_ROWS_FWD), s, p->tr(), u, batch);
+  if (e == hipSuccess) e = launch_seq(of_kind(b->adj_seq, pc::KK_ROWS_FWD), s, p->tr(), gy, batch);
+  const bool kept = state == 2 && p->keep_alloc;
+  if (e == hipSuccess) e = launch_seq(p->sec_bwd[gu ? 1 : 0][kept ? 1 : 0], s, p->tr(), nullptr, batch);
+  if (e == hipSuccess && gu) {
+    e = launch_seq(of_kind(b->adj_seq, pc::KK_ROWS_INV), s, p->tr(), nullptr, batch, gu);
+    if (e == hipSuccess && !p->sec.direct_adj) e = pc::launch_sec_scatter(p->sec, gu, true, batch, s, p->tr());
+  }
+  if (e == hipSuccess && gspec) e = pc::launch_transpose_set(p->tr_grad, gspec, false, s);
+  return e;
 }
 
 hipError_t run_sections(pc_plan p, const float* in, float* out, int64_t batch, bool adjoint, hipStream_t s) {
@@ -1228,7 +1465,10 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
     h = flipped.data();
   }
   std::vector<Section> secs;
-  if (path == 2 && !(d.flags & (PC_PLAN_GRADIENTS | PC_PLAN_FULL_GRID)) && plan_sections(d, windows, h, secs))
+  // sections: unless the full grid is asked for, or gradients of a
+  // product-convolution plan (whose gradient needs both chains swapped)
+  const bool grads = (d.flags & PC_PLAN_GRADIENTS) != 0;
+  if (path == 2 && !(d.flags & PC_PLAN_FULL_GRID) && !(grads && p->pconv) && plan_sections(d, windows, h, secs))
     p->path = path = 3;
   pc_status st;
   if (path == 0)
@@ -1239,11 +1479,11 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
     st = build_2d(p, windows, h, s);
   else
     st = build_sec2d(p, windows, h, secs, s);
-  if (st == PC_SUCCESS) {
+  if (st == PC_SUCCESS && path != 3) {  // sectioned plans count their sections' spectra
     p->spec_count = (int64_t)d.m * (d.ndim == 1 ? d.n0 / 2 + 1 : d.n0 * (d.n1 / 2 + 1));
-    if (p->pconv && path != 3) st = p->alloc(&p->conj_ws, (size_t)p->spec_count, &p->workspace_bytes);
+    if (p->pconv) st = p->alloc(&p->conj_ws, (size_t)p->spec_count, &p->workspace_bytes);
   }
-  if (st == PC_SUCCESS) {
+  if (st == PC_SUCCESS && path != 3) {  // sections hold their gradient planes in their sub-plans
     if (d.flags & PC_PLAN_GRADIENTS) {
       // 1D: pair spectra (pairs x N) or the per-class accumulators (m x N); 2D: m planes
       const int64_t pairs = (d.batch + 1) / 2;
@@ -1251,6 +1491,7 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
       st = p->alloc(&p->grad_ws, (size_t)n, &p->workspace_bytes);
     }
   }
+  if (st == PC_SUCCESS && grads) st = set_keep(p, PC_DEFAULT_KEEP_BUDGET);
   if (st != PC_SUCCESS) {
     (void)hipStreamSynchronize(s);
     delete p;
@@ -1501,6 +1742,7 @@ static pc_status batch_run(pc_batch b, bool adjoint, const float* const* inputs,
     cur[2 * i] = const_cast<float*>(inputs[i]);  // read only: the kernels take it as const
     cur[2 * i + 1] = outputs[i];
   }
+  for (pc_plan p : b->plans) p->saved_state = 0;  // the batch uses the plans' workspaces
   if (cur != b->last[c]) {
     // the staging slot is rewritten only once its previous upload has run
     hipError_t e = hipEventSynchronize(b->ev[c]);
@@ -1572,13 +1814,46 @@ pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* wi
   return PC_SUCCESS;
 }
 
+// The forward of a convolution-product 2D plan leaves the row transforms of
+// the windowed input in the workspace (and, kept, U_k).
+static void remember(pc_plan p, const float* u, int64_t batch, int state) {
+  p->saved_u = u;
+  p->saved_batch = batch;
+  p->saved_state = (p->pconv || p->path < 2) ? 0 : state;
+}
+
 pc_status pc_apply(pc_plan p, const float* u, float* y, int64_t batch, void* stream) {
   pc_status st = check_apply(p, u, y, batch);
   if (st || batch == 0) return st;
   DeviceGuard g(p->device);
   hipError_t e = p->pconv ? run_adjoint(p, u, y, batch, static_cast<hipStream_t>(stream))
                           : run_forward(p, u, y, batch, static_cast<hipStream_t>(stream));
+  remember(p, u, batch, e == hipSuccess ? 1 : 0);
   if (e != hipSuccess) return fail_hip(e, "pc_apply launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_apply_save(pc_plan p, const float* u, float* y, int64_t batch, void* stream) {
+  pc_status st = check_apply(p, u, y, batch);
+  if (st || batch == 0) return st;
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  int state = 1;
+  if (p->pconv || p->path < 2) {
+    e = p->pconv ? run_adjoint(p, u, y, batch, s) : run_forward(p, u, y, batch, s);
+  } else if (p->path == 2) {
+    e = pc::launch_fwd2d(p->p2, u, y, batch, s, p->tr(), true);
+    if (p->p2.keep) state = 2;
+  } else if (p->sec_batch_keep) {
+    e = launch_seq(p->sec_batch_keep->fwd_seq, s, p->tr(), u, batch);
+    if (e == hipSuccess) e = pc::launch_sec_scatter(p->sec, y, false, batch, s, p->tr());
+    state = 2;
+  } else {
+    e = run_sections(p, u, y, batch, false, s);
+  }
+  remember(p, u, batch, e == hipSuccess ? state : 0);
+  if (e != hipSuccess) return fail_hip(e, "pc_apply_save launch");
   return PC_SUCCESS;
 }
 
@@ -1586,6 +1861,7 @@ pc_status pc_apply_adjoint(pc_plan p, const float* v, float* x, int64_t batch, v
   pc_status st = check_apply(p, v, x, batch);
   if (st || batch == 0) return st;
   DeviceGuard g(p->device);
+  p->saved_state = 0;  // the adjoint's planes overwrite the workspace
   hipError_t e = p->pconv ? run_forward(p, v, x, batch, static_cast<hipStream_t>(stream))
                           : run_adjoint(p, v, x, batch, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e, "pc_apply_adjoint launch");
@@ -1634,6 +1910,8 @@ pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
   r.spectra_bytes = p->spectra_bytes;
   r.window_bytes = p->window_bytes;
   r.workspace_bytes = p->workspace_bytes;
+  r.keep_bytes = p->keep_bytes;
+  r.spectra_count = p->spec_count;
   *info = r;
   return PC_SUCCESS;
 }
@@ -1641,11 +1919,17 @@ pc_status pc_plan_query(pc_plan p, pc_plan_info* info) {
 pc_status pc_plan_set_spectra(pc_plan p, const void* spec, void* stream) {
   pc_status st = check_plan(p);
   if (st) return st;
-  if (p->path == 3)
-    return fail(PC_ERROR_UNSUPPORTED, "sectioned plans keep per-section spectra (create the plan with PC_PLAN_FULL_GRID)");
   if (!spec) return fail(PC_ERROR_INVALID_VALUE, "spec is NULL");
+  if (p->path == 3 && p->pconv)
+    return fail(PC_ERROR_UNSUPPORTED, "sectioned product-convolution plans do not import spectra "
+                                      "(create the plan with PC_PLAN_FULL_GRID)");
   DeviceGuard g(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->path == 3) {
+    hipError_t e = pc::launch_transpose_set(p->tr_spec, const_cast<float2*>(static_cast<const float2*>(spec)), true, s);
+    if (e != hipSuccess) return fail_hip(e, "pc_plan_set_spectra launch");
+    return PC_SUCCESS;
+  }
   const float2* in = static_cast<const float2*>(spec);
   hipError_t e;
   if (p->pconv) {  // the plan stores the spectra of the flipped responses
@@ -1666,14 +1950,14 @@ pc_status pc_plan_set_spectra(pc_plan p, const void* spec, void* stream) {
 pc_status pc_plan_get_spectra(pc_plan p, void* spec, void* stream) {
   pc_status st = check_plan(p);
   if (st) return st;
-  if (p->path == 3)
-    return fail(PC_ERROR_UNSUPPORTED, "sectioned plans keep per-section spectra (create the plan with PC_PLAN_FULL_GRID)");
   if (!spec) return fail(PC_ERROR_INVALID_VALUE, "spec is NULL");
   DeviceGuard g(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   float2* out = static_cast<float2*>(spec);
   hipError_t e;
-  if (p->path == 0)
+  if (p->path == 3)
+    e = pc::launch_transpose_set(p->tr_spec, out, false, s);
+  else if (p->path == 0)
     e = pc::launch_spectra1d(&p->s1, nullptr, nullptr, out, false, s);
   else if (p->path == 1)
     e = pc::launch_spectra1d(nullptr, &p->l1, nullptr, out, false, s);
@@ -1684,17 +1968,8 @@ pc_status pc_plan_get_spectra(pc_plan p, void* spec, void* stream) {
   return PC_SUCCESS;
 }
 
-pc_status pc_grad_spectra(pc_plan p, const float* u, const float* gy, void* gspec, int64_t batch, void* stream) {
-  pc_status st = check_plan(p);
-  if (st) return st;
-  if (!p->grad_ws) return fail(PC_ERROR_INVALID_VALUE, "plan was created without PC_PLAN_GRADIENTS");
-  if (batch < 1 || batch > p->d.batch)
-    return fail(PC_ERROR_INVALID_VALUE, "batch " + std::to_string(batch) + " outside [1, " +
-                                            std::to_string(p->d.batch) + "]");
-  if (!u || !gy || !gspec) return fail(PC_ERROR_INVALID_VALUE, "null pointer");
-  DeviceGuard g(p->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  float2* out = static_cast<float2*>(gspec);
+static hipError_t run_grad_spectra(pc_plan p, const float* u, const float* gy, float2* out, int64_t batch,
+                                   bool rows_u, const float2* keep, hipStream_t s) {
   // product-convolution: sum_b conj(F^* u_b) F^*(w_k . gy_b) is the
   // conjugate of the convolution-product sum with u and gy exchanged
   const float* a = p->pconv ? gy : u;
@@ -1704,9 +1979,98 @@ pc_status pc_grad_spectra(pc_plan p, const float* u, const float* gy, void* gspe
     e = pc::launch_grad1d_small(p->s1, a, b, out, batch, p->grad_ws, s, p->tr());
   else if (p->path == 1)
     e = pc::launch_grad1d_large(p->l1, a, b, out, batch, p->grad_ws, s, p->tr());
+  else if (p->path == 2)
+    e = pc::launch_grad2d(p->p2, a, b, out, batch, p->grad_ws, s, p->tr(), rows_u || p->pconv, p->pconv ? nullptr : keep);
   else
-    e = pc::launch_grad2d(p->p2, a, b, out, batch, p->grad_ws, s, p->tr());
+    e = run_sec_backward(p, u, gy, nullptr, out, batch, rows_u ? 0 : 1, s);
   if (e == hipSuccess && p->pconv) e = pc::launch_conj(out, out, p->spec_count, s);
+  return e;
+}
+
+static bool has_gradients(pc_plan p) { return (p->d.flags & PC_PLAN_GRADIENTS) != 0; }
+
+pc_status pc_backward(pc_plan p, const float* u, const float* gy, float* gu, void* gspec, int64_t batch,
+                      int32_t use_saved, void* stream) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (batch < 1 || batch > p->d.batch)
+    return fail(PC_ERROR_INVALID_VALUE, "batch " + std::to_string(batch) + " outside [1, " +
+                                            std::to_string(p->d.batch) + "]");
+  if (!u || !gy || (!gu && !gspec)) return fail(PC_ERROR_INVALID_VALUE, "null pointer");
+  if (gspec && !has_gradients(p)) return fail(PC_ERROR_INVALID_VALUE, "plan was created without PC_PLAN_GRADIENTS");
+  const size_t bytes = (size_t)(batch * p->n_total) * sizeof(float);
+  if (gu && (overlaps(gy, gu, bytes) || overlaps(u, gu, bytes)))
+    return fail(PC_ERROR_INVALID_VALUE, "gu overlaps u or gy");
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* gs = static_cast<float2*>(gspec);
+  const int state = (use_saved && p->saved_u == u && p->saved_batch == batch) ? p->saved_state : 0;
+  hipError_t e = hipSuccess;
+  if (p->path == 3) {
+    if (gspec)
+      e = run_sec_backward(p, u, gy, gu, gs, batch, state, s);
+    else
+      e = p->pconv ? run_forward(p, gy, gu, batch, s) : run_adjoint(p, gy, gu, batch, s);
+  } else if (p->path == 2 && !p->pconv && gspec && !p->p2.adj_fused) {
+    // the gradient pass leaves V = colFFT(rowFFT(gy)) for the adjoint's
+    // column pass, and uses the row transforms or U_k the forward left
+    e = pc::launch_grad2d(p->p2, u, gy, gs, batch, p->grad_ws, s, p->tr(), state == 0,
+                          state == 2 ? p->p2.keep : nullptr);
+    if (e == hipSuccess && gu) e = pc::launch_adj2d_tail(p->p2, gu, batch, s, p->tr());
+  } else {
+    if (gspec) e = run_grad_spectra(p, u, gy, gs, batch, true, nullptr, s);
+    if (e == hipSuccess && gu) e = p->pconv ? run_forward(p, gy, gu, batch, s) : run_adjoint(p, gy, gu, batch, s);
+  }
+  if (gu || p->path < 2 || p->pconv)
+    p->saved_state = 0;
+  else  // the gradient left (or recomputed) the row transforms of u
+    remember(p, u, batch, std::max(state, 1));
+  if (e != hipSuccess) return fail_hip(e, "pc_backward launch");
+  return PC_SUCCESS;
+}
+
+pc_status pc_plan_set_budget(pc_plan p, int64_t bytes) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (bytes < 0) return fail(PC_ERROR_INVALID_VALUE, "budget must be >= 0");
+  DeviceGuard g(p->device);
+  return set_keep(p, bytes);
+}
+
+pc_status pc_plan_sections(pc_plan p, pc_section_info* info, int32_t capacity, int32_t* count) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!count || (!info && capacity > 0) || capacity < 0) return fail(PC_ERROR_INVALID_VALUE, "null count or info");
+  const int n = p->path == 3 ? (int)p->sec_geom.size() : 0;
+  *count = n;
+  int64_t off = 0;
+  for (int i = 0; i < n && i < capacity; ++i) {
+    const std::array<int64_t, 10>& gm = p->sec_geom[(size_t)i];
+    pc_section_info r{};
+    r.term = p->sec_k[(size_t)i];
+    r.win_o1 = gm[0]; r.win_p1 = gm[1]; r.win_o2 = gm[2]; r.win_p2 = gm[3];
+    r.lag_o1 = gm[4]; r.lag_q1 = gm[5]; r.lag_o2 = gm[6]; r.lag_q2 = gm[7];
+    r.m1 = gm[8]; r.m2 = gm[9];
+    r.spec_offset = off;
+    off += gm[8] * (gm[9] / 2 + 1);
+    info[i] = r;
+  }
+  return PC_SUCCESS;
+}
+
+pc_status pc_grad_spectra(pc_plan p, const float* u, const float* gy, void* gspec, int64_t batch, void* stream) {
+  pc_status st = check_plan(p);
+  if (st) return st;
+  if (!has_gradients(p)) return fail(PC_ERROR_INVALID_VALUE, "plan was created without PC_PLAN_GRADIENTS");
+  if (batch < 1 || batch > p->d.batch)
+    return fail(PC_ERROR_INVALID_VALUE, "batch " + std::to_string(batch) + " outside [1, " +
+                                            std::to_string(p->d.batch) + "]");
+  if (!u || !gy || !gspec) return fail(PC_ERROR_INVALID_VALUE, "null pointer");
+  DeviceGuard g(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = run_grad_spectra(p, u, gy, static_cast<float2*>(gspec), batch, true, nullptr, s);
+  // the 2D gradient recomputed the row transforms of u into the workspace
+  remember(p, u, batch, e == hipSuccess ? 1 : 0);
   if (e != hipSuccess) return fail_hip(e, "pc_grad_spectra launch");
   return PC_SUCCESS;
 }

@@ -155,6 +155,9 @@ struct RowJob {
   // new buffers; null: x / y / the launch's pointer argument
   const float* const* xp = nullptr;
   float* const* yp = nullptr;
+  // row-forward: samples of rows r >= mrows or columns n2 >= mcols read as
+  // zero (0: no mask); the section gradient's box of the output gradient
+  int mrows = 0, mcols = 0;
   // row-inverse, section evaluation (oN2 > 0): row r < orows of the job's
   // image img is written, columns n2 < ocols only, to image img of the output
   // (oN1 x oN2 samples) at ((o1 + r) mod oN1, (o2 + n2) mod oN2)
@@ -179,6 +182,21 @@ struct ColJob {
   // skipped), the adjoint pass writes dst entries n1 < nvalid_out only (the
   // rest are never read)
   int nvalid_in = 0, nvalid_out = 0;
+  // forward pass: when keep is set, the transformed windowed column of term
+  // k is also stored at keep[k * keep_stride + img * plane + f2 * N1] (the
+  // windowed spectra U_k kept for the backward pass)
+  float2* keep = nullptr;
+  int64_t keep_stride = 0;
+  // backward pass of a single-term job (k_cols_bwd1): src = row transforms
+  // of the output gradient (rows < nv_src matter), dst = row transforms of
+  // the windowed input (rows < nvalid_in; U_k read from keep instead when
+  // set), overwritten with the adjoint's planes (rows < nvalid_out) when
+  // want_gu; grad (optional) receives sum over the images of conj(U_k) V,
+  // one plane [f2][f1]; nimg images
+  float2* grad = nullptr;
+  int want_gu = 1;
+  int nv_src = 0;
+  int64_t nimg = 1;
 };
 
 // Block of a table-driven launch: job, image, block within the image,
@@ -187,7 +205,7 @@ struct BlockRef {
   int job, img, blk, q;
 };
 
-enum KernelKind { KK_ROWS_FWD = 0, KK_ROWS_INV, KK_COLS_FWD, KK_COLS_SUM, KK_COLS_ADJ, KK_COLS_FFT };
+enum KernelKind { KK_ROWS_FWD = 0, KK_ROWS_INV, KK_COLS_FWD, KK_COLS_SUM, KK_COLS_ADJ, KK_COLS_FFT, KK_COLS_BWD1 };
 
 // A prepared launch: kernel kind and length, device tables, block counts.
 struct LaunchSet {
@@ -203,6 +221,7 @@ struct LaunchSet {
   bool late = false;               // forward column kernel: the late-spectrum variant (cols_fwd_late)
   bool prefetch = false;           // adjoint column kernel: the prefetching variant (cols_adj_prefetch)
   bool pipe = false;               // row-inverse kernel: the pipelined variant (rows_inv_pipe)
+  bool keep = false;               // forward column kernel: the variant storing U_k (jobs' keep pointers)
 };
 
 struct Plan2D {
@@ -221,6 +240,8 @@ struct Plan2D {
   bool adj_fused;            // single term: adj_cols transforms its input itself (adj_fft unused by the adjoint)
   float2* Part;              // col_groups x batch_cap planes of partial spectra (col_groups > 1)
   LaunchSet fwd_rows, fwd_cols, fwd_sum, fwd_rows_out;
+  LaunchSet fwd_cols_keep;   // fwd_cols storing U_k into keep (when the plan keeps them)
+  float2* keep = nullptr;    // m x batch_cap planes of U_k, or null
   LaunchSet adj_rows, adj_fft, adj_cols, adj_rows_out;
   LaunchSet spec_rows, spec_cols;
 };
@@ -260,10 +281,35 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
                         Tracer* tr, int64_t img_limit = INT64_MAX);
 // h (m x N1 x N2, lag layout) -> Hs, through the plan's spectra launch sets
 LaunchStatus launch_spec2d(const Plan2D& p, const float* h, hipStream_t s);
+// keep: store U_k into p.keep on the way (when the plan holds it)
 LaunchStatus launch_fwd2d(const Plan2D& p, const float* u, float* y, int64_t batch, hipStream_t s,
-                          Tracer* tr = nullptr);
+                          Tracer* tr = nullptr, bool keep = false);
+LaunchStatus launch_adj2d_tail(const Plan2D& p, float* x, int64_t batch, hipStream_t s, Tracer* tr = nullptr);
 LaunchStatus launch_adj2d(const Plan2D& p, const float* v, float* x, int64_t batch, hipStream_t s,
                           Tracer* tr = nullptr);
+
+// Table-driven transposes between planes of the internal column-major
+// layout [f2][f1] (plan-owned) and the natural real-FFT layout [f1][f2]
+// (f2 < H2 contiguous) at offsets of a caller's buffer, one job per plane;
+// scale_mode 1 (export only): entries multiplied by c_f2 inv_n (c = 1 on the
+// first and last column, 2 elsewhere), for gradients.
+struct TransposeJob {
+  float2* internal;
+  int64_t ext_off;   // complex entries before the plane in the caller's buffer
+  int N1, H2;
+  int scale_mode;
+  float inv_n;
+  int64_t block0;    // first workgroup of the job in the launch
+};
+struct TransposeSet {
+  const TransposeJob* jobs = nullptr;  // device
+  int njobs = 0;
+  int64_t blocks = 0;
+};
+// workgroups of one plane
+int64_t transpose_blocks(int N1, int H2);
+// to_internal: ext -> the jobs' planes; else the planes -> ext
+LaunchStatus launch_transpose_set(const TransposeSet& ts, float2* ext, bool to_internal, hipStream_t s);
 
 // Spectra as parameters (natural real-FFT layout) and their gradients.
 LaunchStatus launch_spectra1d(const Small1D* ps, const Large1D* pl, const float2* in, float2* out, bool import,
@@ -273,8 +319,12 @@ LaunchStatus launch_grad1d_small(const Small1D& p, const float* u, const float* 
 LaunchStatus launch_grad1d_large(const Large1D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
                                  float2* E, hipStream_t s, Tracer* tr = nullptr);
 LaunchStatus launch_spectra2d(const Plan2D& p, const float2* in, float2* out, bool import, hipStream_t s);
+// rows_u: transform b_q . u first (false: RA already holds them); keep:
+// U_k kept by a forward pass (m x batch_cap planes), read instead of
+// recomputed.  Leaves Tws = colFFT(rowFFT(gy)) and RA unchanged.
 LaunchStatus launch_grad2d(const Plan2D& p, const float* u, const float* gy, float2* gspec, int64_t batch,
-                           float2* E, hipStream_t s, Tracer* tr = nullptr);
+                           float2* E, hipStream_t s, Tracer* tr = nullptr, bool rows_u = true,
+                           const float2* keep = nullptr);
 
 // --------------------------------------------------------------------------
 // 2D sectioned evaluation (compact supports; the complexity lemma of section

@@ -45,7 +45,11 @@ def test_desc_layout_matches_header():
     # int32 ndim, m; int64 n0, n1, batch; int32 w_format, m_rows, m_cols; uint32 flags
     assert ctypes.sizeof(pcm.PlanDesc) == 48
     assert pcm.PlanDesc.batch.offset == 24
-    assert ctypes.sizeof(pcm.PlanInfo) == 40
+    # int32 path, fft_inner, fft_outer, n_items; int64 spectra, window, workspace, keep bytes, spectra count
+    assert ctypes.sizeof(pcm.PlanInfo) == 56
+    # eleven int32 (term, m1, m2, window and lag boxes), then int64 spec_offset
+    assert ctypes.sizeof(pcm.SectionInfo) == 56
+    assert pcm.SectionInfo.spec_offset.offset == 48
 
 
 def _create(lib, desc, w=None, h=None):
@@ -165,3 +169,12 @@ def test_noalloc_wavelet_transform_rejects_oversize_requests(lib):
     assert st == 1 and b"exceeds the fixed scratch" in lib.pc_last_error()
     st = lib.pc_wavelet_transform_noalloc(0, 96, 3, 4, lp.ctypes.data_as(ctypes.c_void_p), 1, 1, 96, a, b, None)
     assert st == 1
+
+
+def test_backward_calls_on_invalid_plans(lib):
+    a = ctypes.c_void_p(4096)
+    assert lib.pc_apply_save(None, a, ctypes.c_void_p(8192), 1, None) == 5
+    assert lib.pc_backward(None, a, a, ctypes.c_void_p(8192), None, 1, 1, None) == 5
+    assert lib.pc_plan_set_budget(None, 0) == 5
+    n = ctypes.c_int32()
+    assert lib.pc_plan_sections(None, None, 0, ctypes.byref(n)) == 5

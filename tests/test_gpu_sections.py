@@ -124,19 +124,20 @@ def test_repeatable_bitwise_and_traced():
     assert "rows_fwd" in stats and "sec_scatter" in stats and "sec_gather" not in stats
 
 
-def test_spectra_and_batches_need_full_grid_plans():
+def test_sectioned_plans_export_section_spectra_and_stay_out_of_batches():
     import torch
     import paper_1604_04374_amd as pcm
     p = _problems()[0]
-    u = torch.from_numpy(p.u).cuda()
     with pcm.Plan(plan_args(p), p.h, batch=p.batch) as plan:
-        assert plan.info()["path"] == 3
-        with pytest.raises(pcm.PCError) as ei:
-            plan.get_spectra()
-        assert ei.value.status == 2
+        info = plan.info()
+        assert info["path"] == 3
+        # the parameters of a sectioned plan are its sections' spectra
+        n = sum(s["m1"] * (s["m2"] // 2 + 1) for s in plan.sections())
+        assert info["spectra_count"] == n and plan.get_spectra().shape == (n,)
         with pytest.raises(pcm.PCError) as ei:
             pcm.Batch([plan])
         assert ei.value.status == 1
+        torch.cuda.synchronize()
 
 
 @pytest.mark.slow
