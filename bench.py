@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--cold-steps", type=int, default=10,
                     help="extra steps timed one by one after a 1 GiB write that evicts L2 and the "
                          "Infinity Cache (reported as cold_ms_per_step; 0 disables)")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="clear the tuning table: every variant from the library's rules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 5 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -281,6 +283,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    pcm.load_library()
+    if args.no_tuning:
+        pcm.tune_set([])
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
@@ -539,6 +544,7 @@ def main():
                         "share": None if v["share"] is None else round(v["share"], 3),
                         "pass_bytes_per_launch": v["pass_bytes_per_launch"],
                         "traffic_per_launch": v["traffic_per_launch"]} for k, v in kernels.items()},
+        "tuning": "rules only (--no-tuning)" if args.no_tuning else "tuning table",
         "max_rel_l2_vs_oracle": err,
         "cpu_baseline": cpu,
         **extra,

@@ -484,6 +484,51 @@ pc_status pc_batch_apply_adjoint(pc_batch batch, const float* const* inputs, flo
  * destroyed.  Errors: INVALID_VALUE (null or destroyed batch), HIP. */
 pc_status pc_batch_destroy(pc_batch batch);
 
+/*
+ * Tuning table.  Per transform length, the 2D passes come in variants
+ * (spectrum loads before or after the transform, prefetching, pipelined
+ * tiles, row tiles of 16 or 4 rows, term groups) and 1D four-step plans have
+ * a choice of inner length.  Plans and batches take each choice from rules
+ * (the runtime's occupancy and register figures for the built kernels),
+ * unless the tuning table holds a measured choice for their workload.  The
+ * package's tuner times the variants on the device and writes the table;
+ * the Python binding loads it at start-up for the device's architecture.
+ *
+ *   key     the workload: pc_tune_key of a plan description, or
+ *           pc_tune_batch_key of a batch's plans (the sections of a sectioned
+ *           plan use the plan's key);
+ *   knob    a PC_TUNE_* choice; length: the transform length it applies to
+ *           (the 1D size for PC_TUNE_FOURSTEP_L);
+ *   value   0 / 1 for the variant switches, the term group count for
+ *           PC_TUNE_COL_GROUPS (clamped to [1, column factors]), the inner
+ *           length for PC_TUNE_FOURSTEP_L (ignored unless it splits N).
+ *
+ * pc_tune_set replaces the process-wide table (count = 0 clears it); it
+ * affects plans and batches created afterwards.  Errors: INVALID_VALUE (null
+ * entries with count > 0, count < 0, unknown knob).
+ */
+enum {
+  PC_TUNE_COLS_FWD_LATE = 1,      /* forward column pass: spectrum loaded after the transform */
+  PC_TUNE_COLS_ADJ_PREFETCH = 2,  /* adjoint column pass: next spectrum column loaded during the transform */
+  PC_TUNE_ROWS_INV_PIPE = 3,      /* row-inverse pass: next plane's tile loaded during the transform */
+  PC_TUNE_ROWS_FWD_SMALL = 4,     /* row-forward passes: 4-row tiles instead of 16-row ones */
+  PC_TUNE_ROWS_INV_SMALL = 5,     /* row-inverse passes: 4-row tiles instead of 16-row ones */
+  PC_TUNE_COL_GROUPS = 6,         /* full-grid forward column pass: term groups */
+  PC_TUNE_FOURSTEP_L = 7          /* 1D four-step: inner transform length */
+};
+typedef struct {
+  uint64_t key;
+  int32_t knob;
+  int32_t length;
+  int32_t value;
+  int32_t reserved; /* 0 */
+} pc_tune_entry;
+pc_status pc_tune_set(const pc_tune_entry* entries, int32_t count);
+/* The workload key of a plan description, and of a batch of plans (order
+ * free).  Errors: INVALID_VALUE (null arguments), INVALID_PLAN. */
+pc_status pc_tune_key(const pc_plan_desc* desc, uint64_t* key);
+pc_status pc_tune_batch_key(int32_t count, const pc_plan* plans, uint64_t* key);
+
 /* Static text for a status code (never NULL). */
 const char* pc_status_string(pc_status status);
 

@@ -19,7 +19,8 @@ from typing import Optional, Sequence, Tuple, Union
 
 import numpy as np
 
-__all__ = ["Plan", "Batch", "PCError", "KernelStat", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
+__all__ = ["Plan", "Batch", "PCError", "KernelStat", "TuneEntry", "TUNE_KNOBS", "load_tuning", "tune_set",
+           "tune_key", "tune_batch_key", "tuning_table_path", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
            "PC_PLAN_FULL_GRID", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE", "construct_project", "construct_interpolate", "wavelet_transform"]
 
@@ -46,6 +47,7 @@ EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_p
            "pc_wavelet_transform", "pc_wavelet_transform_noalloc", "pc_plan_create_meyer",
            "pc_batch_create", "pc_batch_apply", "pc_batch_apply_adjoint", "pc_batch_destroy",
            "pc_plan_sections", "pc_apply_save", "pc_backward", "pc_plan_set_budget",
+           "pc_tune_set", "pc_tune_key", "pc_tune_batch_key",
            "pc_status_string", "pc_last_error")
 
 PC_BATCH_NO_GRAPH = 1
@@ -73,6 +75,17 @@ class SectionInfo(ctypes.Structure):
                 ("win_o1", ctypes.c_int32), ("win_p1", ctypes.c_int32), ("win_o2", ctypes.c_int32),
                 ("win_p2", ctypes.c_int32), ("lag_o1", ctypes.c_int32), ("lag_q1", ctypes.c_int32),
                 ("lag_o2", ctypes.c_int32), ("lag_q2", ctypes.c_int32), ("spec_offset", ctypes.c_int64)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_uint64), ("knob", ctypes.c_int32), ("length", ctypes.c_int32),
+                ("value", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+# knob names of the tuning table (include/pc.h PC_TUNE_*)
+TUNE_KNOBS = {"cols_fwd_late": 1, "cols_adj_prefetch": 2, "rows_inv_pipe": 3, "rows_fwd_small": 4,
+              "rows_inv_small": 5, "col_groups": 6, "fourstep_l": 7}
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
 
 class KernelStat(ctypes.Structure):
@@ -133,6 +146,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_backward.restype = ctypes.c_int
     lib.pc_plan_set_budget.argtypes = [vp, i64]
     lib.pc_plan_set_budget.restype = ctypes.c_int
+    lib.pc_tune_set.argtypes = [ctypes.POINTER(TuneEntry), ctypes.c_int32]
+    lib.pc_tune_set.restype = ctypes.c_int
+    lib.pc_tune_key.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_uint64)]
+    lib.pc_tune_key.restype = ctypes.c_int
+    lib.pc_tune_batch_key.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]
+    lib.pc_tune_batch_key.restype = ctypes.c_int
     lib.pc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp), ctypes.c_uint32, vp]
     lib.pc_batch_create.restype = ctypes.c_int
     for name in ("pc_batch_apply", "pc_batch_apply_adjoint"):
@@ -162,7 +181,73 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pc_last_error.restype = ctypes.c_char_p
     if path == LIB_PATH:
         _lib = lib
+        _load_default_tuning(lib)
     return lib
+
+
+def _device_arch() -> Optional[str]:
+    """gfx name of device 0, or None without a GPU (no device call is made
+    when torch sees none)."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return None
+
+
+def tuning_table_path(arch: str) -> str:
+    return os.path.join(TUNING_DIR, f"{arch}.json")
+
+
+def _load_default_tuning(lib):
+    arch = _device_arch()
+    if arch is None:
+        return
+    path = tuning_table_path(arch)
+    if os.path.exists(path):
+        load_tuning(path, lib)
+
+
+def load_tuning(path: str, lib=None) -> int:
+    """Load a tuning table written by the tuner (JSON) into the library;
+    returns the number of entries.  Plans and batches created afterwards use
+    it."""
+    import json
+    with open(path) as fh:
+        table = json.load(fh)
+    entries = [(int(e["key"], 16), TUNE_KNOBS[e["knob"]], int(e["length"]), int(e["value"]))
+               for e in table.get("entries", [])]
+    tune_set(entries, lib)
+    return len(entries)
+
+
+def tune_set(entries, lib=None):
+    """Replace the library's tuning table by (key, knob, length, value)
+    tuples (knob: a PC_TUNE_* number); an empty list clears it."""
+    lib = lib or load_library()
+    n = len(entries)
+    arr = (TuneEntry * max(n, 1))(*[TuneEntry(k, kn, ln, v, 0) for k, kn, ln, v in entries])
+    _check(lib, lib.pc_tune_set(arr, n), "pc_tune_set")
+
+
+def tune_key(desc) -> int:
+    """Workload key of a plan description (PlanDesc)."""
+    lib = load_library()
+    k = ctypes.c_uint64()
+    _check(lib, lib.pc_tune_key(ctypes.byref(desc), ctypes.byref(k)), "pc_tune_key")
+    return k.value
+
+
+def tune_batch_key(plans) -> int:
+    """Workload key of a batch of plans."""
+    lib = load_library()
+    n = len(plans)
+    hp = (ctypes.c_void_p * n)(*[p._handle.value for p in plans])
+    k = ctypes.c_uint64()
+    _check(lib, lib.pc_tune_batch_key(n, hp, ctypes.byref(k)), "pc_tune_batch_key")
+    return k.value
 
 
 def _check(lib, status: int, call: str):

@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libpc.so")
 BUILD_DIR = os.path.join(os.path.dirname(PKG), "_build")
 
-SOURCES = ["kern_1d.hip", "kern_2d.hip", "kern_sec.hip", "kern_construct.hip", "kern_wavelet.hip", "pc_api.cpp"]
+SOURCES = ["kern_1d.hip", "kern_2d.hip", "kern_sec.hip", "kern_construct.hip", "kern_wavelet.hip", "pc_api.cpp",
+           "tune.cpp"]
 ARCH = "gfx950"
 # Packed FP32 instructions are switched off for the device code (the
 # compiler otherwise forms them from float / float2 arithmetic).

@@ -644,12 +644,10 @@ static bool prefetch_pays() {
   return pf >= plain;
 }
 
-// One decision per length, cached.  The environment variable (0 or 1), when
-// set, overrides it for tuning; it is read at every plan creation, so a
-// process can build plans of both variants.
+// One decision per length, cached.  (A tuning table entry, when the plan's
+// workload has one, overrides these rules: see tune.cpp.)
 template <class Decide>
-static bool decide_once(std::map<int, bool>& known, std::mutex& mu, const char* env, int L1, Decide decide) {
-  if (const char* e = std::getenv(env)) return std::atoi(e) != 0;
+static bool decide_once(std::map<int, bool>& known, std::mutex& mu, int L1, Decide decide) {
   std::lock_guard<std::mutex> g(mu);
   const auto it = known.find(L1);
   if (it != known.end()) return it->second;
@@ -661,7 +659,7 @@ static bool decide_once(std::map<int, bool>& known, std::mutex& mu, const char* 
 bool cols_fwd_late(int L1, bool multi_term) {
   static std::mutex mu;
   static std::map<int, bool> known;
-  return decide_once(known, mu, "PC_COLS_FWD_LATE", multi_term ? -L1 : L1, [](int key) {
+  return decide_once(known, mu, multi_term ? -L1 : L1, [](int key) {
     const bool b = key < 0;
     switch (b ? -key : key) {
 #define PC_CASE(LL) \
@@ -693,7 +691,7 @@ static bool pipe_pays() {
 bool rows_inv_pipe(int L2, bool small) {
   static std::mutex mu;
   static std::map<int, bool> known;
-  return decide_once(known, mu, "PC_ROWS_INV_PIPE", small ? -L2 : L2, [](int key) {
+  return decide_once(known, mu, small ? -L2 : L2, [](int key) {
     const bool sm = key < 0;
     switch (sm ? -key : key) {
 #define PC_CASE(LL) \
@@ -709,7 +707,7 @@ bool rows_inv_pipe(int L2, bool small) {
 bool cols_adj_prefetch(int L1) {
   static std::mutex mu;
   static std::map<int, bool> known;
-  return decide_once(known, mu, "PC_COLS_ADJ_PREFETCH", L1, [](int L) {
+  return decide_once(known, mu, L1, [](int L) {
     switch (L) {
 #define PC_CASE(LL) \
   case LL:          \

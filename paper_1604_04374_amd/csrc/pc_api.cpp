@@ -33,6 +33,13 @@ namespace {
 
 thread_local std::string g_last_error;
 
+}  // namespace
+namespace pc {
+uint64_t tune_key(const pc_plan_desc& d);
+uint64_t tune_batch_key(const std::vector<pc_plan_desc>& ds);
+}  // namespace pc
+namespace {
+
 // Default budget of the kept windowed spectra of a plan with gradients.
 constexpr int64_t PC_DEFAULT_KEEP_BUDGET = (int64_t)1 << 30;
 
@@ -86,8 +93,8 @@ std::vector<float2> unit_roots(int64_t N) {
 // whose windows fit in two chunks of L samples (the short-support kernels;
 // shorter transforms have fewer LDS exchanges, and at L = 4096 two
 // workgroups share a compute unit), else the longest L (long-support path).
-// PC_FOURSTEP_L overrides the choice (tuning).
-bool large_split(int64_t N, int64_t max_support, int& L, int& R) {
+// A tuning entry for the workload overrides the choice.
+bool large_split(int64_t N, int64_t max_support, int& L, int& R, uint64_t key = 0) {
   auto fits = [&](int l) {
     for (int r : {2, 4, 8, 16})
       if ((int64_t)l * r == N) {
@@ -97,8 +104,10 @@ bool large_split(int64_t N, int64_t max_support, int& L, int& R) {
       }
     return false;
   };
-  if (const char* env = std::getenv("PC_FOURSTEP_L"))
-    if (fits(std::atoi(env))) return true;
+  if (key) {  // a measured choice for this workload
+    const int l = pc::tune_get(key, PC_TUNE_FOURSTEP_L, (int)N, 0);
+    if (l && fits(l)) return true;
+  }
   for (int l : {4096, 6144, 8192})
     if (max_support <= 2 * (int64_t)l && fits(l)) return true;
   for (int l : {8192, 6144, 4096})
@@ -213,6 +222,7 @@ struct pc_plan_s {
   std::vector<pc_plan_s*> sec_sub;
   pc_batch_s* sec_batch = nullptr;
   int batch_refs = 0;  // live batches holding the plan (guarded by g_registry_mu)
+  uint64_t tune_key = 0;  // workload key of the tuning table
   // What the last forward left for pc_backward: saved_state 1, the row
   // transforms of the windowed input saved_u (batch saved_batch) are still
   // in the workspace; 2, the windowed spectra U_k are also in keep.  Any
@@ -527,9 +537,10 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   ls.L = L;
   ls.threads = rows ? pc::row_threads(L, small_rows) : pc::col_threads(L);
   ls.small_rows = rows && small_rows;
-  ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L, multi_term);
-  ls.prefetch = kind == pc::KK_COLS_ADJ && pc::cols_adj_prefetch(L);
-  ls.pipe = kind == pc::KK_ROWS_INV && pc::rows_inv_pipe(L, ls.small_rows);
+  const uint64_t key = p->tune_key;
+  ls.late = kind == pc::KK_COLS_FWD && pc::tune_get(key, PC_TUNE_COLS_FWD_LATE, L, pc::cols_fwd_late(L, multi_term));
+  ls.prefetch = kind == pc::KK_COLS_ADJ && pc::tune_get(key, PC_TUNE_COLS_ADJ_PREFETCH, L, pc::cols_adj_prefetch(L));
+  ls.pipe = kind == pc::KK_ROWS_INV && pc::tune_get(key, PC_TUNE_ROWS_INV_PIPE, L, pc::rows_inv_pipe(L, ls.small_rows));
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();
@@ -583,7 +594,8 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   const int nq = dense ? m : q.m2;
   if ((st = p->alloc(&q.RA, (size_t)(nq * cap * plane), &p->workspace_bytes))) return st;
   if ((st = p->alloc(&q.Tws, (size_t)(cap * plane), &p->workspace_bytes))) return st;
-  q.col_groups = pc::col_groups_for(H2, cap, nq);
+  q.col_groups = std::max(1, std::min(nq, pc::tune_get(p->tune_key, PC_TUNE_COL_GROUPS, N1,
+                                                        pc::col_groups_for(H2, cap, nq))));
   q.Part = nullptr;
   if (q.col_groups > 1 && (st = p->alloc(&q.Part, (size_t)(q.col_groups * cap * plane), &p->workspace_bytes)))
     return st;
@@ -594,10 +606,16 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   // launches too small to fill the chip with the default row tiles (one row
   // block per compute unit at least) take the small tiles; the forward row
   // pass launches its blocks once per column factor
+  // (a tuning entry for the workload decides instead)
   const bool sr = (int64_t)(N1 / pc::row_block_rows(N2)) * cap < 256;
   const int rpi = N1 / pc::row_block_rows(N2, sr);                 // row blocks per image
-  const bool sr_q = (int64_t)(N1 / pc::row_block_rows(N2)) * cap * nq < 256;
+  const bool sr_q = pc::tune_get(p->tune_key, PC_TUNE_ROWS_FWD_SMALL, N2,
+                                 (int64_t)(N1 / pc::row_block_rows(N2)) * cap * nq < 256);
   const int rpi_q = N1 / pc::row_block_rows(N2, sr_q);
+  const bool sr_f = pc::tune_get(p->tune_key, PC_TUNE_ROWS_FWD_SMALL, N2, sr);   // adjoint's row-forward
+  const int rpi_f = N1 / pc::row_block_rows(N2, sr_f);
+  const bool sr_i = pc::tune_get(p->tune_key, PC_TUNE_ROWS_INV_SMALL, N2, sr);   // row-inverse passes
+  const int rpi_i = N1 / pc::row_block_rows(N2, sr_i);
   const int cpi = (H2 + pc::col_block_cols(N1) - 1) / pc::col_block_cols(N1);  // column blocks per image
   std::vector<pc::BlockRef> bm;
   {  // forward: rows of b_q . u -> RA
@@ -621,15 +639,16 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   {  // forward: rows of T -> y
     pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 1, scale, q.Tws, nullptr, 0};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr);
-    if ((st = make_set(p, q.fwd_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr)))
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr_i);
+    if ((st = make_set(p, q.fwd_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi_i, tw2, s, sr_i)))
       return st;
   }
   {  // adjoint: rows of v -> Tws
     pc::RowJob j{nullptr, nullptr, nullptr, 0, N1, 0, 0.f, nullptr, q.Tws, plane * cap};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr);
-    if ((st = make_set(p, q.adj_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr))) return st;
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr_f);
+    if ((st = make_set(p, q.adj_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi_f, tw2, s, sr_f)))
+      return st;
   }
   // a single term needs one column transform of V per column: the adjoint
   // column pass does it itself
@@ -647,8 +666,8 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   {  // adjoint: sum_q b_q . rows of Q_q -> x
     pc::RowJob j{nullptr, nullptr, q.wcols, mode, N1, nq, scale, q.RA, nullptr, plane * cap};
     bm.clear();
-    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr);
-    if ((st = make_set(p, q.adj_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr)))
+    pc::append_row_blocks(bm, 0, cap, N1, N2, 1, sr_i);
+    if ((st = make_set(p, q.adj_rows_out, pc::KK_ROWS_INV, N2, std::vector<pc::RowJob>{j}, bm, rpi_i, tw2, s, sr_i)))
       return st;
   }
   {  // spectra: rows of h_k -> Hs, then columns in place
@@ -693,6 +712,7 @@ pc_status check_apply(pc_plan p, const float* in, float* out, int64_t batch) {
 
 struct pc_batch_s {
   int device = 0;
+  uint64_t tune_key = 0;  // workload key of the tuning table (sections: the sectioned plan's)
   std::vector<pc_plan> plans;
   std::vector<void*> allocs;
   std::vector<pc::LaunchSet> fwd_seq, adj_seq;
@@ -744,7 +764,8 @@ std::set<const void*> g_batches;  // live batches (guarded by g_registry_mu)
 
 template <class J>
 pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L, const std::vector<J>& jobs,
-                    const std::vector<pc::BlockRef>& bm, const float2* tw, bool multi_term = true) {
+                    const std::vector<pc::BlockRef>& bm, const float2* tw, bool multi_term = true,
+                    bool small_rows = false) {
   if (jobs.empty()) return PC_SUCCESS;
   J* dj = nullptr;
   pc::BlockRef* db = nullptr;
@@ -755,10 +776,12 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   const bool rows = kind == pc::KK_ROWS_FWD || kind == pc::KK_ROWS_INV;
   ls.kind = kind;
   ls.L = L;
-  ls.threads = rows ? pc::row_threads(L) : pc::col_threads(L);
-  ls.late = kind == pc::KK_COLS_FWD && pc::cols_fwd_late(L, multi_term);
-  ls.prefetch = kind == pc::KK_COLS_ADJ && pc::cols_adj_prefetch(L);
-  ls.pipe = kind == pc::KK_ROWS_INV && pc::rows_inv_pipe(L, false);
+  ls.threads = rows ? pc::row_threads(L, small_rows) : pc::col_threads(L);
+  ls.small_rows = rows && small_rows;
+  const uint64_t key = b->tune_key;
+  ls.late = kind == pc::KK_COLS_FWD && pc::tune_get(key, PC_TUNE_COLS_FWD_LATE, L, pc::cols_fwd_late(L, multi_term));
+  ls.prefetch = kind == pc::KK_COLS_ADJ && pc::tune_get(key, PC_TUNE_COLS_ADJ_PREFETCH, L, pc::cols_adj_prefetch(L));
+  ls.pipe = kind == pc::KK_ROWS_INV && pc::tune_get(key, PC_TUNE_ROWS_INV_PIPE, L, pc::rows_inv_pipe(L, ls.small_rows));
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();
@@ -857,6 +880,8 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
   for (int c = 0; c < 2; ++c) {
     BatchLists& bl = lists[c];
     for (int L2 : n2s) {
+      const bool sf = pc::tune_get(b->tune_key, PC_TUNE_ROWS_FWD_SMALL, L2, 0) != 0;  // row tiles
+      const bool si = pc::tune_get(b->tune_key, PC_TUNE_ROWS_INV_SMALL, L2, 0) != 0;
       std::vector<pc::RowJob> jf, jfo, ja, jao;
       std::vector<pc::BlockRef> bf, bfo, ba, bao;
       const float2* tw = nullptr;
@@ -886,20 +911,20 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         const pc::SecTerm* st = gather ? &(*gather->terms)[i] : nullptr;
         const int win_rows = st ? st->ea1 : 0, out_rows = st ? st->ef1 : 0;
         if (fwd_type(i, c)) {
-          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, false, win_rows);
+          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, sf, win_rows);
           jf.push_back(gathered(pc::RowJob{inp, nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap}));
-          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, false, out_rows);
+          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, si, out_rows);
           pc::RowJob jo{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0};
           jo.yp = out_slot(i, c);
           jfo.push_back(jo);
         } else {
-          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1);
+          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1, sf);
           ja.push_back(gathered(pc::RowJob{inp, nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
           if (st) {  // only the output box of the forward section is read (the gradient needs the mask)
             ja.back().mrows = st->ef1;
             ja.back().mcols = st->ef2;
           }
-          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, false, win_rows);
+          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, si, win_rows);
           pc::RowJob jo{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap};
           jo.yp = out_slot(i, c);
           if (st && gather->direct_adj) {
@@ -914,10 +939,10 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           jao.push_back(jo);
         }
       }
-      if ((st = batch_set(b, bl.f_rows_in, pc::KK_ROWS_FWD, L2, jf, bf, tw))) return st;
-      if ((st = batch_set(b, bl.f_rows_out, pc::KK_ROWS_INV, L2, jfo, bfo, tw))) return st;
-      if ((st = batch_set(b, bl.a_rows_in, pc::KK_ROWS_FWD, L2, ja, ba, tw))) return st;
-      if ((st = batch_set(b, bl.a_rows_out, pc::KK_ROWS_INV, L2, jao, bao, tw))) return st;
+      if ((st = batch_set(b, bl.f_rows_in, pc::KK_ROWS_FWD, L2, jf, bf, tw, true, sf))) return st;
+      if ((st = batch_set(b, bl.f_rows_out, pc::KK_ROWS_INV, L2, jfo, bfo, tw, true, si))) return st;
+      if ((st = batch_set(b, bl.a_rows_in, pc::KK_ROWS_FWD, L2, ja, ba, tw, true, sf))) return st;
+      if ((st = batch_set(b, bl.a_rows_out, pc::KK_ROWS_INV, L2, jao, bao, tw, true, si))) return st;
     }
     for (int L1 : n1s) {
       std::vector<pc::ColJob> jf, jt, ja;
@@ -949,7 +974,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           pc::ColJob j{q.Tws, q.RA, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1};
           j.fft_src = q.adj_fused ? 1 : 0;
           if (st) {  // the row-inverse pass reads whole row blocks of the window box rows
-            const int br = pc::row_block_rows(q.N2);
+            const int br = pc::row_block_rows(q.N2, pc::tune_get(b->tune_key, PC_TUNE_ROWS_INV_SMALL, q.N2, 0) != 0);
             j.nvalid_out = std::min(q.N1, (st->ea1 + br - 1) / br * br);
           }
           ja.push_back(j);
@@ -1079,7 +1104,7 @@ pc_status build_sec_bwd(pc_plan p, const std::vector<pc::SecTerm>& terms, bool k
         tw = q.tw1;
         pc::ColJob j{q.Tws, q.RA, nullptr, q.Hs, nullptr, plane * cap, 0, q.H2, 1, 1, 1, 1};
         const pc::SecTerm& t = terms[i];
-        const int br = pc::row_block_rows(q.N2);
+        const int br = pc::row_block_rows(q.N2, pc::tune_get(p->tune_key, PC_TUNE_ROWS_INV_SMALL, q.N2, 0) != 0);
         j.nvalid_in = t.ea1;
         j.nvalid_out = std::min(q.N1, (t.ea1 + br - 1) / br * br);
         j.nv_src = t.ef1;
@@ -1228,6 +1253,7 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
   if (!b) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
   p->sec_batch = b;
   b->device = p->device;
+  b->tune_key = p->tune_key;
   b->plans.assign(p->sec_sub.begin(), p->sec_sub.end());
   b->has_fwd = b->has_adj = true;
   std::vector<const float*> in(terms.size(), nullptr);
@@ -1325,6 +1351,7 @@ pc_status set_keep(pc_plan p, int64_t budget) {
     if (!b) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
     p->sec_batch_keep = b;
     b->device = p->device;
+    b->tune_key = p->tune_key;
     b->plans.assign(p->sec_sub.begin(), p->sec_sub.end());
     b->has_fwd = b->has_adj = true;
     b->use_graph = false;
@@ -1428,7 +1455,7 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
         circular_support(windows + (size_t)k * d.n0, d.n0, o, S);
         max_support = std::max(max_support, S);
       }
-      large_split(d.n0, max_support, L, R);
+      large_split(d.n0, max_support, L, R, pc::tune_key(d));
       path = 1;
     } else {
       return fail(PC_ERROR_UNSUPPORTED, "1D size " + std::to_string(d.n0) + " is not supported");
@@ -1447,6 +1474,7 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
   p->d = d;
   p->path = path;
   p->n_total = d.n0 * d.n1;
+  p->tune_key = pc::tune_key(d);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
@@ -1646,6 +1674,11 @@ pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, ui
   b->device = device;
   b->plans.assign(plans, plans + count);
   b->has_fwd = b->has_adj = true;
+  {
+    std::vector<pc_plan_desc> ds;
+    for (pc_plan q : b->plans) ds.push_back(q->d);
+    b->tune_key = pc::tune_batch_key(ds);
+  }
   b->use_graph = !(flags & PC_BATCH_NO_GRAPH);
   DeviceGuard g(device);
   const size_t tab_bytes = (size_t)4 * count * sizeof(float*);
@@ -1796,6 +1829,37 @@ const char* pc_status_string(pc_status st) {
 }
 
 const char* pc_last_error(void) { return g_last_error.c_str(); }
+
+pc_status pc_tune_set(const pc_tune_entry* entries, int32_t count) {
+  if (count < 0 || (count > 0 && !entries)) return fail(PC_ERROR_INVALID_VALUE, "null entries or negative count");
+  std::vector<pc::TuneEntry> t;
+  for (int32_t i = 0; i < count; ++i) {
+    const pc_tune_entry& e = entries[i];
+    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_FOURSTEP_L)
+      return fail(PC_ERROR_INVALID_VALUE, "unknown knob " + std::to_string(e.knob) + " in entry " + std::to_string(i));
+    t.push_back({e.key, e.knob, e.length, e.value});
+  }
+  pc::tune_set(t);
+  return PC_SUCCESS;
+}
+
+pc_status pc_tune_key(const pc_plan_desc* desc, uint64_t* key) {
+  if (!desc || !key) return fail(PC_ERROR_INVALID_VALUE, "null argument");
+  *key = pc::tune_key(*desc);
+  return PC_SUCCESS;
+}
+
+pc_status pc_tune_batch_key(int32_t count, const pc_plan* plans, uint64_t* key) {
+  if (count < 1 || !plans || !key) return fail(PC_ERROR_INVALID_VALUE, "null argument or count < 1");
+  std::vector<pc_plan_desc> ds;
+  for (int32_t i = 0; i < count; ++i) {
+    pc_status st = check_plan(plans[i]);
+    if (st) return st;
+    ds.push_back(plans[i]->d);
+  }
+  *key = pc::tune_batch_key(ds);
+  return PC_SUCCESS;
+}
 
 pc_status pc_plan_create(pc_plan* out, const pc_plan_desc* desc, const float* windows, const float* h,
                          void* stream) {

@@ -247,21 +247,36 @@ struct Plan2D {
 };
 
 int col_groups_for(int H2, int64_t batch, int nq);
+
+// ---------------------------------------------------------------------------
+// Tuning table (tune.cpp): measured choices of the per-length variants for
+// given workloads, overriding the rules above.  A workload is named by a
+// 64-bit key of its plan description (or, for a batch, of its plans'
+// descriptions); an entry gives the value of one knob (PC_TUNE_*) at one
+// transform length.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  uint64_t key;
+  int knob, length, value;
+};
+void tune_set(const std::vector<TuneEntry>& entries);
+// the entry's value, or `rule` when the table has none for (key, knob, length)
+int tune_get(uint64_t key, int knob, int length, int rule);
 // Whether the forward column kernel of length L1 runs its late-spectrum
 // variant (spectrum loaded after the transform: fewer registers, no latency
 // hiding), for a launch whose instances loop over several terms or have one
 // term each: decided once per length and kind from the runtime's occupancy
-// figures for both variants; PC_COLS_FWD_LATE=0/1 overrides it.
+// figures for both variants (the rule a tuning entry can override).
 bool cols_fwd_late(int L1, bool multi_term);
 // Whether the adjoint column kernel of length L1 loads the next spectrum
 // column while it transforms the current one: decided once per length, true
 // where the runtime's occupancy figures show it costs no resident workgroup;
-// PC_COLS_ADJ_PREFETCH=0/1 overrides it.
+// (the rule a tuning entry can override).
 bool cols_adj_prefetch(int L1);
 // Whether the row-inverse kernel of length L2 (small: the small-tile variant)
 // loads the next plane's tile while it transforms the current one: decided
 // once per variant, true where the runtime's figures show at least two waves
-// per SIMD and no spilled registers; PC_ROWS_INV_PIPE=0/1 overrides it.
+// per SIMD and no spilled registers (the rule a tuning entry can override).
 bool rows_inv_pipe(int L2, bool small);
 // Row kernels take 2 G rows per workgroup; the small-tile variant (fewer
 // rows, more workgroups) serves single images too small to fill the chip.
