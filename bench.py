@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--cold-steps", type=int, default=10,
                     help="extra steps timed one by one after a 1 GiB write that evicts L2 and the "
                          "Infinity Cache (reported as cold_ms_per_step; 0 disables)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="c4: one persistent launch per pass (PC_BATCH_PERSISTENT)")
     ap.add_argument("--no-tuning", action="store_true",
                     help="clear the tuning table: every variant from the library's rules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -345,7 +347,7 @@ def main():
     batch = None
     if args.workload == "c4":
         # all instances in one graph launch per direction, against the loop of single plans
-        batch = pcm.Batch([j[1] for j in jobs])
+        batch = pcm.Batch([j[1] for j in jobs], persistent=args.persistent)
         b_in, b_y, b_x = [j[2] for j in jobs], [j[3] for j in jobs], [j[4] for j in jobs]
 
         def step_batch():

@@ -451,14 +451,26 @@ pc_status pc_wavelet_transform_noalloc(int32_t inverse, int64_t n, int32_t level
  *           Convolution-product and product-convolution plans may share a
  *           batch.
  *   flags   PC_BATCH_NO_GRAPH: launch the passes directly instead of
- *           through the captured graphs.
+ *           through the captured graphs; PC_BATCH_PERSISTENT: one persistent
+ *           launch per pass (below).
  *   stream  unused (creation is synchronous).
  * Errors: INVALID_VALUE (count < 1, null array, a repeated plan, a plan that
  * is not 2D or is sectioned, plans on different devices, unknown flags),
  * INVALID_PLAN, OUT_OF_MEMORY, HIP.
  */
 typedef struct pc_batch_s* pc_batch;
-enum { PC_BATCH_NO_GRAPH = 1u };
+enum {
+  PC_BATCH_NO_GRAPH = 1u,
+  /* Persistent passes: one launch per pass (rows in, forward column passes
+   * and column transforms, adjoint column passes, rows out) and length group
+   * (points per thread 8: 64, 128; 12: 96, 192, 384; 16: 256, 512) instead
+   * of one launch per pass and transform length: every block of the pass
+   * over all instances of the group's lengths is a work item of a list
+   * (longest transforms first) that the launch's workgroups walk with a grid
+   * stride.  Other lengths keep their own launches.  Without the flag, a
+   * tuning table entry for the batch (PC_TUNE_BATCH_PERSISTENT) decides. */
+  PC_BATCH_PERSISTENT = 2u
+};
 pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, uint32_t flags, void* stream);
 /*
  * pc_batch_apply - outputs[i] = H_i inputs[i] for every instance i (G_i for a
@@ -514,7 +526,8 @@ enum {
   PC_TUNE_ROWS_FWD_SMALL = 4,     /* row-forward passes: 4-row tiles instead of 16-row ones */
   PC_TUNE_ROWS_INV_SMALL = 5,     /* row-inverse passes: 4-row tiles instead of 16-row ones */
   PC_TUNE_COL_GROUPS = 6,         /* full-grid forward column pass: term groups */
-  PC_TUNE_FOURSTEP_L = 7          /* 1D four-step: inner transform length */
+  PC_TUNE_FOURSTEP_L = 7,         /* 1D four-step: inner transform length */
+  PC_TUNE_BATCH_PERSISTENT = 8    /* batches: persistent passes (length 0) */
 };
 typedef struct {
   uint64_t key;

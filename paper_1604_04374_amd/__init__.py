@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = ["Plan", "Batch", "PCError", "KernelStat", "TuneEntry", "TUNE_KNOBS", "load_tuning", "tune_set",
            "tune_key", "tune_batch_key", "tuning_table_path", "PC_PLAN_GRADIENTS", "PC_PLAN_PRODUCT_CONVOLUTION",
-           "PC_PLAN_FULL_GRID", "PC_BATCH_NO_GRAPH", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
+           "PC_PLAN_FULL_GRID", "PC_BATCH_NO_GRAPH", "PC_BATCH_PERSISTENT", "load_library", "LIB_PATH", "EXPORTS", "PlanDesc", "PlanInfo",
            "PC_W_DENSE", "PC_W_SEPARABLE", "construct_project", "construct_interpolate", "wavelet_transform"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +51,7 @@ EXPORTS = ("pc_plan_create", "pc_apply", "pc_apply_adjoint", "pc_destroy", "pc_p
            "pc_status_string", "pc_last_error")
 
 PC_BATCH_NO_GRAPH = 1
+PC_BATCH_PERSISTENT = 2
 
 PC_PLAN_GRADIENTS = 1
 PC_PLAN_PRODUCT_CONVOLUTION = 2
@@ -84,7 +85,7 @@ class TuneEntry(ctypes.Structure):
 
 # knob names of the tuning table (include/pc.h PC_TUNE_*)
 TUNE_KNOBS = {"cols_fwd_late": 1, "cols_adj_prefetch": 2, "rows_inv_pipe": 3, "rows_fwd_small": 4,
-              "rows_inv_small": 5, "col_groups": 6, "fourstep_l": 7}
+              "rows_inv_small": 5, "col_groups": 6, "fourstep_l": 7, "batch_persistent": 8}
 TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
 
@@ -636,14 +637,14 @@ class Batch:
     the batch lives its plans cannot be destroyed.
     """
 
-    def __init__(self, plans, graph: bool = True, stream=None):
+    def __init__(self, plans, graph: bool = True, persistent: bool = False, stream=None):
         self._lib = load_library()
         self.plans = list(plans)
         n = len(self.plans)
         self._handle = ctypes.c_void_p()
         hp = (ctypes.c_void_p * n)(*[p._handle.value for p in self.plans])
-        st = self._lib.pc_batch_create(ctypes.byref(self._handle), n, hp, 0 if graph else PC_BATCH_NO_GRAPH,
-                                       ctypes.c_void_p(_stream_ptr(stream)))
+        flags = (0 if graph else PC_BATCH_NO_GRAPH) | (PC_BATCH_PERSISTENT if persistent else 0)
+        st = self._lib.pc_batch_create(ctypes.byref(self._handle), n, hp, flags, ctypes.c_void_p(_stream_ptr(stream)))
         _check(self._lib, st, "pc_batch_create")
 
     def _call(self, fn, name, inputs, outputs, stream):

@@ -103,21 +103,19 @@ constexpr int row_pairs_per_block(int L2) {
 constexpr int row_pairs_small(int L2) { return row_pairs_per_block(L2) < 2 ? row_pairs_per_block(L2) : 2; }
 
 // Half-spectra of windowed rows, transposed: sout[q][img][f2][n1], f2 < H2.
-template <int L2, int G = row_pairs_per_block(L2)>
-__global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
-    const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
-    const float2* __restrict__ tw, int64_t img_limit) {
+// The body of a row-forward block bm (G row pairs, G * T threads), with the
+// workgroup's LDS (G * lds_len<L2>() entries) and the staged twiddles; the
+// per-length kernel and the persistent batch kernel both run it.
+template <int L2, int G>
+__device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, const BlockRef bm,
+                                              const float* __restrict__ x_arg, float2* __restrict__ lds,
+                                              const float2* __restrict__ twl, const int tid) {
   constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
-  __shared__ float2 lds[G * lds_len<L2>()];
-  __shared__ float2 twl[L2];
-  const BlockRef bm = bmap[blockIdx.x];
-  if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L2>(twl, tw);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
   const float* x = jb.xp ? *jb.xp : (jb.x ? jb.x : x_arg);
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = tid / T, t = tid % T;
   const int64_t img = bm.img;
   const int r0 = bm.blk * 2 * G;
   const int r = r0 + 2 * c;
@@ -179,10 +177,22 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
   }
   __syncthreads();
   float2* o = jb.sout + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
-  for (int idx = threadIdx.x; idx < H2 * 2 * G; idx += NT) {
+  for (int idx = tid; idx < H2 * 2 * G; idx += NT) {
     const int f = idx / (2 * G), ri = idx % (2 * G);
     gst(o, (int64_t)f * N1 + ri, lds[idx]);
   }
+}
+
+template <int L2, int G = row_pairs_per_block(L2)>
+__global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
+    const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
+    const float2* __restrict__ tw, int64_t img_limit) {
+  __shared__ float2 lds[G * lds_len<L2>()];
+  __shared__ float2 twl[L2];
+  const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L2>(twl, tw);
+  rows_fwd_body<L2, G>(jobs, bm, x_arg, lds, twl, threadIdx.x);
 }
 
 // Real rows from transposed half-spectra:
@@ -191,20 +201,15 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
 // transformed (latency hidden inside the workgroup, for a tile's share of
 // registers per thread; see rows_inv_pipe for when that pays).
 template <int L2, int G, bool PIPE>
-__global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
-    const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
-    const float2* __restrict__ tw, int64_t img_limit) {
+__device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, const BlockRef bm,
+                                              float* __restrict__ y_arg, float2* __restrict__ lds,
+                                              const float2* __restrict__ twl, const int tid) {
   constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
-  __shared__ float2 lds[G * lds_len<L2>()];
-  __shared__ float2 twl[L2];
-  const BlockRef bm = bmap[blockIdx.x];
-  if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L2>(twl, tw);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
   float* yout = jb.yp ? *jb.yp : (jb.y ? jb.y : y_arg);
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = tid / T, t = tid % T;
   const int64_t img = bm.img;
   const int r0 = bm.blk * 2 * G;
   const int r = r0 + 2 * c;
@@ -218,7 +223,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
   if constexpr (PIPE) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int idx = threadIdx.x + i * NT;
+      const int idx = tid + i * NT;
       if (idx < TILE) nxt[i] = gld(src0, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
     }
   }
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
     if constexpr (PIPE) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        const int idx = threadIdx.x + i * NT;
+        const int idx = tid + i * NT;
         if (idx < TILE) lds[idx] = nxt[i];
       }
       __syncthreads();
@@ -235,13 +240,13 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
         const float2* src = src0 + (int64_t)(q + 1) * jb.q_stride;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-          const int idx = threadIdx.x + i * NT;
+          const int idx = tid + i * NT;
           if (idx < TILE) nxt[i] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
         }
       }
     } else {
       const float2* src = src0 + (int64_t)q * jb.q_stride;
-      for (int idx = threadIdx.x; idx < TILE; idx += NT) lds[idx] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
+      for (int idx = tid; idx < TILE; idx += NT) lds[idx] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
       __syncthreads();
     }
     float2 v[P];
@@ -301,6 +306,18 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
   }
 }
 
+template <int L2, int G, bool PIPE>
+__global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
+    const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
+    const float2* __restrict__ tw, int64_t img_limit) {
+  __shared__ float2 lds[G * lds_len<L2>()];
+  __shared__ float2 twl[L2];
+  const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L2>(twl, tw);
+  rows_inv_body<L2, G, PIPE>(jobs, bm, y_arg, lds, twl, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // column kernels: NF columns per workgroup, each column contiguous
 // ---------------------------------------------------------------------------
@@ -311,17 +328,12 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 // inverse column transform of the sum is written to dst; otherwise the
 // partial spectrum goes to part[group] for k_cols_sum_inv.
 template <int L1, bool LATE, bool KEEP>
-__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
-    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
+__device__ __forceinline__ void cols_fwd_body(const ColJob* __restrict__ jobs, const BlockRef bm,
+                                              float2* __restrict__ lds, const float2* __restrict__ twl, const int tid) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
-  __shared__ float2 lds[NF * lds_len<L1>()];
-  __shared__ float2 twl[L1];
-  const BlockRef bm = bmap[blockIdx.x];
-  if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L1>(twl, tw);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense, ngroups = jb.ngroups;
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = tid / T, t = tid % T;
   const int64_t img = bm.img;
   const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
@@ -381,6 +393,18 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   }
 }
 
+template <int L1, bool LATE, bool KEEP>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fwd(
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
+  constexpr int NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L1>(twl, tw);
+  cols_fwd_body<L1, LATE, KEEP>(jobs, bm, lds, twl, threadIdx.x);
+}
+
 // dst[img][f2][:] = colIFFT(sum_g part[g][img][f2][:]).
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_sum_inv(
@@ -419,17 +443,12 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
 // PF: the next term's spectrum column is loaded before the current transform
 // (its latency hides behind it, for P more complex registers).
 template <int L1, bool PF>
-__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
-    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
+__device__ __forceinline__ void cols_adj_body(const ColJob* __restrict__ jobs, const BlockRef bm,
+                                              float2* __restrict__ lds, const float2* __restrict__ twl, const int tid) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
-  __shared__ float2 lds[NF * lds_len<L1>()];
-  __shared__ float2 twl[L1];
-  const BlockRef bm = bmap[blockIdx.x];
-  if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L1>(twl, tw);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense;
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = tid / T, t = tid % T;
   const int64_t img = bm.img;
   const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
@@ -488,19 +507,26 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   }
 }
 
-// In-place column FFTs of dst: dst[img][f2][:] = colFFT(dst[img][f2][:]).
-template <int L1>
-__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fft(
+template <int L1, bool PF>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_adj(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
-  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  constexpr int NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
   stage_twiddles<L1>(twl, tw);
+  cols_adj_body<L1, PF>(jobs, bm, lds, twl, threadIdx.x);
+}
+
+// In-place column FFTs of dst: dst[img][f2][:] = colFFT(dst[img][f2][:]).
+template <int L1>
+__device__ __forceinline__ void cols_fft_body(const ColJob* __restrict__ jobs, const BlockRef bm,
+                                              float2* __restrict__ lds, const float2* __restrict__ twl, const int tid) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2;
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = tid / T, t = tid % T;
   const int64_t img = bm.img;
   const int f2raw = bm.blk * NF + c;
   const bool valid = f2raw < H2;
@@ -514,6 +540,18 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
 #pragma unroll
     for (int e = 0; e < P; ++e) gst(jb.dst, off + t + T * e, v[e]);
   }
+}
+
+template <int L1>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_fft(
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw, int64_t img_limit) {
+  constexpr int NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  stage_twiddles<L1>(twl, tw);
+  cols_fft_body<L1>(jobs, bm, lds, twl, threadIdx.x);
 }
 
 // Backward column pass of a single-term job (the sections of Lemma 3.2):
@@ -586,6 +624,156 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_b
 }
 
 // ---------------------------------------------------------------------------
+// Persistent batch passes.  One launch per pass and length group runs the
+// blocks of every transform length of the group; its workgroups
+// (PERSIST_THREADS threads, row passes with G = PERSIST_THREADS / T row
+// pairs) walk the item list with a grid stride, stage the item's twiddles and
+// run the pass body.  The
+// variants are fixed to the ones with the fewest registers (spectrum loaded
+// after the transform, no prefetch, no pipelined row-inverse tiles): a
+// launch holds the code of every length of its group, so its register count
+// is the largest of them.
+// ---------------------------------------------------------------------------
+#define PC_FOR_EACH_PL(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+// lengths by points per thread (8, 12, 16): one persistent launch per group,
+// so each holds the code of lengths with similar register needs
+#define PC_FOR_EACH_PG0(X) X(64) X(128)
+#define PC_FOR_EACH_PG1(X) X(96) X(192) X(384)
+#define PC_FOR_EACH_PG2(X) X(256) X(512)
+
+template <int L>
+constexpr int prow_pairs() { return PERSIST_THREADS / fft_threads(L); }
+
+template <int KIND, int L>
+constexpr int plds_entries() {
+  return ((KIND == PK_ROWS_FWD || KIND == PK_ROWS_INV) ? prow_pairs<L>() : ffts_per_block(L)) * lds_len<L>() + L;
+}
+
+template <int KIND, int L>
+__device__ __forceinline__ void persist_item(const PItem& w, float2* smem, const float* x_arg, float* y_arg) {
+  float2* twl = smem;
+  float2* lds = smem + L;
+  stage_twiddles<L>(twl, w.tw);
+  // an opaque copy of the thread index: the body's per-element addresses are
+  // recomputed per item instead of living across the item loop
+  const int tid = opaque((int)threadIdx.x);
+  if constexpr (KIND == PK_ROWS_FWD) {
+    rows_fwd_body<L, prow_pairs<L>()>(static_cast<const RowJob*>(w.jobs), w.bm, x_arg, lds, twl, tid);
+  } else if constexpr (KIND == PK_ROWS_INV) {
+    rows_inv_body<L, prow_pairs<L>(), false>(static_cast<const RowJob*>(w.jobs), w.bm, y_arg, lds, twl, tid);
+  } else if constexpr (KIND == PK_COLS_A) {
+    if (w.sub == 0)
+      cols_fwd_body<L, true, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
+    else
+      cols_fft_body<L>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
+  } else {
+    cols_adj_body<L, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
+  }
+}
+
+template <int KIND, int PG>
+__global__ __launch_bounds__(PERSIST_THREADS) void k_persist(const PItem* __restrict__ items, int n_items,
+                                                            const float* __restrict__ x_arg, float* __restrict__ y_arg) {
+  extern __shared__ float2 smem[];
+  // workgroup b takes items b, b + grid, b + 2 grid, ... of the list (longest
+  // first): no shared counter, whose same-address atomics would serialise
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    __syncthreads();  // the previous item is done with LDS
+    const PItem w = items[it];
+#define PC_CASE(LL)                                  \
+  case LL:                                           \
+    persist_item<KIND, LL>(w, smem, x_arg, y_arg);   \
+    break;
+    if constexpr (PG == 0) {
+      switch (w.L) { PC_FOR_EACH_PG0(PC_CASE) }
+    } else if constexpr (PG == 1) {
+      switch (w.L) { PC_FOR_EACH_PG1(PC_CASE) }
+    } else {
+      switch (w.L) { PC_FOR_EACH_PG2(PC_CASE) }
+    }
+#undef PC_CASE
+  }
+}
+
+bool persist_length(int L) {
+  switch (L) {
+#define PC_CASE(LL) case LL:
+    PC_FOR_EACH_PL(PC_CASE)
+#undef PC_CASE
+    return true;
+  }
+  return false;
+}
+
+int persist_group(int L) { return points_per_thread(L) == 8 ? 0 : points_per_thread(L) == 12 ? 1 : 2; }
+
+int persist_block_rows(int L2) {
+  switch (L2) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return 2 * prow_pairs<LL>();
+    PC_FOR_EACH_PL(PC_CASE)
+#undef PC_CASE
+  }
+  return 0;
+}
+
+template <int KIND>
+static int plds_bytes_of(int L) {
+  switch (L) {
+#define PC_CASE(LL) \
+  case LL:          \
+    return plds_entries<KIND, LL>() * (int)sizeof(float2);
+    PC_FOR_EACH_PL(PC_CASE)
+#undef PC_CASE
+  }
+  return 0;
+}
+
+int persist_lds_bytes(int kind, const std::vector<int>& lengths) {
+  int b = 0;
+  for (int L : lengths) {
+    const int x = kind == PK_ROWS_FWD   ? plds_bytes_of<PK_ROWS_FWD>(L)
+                  : kind == PK_ROWS_INV ? plds_bytes_of<PK_ROWS_INV>(L)
+                  : kind == PK_COLS_A   ? plds_bytes_of<PK_COLS_A>(L)
+                                        : plds_bytes_of<PK_COLS_ADJ>(L);
+    b = std::max(b, x);
+  }
+  return b;
+}
+
+template <int KIND>
+static const void* persist_fn_k(int pg) {
+  if (pg == 0) return reinterpret_cast<const void*>(k_persist<KIND, 0>);
+  if (pg == 1) return reinterpret_cast<const void*>(k_persist<KIND, 1>);
+  return reinterpret_cast<const void*>(k_persist<KIND, 2>);
+}
+
+static const void* persist_fn(int kind, int pg) {
+  switch (kind) {
+    case PK_ROWS_FWD: return persist_fn_k<PK_ROWS_FWD>(pg);
+    case PK_COLS_A: return persist_fn_k<PK_COLS_A>(pg);
+    case PK_COLS_ADJ: return persist_fn_k<PK_COLS_ADJ>(pg);
+  }
+  return persist_fn_k<PK_ROWS_INV>(pg);
+}
+
+// workgroups of a persistent launch: as many as the device holds at once
+// (never more than the items)
+int persist_grid(int kind, int pg, int lds_bytes, int64_t n_items) {
+  int dev = 0, cus = 256, per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(kind, pg), PERSIST_THREADS, lds_bytes) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (int)std::min<int64_t>(n_items, (int64_t)cus * per_cu);
+}
+
+// ---------------------------------------------------------------------------
 // host side: block maps and launches
 // ---------------------------------------------------------------------------
 int row_block_rows(int L2, bool small) { return 2 * (small ? row_pairs_small(L2) : row_pairs_per_block(L2)); }
@@ -596,8 +784,8 @@ int row_threads(int L2, bool small) {
 int col_threads(int L1) { return ffts_per_block(L1) * fft_threads(L1); }
 
 void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq, bool small,
-                       int rows) {
-  const int br = row_block_rows(L2, small);
+                       int rows, int block_rows) {
+  const int br = block_rows > 0 ? block_rows : row_block_rows(L2, small);
   const int nb = rows > 0 && rows < N1 ? (rows + br - 1) / br : N1 / br;
   for (int64_t img = 0; img < n_img; ++img)
     for (int b = 0; b < nb; ++b)
@@ -735,6 +923,16 @@ int col_groups_for(int H2, int64_t batch, int nq) {
 LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg, float* y_arg, hipStream_t s,
                         Tracer* tr, int64_t img_limit) {
   if (nblocks <= 0) return hipSuccess;
+  if (ls.persist >= 0) {
+    static const char* const names[] = {"persist_rows_fwd", "persist_cols_a", "persist_cols_adj", "persist_rows_inv"};
+    TraceScope ts(tr, names[ls.persist & 3], s);
+    const dim3 pg((unsigned)nblocks), pb(PERSIST_THREADS);
+    const void* fn = persist_fn(ls.persist, ls.pgroup);
+    void* args[] = {(void*)&ls.items, (void*)&ls.n_items, (void*)&x_arg, (void*)&y_arg};
+    const hipError_t e = hipLaunchKernel(fn, pg, pb, args, (size_t)ls.lds_bytes, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+  }
   TraceScope ts(tr, kernel_kind_name(ls.kind), s);
   const dim3 grid((unsigned)nblocks), block((unsigned)ls.threads);
   const RowJob* rj = static_cast<const RowJob*>(ls.jobs);

@@ -717,6 +717,7 @@ struct pc_batch_s {
   std::vector<void*> allocs;
   std::vector<pc::LaunchSet> fwd_seq, adj_seq;
   bool has_fwd = false, has_adj = false, use_graph = true;
+  bool persistent = false;  // one persistent launch per pass for the lengths it holds code for
   hipGraph_t gf = nullptr, ga = nullptr;
   hipGraphExec_t ef = nullptr, ea = nullptr;
   // Buffers of the calls: the jobs read each instance's input and output
@@ -762,15 +763,39 @@ namespace {
 
 std::set<const void*> g_batches;  // live batches (guarded by g_registry_mu)
 
+// Launch lists of one batch call.  Each call (apply, apply_adjoint) runs a
+// forward-type chain (windowed row FFTs, term-split column pass with the
+// spectral sum, inverse rows) for the instances that need the
+// convolution-product direction, and an adjoint-type chain (row FFTs, column
+// FFTs, per-(column, factor) adjoint columns, windowed inverse rows) for the
+// others; a product-convolution plan takes the opposite chain of a
+// convolution-product one.
+struct BatchLists {
+  std::vector<pc::LaunchSet> f_rows_in, f_cols, f_rows_out, a_rows_in, a_fft, a_cols, a_rows_out;
+  // persistent passes (pc::PersistKind): their work items and lengths, and
+  // the launches made of them
+  std::vector<pc::PItem> items[4][3];  // [pass][length group]
+  std::vector<int> lens[4][3];
+  std::vector<pc::LaunchSet> persist[4];
+};
+
 template <class J>
 pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L, const std::vector<J>& jobs,
                     const std::vector<pc::BlockRef>& bm, const float2* tw, bool multi_term = true,
-                    bool small_rows = false) {
+                    bool small_rows = false, BatchLists* pl = nullptr, int pkind = -1, int psub = 0) {
   if (jobs.empty()) return PC_SUCCESS;
   J* dj = nullptr;
   pc::BlockRef* db = nullptr;
   pc_status st = b->upload(&dj, jobs);
   if (st) return st;
+  if (pl && pkind >= 0 && b->persistent && pc::persist_length(L)) {
+    // a length of the persistent pass: its blocks become work items
+    const int g = pc::persist_group(L);
+    for (const pc::BlockRef& r : bm) pl->items[pkind][g].push_back(pc::PItem{dj, r, tw, L, psub});
+    if (std::find(pl->lens[pkind][g].begin(), pl->lens[pkind][g].end(), L) == pl->lens[pkind][g].end())
+      pl->lens[pkind][g].push_back(L);
+    return PC_SUCCESS;
+  }
   if ((st = b->upload(&db, bm))) return st;
   pc::LaunchSet ls;
   const bool rows = kind == pc::KK_ROWS_FWD || kind == pc::KK_ROWS_INV;
@@ -822,16 +847,6 @@ pc_status capture(const std::vector<pc::LaunchSet>& seq, hipStream_t cs, hipGrap
   return PC_SUCCESS;
 }
 
-// Launch lists of one batch call.  Each call (apply, apply_adjoint) runs a
-// forward-type chain (windowed row FFTs, term-split column pass with the
-// spectral sum, inverse rows) for the instances that need the
-// convolution-product direction, and an adjoint-type chain (row FFTs, column
-// FFTs, per-(column, factor) adjoint columns, windowed inverse rows) for the
-// others; a product-convolution plan takes the opposite chain of a
-// convolution-product one.
-struct BatchLists {
-  std::vector<pc::LaunchSet> f_rows_in, f_cols, f_rows_out, a_rows_in, a_fft, a_cols, a_rows_out;
-};
 
 // Section evaluation: the row-forward jobs read the boxes of the call's
 // input in place (origins per instance: window box for apply, output box for
@@ -882,6 +897,12 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
     for (int L2 : n2s) {
       const bool sf = pc::tune_get(b->tune_key, PC_TUNE_ROWS_FWD_SMALL, L2, 0) != 0;  // row tiles
       const bool si = pc::tune_get(b->tune_key, PC_TUNE_ROWS_INV_SMALL, L2, 0) != 0;
+      // the persistent row passes take G = 256 / T row pairs per block, when
+      // that many rows divide every image of this row length
+      int pbr = b->persistent && pc::persist_length(L2) ? pc::persist_block_rows(L2) : 0;
+      for (pc_plan q : b->plans)
+        if (pbr && q->p2.N2 == L2 && q->p2.N1 % pbr) pbr = 0;
+      BatchLists* prow = pbr ? &bl : nullptr;
       std::vector<pc::RowJob> jf, jfo, ja, jao;
       std::vector<pc::BlockRef> bf, bfo, ba, bao;
       const float2* tw = nullptr;
@@ -911,20 +932,20 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         const pc::SecTerm* st = gather ? &(*gather->terms)[i] : nullptr;
         const int win_rows = st ? st->ea1 : 0, out_rows = st ? st->ef1 : 0;
         if (fwd_type(i, c)) {
-          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, sf, win_rows);
+          pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, sf, win_rows, pbr);
           jf.push_back(gathered(pc::RowJob{inp, nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap}));
-          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, si, out_rows);
+          pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, si, out_rows, pbr);
           pc::RowJob jo{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0};
           jo.yp = out_slot(i, c);
           jfo.push_back(jo);
         } else {
-          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1, sf);
+          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1, sf, 0, pbr);
           ja.push_back(gathered(pc::RowJob{inp, nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
           if (st) {  // only the output box of the forward section is read (the gradient needs the mask)
             ja.back().mrows = st->ef1;
             ja.back().mcols = st->ef2;
           }
-          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, si, win_rows);
+          pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, si, win_rows, pbr);
           pc::RowJob jo{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap};
           jo.yp = out_slot(i, c);
           if (st && gather->direct_adj) {
@@ -939,10 +960,14 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           jao.push_back(jo);
         }
       }
-      if ((st = batch_set(b, bl.f_rows_in, pc::KK_ROWS_FWD, L2, jf, bf, tw, true, sf))) return st;
-      if ((st = batch_set(b, bl.f_rows_out, pc::KK_ROWS_INV, L2, jfo, bfo, tw, true, si))) return st;
-      if ((st = batch_set(b, bl.a_rows_in, pc::KK_ROWS_FWD, L2, ja, ba, tw, true, sf))) return st;
-      if ((st = batch_set(b, bl.a_rows_out, pc::KK_ROWS_INV, L2, jao, bao, tw, true, si))) return st;
+      if ((st = batch_set(b, bl.f_rows_in, pc::KK_ROWS_FWD, L2, jf, bf, tw, true, sf, prow, pc::PK_ROWS_FWD)))
+        return st;
+      if ((st = batch_set(b, bl.f_rows_out, pc::KK_ROWS_INV, L2, jfo, bfo, tw, true, si, prow, pc::PK_ROWS_INV)))
+        return st;
+      if ((st = batch_set(b, bl.a_rows_in, pc::KK_ROWS_FWD, L2, ja, ba, tw, true, sf, prow, pc::PK_ROWS_FWD)))
+        return st;
+      if ((st = batch_set(b, bl.a_rows_out, pc::KK_ROWS_INV, L2, jao, bao, tw, true, si, prow, pc::PK_ROWS_INV)))
+        return st;
     }
     for (int L1 : n1s) {
       std::vector<pc::ColJob> jf, jt, ja;
@@ -980,15 +1005,40 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           ja.push_back(j);
         }
       }
-      if ((st = batch_set(b, bl.f_cols, pc::KK_COLS_FWD, L1, jf, bf, tw, f_multi))) return st;
-      if ((st = batch_set(b, bl.a_fft, pc::KK_COLS_FFT, L1, jt, bt, tw))) return st;
-      if ((st = batch_set(b, bl.a_cols, pc::KK_COLS_ADJ, L1, ja, ba, tw))) return st;
+      const bool nokeep = keep == nullptr;  // the persistent forward column pass keeps nothing
+      if ((st = batch_set(b, bl.f_cols, pc::KK_COLS_FWD, L1, jf, bf, tw, f_multi, false, nokeep ? &bl : nullptr,
+                          pc::PK_COLS_A, 0)))
+        return st;
+      if ((st = batch_set(b, bl.a_fft, pc::KK_COLS_FFT, L1, jt, bt, tw, true, false, &bl, pc::PK_COLS_A, 1))) return st;
+      if ((st = batch_set(b, bl.a_cols, pc::KK_COLS_ADJ, L1, ja, ba, tw, true, false, &bl, pc::PK_COLS_ADJ))) return st;
     }
   }
   for (int c = 0; c < 2; ++c) {
-    std::vector<pc::LaunchSet>& seq = c == 0 ? b->fwd_seq : b->adj_seq;
     BatchLists& bl = lists[c];
-    for (auto* v : {&bl.f_rows_in, &bl.a_rows_in, &bl.f_cols, &bl.a_fft, &bl.a_cols, &bl.f_rows_out, &bl.a_rows_out})
+    for (int k = 0; k < 4; ++k)
+      for (int g = 2; g >= 0; --g) {  // the launches of longer transforms first
+      std::vector<pc::PItem>& it = bl.items[k][g];
+      if (it.empty()) continue;
+      // longer transforms first (within a length, the instances with the
+      // most terms first, as listed)
+      std::stable_sort(it.begin(), it.end(), [](const pc::PItem& x, const pc::PItem& y) { return x.L > y.L; });
+      pc::PItem* di = nullptr;
+      if ((st = b->upload(&di, it))) return st;
+      pc::LaunchSet ls;
+      ls.persist = k;
+      ls.pgroup = g;
+      ls.items = di;
+      ls.n_items = (int)it.size();
+      ls.lds_bytes = pc::persist_lds_bytes(k, bl.lens[k][g]);
+      ls.blocks = pc::persist_grid(k, g, ls.lds_bytes, ls.n_items);
+      ls.threads = pc::PERSIST_THREADS;
+      ls.kind = k == pc::PK_ROWS_FWD ? pc::KK_ROWS_FWD : k == pc::PK_ROWS_INV ? pc::KK_ROWS_INV : pc::KK_COLS_FWD;
+      bl.persist[k].push_back(ls);
+      }
+    std::vector<pc::LaunchSet>& seq = c == 0 ? b->fwd_seq : b->adj_seq;
+    for (auto* v : {&bl.persist[pc::PK_ROWS_FWD], &bl.f_rows_in, &bl.a_rows_in, &bl.persist[pc::PK_COLS_A], &bl.f_cols,
+                    &bl.a_fft, &bl.persist[pc::PK_COLS_ADJ], &bl.a_cols, &bl.persist[pc::PK_ROWS_INV], &bl.f_rows_out,
+                    &bl.a_rows_out})
       seq.insert(seq.end(), v->begin(), v->end());
   }
   return PC_SUCCESS;
@@ -1654,7 +1704,8 @@ pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, ui
   if (!out) return fail(PC_ERROR_INVALID_VALUE, "out is NULL");
   *out = nullptr;
   if (count < 1 || !plans) return fail(PC_ERROR_INVALID_VALUE, "count < 1 or null plan array");
-  if (flags & ~(uint32_t)PC_BATCH_NO_GRAPH) return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
+  if (flags & ~(uint32_t)(PC_BATCH_NO_GRAPH | PC_BATCH_PERSISTENT))
+    return fail(PC_ERROR_INVALID_VALUE, "unknown flag bits");
   int device = -1;
   std::set<pc_plan> seen;
   for (int i = 0; i < count; ++i) {
@@ -1679,6 +1730,7 @@ pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, ui
     for (pc_plan q : b->plans) ds.push_back(q->d);
     b->tune_key = pc::tune_batch_key(ds);
   }
+  b->persistent = (flags & PC_BATCH_PERSISTENT) || pc::tune_get(b->tune_key, PC_TUNE_BATCH_PERSISTENT, 0, 0) != 0;
   b->use_graph = !(flags & PC_BATCH_NO_GRAPH);
   DeviceGuard g(device);
   const size_t tab_bytes = (size_t)4 * count * sizeof(float*);
@@ -1835,7 +1887,7 @@ pc_status pc_tune_set(const pc_tune_entry* entries, int32_t count) {
   std::vector<pc::TuneEntry> t;
   for (int32_t i = 0; i < count; ++i) {
     const pc_tune_entry& e = entries[i];
-    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_FOURSTEP_L)
+    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_BATCH_PERSISTENT)
       return fail(PC_ERROR_INVALID_VALUE, "unknown knob " + std::to_string(e.knob) + " in entry " + std::to_string(i));
     t.push_back({e.key, e.knob, e.length, e.value});
   }

@@ -207,6 +207,28 @@ struct BlockRef {
 
 enum KernelKind { KK_ROWS_FWD = 0, KK_ROWS_INV, KK_COLS_FWD, KK_COLS_SUM, KK_COLS_ADJ, KK_COLS_FFT, KK_COLS_BWD1 };
 
+// Persistent batch passes: every row or column block of a pass, whatever
+// its transform length (within a length group), is one work item of one
+// launch; the workgroups walk the list with a grid stride.
+enum PersistKind { PK_ROWS_FWD = 0, PK_COLS_A = 1, PK_COLS_ADJ = 2, PK_ROWS_INV = 3 };
+struct PItem {
+  const void* jobs;  // device RowJob[] or ColJob[] of the item's length
+  BlockRef bm;
+  const float2* tw;  // engine twiddles for L
+  int L;
+  int sub;           // PK_COLS_A: 0 forward column pass, 1 column transform of V
+};
+constexpr int PERSIST_THREADS = 256;
+// transform lengths the persistent kernels hold code for
+bool persist_length(int L);
+// rows per block of the persistent row passes (G = PERSIST_THREADS / T row pairs)
+int persist_block_rows(int L2);
+// dynamic LDS bytes of a persistent pass over the given lengths
+int persist_lds_bytes(int kind, const std::vector<int>& lengths);
+// length group of a persistent launch (points per thread 8, 12, 16)
+int persist_group(int L);
+int persist_grid(int kind, int pg, int lds_bytes, int64_t n_items);
+
 // A prepared launch: kernel kind and length, device tables, block counts.
 struct LaunchSet {
   int kind = 0;
@@ -222,6 +244,13 @@ struct LaunchSet {
   bool prefetch = false;           // adjoint column kernel: the prefetching variant (cols_adj_prefetch)
   bool pipe = false;               // row-inverse kernel: the pipelined variant (rows_inv_pipe)
   bool keep = false;               // forward column kernel: the variant storing U_k (jobs' keep pointers)
+  // persistent pass (persist >= 0: a PersistKind) of length group pgroup:
+  // items (device PItem[]), their count and the dynamic LDS bytes
+  int persist = -1;
+  int pgroup = 0;
+  const PItem* items = nullptr;
+  int n_items = 0;
+  int lds_bytes = 0;
 };
 
 struct Plan2D {
@@ -285,9 +314,10 @@ int col_block_cols(int L1);
 int row_threads(int L2, bool small = false);
 int col_threads(int L1);
 // rows: the leading rows of each image the blocks cover (0: all N1; rounded
-// up to whole row blocks)
+// up to whole row blocks); block_rows: rows per block (0: the tile of
+// row_block_rows(L2, small))
 void append_row_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int N1, int L2, int nq,
-                       bool small = false, int rows = 0);
+                       bool small = false, int rows = 0, int block_rows = 0);
 void append_col_blocks(std::vector<BlockRef>& out, int job, int64_t n_img, int H2, int L1, int nsub);
 const char* kernel_kind_name(int kind);
 // img_limit: blocks of images >= img_limit return at once (their input and

@@ -112,6 +112,8 @@ class Workload:
                     ("cols_adj_prefetch", L, KNOB_VALUES["cols_adj_prefetch"])]
         for L in rows:
             out += [(k, L, KNOB_VALUES[k]) for k in ("rows_fwd_small", "rows_inv_small", "rows_inv_pipe")]
+        if self.name == "c4":
+            out += [("batch_persistent", 0, (0, 1))]
         if self.name == "c3":
             pl = self.plans[0]
             nq = pl.desc.m_cols if pl.desc.w_format == 1 else pl.desc.m

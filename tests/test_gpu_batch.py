@@ -28,13 +28,13 @@ def _setup(count, seed=4):
     return probs, plans, inputs
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_matches_oracle_and_single_plans(graph):
+@pytest.mark.parametrize("graph,persistent", [(True, False), (False, False), (True, True), (False, True)])
+def test_batch_matches_oracle_and_single_plans(graph, persistent):
     import torch
     import paper_1604_04374_amd as pcm
     probs, plans, inputs = _setup(24)
-    print(f"[gpu] batch of {len(plans)} (graph={graph})", flush=True)
-    b = pcm.Batch(plans, graph=graph)
+    print(f"[gpu] batch of {len(plans)} (graph={graph}, persistent={persistent})", flush=True)
+    b = pcm.Batch(plans, graph=graph, persistent=persistent)
     y = [t.clone() for t in b.apply(inputs)]
     x = [t.clone() for t in b.apply_adjoint(inputs)]
     torch.cuda.synchronize()
@@ -87,12 +87,13 @@ def _oracle_on(p, u):
     return ex.apply_fft(uu, w, h), ex.adjoint_fft(uu, w, h)
 
 
-def test_graph_replays_are_identical_and_match_direct_launches():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replays_are_identical_and_match_direct_launches(persistent):
     import torch
     import paper_1604_04374_amd as pcm
     probs, plans, inputs = _setup(16, seed=9)
-    print("[gpu] batch graph replays", flush=True)
-    bg = pcm.Batch(plans, graph=True)
+    print(f"[gpu] batch graph replays (persistent={persistent})", flush=True)
+    bg = pcm.Batch(plans, graph=True, persistent=persistent)
     first = [t.clone() for t in bg.apply(inputs)]
     firsta = [t.clone() for t in bg.apply_adjoint(inputs)]
     for rep in range(4):
@@ -108,7 +109,7 @@ def test_graph_replays_are_identical_and_match_direct_launches():
             assert torch.equal(a, b), rep
         del z
     bg.destroy()
-    bd = pcm.Batch(plans, graph=False)
+    bd = pcm.Batch(plans, graph=False, persistent=persistent)
     yd = bd.apply(inputs)
     xd = bd.apply_adjoint(inputs)
     torch.cuda.synchronize()
@@ -122,14 +123,15 @@ def test_graph_replays_are_identical_and_match_direct_launches():
 
 
 @pytest.mark.slow
-def test_c4_full_size_batch():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_c4_full_size_batch(persistent):
     # the uneven-batch workload at its stated size: all 256 instances in one
     # batch, one graph launch per direction, every instance against the oracle
     import torch
     import paper_1604_04374_amd as pcm
     probs, plans, inputs = _setup(256, seed=4)
-    print(f"[gpu] C4 full batch: {len(plans)} instances", flush=True)
-    b = pcm.Batch(plans, graph=True)
+    print(f"[gpu] C4 full batch: {len(plans)} instances (persistent={persistent})", flush=True)
+    b = pcm.Batch(plans, graph=True, persistent=persistent)
     y = b.apply(inputs)
     x = b.apply_adjoint(inputs)
     torch.cuda.synchronize()
