@@ -37,8 +37,10 @@ namespace pc {
   X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) \
   X(96) X(192) X(384) X(768) X(1536) X(3072) X(6144)
 
-// Window applied by the row kernels.
-enum RowWin { RW_NONE = 0, RW_FACTOR = 1, RW_DENSE = 2 };
+// Window applied by the row kernels.  RW_BOX: one term whose window is the
+// product of a row factor and a column factor, wsrc = [a[N1] | b[L2]]; the
+// row kernels run it as RW_FACTOR on b, times a[r] per row.
+enum RowWin { RW_NONE = 0, RW_FACTOR = 1, RW_DENSE = 2, RW_BOX = 3 };
 
 // Device-memory access through the job tables' pointers.  The compiler
 // cannot tell that a pointer read from a table addresses global memory and
@@ -55,19 +57,6 @@ __device__ __forceinline__ float2 gld(const float2* p, int64_t i) {
 __device__ __forceinline__ void gst(float2* p, int64_t i, float2 v) { ((PC_GLOBAL pc_f2*)p)[i] = pc_f2{v.x, v.y}; }
 __device__ __forceinline__ float gldf(const float* p, int64_t i) { return ((const PC_GLOBAL float*)p)[i]; }
 __device__ __forceinline__ void gstf(float* p, int64_t i, float v) { ((PC_GLOBAL float*)p)[i] = v; }
-
-__device__ __forceinline__ void row_weights(const float* __restrict__ wsrc, int mode, int q, int N1, int L2, int r,
-                                            int n2, float& wa, float& wb) {
-  if (mode == RW_FACTOR) {
-    wa = wb = gldf(wsrc, (int64_t)q * L2 + n2);
-  } else if (mode == RW_DENSE) {
-    const float* base = wsrc + ((int64_t)q * N1 + r) * L2 + n2;
-    wa = gldf(base, 0);
-    wb = gldf(base, L2);
-  } else {
-    wa = wb = 1.0f;
-  }
-}
 
 // The thread index, opaque to the compiler (an empty asm statement that
 // claims to modify it).  Passed to a transform inside a runtime loop, it keeps
@@ -135,19 +124,61 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
     rb = ra + L2;
   }
   float2 v[P];
-  // masked rows and columns count as zero (the gradient's box of the output
-  // gradient); the samples are read anyway (they lie inside the image)
-  const float ma = (jb.mrows > 0 && r >= jb.mrows) ? 0.f : 1.f;
-  const float mb = (jb.mrows > 0 && r + 1 >= jb.mrows) ? 0.f : 1.f;
+  // masked rows and columns count as zero and are not read (the window box
+  // of a section, the gradient's box of the output gradient)
+  const bool la = jb.mrows <= 0 || r < jb.mrows, lb = jb.mrows <= 0 || r + 1 < jb.mrows;
   const int mc = jb.mcols > 0 ? jb.mcols : L2;
+  int mode = jb.mode;
+  const float* ws = jb.wsrc;
+  float sa = 1.f, sb = 1.f;
+  if (mode == RW_BOX) {
+    sa = gldf(ws, r);
+    sb = gldf(ws, r + 1);
+    ws += N1;
+    mode = RW_FACTOR;
+  }
+  // every load is issued unconditionally, masked samples at the row's first
+  // address (lane 0's line: no extra traffic), then zeroed by a select; one
+  // branch per window mode around straight-line code (a branch per element
+  // made the compiler wait for each element's loads in turn)
+  float xa[P], xb[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
-    const int o = n2 < wrap ? n2 : n2 - jb.gN2;
-    float wa, wb;
-    row_weights(jb.wsrc, jb.mode, q, N1, L2, r, n2, wa, wb);
-    const float mcol = n2 < mc ? 1.f : 0.f;
-    v[e] = make_float2(wa * ma * mcol * gldf(ra, o), wb * mb * mcol * gldf(rb, o));
+    const int o = n2 < mc ? (n2 < wrap ? n2 : n2 - jb.gN2) : 0;
+    xa[e] = gldf(ra, o);
+    xb[e] = gldf(rb, o);
+  }
+  if (mode == RW_DENSE) {
+    const float* wp = ws + ((int64_t)q * N1 + r) * L2;
+    float wa[P], wb[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n2 = t + T * e < mc ? t + T * e : 0;
+      wa[e] = gldf(wp, n2);
+      wb[e] = gldf(wp, L2 + n2);
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const bool in = t + T * e < mc;
+      v[e] = make_float2(in && la ? wa[e] * xa[e] : 0.f, in && lb ? wb[e] * xb[e] : 0.f);
+    }
+  } else if (mode == RW_FACTOR) {
+    const float* wp = ws + (int64_t)q * L2;
+    float w[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) w[e] = gldf(wp, t + T * e < mc ? t + T * e : 0);
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const bool in = t + T * e < mc;
+      v[e] = make_float2(in && la ? sa * w[e] * xa[e] : 0.f, in && lb ? sb * w[e] * xb[e] : 0.f);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const bool in = t + T * e < mc;
+      v[e] = make_float2(in && la ? xa[e] : 0.f, in && lb ? xb[e] : 0.f);
+    }
   }
   float2* my = lds + c * lds_len<L2>();
   fft_wv<L2, P, false, SYNC_WAVE>(v, my, twl, t);
@@ -203,7 +234,8 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
 template <int L2, int G, bool PIPE>
 __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, const BlockRef bm,
                                               float* __restrict__ y_arg, float2* __restrict__ lds,
-                                              const float2* __restrict__ twl, const int tid) {
+                                              const float2* __restrict__ twl, float* __restrict__ rfac,
+                                              const int tid) {
   constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
   const RowJob& jb = jobs[bm.job];
@@ -220,6 +252,8 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
   constexpr int TILE = H2 * 2 * G, PER = PIPE ? (TILE + NT - 1) / NT : 1;
   const float2* src0 = jb.sin + img * ((int64_t)H2 * N1) + r0;
   float2 nxt[PER];
+  const int mode = jb.mode == RW_BOX ? RW_FACTOR : jb.mode;
+  const float* ws = jb.mode == RW_BOX ? jb.wsrc + N1 : jb.wsrc;
   if constexpr (PIPE) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -227,6 +261,10 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
       if (idx < TILE) nxt[i] = gld(src0, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
     }
   }
+  // a factored window's row factors, staged in LDS (visible after the
+  // loop's first barrier) so that no register holds them across the transforms
+  const bool box = jb.mode == RW_BOX;
+  if (box && tid < 2 * G) rfac[tid] = gldf(jb.wsrc, r0 + tid);
   for (int q = 0; q < jb.nq; ++q) {
     __syncthreads();  // the previous transform is done with LDS
     if constexpr (PIPE) {
@@ -268,14 +306,39 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
       v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
     }
     fft_wv<L2, P, true, SYNC_WAVE_ENTRY>(v, my, twl, opaque(t));
+    // one branch per window mode around straight-line loads
+    if (mode == RW_DENSE) {
+      const float* wp = ws + ((int64_t)q * N1 + r) * L2 + t;
+      float wa[P], wb[P];
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      float wa, wb;
-      row_weights(jb.wsrc, jb.mode, q, N1, L2, r, t + T * e, wa, wb);
-      acc[e].x = fmaf(wa, v[e].x, acc[e].x);
-      acc[e].y = fmaf(wb, v[e].y, acc[e].y);
+      for (int e = 0; e < P; ++e) {
+        wa[e] = gldf(wp, T * e);
+        wb[e] = gldf(wp, L2 + T * e);
+      }
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        acc[e].x = fmaf(wa[e], v[e].x, acc[e].x);
+        acc[e].y = fmaf(wb[e], v[e].y, acc[e].y);
+      }
+    } else if (mode == RW_FACTOR) {
+      const float* wp = ws + (int64_t)q * L2 + t;
+      float w[P];
+#pragma unroll
+      for (int e = 0; e < P; ++e) w[e] = gldf(wp, T * e);
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        acc[e].x = fmaf(w[e], v[e].x, acc[e].x);
+        acc[e].y = fmaf(w[e], v[e].y, acc[e].y);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        acc[e].x += v[e].x;
+        acc[e].y += v[e].y;
+      }
     }
   }
+  const float sa = box ? rfac[2 * c] * jb.scale : jb.scale, sb = box ? rfac[2 * c + 1] * jb.scale : jb.scale;
   if (jb.oN2 > 0) {
     // section evaluation: the leading orows x ocols block goes straight to
     // its place in the output image (both axes wrapped)
@@ -291,8 +354,8 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
       int o = jb.o2 + n2;
       if (o >= jb.oN2) o -= jb.oN2;
       if (n2 < jb.ocols) {
-        if (wa) gstf(oa, o, acc[e].x * jb.scale);
-        if (wb) gstf(ob, o, acc[e].y * jb.scale);
+        if (wa) gstf(oa, o, acc[e].x * sa);
+        if (wb) gstf(ob, o, acc[e].y * sb);
       }
     }
     return;
@@ -301,8 +364,8 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
-    gstf(oa, n2, acc[e].x * jb.scale);
-    gstf(oa, n2 + L2, acc[e].y * jb.scale);
+    gstf(oa, n2, acc[e].x * sa);
+    gstf(oa, n2 + L2, acc[e].y * sb);
   }
 }
 
@@ -312,10 +375,11 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
     const float2* __restrict__ tw, int64_t img_limit) {
   __shared__ float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
+  __shared__ float rfac[2 * G];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
   stage_twiddles<L2>(twl, tw);
-  rows_inv_body<L2, G, PIPE>(jobs, bm, y_arg, lds, twl, threadIdx.x);
+  rows_inv_body<L2, G, PIPE>(jobs, bm, y_arg, lds, twl, rfac, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,8 +431,18 @@ __device__ __forceinline__ void cols_fwd_body(const ColJob* __restrict__ jobs, c
 #pragma unroll
         for (int e = 0; e < P; ++e) hv[e] = gld(Hk, t + T * e);
       }
+      // row factor: loads issued together (a select per element would make
+      // the compiler wait for each in turn)
+      if (dense) {
 #pragma unroll
-      for (int e = 0; e < P; ++e) v[e] = dense ? cv[e] : cscale(cv[e], gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e));
+        for (int e = 0; e < P; ++e) v[e] = cv[e];
+      } else {
+        float w[P];
+#pragma unroll
+        for (int e = 0; e < P; ++e) w[e] = gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e);
+#pragma unroll
+        for (int e = 0; e < P; ++e) v[e] = cscale(cv[e], w[e]);
+      }
       fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
       if (KEEP && valid) {
         float2* kp = jb.keep + (int64_t)k * jb.keep_stride + img * plane + (int64_t)f2 * L1;
@@ -382,9 +456,13 @@ __device__ __forceinline__ void cols_fwd_body(const ColJob* __restrict__ jobs, c
   if (ngroups == 1) {
     fft_wv<L1, P, true, SYNC_WAVE>(acc, my, twl, t);
     if (valid) {
+      // rows t + T e < nvalid_out are stored (the rows the row-inverse pass reads)
+      const int nvo = jb.nvalid_out == 0 ? L1 : jb.nvalid_out;
+      const int no = nvo > t ? (nvo - t + T - 1) / T : 0;
       float2* dst = jb.dst + img * plane + (int64_t)f2 * L1;
 #pragma unroll
-      for (int e = 0; e < P; ++e) gst(dst, t + T * e, acc[e]);
+      for (int e = 0; e < P; ++e)
+        if (e < no) gst(dst, t + T * e, acc[e]);
     }
   } else if (valid) {
     float2* dst = jb.part + g * jb.part_stride + img * plane + (int64_t)f2 * L1;
@@ -489,11 +567,21 @@ __device__ __forceinline__ void cols_adj_body(const ColJob* __restrict__ jobs, c
       for (int e = 0; e < P; ++e) g[e] = cmulc(vh[e], gld(Hk, t + T * e));
     }
     fft_wv<L1, P, true, SYNC_WAVE>(g, my, twl, opaque(t));
+    if (dense) {
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      const float wv = dense ? 1.0f : gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e);
-      acc[e].x = fmaf(wv, g[e].x, acc[e].x);
-      acc[e].y = fmaf(wv, g[e].y, acc[e].y);
+      for (int e = 0; e < P; ++e) {
+        acc[e].x += g[e].x;
+        acc[e].y += g[e].y;
+      }
+    } else {
+      float w[P];
+#pragma unroll
+      for (int e = 0; e < P; ++e) w[e] = gldf(jb.wrows, (int64_t)k1 * L1 + t + T * e);
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        acc[e].x = fmaf(w[e], g[e].x, acc[e].x);
+        acc[e].y = fmaf(w[e], g[e].y, acc[e].y);
+      }
     }
   }
   if (valid) {
@@ -646,7 +734,9 @@ constexpr int prow_pairs() { return PERSIST_THREADS / fft_threads(L); }
 
 template <int KIND, int L>
 constexpr int plds_entries() {
-  return ((KIND == PK_ROWS_FWD || KIND == PK_ROWS_INV) ? prow_pairs<L>() : ffts_per_block(L)) * lds_len<L>() + L;
+  // transform buffers, twiddles and (row-inverse) the 2G row factors
+  return ((KIND == PK_ROWS_FWD || KIND == PK_ROWS_INV) ? prow_pairs<L>() : ffts_per_block(L)) * lds_len<L>() + L +
+         (KIND == PK_ROWS_INV ? prow_pairs<L>() : 0);
 }
 
 template <int KIND, int L>
@@ -660,7 +750,8 @@ __device__ __forceinline__ void persist_item(const PItem& w, float2* smem, const
   if constexpr (KIND == PK_ROWS_FWD) {
     rows_fwd_body<L, prow_pairs<L>()>(static_cast<const RowJob*>(w.jobs), w.bm, x_arg, lds, twl, tid);
   } else if constexpr (KIND == PK_ROWS_INV) {
-    rows_inv_body<L, prow_pairs<L>(), false>(static_cast<const RowJob*>(w.jobs), w.bm, y_arg, lds, twl, tid);
+    rows_inv_body<L, prow_pairs<L>(), false>(static_cast<const RowJob*>(w.jobs), w.bm, y_arg, lds, twl,
+                                             reinterpret_cast<float*>(lds + prow_pairs<L>() * lds_len<L>()), tid);
   } else if constexpr (KIND == PK_COLS_A) {
     if (w.sub == 0)
       cols_fwd_body<L, true, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
@@ -1202,9 +1293,13 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_grad2d
         for (int e = 0; e < P; ++e) v[e] = kp[t + T * e];
       } else {
 #pragma unroll
-        for (int e = 0; e < P; ++e) {
-          v[e] = col[t + T * e];
-          if (!dense) v[e] = cscale(v[e], wrows[(int64_t)k1 * L1 + t + T * e]);
+        for (int e = 0; e < P; ++e) v[e] = col[t + T * e];
+        if (!dense) {
+          float w[P];
+#pragma unroll
+          for (int e = 0; e < P; ++e) w[e] = wrows[(int64_t)k1 * L1 + t + T * e];
+#pragma unroll
+          for (int e = 0; e < P; ++e) v[e] = cscale(v[e], w[e]);
         }
         fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
       }

@@ -549,7 +549,10 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   return PC_SUCCESS;
 }
 
-pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t s) {
+// box: a single-term plan whose window is the product of a row factor and a
+// column factor, given as [a[N1] | b[N2]] (windows unused): the row passes
+// form the window from the two factors instead of reading a dense plane.
+pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t s, const float* box = nullptr) {
   const int N1 = (int)p->d.n0, N2 = (int)p->d.n1, H2 = N2 / 2 + 1;
   const int m = p->d.m;
   const int64_t cap = p->d.batch;
@@ -559,13 +562,19 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   q.N2 = N2;
   q.H2 = H2;
   q.m = m;
-  q.dense = dense;
+  q.dense = dense || box;
+  q.wmode = box ? 3 : dense ? 2 : 1;
   q.batch_cap = cap;
-  q.m1 = dense ? 1 : p->d.m_rows;
-  q.m2 = dense ? m : p->d.m_cols;
+  q.m1 = q.dense ? 1 : p->d.m_rows;
+  q.m2 = q.dense ? m : p->d.m_cols;
   pc_status st;
   const int64_t plane = (int64_t)N1 * H2;
-  if (dense) {
+  if (box) {
+    float* w = nullptr;
+    if ((st = p->upload(&w, std::vector<float>(box, box + (size_t)N1 + N2), s, &p->window_bytes))) return st;
+    q.wcols = w;
+    q.wrows = nullptr;
+  } else if (dense) {
     float* w = nullptr;
     if ((st = p->upload(&w, std::vector<float>(windows, windows + (size_t)m * N1 * N2), s, &p->window_bytes)))
       return st;
@@ -591,7 +600,7 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   float2* Hs = nullptr;
   if ((st = p->alloc(&Hs, (size_t)m * plane, &p->spectra_bytes))) return st;
   q.Hs = Hs;
-  const int nq = dense ? m : q.m2;
+  const int nq = q.dense ? m : q.m2;
   if ((st = p->alloc(&q.RA, (size_t)(nq * cap * plane), &p->workspace_bytes))) return st;
   if ((st = p->alloc(&q.Tws, (size_t)(cap * plane), &p->workspace_bytes))) return st;
   q.col_groups = std::max(1, std::min(nq, pc::tune_get(p->tune_key, PC_TUNE_COL_GROUPS, N1,
@@ -601,7 +610,7 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
     return st;
 
   // launch tables
-  const int mode = dense ? 2 : 1;
+  const int mode = q.wmode;
   const float scale = 1.0f / ((float)N1 * (float)N2);
   // launches too small to fill the chip with the default row tiles (one row
   // block per compute unit at least) take the small tiles; the forward row
@@ -626,7 +635,7 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
                        sr_q)))
       return st;
   }
-  pc::ColJob cf{q.RA, q.Tws, q.Part, Hs, q.wrows, plane * cap, plane * cap, H2, q.m1, q.m2, dense ? 1 : 0,
+  pc::ColJob cf{q.RA, q.Tws, q.Part, Hs, q.wrows, plane * cap, plane * cap, H2, q.m1, q.m2, q.dense ? 1 : 0,
                 q.col_groups};
   bm.clear();
   pc::append_col_blocks(bm, 0, cap, H2, N1, q.col_groups);
@@ -653,9 +662,9 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
   // a single term needs one column transform of V per column: the adjoint
   // column pass does it itself
   q.adj_fused = m == 1;
-  pc::ColJob ca{q.Tws, q.RA, nullptr, Hs, q.wrows, plane * cap, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+  pc::ColJob ca{q.Tws, q.RA, nullptr, Hs, q.wrows, plane * cap, 0, H2, q.m1, q.m2, q.dense ? 1 : 0, 1};
   ca.fft_src = q.adj_fused ? 1 : 0;
-  pc::ColJob cfft{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+  pc::ColJob cfft{nullptr, q.Tws, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, q.dense ? 1 : 0, 1};
   bm.clear();
   pc::append_col_blocks(bm, 0, cap, H2, N1, 1);
   if ((st = make_set(p, q.adj_fft, pc::KK_COLS_FFT, N1, std::vector<pc::ColJob>{cfft}, bm, cpi, tw1, s))) return st;
@@ -675,7 +684,7 @@ pc_status build_2d(pc_plan p, const float* windows, const float* h, hipStream_t 
     bm.clear();
     pc::append_row_blocks(bm, 0, m, N1, N2, 1, sr);
     if ((st = make_set(p, q.spec_rows, pc::KK_ROWS_FWD, N2, std::vector<pc::RowJob>{j}, bm, rpi, tw2, s, sr))) return st;
-    pc::ColJob c{nullptr, Hs, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, dense ? 1 : 0, 1};
+    pc::ColJob c{nullptr, Hs, nullptr, nullptr, nullptr, 0, 0, H2, q.m1, q.m2, q.dense ? 1 : 0, 1};
     bm.clear();
     pc::append_col_blocks(bm, 0, m, H2, N1, 1);
     if ((st = make_set(p, q.spec_cols, pc::KK_COLS_FFT, N1, std::vector<pc::ColJob>{c}, bm, cpi, tw1, s))) return st;
@@ -913,7 +922,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         const float* inp = table ? nullptr : in[i];
         tw = q.tw2;
         const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
-        const int nq = q.dense ? q.m : q.m2, mode = q.dense ? 2 : 1;
+        const int nq = q.dense ? q.m : q.m2, mode = q.wmode;
         const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
         auto gathered = [&](pc::RowJob j) {
           j.xp = in_slot(i, c);
@@ -934,6 +943,10 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         if (fwd_type(i, c)) {
           pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, sf, win_rows, pbr);
           jf.push_back(gathered(pc::RowJob{inp, nullptr, q.wcols, mode, q.N1, 0, 0.f, nullptr, q.RA, plane * cap}));
+          if (st) {  // samples outside the window box are zero and not read
+            jf.back().mrows = st->ea1;
+            jf.back().mcols = st->ea2;
+          }
           pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, si, out_rows, pbr);
           pc::RowJob jo{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0};
           jo.yp = out_slot(i, c);
@@ -985,7 +998,12 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
           f_multi = f_multi || q.m > 1;
           jf.push_back(pc::ColJob{q.RA, q.Tws, nullptr, q.Hs, q.wrows, plane * cap, 0, q.H2, q.m1, q.m2, dense, 1});
-          if (st) jf.back().nvalid_in = st->ea1;  // the row pass transformed the window box rows only
+          if (st) {
+            jf.back().nvalid_in = st->ea1;  // the row pass transformed the window box rows only
+            // the row-inverse pass reads whole row blocks of the output box rows
+            const int br = pc::row_block_rows(q.N2, pc::tune_get(b->tune_key, PC_TUNE_ROWS_INV_SMALL, q.N2, 0) != 0);
+            jf.back().nvalid_out = std::min(q.N1, (st->ef1 + br - 1) / br * br);
+          }
           if (keep) {
             jf.back().keep = (*keep)[i];
             jf.back().keep_stride = plane * cap;
@@ -1110,7 +1128,8 @@ bool plan_sections(const pc_plan_desc& d, const float* windows, const float* h, 
   return !out.empty() && 2.0 * c_sec < c_full;
 }
 
-pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out);
+pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out,
+                      const float* box = nullptr);
 
 pc_status make_transpose_set(pc_plan p, pc::TransposeSet& ts, std::vector<pc::TransposeJob> jobs) {
   int64_t b0 = 0;
@@ -1227,6 +1246,34 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
     for (int64_t i = 0; i < sc.q1; ++i)
       for (int64_t j = 0; j < sc.q2; ++j)
         hsub[(size_t)(i * sc.M2 + j)] = h[((size_t)sc.k * N1 + (sc.a1 + i) % N1) * N2 + (sc.a2 + j) % N2];
+    // the window box as a row factor times a column factor when that
+    // product reproduces every float32 sample exactly (always, for
+    // separable windows), so the row passes need no dense window plane
+    std::vector<float> box((size_t)(sc.M1 + sc.M2), 0.f);
+    bool factored = true;
+    if (!dense) {
+      for (int64_t i = 0; i < sc.p1; ++i) box[(size_t)i] = windows[(size_t)(sc.k / d.m_cols) * N1 + (sc.o1 + i) % N1];
+      for (int64_t j = 0; j < sc.p2; ++j)
+        box[(size_t)(sc.M1 + j)] = windows[(size_t)d.m_rows * N1 + (size_t)(sc.k % d.m_cols) * N2 + (sc.o2 + j) % N2];
+    } else {
+      // pivot: the largest sample; a = its column, b = its row over the pivot
+      int64_t pi = 0, pj = 0;
+      for (int64_t i = 0; i < sc.p1; ++i)
+        for (int64_t j = 0; j < sc.p2; ++j)
+          if (std::fabs(wsub[(size_t)(i * sc.M2 + j)]) > std::fabs(wsub[(size_t)(pi * sc.M2 + pj)])) {
+            pi = i;
+            pj = j;
+          }
+      const float piv = wsub[(size_t)(pi * sc.M2 + pj)];
+      for (int64_t i = 0; i < sc.p1; ++i) box[(size_t)i] = wsub[(size_t)(i * sc.M2 + pj)];
+      for (int64_t j = 0; j < sc.p2; ++j) box[(size_t)(sc.M1 + j)] = wsub[(size_t)(pi * sc.M2 + j)] / piv;
+    }
+    for (int64_t i = 0; i < sc.p1 && factored; ++i)
+      for (int64_t j = 0; j < sc.p2; ++j)
+        if (box[(size_t)i] * box[(size_t)(sc.M1 + j)] != wsub[(size_t)(i * sc.M2 + j)]) {
+          factored = false;
+          break;
+        }
     pc_plan_desc sd{};
     sd.ndim = 2;
     sd.m = 1;
@@ -1236,7 +1283,7 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
     sd.w_format = PC_W_DENSE;
     sd.flags = PC_PLAN_FULL_GRID | (d.flags & PC_PLAN_GRADIENTS);
     pc_plan_s* sub = nullptr;
-    if ((st = create_plan(sd, wsub.data(), hsub.data(), s, &sub))) return st;
+    if ((st = create_plan(sd, wsub.data(), hsub.data(), s, &sub, factored ? box.data() : nullptr))) return st;
     p->sec_sub.push_back(sub);
     p->spectra_bytes += sub->spectra_bytes;
     p->window_bytes += sub->window_bytes;
@@ -1483,7 +1530,8 @@ pc_status check_batch(pc_batch b) {
   return PC_SUCCESS;
 }
 
-pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out) {
+pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* h, hipStream_t s, pc_plan_s** out,
+                      const float* box) {
   if (d.ndim != 1 && d.ndim != 2) return fail(PC_ERROR_INVALID_VALUE, "ndim must be 1 or 2");
   if (d.m < 1) return fail(PC_ERROR_INVALID_VALUE, "m must be >= 1");
   if (d.batch < 1) return fail(PC_ERROR_INVALID_VALUE, "batch must be >= 1");
@@ -1554,7 +1602,7 @@ pc_status create_plan(const pc_plan_desc& d, const float* windows, const float* 
   else if (path == 1)
     st = build_large1d(p, L, R, windows, h, s);
   else if (path == 2)
-    st = build_2d(p, windows, h, s);
+    st = build_2d(p, windows, h, s, box);
   else
     st = build_sec2d(p, windows, h, secs, s);
   if (st == PC_SUCCESS && path != 3) {  // sectioned plans count their sections' spectra

@@ -138,7 +138,8 @@ struct RowJob {
   const float* x;      // input images (row-forward); null: the launch's pointer argument
   float* y;            // output images (row-inverse); null: the launch's pointer argument
   const float* wsrc;   // window source (see RowWin in the 2D kernels)
-  int mode;            // 0 none, 1 column factors b_q[n2], 2 dense windows w_q[n1][n2]
+  int mode;            // 0 none, 1 column factors b_q[n2], 2 dense windows w_q[n1][n2],
+                       // 3 one term's row and column factors [a[N1] | b[N2]]
   int N1;              // rows per image
   int nq;              // row-inverse: factor planes accumulated
   float scale;         // row-inverse: output scale
@@ -179,8 +180,8 @@ struct ColJob {
   int fft_src = 0;
   // rows of the columns known to matter (0: all N1): the forward pass reads
   // src entries n1 < nvalid_in only (the rest are zero: rows the row pass
-  // skipped), the adjoint pass writes dst entries n1 < nvalid_out only (the
-  // rest are never read)
+  // skipped); both passes write dst entries n1 < nvalid_out only (the rest
+  // are never read)
   int nvalid_in = 0, nvalid_out = 0;
   // forward pass: when keep is set, the transformed windowed column of term
   // k is also stored at keep[k * keep_stride + img * plane + f2 * N1] (the
@@ -256,10 +257,12 @@ struct LaunchSet {
 struct Plan2D {
   int N1, N2, H2;            // H2 = N2/2 + 1
   int m, m1, m2;             // separable: m = m1*m2, term k = k1*m2 + k2; dense: m1 = 1, m2 = m
-  bool dense;                // dense windows m x N1 x N2
+  bool dense;                // dense windows m x N1 x N2 (or, wmode 3, one term's two factors)
+  int wmode;                 // the row passes' window mode (1 separable, 2 dense, 3 factored single term)
   int64_t batch_cap;         // images the workspaces hold
   const float* wrows;        // separable: m1 x N1 (factor along rows, a_k1[n1])
-  const float* wcols;        // separable: m2 x N2 (factor along columns, b_k2[n2]); dense: m x N1 x N2
+  const float* wcols;        // separable: m2 x N2 (factor along columns, b_k2[n2]); dense: m x N1 x N2;
+                             // wmode 3: a[N1] then b[N2]
   const float2* Hs;          // m planes, column-major: Hs[k][f2][f1]
   const float2* tw1;         // engine twiddles for N1
   const float2* tw2;         // engine twiddles for N2
