@@ -527,7 +527,8 @@ enum {
   PC_TUNE_ROWS_INV_SMALL = 5,     /* row-inverse passes: 4-row tiles instead of 16-row ones */
   PC_TUNE_COL_GROUPS = 6,         /* full-grid forward column pass: term groups */
   PC_TUNE_FOURSTEP_L = 7,         /* 1D four-step: inner transform length */
-  PC_TUNE_BATCH_PERSISTENT = 8    /* batches: persistent passes (length 0) */
+  PC_TUNE_BATCH_PERSISTENT = 8,   /* batches: persistent passes (length 0) */
+  PC_TUNE_SEC_STREAMS = 9         /* sectioned plans: two launch chains, on two streams (length 0) */
 };
 typedef struct {
   uint64_t key;

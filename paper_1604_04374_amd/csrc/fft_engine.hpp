@@ -478,6 +478,31 @@ __device__ __forceinline__ void stage_twiddles(float2* tw_lds, const float2* __r
   __syncthreads();
 }
 
+// The same staging in two steps, for NT threads: load() issues the table's
+// loads into registers, commit() stores them into LDS and ends with a
+// barrier.  A kernel issues its own first loads in between, so that the
+// twiddles' round trip overlaps them instead of preceding them.
+template <int L, int NT>
+struct TwStage {
+  static constexpr int N = (L + NT - 1) / NT;
+  float2 r[N];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int tid) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int idx = tid + i * NT;
+      if (tid < NT && idx < L) r[i] = tw[idx];
+    }
+  }
+  __device__ __forceinline__ void commit(float2* tw_lds, int tid) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int idx = tid + i * NT;
+      if (tid < NT && idx < L) tw_lds[idx] = r[i];
+    }
+    __syncthreads();
+  }
+};
+
 // In-place transform of the register array v (see the header comment).
 // Every thread of the workgroup must call it (it contains barriers), even
 // threads whose FFT slot is unused.

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_fwd1d_sm
 
 // x = H_m^* v for signal pairs.
 template <int L>
-__global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) void k_adj1d_small(
+__global__ __launch_bounds__(ffts_per_block(L) * fft_threads(L)) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_adj1d_small(
     const float* __restrict__ vin, float* __restrict__ x, int64_t batch, int m, const float* __restrict__ w,
     const float2* __restrict__ H, const float2* __restrict__ tw, int split) {
   constexpr int P = points_per_thread(L), T = L / P, NF = ffts_per_block(L);

@@ -98,9 +98,12 @@ constexpr int row_pairs_small(int L2) { return row_pairs_per_block(L2) < 2 ? row
 template <int L2, int G>
 __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, const BlockRef bm,
                                               const float* __restrict__ x_arg, float2* __restrict__ lds,
-                                              const float2* __restrict__ twl, const int tid) {
+                                              float2* __restrict__ twl, const float2* __restrict__ tw,
+                                              const int tid) {
   constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
+  TwStage<L2, NT> ts;
+  ts.load(tw, tid);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
   const float* x = jb.xp ? *jb.xp : (jb.x ? jb.x : x_arg);
@@ -181,6 +184,7 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
     }
   }
   float2* my = lds + c * lds_len<L2>();
+  ts.commit(twl, tid);
   fft_wv<L2, P, false, SYNC_WAVE>(v, my, twl, t);
   __syncthreads();
 #pragma unroll
@@ -222,8 +226,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
   __shared__ float2 twl[L2];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L2>(twl, tw);
-  rows_fwd_body<L2, G>(jobs, bm, x_arg, lds, twl, threadIdx.x);
+  rows_fwd_body<L2, G>(jobs, bm, x_arg, lds, twl, tw, threadIdx.x);
 }
 
 // Real rows from transposed half-spectra:
@@ -234,10 +237,12 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
 template <int L2, int G, bool PIPE>
 __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, const BlockRef bm,
                                               float* __restrict__ y_arg, float2* __restrict__ lds,
-                                              const float2* __restrict__ twl, float* __restrict__ rfac,
-                                              const int tid) {
+                                              float2* __restrict__ twl, const float2* __restrict__ tw,
+                                              float* __restrict__ rfac, const int tid) {
   constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
   constexpr int NT = G * T;
+  TwStage<L2, NT> ts;
+  ts.load(tw, tid);
   const RowJob& jb = jobs[bm.job];
   const int N1 = jb.N1;
   float* yout = jb.yp ? *jb.yp : (jb.y ? jb.y : y_arg);
@@ -265,6 +270,7 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
   // loop's first barrier) so that no register holds them across the transforms
   const bool box = jb.mode == RW_BOX;
   if (box && tid < 2 * G) rfac[tid] = gldf(jb.wsrc, r0 + tid);
+  ts.commit(twl, tid);
   for (int q = 0; q < jb.nq; ++q) {
     __syncthreads();  // the previous transform is done with LDS
     if constexpr (PIPE) {
@@ -378,8 +384,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
   __shared__ float rfac[2 * G];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L2>(twl, tw);
-  rows_inv_body<L2, G, PIPE>(jobs, bm, y_arg, lds, twl, rfac, threadIdx.x);
+  rows_inv_body<L2, G, PIPE>(jobs, bm, y_arg, lds, twl, tw, rfac, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,8 +398,11 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
 // partial spectrum goes to part[group] for k_cols_sum_inv.
 template <int L1, bool LATE, bool KEEP>
 __device__ __forceinline__ void cols_fwd_body(const ColJob* __restrict__ jobs, const BlockRef bm,
-                                              float2* __restrict__ lds, const float2* __restrict__ twl, const int tid) {
+                                              float2* __restrict__ lds, float2* __restrict__ twl,
+                                              const float2* __restrict__ tw, const int tid) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  TwStage<L1, NF * T> ts;
+  ts.load(tw, tid);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense, ngroups = jb.ngroups;
   const int c = tid / T, t = tid % T;
@@ -411,15 +419,21 @@ __device__ __forceinline__ void cols_fwd_body(const ColJob* __restrict__ jobs, c
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  for (int q = q0; q < q1; ++q) {
+  // elements e < ne of this thread are loaded (t + T e < nvalid_in), the
+  // rest are zero
+  const int nv = jb.nvalid_in == 0 ? L1 : jb.nvalid_in;
+  const int ne = nv > t ? (nv - t + T - 1) / T : 0;
+  float2 cv[P];
+  auto load_col = [&](int q) {
     const float2* col = jb.src + q * jb.q_stride + img * plane + (int64_t)f2 * L1;
-    float2 cv[P];
-    // elements e < ne of this thread are loaded (t + T e < nvalid_in), the
-    // rest are zero
-    const int nv = jb.nvalid_in == 0 ? L1 : jb.nvalid_in;
-    const int ne = nv > t ? (nv - t + T - 1) / T : 0;
 #pragma unroll
     for (int e = 0; e < P; ++e) cv[e] = e < ne ? gld(col, t + T * e) : make_float2(0.f, 0.f);
+  };
+  // the first column's loads go out before the twiddles are committed
+  if (q0 < q1) load_col(q0);
+  ts.commit(twl, tid);
+  for (int q = q0; q < q1; ++q) {
+    if (q > q0) load_col(q);
     for (int k1 = 0; k1 < nk1; ++k1) {
       const int k = dense ? q : k1 * m2 + q;
       const float2* Hk = jb.Hs + (int64_t)k * plane + (int64_t)f2 * L1;
@@ -479,8 +493,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   __shared__ float2 twl[L1];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L1>(twl, tw);
-  cols_fwd_body<L1, LATE, KEEP>(jobs, bm, lds, twl, threadIdx.x);
+  cols_fwd_body<L1, LATE, KEEP>(jobs, bm, lds, twl, tw, threadIdx.x);
 }
 
 // dst[img][f2][:] = colIFFT(sum_g part[g][img][f2][:]).
@@ -522,8 +535,11 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_s
 // (its latency hides behind it, for P more complex registers).
 template <int L1, bool PF>
 __device__ __forceinline__ void cols_adj_body(const ColJob* __restrict__ jobs, const BlockRef bm,
-                                              float2* __restrict__ lds, const float2* __restrict__ twl, const int tid) {
+                                              float2* __restrict__ lds, float2* __restrict__ twl,
+                                              const float2* __restrict__ tw, const int tid) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  TwStage<L1, NF * T> ts;
+  ts.load(tw, tid);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2, m1 = jb.m1, m2 = jb.m2, dense = jb.dense;
   const int c = tid / T, t = tid % T;
@@ -539,6 +555,7 @@ __device__ __forceinline__ void cols_adj_body(const ColJob* __restrict__ jobs, c
   for (int e = 0; e < P; ++e) vh[e] = gld(jb.src, coff + t + T * e);
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
+  ts.commit(twl, tid);
   if (jb.fft_src) fft_wv<L1, P, false, SYNC_WAVE>(vh, my, twl, t);  // uniform over the workgroup
   float2 acc[P];
 #pragma unroll
@@ -603,15 +620,17 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   __shared__ float2 twl[L1];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L1>(twl, tw);
-  cols_adj_body<L1, PF>(jobs, bm, lds, twl, threadIdx.x);
+  cols_adj_body<L1, PF>(jobs, bm, lds, twl, tw, threadIdx.x);
 }
 
 // In-place column FFTs of dst: dst[img][f2][:] = colFFT(dst[img][f2][:]).
 template <int L1>
 __device__ __forceinline__ void cols_fft_body(const ColJob* __restrict__ jobs, const BlockRef bm,
-                                              float2* __restrict__ lds, const float2* __restrict__ twl, const int tid) {
+                                              float2* __restrict__ lds, float2* __restrict__ twl,
+                                              const float2* __restrict__ tw, const int tid) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  TwStage<L1, NF * T> ts;
+  ts.load(tw, tid);
   const ColJob& jb = jobs[bm.job];
   const int H2 = jb.H2;
   const int c = tid / T, t = tid % T;
@@ -623,6 +642,7 @@ __device__ __forceinline__ void cols_fft_body(const ColJob* __restrict__ jobs, c
   float2 v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) v[e] = gld(jb.dst, off + t + T * e);
+  ts.commit(twl, tid);
   fft_wv<L1, P, false, SYNC_WAVE>(v, lds + c * lds_len<L1>(), twl, t);
   if (valid) {
 #pragma unroll
@@ -638,8 +658,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
   __shared__ float2 twl[L1];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
-  stage_twiddles<L1>(twl, tw);
-  cols_fft_body<L1>(jobs, bm, lds, twl, threadIdx.x);
+  cols_fft_body<L1>(jobs, bm, lds, twl, tw, threadIdx.x);
 }
 
 // Backward column pass of a single-term job (the sections of Lemma 3.2):
@@ -743,22 +762,22 @@ template <int KIND, int L>
 __device__ __forceinline__ void persist_item(const PItem& w, float2* smem, const float* x_arg, float* y_arg) {
   float2* twl = smem;
   float2* lds = smem + L;
-  stage_twiddles<L>(twl, w.tw);
+  // (each body stages the item's twiddles itself)
   // an opaque copy of the thread index: the body's per-element addresses are
   // recomputed per item instead of living across the item loop
   const int tid = opaque((int)threadIdx.x);
   if constexpr (KIND == PK_ROWS_FWD) {
-    rows_fwd_body<L, prow_pairs<L>()>(static_cast<const RowJob*>(w.jobs), w.bm, x_arg, lds, twl, tid);
+    rows_fwd_body<L, prow_pairs<L>()>(static_cast<const RowJob*>(w.jobs), w.bm, x_arg, lds, twl, w.tw, tid);
   } else if constexpr (KIND == PK_ROWS_INV) {
-    rows_inv_body<L, prow_pairs<L>(), false>(static_cast<const RowJob*>(w.jobs), w.bm, y_arg, lds, twl,
+    rows_inv_body<L, prow_pairs<L>(), false>(static_cast<const RowJob*>(w.jobs), w.bm, y_arg, lds, twl, w.tw,
                                              reinterpret_cast<float*>(lds + prow_pairs<L>() * lds_len<L>()), tid);
   } else if constexpr (KIND == PK_COLS_A) {
     if (w.sub == 0)
-      cols_fwd_body<L, true, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
+      cols_fwd_body<L, true, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, w.tw, tid);
     else
-      cols_fft_body<L>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
+      cols_fft_body<L>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, w.tw, tid);
   } else {
-    cols_adj_body<L, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, tid);
+    cols_adj_body<L, false>(static_cast<const ColJob*>(w.jobs), w.bm, lds, twl, w.tw, tid);
   }
 }
 

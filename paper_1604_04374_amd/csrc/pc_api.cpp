@@ -244,6 +244,12 @@ struct pc_plan_s {
   std::vector<pc::LaunchSet> sec_bwd[2][2];
   pc_batch_s* sec_batch_keep = nullptr;  // the forward launches storing U_k into keep
   std::vector<pc::SecTerm> sec_terms;
+  // sectioned plans: the sections in two halves, whose launch chains run on
+  // the call's stream and on sec_aux (forked and joined with events), so that
+  // each pass of one half overlaps the other half's passes
+  pc_batch_s* sec_half[2] = {nullptr, nullptr};
+  hipStream_t sec_aux = nullptr;
+  hipEvent_t sec_fork = nullptr, sec_join = nullptr;
   pc::Tracer* tr() { return tracing ? &tracer : nullptr; }
 
   ~pc_plan_s();
@@ -763,6 +769,11 @@ struct pc_batch_s {
 pc_plan_s::~pc_plan_s() {
   delete sec_batch;
   delete sec_batch_keep;
+  delete sec_half[0];
+  delete sec_half[1];
+  if (sec_fork) (void)hipEventDestroy(sec_fork);
+  if (sec_join) (void)hipEventDestroy(sec_join);
+  if (sec_aux) (void)hipStreamDestroy(sec_aux);
   if (keep_alloc) (void)hipFree(keep_alloc);
   for (pc_plan_s* q : sec_sub) delete q;
   for (void* p : allocs) (void)hipFree(p);
@@ -1361,6 +1372,34 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
   // the launches take the call's input pointer, so they are not captured
   b->use_graph = false;
   if ((st = build_batch(b, in.data(), outs.data(), outs.data(), &gs))) return st;
+  if (terms.size() >= 2 && pc::tune_get(p->tune_key, PC_TUNE_SEC_STREAMS, 0, 0)) {
+    // the two halves (alternate sections), for the calls' two launch chains
+    for (int h = 0; h < 2; ++h) {
+      pc_batch_s* hb = new (std::nothrow) pc_batch_s();
+      if (!hb) return fail(PC_ERROR_OUT_OF_MEMORY, "host allocation failed");
+      p->sec_half[h] = hb;
+      hb->device = p->device;
+      hb->tune_key = p->tune_key;
+      hb->has_fwd = hb->has_adj = true;
+      hb->use_graph = false;
+      std::vector<pc::SecTerm> ht;
+      std::vector<const float*> hin;
+      std::vector<float*> hout;
+      for (size_t i = (size_t)h; i < terms.size(); i += 2) {
+        hb->plans.push_back(p->sec_sub[i]);
+        ht.push_back(terms[i]);
+        hin.push_back(nullptr);
+        hout.push_back(q.Sout + terms[i].off);
+      }
+      GatherSpec hs{(int)N1, (int)N2, &ht};
+      hs.direct_adj = q.direct_adj;
+      if ((st = build_batch(hb, hin.data(), hout.data(), hout.data(), &hs))) return st;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&p->sec_aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->sec_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->sec_join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail_hip(e, "section streams");
+  }
   // spectra as parameters: the sections' spectra, one after another, each in
   // the natural layout of its M1 x M2 grid
   {
@@ -1501,9 +1540,22 @@ hipError_t run_sec_backward(pc_plan p, const float* u, const float* gy, float* g
 }
 
 hipError_t run_sections(pc_plan p, const float* in, float* out, int64_t batch, bool adjoint, hipStream_t s) {
-  const pc_batch_s* b = p->sec_batch;
-  // blocks of images >= batch return at once in every pass
-  hipError_t e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr(), in, batch, out);
+  hipError_t e;
+  if (p->sec_half[0]) {
+    // the second half's chain on sec_aux, between a fork and a join event
+    e = hipEventRecord(p->sec_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->sec_aux, p->sec_fork, 0);
+    for (int h = 1; h >= 0 && e == hipSuccess; --h) {
+      const pc_batch_s* b = p->sec_half[h];
+      e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, h ? p->sec_aux : s, p->tr(), in, batch, out);
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->sec_join, p->sec_aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->sec_join, 0);
+  } else {
+    const pc_batch_s* b = p->sec_batch;
+    // blocks of images >= batch return at once in every pass
+    e = launch_seq(adjoint ? b->adj_seq : b->fwd_seq, s, p->tr(), in, batch, out);
+  }
   if (e != hipSuccess) return e;
   if (adjoint && p->sec.direct_adj) return hipSuccess;  // the row pass wrote the output
   return pc::launch_sec_scatter(p->sec, out, adjoint, batch, s, p->tr());
@@ -1935,7 +1987,7 @@ pc_status pc_tune_set(const pc_tune_entry* entries, int32_t count) {
   std::vector<pc::TuneEntry> t;
   for (int32_t i = 0; i < count; ++i) {
     const pc_tune_entry& e = entries[i];
-    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_BATCH_PERSISTENT)
+    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_SEC_STREAMS)
       return fail(PC_ERROR_INVALID_VALUE, "unknown knob " + std::to_string(e.knob) + " in entry " + std::to_string(i));
     t.push_back({e.key, e.knob, e.length, e.value});
   }

@@ -124,6 +124,39 @@ def test_repeatable_bitwise_and_traced():
     assert "rows_fwd" in stats and "sec_scatter" in stats and "sec_gather" not in stats
 
 
+@pytest.mark.parametrize("idx", [0, 1])
+def test_two_launch_chains_match_one(idx):
+    # the sections' two halves on two streams (the default) against one
+    # chain on the call's stream (tuning entry PC_TUNE_SEC_STREAMS = 0): the
+    # same kernels on the same data, so the outputs agree bit for bit
+    import torch
+    import paper_1604_04374_amd as pcm
+    p = _problems()[idx]
+    u = torch.from_numpy(p.u).cuda()
+    out = {}
+    for v in (1, 0):
+        with pcm.Plan(plan_args(p), p.h, batch=p.batch) as probe:
+            key = pcm.tune_key(probe.desc)
+        pcm.tune_set([(key, pcm.TUNE_KNOBS["sec_streams"], 0, v)])
+        try:
+            print(f"[gpu] sectioned {p.name}: sec_streams = {v}", flush=True)
+            with pcm.Plan(plan_args(p), p.h, batch=p.batch) as plan:
+                assert plan.info()["path"] == 3
+                for _ in range(2):  # repeated calls reuse the fork and join events
+                    y = plan.apply(u)
+                    x = plan.apply_adjoint(u)
+                out[v] = (y.cpu(), x.cpu())
+        finally:
+            pcm.tune_set([])
+            arch = pcm._device_arch()
+            if arch and __import__("os").path.exists(pcm.tuning_table_path(arch)):
+                pcm.load_tuning(pcm.tuning_table_path(arch))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    w, h, uu = p.dense_windows(), p.h.astype(np.float64), p.u.astype(np.float64)
+    assert per_instance_rel(out[1][0].numpy(), ex.apply_fft(uu, w, h)) <= TOL
+    assert per_instance_rel(out[1][1].numpy(), ex.adjoint_fft(uu, w, h)) <= TOL
+
+
 def test_sectioned_plans_export_section_spectra_and_stay_out_of_batches():
     import torch
     import paper_1604_04374_amd as pcm
