@@ -229,6 +229,32 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
   rows_fwd_body<L2, G>(jobs, bm, x_arg, lds, twl, tw, threadIdx.x);
 }
 
+// The transposed tile [f][2G rows] (f < L2/2 + 1) of a plane whose rows
+// r0 .. r0 + 2G start at src (row stride N1 entries), copied straight from
+// global memory into LDS (global_load_lds_dwordx4: no registers, no wait
+// per load): chunk ch of the tile is entries 2 ch and 2 ch + 1, the rows
+// 2 (ch mod G) and 2 (ch mod G) + 1 of column f = ch / G, 16 bytes whose
+// global address is 16-byte aligned (N1, r0 and the plane offsets even).
+template <int L2, int G>
+__device__ __forceinline__ void tile_to_lds(const float2* __restrict__ src, int N1, float2* lds, int tid) {
+  constexpr int T = fft_threads(L2), NT = G * T, CH = (L2 / 2 + 1) * G;
+  // WL lanes per wave (a workgroup of fewer than 64 threads is one partial
+  // wave; otherwise NT is a multiple of 64), NW waves
+  constexpr int WL = NT < 64 ? NT : 64, NW = NT / WL, IT = (CH + NT - 1) / NT;
+  static_assert(NW * WL == NT, "row workgroups are whole waves or one partial wave");
+  const int w = tid / WL, lane = tid % WL;
+#pragma unroll
+  for (int j = 0; j < IT; ++j) {
+    const int c0 = (j * NW + w) * WL;  // the wave's first chunk: its LDS destination
+    const int ch = c0 + lane;
+    if (ch < CH) {
+      const int f = ch / G, r = 2 * (ch % G);
+      __builtin_amdgcn_global_load_lds((const PC_GLOBAL void*)(src + (int64_t)f * N1 + r),
+                                       (__attribute__((address_space(3))) void*)(lds + 2 * c0), 16, 0, 0);
+    }
+  }
+}
+
 // Real rows from transposed half-spectra:
 // y[img][n1][n2] = scale * sum_{q < nq} w_q . rowIFFT(sin[q][img][:, n1]).
 // PIPE: plane q + 1's tile is loaded into registers while plane q is
@@ -289,8 +315,7 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
         }
       }
     } else {
-      const float2* src = src0 + (int64_t)q * jb.q_stride;
-      for (int idx = tid; idx < TILE; idx += NT) lds[idx] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
+      tile_to_lds<L2, G>(src0 + (int64_t)q * jb.q_stride, N1, lds, opaque(tid));
       __syncthreads();
     }
     float2 v[P];
@@ -366,12 +391,16 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
     }
     return;
   }
+  // columns n2 < ocols only (0: all)
+  const int sc = jb.ocols > 0 ? jb.ocols : L2;
   float* oa = yout + (img * N1 + r) * L2;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int n2 = t + T * e;
-    gstf(oa, n2, acc[e].x * sa);
-    gstf(oa, n2 + L2, acc[e].y * sb);
+    if (n2 < sc) {
+      gstf(oa, n2, acc[e].x * sa);
+      gstf(oa, n2 + L2, acc[e].y * sb);
+    }
   }
 }
 
@@ -550,9 +579,13 @@ __device__ __forceinline__ void cols_adj_body(const ColJob* __restrict__ jobs, c
   const int q = bm.q;
   const int64_t plane = (int64_t)L1 * H2;
   const int64_t coff = img * plane + (int64_t)f2 * L1;
+  // elements e < ne of this thread are loaded (t + T e < nvalid_in), the
+  // rest are zero
+  const int nvi = jb.nvalid_in == 0 ? L1 : jb.nvalid_in;
+  const int nei = nvi > t ? (nvi - t + T - 1) / T : 0;
   float2 vh[P];
 #pragma unroll
-  for (int e = 0; e < P; ++e) vh[e] = gld(jb.src, coff + t + T * e);
+  for (int e = 0; e < P; ++e) vh[e] = e < nei ? gld(jb.src, coff + t + T * e) : make_float2(0.f, 0.f);
   const int nk1 = dense ? 1 : m1;
   float2* my = lds + c * lds_len<L1>();
   ts.commit(twl, tid);

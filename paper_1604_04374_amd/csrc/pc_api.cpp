@@ -961,9 +961,11 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           pc::append_row_blocks(bfo, (int)jfo.size(), cap, q.N1, L2, 1, si, out_rows, pbr);
           pc::RowJob jo{nullptr, out, nullptr, 0, q.N1, 1, scale, q.Tws, nullptr, 0};
           jo.yp = out_slot(i, c);
+          if (st) jo.ocols = st->ef2;  // the overlap-add reads the output box's columns only
           jfo.push_back(jo);
         } else {
-          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1, sf, 0, pbr);
+          // sections: the rows of the forward output box only (the rest are zero)
+          pc::append_row_blocks(ba, (int)ja.size(), cap, q.N1, L2, 1, sf, out_rows, pbr);
           ja.push_back(gathered(pc::RowJob{inp, nullptr, nullptr, 0, q.N1, 0, 0.f, nullptr, q.Tws, plane * cap}));
           if (st) {  // only the output box of the forward section is read (the gradient needs the mask)
             ja.back().mrows = st->ef1;
@@ -1030,6 +1032,7 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           if (st) {  // the row-inverse pass reads whole row blocks of the window box rows
             const int br = pc::row_block_rows(q.N2, pc::tune_get(b->tune_key, PC_TUNE_ROWS_INV_SMALL, q.N2, 0) != 0);
             j.nvalid_out = std::min(q.N1, (st->ea1 + br - 1) / br * br);
+            j.nvalid_in = st->ef1;  // the row pass transformed the output box rows only
           }
           ja.push_back(j);
         }

@@ -161,7 +161,8 @@ struct RowJob {
   int mrows = 0, mcols = 0;
   // row-inverse, section evaluation (oN2 > 0): row r < orows of the job's
   // image img is written, columns n2 < ocols only, to image img of the output
-  // (oN1 x oN2 samples) at ((o1 + r) mod oN1, (o2 + n2) mod oN2)
+  // (oN1 x oN2 samples) at ((o1 + r) mod oN1, (o2 + n2) mod oN2); with
+  // oN2 == 0, ocols > 0 limits the stored columns of every row
   int oN1 = 0, oN2 = 0, o1 = 0, o2 = 0, orows = 0, ocols = 0;
 };
 
@@ -178,10 +179,10 @@ struct ColJob {
   // adjoint pass of a single-term job: transform src's columns first, in
   // registers (no separate k_cols_fft pass and plane round trip)
   int fft_src = 0;
-  // rows of the columns known to matter (0: all N1): the forward pass reads
-  // src entries n1 < nvalid_in only (the rest are zero: rows the row pass
-  // skipped); both passes write dst entries n1 < nvalid_out only (the rest
-  // are never read)
+  // rows of the columns known to matter (0: all N1): both passes read src
+  // entries n1 < nvalid_in only (the rest are zero: rows the row pass
+  // skipped) and write dst entries n1 < nvalid_out only (the rest are never
+  // read)
   int nvalid_in = 0, nvalid_out = 0;
   // forward pass: when keep is set, the transformed windowed column of term
   // k is also stored at keep[k * keep_stride + img * plane + f2 * N1] (the
