@@ -124,6 +124,36 @@ def test_repeatable_bitwise_and_traced():
     assert "rows_fwd" in stats and "sec_scatter" in stats and "sec_gather" not in stats
 
 
+def test_dense_windows_factored_or_kept_dense():
+    # dense windows that are exactly a row factor times a column factor on
+    # each box (tile indicators) are stored as the two factors; perturbed
+    # ones keep a dense box; both against the oracle
+    import torch
+    import paper_1604_04374_amd as pcm
+    p = _problems()[0]
+    w = p.dense_windows().astype(np.float32)
+    rng = np.random.default_rng(130)
+    w_bent = (w * (1.0 + 0.25 * rng.random(w.shape))).astype(np.float32)  # same supports, not rank one
+    u = torch.from_numpy(p.u).cuda()
+    nbytes = {}
+    for name, ww in (("factored", w), ("dense", w_bent)):
+        print(f"[gpu] sectioned {p.name}: {name} dense-format windows", flush=True)
+        with pcm.Plan(ww, p.h, batch=p.batch) as plan:
+            info = plan.info()
+            assert info["path"] == 3
+            nbytes[name] = info["window_bytes"]
+            y = plan.apply(u).cpu().numpy()
+            x = plan.apply_adjoint(u).cpu().numpy()
+        h, uu = p.h.astype(np.float64), p.u.astype(np.float64)
+        assert per_instance_rel(y, ex.apply_fft(uu, ww.astype(np.float64), h)) <= TOL
+        assert per_instance_rel(x, ex.adjoint_fft(uu, ww.astype(np.float64), h)) <= TOL
+    secs = None
+    with pcm.Plan(w, p.h, batch=p.batch) as plan:
+        secs = plan.sections()
+    assert nbytes["factored"] == sum(4 * (s["m1"] + s["m2"]) for s in secs)
+    assert nbytes["dense"] == sum(4 * s["m1"] * s["m2"] for s in secs)
+
+
 @pytest.mark.parametrize("idx", [0, 1])
 def test_two_launch_chains_match_one(idx):
     # the sections' two halves on two streams (the default) against one
