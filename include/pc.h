@@ -87,9 +87,9 @@ enum {
    * only when it is estimated to be at least twice as cheap (never for a
    * product-convolution plan with gradients); pc_plan_query reports it as
    * path 3 and pc_plan_sections lists the sections.  A sectioned plan's
-   * parameters are its sections' spectra (see the spectra calls); it cannot
-   * join a batch, and pc_plan_set_responses returns PC_ERROR_UNSUPPORTED for
-   * it.  Every pass skips images beyond the call's batch. */
+   * parameters are its sections' spectra (see the spectra calls), and
+   * pc_plan_set_responses returns PC_ERROR_UNSUPPORTED for it.  Every pass
+   * skips images beyond the call's batch. */
   PC_PLAN_FULL_GRID = 4u
 };
 
@@ -443,9 +443,11 @@ pc_status pc_wavelet_transform_noalloc(int32_t inverse, int64_t n, int32_t level
  * graph launch.  The kernels read each instance's input and output pointers
  * from a device table, so every call may name new buffers.
  *
- *   plans   (host array of count handles) distinct 2D full-grid plans (a
- *           handle listed twice is rejected: its instances would share the
- *           plan's workspace).  While the batch lives, pc_destroy refuses its
+ *   plans   (host array of count handles) distinct 2D plans, full-grid or
+ *           sectioned (a sectioned plan's sections join the launches of
+ *           their lengths, followed by the plan's overlap-add into the
+ *           call's output; a handle listed twice is rejected: its
+ *           instances would share the plan's workspace).  While the batch lives, pc_destroy refuses its
  *           plans, and the plans must not be used by other calls while a
  *           batch call runs (the batch uses their workspaces).
  *           Convolution-product and product-convolution plans may share a
@@ -455,7 +457,7 @@ pc_status pc_wavelet_transform_noalloc(int32_t inverse, int64_t n, int32_t level
  *           launch per pass (below).
  *   stream  unused (creation is synchronous).
  * Errors: INVALID_VALUE (count < 1, null array, a repeated plan, a plan that
- * is not 2D or is sectioned, plans on different devices, unknown flags),
+ * is not 2D, plans on different devices, unknown flags),
  * INVALID_PLAN, OUT_OF_MEMORY, HIP.
  */
 typedef struct pc_batch_s* pc_batch;

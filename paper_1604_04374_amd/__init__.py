@@ -630,7 +630,7 @@ def wavelet_transform(x, lowpass, levels, inverse=False, axis=-1, stream=None, o
 class Batch:
     """Many 2D operators of uneven sizes run together (see pc_batch_create).
 
-    ``plans``: distinct 2D full-grid :class:`Plan` objects.  ``apply(inputs)``
+    ``plans``: distinct 2D :class:`Plan` objects (full-grid or sectioned).  ``apply(inputs)``
     enqueues ``H_i inputs[i]`` for every instance with one graph launch and
     returns the outputs (allocated here unless ``outputs`` is given);
     ``apply_adjoint`` the adjoints.  Each call may pass new tensors.  While

@@ -1076,6 +1076,9 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
     if (e != hipSuccess) return e;
     return hipGetLastError();
   }
+  if (ls.kind == KK_SEC_SCATTER)  // (traced as sec_scatter by the launcher)
+    return launch_sec_scatter(*ls.sec, nullptr, ls.sec_adjoint, nblocks < ls.sec->cap ? nblocks : ls.sec->cap, s, tr,
+                              ls.sec_out);
   TraceScope ts(tr, kernel_kind_name(ls.kind), s);
   const dim3 grid((unsigned)nblocks), block((unsigned)ls.threads);
   const RowJob* rj = static_cast<const RowJob*>(ls.jobs);
@@ -1184,6 +1187,7 @@ const char* kernel_kind_name(int kind) {
     case KK_COLS_ADJ: return "cols_adj";
     case KK_COLS_FFT: return "cols_fft";
     case KK_COLS_BWD1: return "cols_bwd";
+    case KK_SEC_SCATTER: return "sec_scatter";
   }
   return "unknown";
 }

@@ -19,8 +19,10 @@ namespace pc {
 constexpr int SEC_THREADS = 256, SEC_ROWS_PER_THREAD = SEC_TILE_R * SEC_TILE_C / SEC_THREADS,
               SEC_ROW_STEP = SEC_THREADS / SEC_TILE_C;
 __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
-    const SecTerm* __restrict__ terms, const float* __restrict__ S, float* __restrict__ y, int N1, int N2,
-    int tiles2, const int* __restrict__ toff, const int* __restrict__ titems, int adjoint) {
+    const SecTerm* __restrict__ terms, const float* __restrict__ S, float* __restrict__ y_arg,
+    float* const* __restrict__ yp, int N1, int N2, int tiles2, const int* __restrict__ toff,
+    const int* __restrict__ titems, int adjoint) {
+  float* y = yp ? *yp : y_arg;
   const int tile = blockIdx.x;
   const int64_t b = blockIdx.y;
   const int i10 = (tile / tiles2) * SEC_TILE_R + (int)threadIdx.x / SEC_TILE_C;  // rows i10 + SEC_ROW_STEP r
@@ -47,11 +49,12 @@ __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
   for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) y[(b * N1 + i10 + SEC_ROW_STEP * r) * N2 + i2] = acc[r];
 }
 
-LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr) {
+LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr,
+                                float* const* yp) {
   TraceScope ts(tr, "sec_scatter", s);
   const int tiles = (q.N1 / SEC_TILE_R) * q.tiles2;
   hipLaunchKernelGGL(k_sec_scatter, dim3((unsigned)tiles, (unsigned)batch), dim3(SEC_THREADS), 0, s,
-                     q.terms, q.Sout, y, q.N1, q.N2, q.tiles2, adjoint ? q.ta_off : q.tf_off,
+                     q.terms, q.Sout, y, yp, q.N1, q.N2, q.tiles2, adjoint ? q.ta_off : q.tf_off,
                      adjoint ? q.ta_items : q.tf_items, adjoint ? 1 : 0);
   return hipGetLastError();
 }

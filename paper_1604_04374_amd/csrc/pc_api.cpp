@@ -884,33 +884,65 @@ struct GatherSpec {
 pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa,
                       const GatherSpec* gather = nullptr, const std::vector<float2*>* keep = nullptr) {
   const bool table = in == nullptr;
-  const size_t nb = b->plans.size();
+  const size_t nb = b->plans.size();  // rows of the pointer table
+  // The instances: a full-grid plan is one; a sectioned plan contributes one
+  // single-term instance per section, which reads its input box in place and
+  // stages its output for the plan's overlap-add (or, adjoint with window
+  // boxes that partition the image, writes the output itself).
+  struct BInst {
+    pc_plan q;              // the plan whose Plan2D runs (a section's sub-plan)
+    size_t slot;            // its entry of the pointer table, or of in / fo / fa
+    bool pconv;             // directions exchanged
+    const pc::SecTerm* st;  // section geometry, or null
+    int gN1, gN2;           // the section's image
+    bool direct_adj;
+    float* sout;            // the section's staging block (table mode)
+  };
+  std::vector<BInst> inst;
+  for (size_t i = 0; i < nb; ++i) {
+    pc_plan p = b->plans[i];
+    if (gather) {
+      inst.push_back({p, i, p->pconv, &(*gather->terms)[i], gather->N1, gather->N2, gather->direct_adj, nullptr});
+    } else if (p->path == 3) {
+      for (size_t k = 0; k < p->sec_sub.size(); ++k)
+        inst.push_back({p->sec_sub[k], i, p->pconv, &p->sec_terms[k], p->sec.N1, p->sec.N2, p->sec.direct_adj,
+                        p->sec.Sout + p->sec_terms[k].off});
+    } else {
+      inst.push_back({p, i, p->pconv, nullptr, 0, 0, false, nullptr});
+    }
+  }
   // group instances by row length (N2) and by column length (N1)
   std::vector<int> n2s, n1s;
-  for (pc_plan p : b->plans) {
-    if (std::find(n2s.begin(), n2s.end(), p->p2.N2) == n2s.end()) n2s.push_back(p->p2.N2);
-    if (std::find(n1s.begin(), n1s.end(), p->p2.N1) == n1s.end()) n1s.push_back(p->p2.N1);
+  for (const BInst& x : inst) {
+    if (std::find(n2s.begin(), n2s.end(), x.q->p2.N2) == n2s.end()) n2s.push_back(x.q->p2.N2);
+    if (std::find(n1s.begin(), n1s.end(), x.q->p2.N1) == n1s.end()) n1s.push_back(x.q->p2.N1);
   }
   BatchLists lists[2];  // [0]: pc_batch_apply, [1]: pc_batch_apply_adjoint
   // Blocks are listed instance by instance, the instances with the most
   // terms first: a block's work grows with its instance's terms, and the
   // chip takes blocks roughly in list order, so the short blocks fill the
   // last, partly occupied round instead of the long ones.
-  std::vector<size_t> order(b->plans.size());
+  std::vector<size_t> order(inst.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
-                   [&](size_t x, size_t y) { return b->plans[x]->p2.m > b->plans[y]->p2.m; });
-  // instance i, call c: output buffer and whether it takes the forward-type chain
+                   [&](size_t x, size_t y) { return inst[x].q->p2.m > inst[y].q->p2.m; });
+  auto fwd_type = [&](size_t i, int c) { return (c == 0) != inst[i].pconv; };
+  // a section instance whose chain ends in the staging block
+  auto staged = [&](size_t i, int c) { return inst[i].st && (fwd_type(i, c) || !inst[i].direct_adj); };
+  // instance i, call c: whether it runs (fixed pointers: a null output skips it)
+  auto has = [&](size_t i, int c) { return table || (c == 0 ? fo[inst[i].slot] : fa[inst[i].slot]) != nullptr; };
+  // its fixed output buffer (null: the table's, or the launch's argument)
   auto out_of = [&](size_t i, int c) -> float* {
-    if (table) return reinterpret_cast<float*>(1);  // every instance has both directions
-    return c == 0 ? fo[i] : fa[i];
+    if (!table) return c == 0 ? fo[inst[i].slot] : fa[inst[i].slot];
+    return staged(i, c) ? inst[i].sout : nullptr;
   };
   // the device table entries of instance i, call c
   auto in_slot = [&](size_t i, int c) -> const float* const* {
-    return table ? const_cast<const float* const*>(b->dtab + (c * nb + i) * 2) : nullptr;
+    return table ? const_cast<const float* const*>(b->dtab + (c * nb + inst[i].slot) * 2) : nullptr;
   };
-  auto out_slot = [&](size_t i, int c) -> float* const* { return table ? b->dtab + (c * nb + i) * 2 + 1 : nullptr; };
-  auto fwd_type = [&](size_t i, int c) { return (c == 0) != b->plans[i]->pconv; };
+  auto out_slot = [&](size_t i, int c) -> float* const* {
+    return table && !staged(i, c) ? b->dtab + (c * nb + inst[i].slot) * 2 + 1 : nullptr;
+  };
   pc_status st;
   for (int c = 0; c < 2; ++c) {
     BatchLists& bl = lists[c];
@@ -920,16 +952,16 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
       // the persistent row passes take G = 256 / T row pairs per block, when
       // that many rows divide every image of this row length
       int pbr = b->persistent && pc::persist_length(L2) ? pc::persist_block_rows(L2) : 0;
-      for (pc_plan q : b->plans)
-        if (pbr && q->p2.N2 == L2 && q->p2.N1 % pbr) pbr = 0;
+      for (const BInst& x : inst)
+        if (pbr && x.q->p2.N2 == L2 && x.q->p2.N1 % pbr) pbr = 0;
       BatchLists* prow = pbr ? &bl : nullptr;
       std::vector<pc::RowJob> jf, jfo, ja, jao;
       std::vector<pc::BlockRef> bf, bfo, ba, bao;
       const float2* tw = nullptr;
       for (size_t i : order) {
-        const pc::Plan2D& q = b->plans[i]->p2;
-        float* out = table ? nullptr : out_of(i, c);
-        if (q.N2 != L2 || !out_of(i, c)) continue;
+        const pc::Plan2D& q = inst[i].q->p2;
+        float* out = out_of(i, c);
+        if (q.N2 != L2 || !has(i, c)) continue;
         const float* inp = table ? nullptr : in[i];
         tw = q.tw2;
         const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
@@ -937,19 +969,20 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         const float scale = 1.0f / ((float)q.N1 * (float)q.N2);
         auto gathered = [&](pc::RowJob j) {
           j.xp = in_slot(i, c);
-          if (gather) {
-            const pc::SecTerm& t = (*gather->terms)[i];
+          if (inst[i].st) {
+            const pc::SecTerm& t = *inst[i].st;
+            const bool f = fwd_type(i, c);
             j.x = nullptr;
-            j.gN1 = gather->N1;
-            j.gN2 = gather->N2;
-            j.g1 = c == 0 ? t.gf1 : t.ga1;
-            j.g2 = c == 0 ? t.gf2 : t.ga2;
+            j.gN1 = inst[i].gN1;
+            j.gN2 = inst[i].gN2;
+            j.g1 = f ? t.gf1 : t.ga1;
+            j.g2 = f ? t.gf2 : t.ga2;
           }
           return j;
         };
         // sections: rows that matter (the window box leads the section in
         // both directions; the forward output box is p + q - 1 rows)
-        const pc::SecTerm* st = gather ? &(*gather->terms)[i] : nullptr;
+        const pc::SecTerm* st = inst[i].st;
         const int win_rows = st ? st->ea1 : 0, out_rows = st ? st->ef1 : 0;
         if (fwd_type(i, c)) {
           pc::append_row_blocks(bf, (int)jf.size(), cap, q.N1, L2, nq, sf, win_rows, pbr);
@@ -974,10 +1007,10 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
           pc::append_row_blocks(bao, (int)jao.size(), cap, q.N1, L2, 1, si, win_rows, pbr);
           pc::RowJob jo{nullptr, out, q.wcols, mode, q.N1, nq, scale, q.RA, nullptr, plane * cap};
           jo.yp = out_slot(i, c);
-          if (st && gather->direct_adj) {
-            jo.y = nullptr;  // the launch's output argument: the call's output image
-            jo.oN1 = gather->N1;
-            jo.oN2 = gather->N2;
+          if (st && inst[i].direct_adj) {
+            jo.y = nullptr;  // the table's or the launch's output argument: the call's output image
+            jo.oN1 = inst[i].gN1;
+            jo.oN2 = inst[i].gN2;
             jo.o1 = st->sa1;
             jo.o2 = st->sa2;
             jo.orows = st->ea1;
@@ -1001,12 +1034,12 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
       const float2* tw = nullptr;
       bool f_multi = false;  // some forward-type instance loops over several terms
       for (size_t i : order) {
-        const pc::Plan2D& q = b->plans[i]->p2;
-        if (q.N1 != L1 || !out_of(i, c)) continue;
+        const pc::Plan2D& q = inst[i].q->p2;
+        if (q.N1 != L1 || !has(i, c)) continue;
         tw = q.tw1;
         const int64_t cap = q.batch_cap, plane = (int64_t)q.N1 * q.H2;
         const int nq = q.dense ? q.m : q.m2, dense = q.dense ? 1 : 0;
-        const pc::SecTerm* st = gather ? &(*gather->terms)[i] : nullptr;
+        const pc::SecTerm* st = inst[i].st;
         if (fwd_type(i, c)) {  // one term group: the many instances already fill the device
           pc::append_col_blocks(bf, (int)jf.size(), cap, q.H2, L1, 1);
           f_multi = f_multi || q.m > 1;
@@ -1072,6 +1105,22 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
                     &bl.a_fft, &bl.persist[pc::PK_COLS_ADJ], &bl.a_cols, &bl.persist[pc::PK_ROWS_INV], &bl.f_rows_out,
                     &bl.a_rows_out})
       seq.insert(seq.end(), v->begin(), v->end());
+    // the overlap-add of each sectioned plan of a user batch, into the
+    // table's output entry (a sectioned plan's own calls add it themselves)
+    if (table)
+      for (size_t i = 0; i < nb; ++i) {
+        pc_plan p = b->plans[i];
+        if (p->path != 3) continue;
+        const bool fwd = (c == 0) != p->pconv;
+        if (!fwd && p->sec.direct_adj) continue;  // the row-inverse pass wrote the output
+        pc::LaunchSet ls;
+        ls.kind = pc::KK_SEC_SCATTER;
+        ls.sec = &p->sec;
+        ls.sec_adjoint = !fwd;
+        ls.sec_out = b->dtab + (c * nb + i) * 2 + 1;
+        ls.blocks = p->sec.cap;  // images
+        seq.push_back(ls);
+      }
   }
   return PC_SUCCESS;
 }
@@ -1818,8 +1867,7 @@ pc_status pc_batch_create(pc_batch* out, int32_t count, const pc_plan* plans, ui
     if (!seen.insert(p).second)
       return fail(PC_ERROR_INVALID_VALUE, "plan of instance " + std::to_string(i) +
                                               " appears twice (instances share a plan's workspace)");
-    if (p->path != 2)
-      return fail(PC_ERROR_INVALID_VALUE, "batches take 2D full-grid plans (sectioned plans: use PC_PLAN_FULL_GRID)");
+    if (p->path != 2 && p->path != 3) return fail(PC_ERROR_INVALID_VALUE, "batches take 2D plans");
     if (device < 0) device = p->device;
     if (p->device != device) return fail(PC_ERROR_INVALID_VALUE, "plans of a batch must share a device");
   }

@@ -207,7 +207,7 @@ struct BlockRef {
   int job, img, blk, q;
 };
 
-enum KernelKind { KK_ROWS_FWD = 0, KK_ROWS_INV, KK_COLS_FWD, KK_COLS_SUM, KK_COLS_ADJ, KK_COLS_FFT, KK_COLS_BWD1 };
+enum KernelKind { KK_ROWS_FWD = 0, KK_ROWS_INV, KK_COLS_FWD, KK_COLS_SUM, KK_COLS_ADJ, KK_COLS_FFT, KK_COLS_BWD1, KK_SEC_SCATTER };
 
 // Persistent batch passes: every row or column block of a pass, whatever
 // its transform length (within a length group), is one work item of one
@@ -232,6 +232,8 @@ int persist_group(int L);
 int persist_grid(int kind, int pg, int lds_bytes, int64_t n_items);
 
 // A prepared launch: kernel kind and length, device tables, block counts.
+struct Sec2D;
+
 struct LaunchSet {
   int kind = 0;
   int L = 0;
@@ -253,6 +255,11 @@ struct LaunchSet {
   const PItem* items = nullptr;
   int n_items = 0;
   int lds_bytes = 0;
+  // overlap-add of a sectioned plan in a batch (KK_SEC_SCATTER): its section
+  // geometry, the direction, and the batch table entry holding the output
+  const Sec2D* sec = nullptr;
+  bool sec_adjoint = false;
+  float* const* sec_out = nullptr;
 };
 
 struct Plan2D {
@@ -409,8 +416,11 @@ struct Sec2D {
   bool direct_adj = false;
 };
 constexpr int SEC_TILE_R = 32, SEC_TILE_C = 32;  // tile sides divide every supported size (>= 64, 2^a or 3 x 2^a)
-// every output pixel of the first `batch` images <- sum of the sections covering it
-LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr);
+// every output pixel of the first `batch` images <- sum of the sections
+// covering it; the output is y, or (yp non-null) the pointer held at *yp
+// when the kernel runs (a batch's table entry)
+LaunchStatus launch_sec_scatter(const Sec2D& q, float* y, bool adjoint, int64_t batch, hipStream_t s, Tracer* tr,
+                                float* const* yp = nullptr);
 
 // --------------------------------------------------------------------------
 // Construction of h_k from a TVIR (section 4.2 projection, section 4.4

@@ -187,7 +187,7 @@ def test_two_launch_chains_match_one(idx):
     assert per_instance_rel(out[1][1].numpy(), ex.adjoint_fft(uu, w, h)) <= TOL
 
 
-def test_sectioned_plans_export_section_spectra_and_stay_out_of_batches():
+def test_sectioned_plans_export_section_spectra():
     import torch
     import paper_1604_04374_amd as pcm
     p = _problems()[0]
@@ -197,10 +197,44 @@ def test_sectioned_plans_export_section_spectra_and_stay_out_of_batches():
         # the parameters of a sectioned plan are its sections' spectra
         n = sum(s["m1"] * (s["m2"] // 2 + 1) for s in plan.sections())
         assert info["spectra_count"] == n and plan.get_spectra().shape == (n,)
-        with pytest.raises(pcm.PCError) as ei:
-            pcm.Batch([plan])
-        assert ei.value.status == 1
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["graph", "direct", "persistent"])
+def test_sectioned_plans_in_batches(mode):
+    # sectioned plans (one with window boxes that partition the image, one
+    # that does not, a product-convolution one) and a full-grid plan in one
+    # batch; two calls with new tensors; every instance against the oracle
+    # and against the plan's own calls
+    import torch
+    import paper_1604_04374_amd as pcm
+    probs = _problems()
+    specs = [(probs[0], False, False), (probs[1], False, False), (probs[3], True, False), (probs[2], False, True)]
+    plans = [pcm.Plan(plan_args(p), p.h, batch=p.batch, product_convolution=pc, full_grid=fg) for p, pc, fg in specs]
+    try:
+        assert [pl.info()["path"] for pl in plans] == [3, 3, 3, 2]
+        b = pcm.Batch(plans, graph=mode == "graph", persistent=mode == "persistent")
+        try:
+            for call in range(2):
+                print(f"[gpu] batch of sectioned plans ({mode}), call {call}", flush=True)
+                ins = [torch.from_numpy(p.u).cuda() * (1.0 + call) for p, _, _ in specs]
+                ys = [t.clone() for t in b.apply(ins)]
+                xs = [t.clone() for t in b.apply_adjoint(ins)]
+                for k, ((p, pc, _), pl) in enumerate(zip(specs, plans)):
+                    w, h = p.dense_windows(), p.h.astype(np.float64)
+                    uu = p.u.astype(np.float64) * (1.0 + call)
+                    ry = ex.apply_pc_fft(uu, w, h) if pc else ex.apply_fft(uu, w, h)
+                    rx = ex.adjoint_pc_fft(uu, w, h) if pc else ex.adjoint_fft(uu, w, h)
+                    assert per_instance_rel(ys[k].cpu().numpy(), ry) <= TOL, (mode, call, k)
+                    assert per_instance_rel(xs[k].cpu().numpy(), rx) <= TOL, (mode, call, k)
+                    y1, x1 = pl.apply(ins[k]), pl.apply_adjoint(ins[k])
+                    assert rel_l2(ys[k].cpu().numpy(), y1.cpu().numpy()) <= 1e-6
+                    assert rel_l2(xs[k].cpu().numpy(), x1.cpu().numpy()) <= 1e-6
+        finally:
+            b.destroy()
+    finally:
+        for pl in plans:
+            pl.destroy()
 
 
 @pytest.mark.slow
