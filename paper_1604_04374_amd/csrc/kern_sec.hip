@@ -15,9 +15,12 @@ namespace pc {
 
 // One workgroup per (tile, image) of SEC_TILE_R x SEC_TILE_C pixels, each
 // thread SEC_ROWS_PER_THREAD rows of one column: every pixel is the sum, in
-// section order, of the sections whose output box covers it.
+// section order, of the sections whose output box covers it.  The sections
+// of a tile's list are taken SEC_GROUP at a time, every sample of the group
+// loaded before any is added (one wait per group instead of one per
+// section), then added in list order.
 constexpr int SEC_THREADS = 256, SEC_ROWS_PER_THREAD = SEC_TILE_R * SEC_TILE_C / SEC_THREADS,
-              SEC_ROW_STEP = SEC_THREADS / SEC_TILE_C;
+              SEC_ROW_STEP = SEC_THREADS / SEC_TILE_C, SEC_GROUP = 4;
 __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
     const SecTerm* __restrict__ terms, const float* __restrict__ S, float* __restrict__ y_arg,
     float* const* __restrict__ yp, int N1, int N2, int tiles2, const int* __restrict__ toff,
@@ -30,20 +33,38 @@ __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
   float acc[SEC_ROWS_PER_THREAD];
 #pragma unroll
   for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) acc[r] = 0.f;
-  for (int j = toff[tile]; j < toff[tile + 1]; ++j) {
-    const SecTerm tm = terms[titems[j]];
-    const int s1 = adjoint ? tm.sa1 : tm.sf1, s2 = adjoint ? tm.sa2 : tm.sf2;
-    const int e1 = adjoint ? tm.ea1 : tm.ef1, e2 = adjoint ? tm.ea2 : tm.ef2;
-    int d2 = i2 - s2;
-    if (d2 < 0) d2 += N2;
-    if (d2 >= e2) continue;
-    const float* Sb = S + tm.off + b * tm.M1 * tm.M2 + d2;
+  const int j0 = toff[tile], j1 = toff[tile + 1];
+  for (int j = j0; j < j1; j += SEC_GROUP) {
+    float v[SEC_GROUP][SEC_ROWS_PER_THREAD];
 #pragma unroll
-    for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) {
-      int d1 = i10 + SEC_ROW_STEP * r - s1;
-      if (d1 < 0) d1 += N1;
-      if (d1 < e1) acc[r] += Sb[(int64_t)d1 * tm.M2];
+    for (int g = 0; g < SEC_GROUP; ++g) {
+      // a sample outside the section's box, or past the list's end, is zero
+      bool in2 = false;
+      const float* Sb = S;  // the section's column d2 of image b
+      int64_t M2 = 0;
+      int s1 = 0, e1 = 0;
+      if (j + g < j1) {
+        const SecTerm tm = terms[titems[j + g]];
+        const int s2 = adjoint ? tm.sa2 : tm.sf2, e2 = adjoint ? tm.ea2 : tm.ef2;
+        s1 = adjoint ? tm.sa1 : tm.sf1;
+        e1 = adjoint ? tm.ea1 : tm.ef1;
+        int d2 = i2 - s2;
+        if (d2 < 0) d2 += N2;
+        in2 = d2 < e2;
+        M2 = tm.M2;
+        Sb = S + tm.off + b * tm.M1 * tm.M2 + d2;
+      }
+#pragma unroll
+      for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) {
+        int d1 = i10 + SEC_ROW_STEP * r - s1;
+        if (d1 < 0) d1 += N1;
+        v[g][r] = in2 && d1 < e1 ? Sb[(int64_t)d1 * M2] : 0.f;
+      }
     }
+#pragma unroll
+    for (int g = 0; g < SEC_GROUP; ++g)
+#pragma unroll
+      for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) acc[r] += v[g][r];
   }
 #pragma unroll
   for (int r = 0; r < SEC_ROWS_PER_THREAD; ++r) y[(b * N1 + i10 + SEC_ROW_STEP * r) * N2 + i2] = acc[r];
