@@ -211,10 +211,20 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
     }
   }
   __syncthreads();
+  // the tile's LDS reads first, then its stores (a read-store loop waited
+  // for each read in turn)
+  constexpr int TILE = H2 * 2 * G, PT = (TILE + NT - 1) / NT;
+  float2 sv[PT];
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = tid + i * NT;
+    if (idx < TILE) sv[i] = lds[idx];
+  }
   float2* o = jb.sout + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
-  for (int idx = tid; idx < H2 * 2 * G; idx += NT) {
-    const int f = idx / (2 * G), ri = idx % (2 * G);
-    gst(o, (int64_t)f * N1 + ri, lds[idx]);
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = tid + i * NT;
+    if (idx < TILE) gst(o, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G), sv[i]);
   }
 }
 
@@ -1262,15 +1272,23 @@ __global__ __launch_bounds__(SPEC_THREADS) void k_transpose_spec(const float2* _
   const int a0 = ib * TA, b0 = jb * TB;
   src += k * plane;
   dst += k * plane;
-  // natural side: lanes run along f2; internal side: lanes run along f1
-  for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
-    if (TO_INTERNAL) {
-      const int i = idx / TB, j = idx % TB;
-      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = src[(int64_t)(a0 + i) * H2 + b0 + j];
-    } else {
-      const int i = idx % TA, j = idx / TA;
-      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = src[(int64_t)(b0 + j) * N1 + a0 + i];
-    }
+  // natural side: lanes run along f2; internal side: lanes run along f1;
+  // every load of the thread issued before the tile is written
+  constexpr int PER = TA * TB / SPEC_THREADS;
+  static_assert(PER * SPEC_THREADS == TA * TB, "whole tiles per thread count");
+  float2 tv[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int idx = (int)threadIdx.x + r * SPEC_THREADS;
+    const int i = TO_INTERNAL ? idx / TB : idx % TA, j = TO_INTERNAL ? idx % TB : idx / TA;
+    if (a0 + i < N1 && b0 + j < H2)
+      tv[r] = TO_INTERNAL ? src[(int64_t)(a0 + i) * H2 + b0 + j] : src[(int64_t)(b0 + j) * N1 + a0 + i];
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int idx = (int)threadIdx.x + r * SPEC_THREADS;
+    const int i = TO_INTERNAL ? idx / TB : idx % TA, j = TO_INTERNAL ? idx % TB : idx / TA;
+    if (a0 + i < N1 && b0 + j < H2) tile[i][j] = tv[r];
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
@@ -1404,27 +1422,35 @@ __global__ __launch_bounds__(SPEC_THREADS) void k_transpose_tab(const TransposeJ
   const int64_t b = blk - jb.block0;
   const int a0 = (int)(b / nbB) * TA, b0 = (int)(b % nbB) * TB;
   float2* nat = ext + jb.ext_off;
-  for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
-    if (to_internal) {
-      const int i = idx / TB, j = idx % TB;
-      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = nat[(int64_t)(a0 + i) * H2 + b0 + j];
-    } else {
-      const int i = idx % TA, j = idx / TA;
-      if (a0 + i < N1 && b0 + j < H2) tile[i][j] = jb.internal[(int64_t)(b0 + j) * N1 + a0 + i];
-    }
+  // every load of the thread issued before the tile is written
+  constexpr int PER = TA * TB / SPEC_THREADS;
+  static_assert(PER * SPEC_THREADS == TA * TB, "whole tiles per thread count");
+  float2 tv[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int idx = (int)threadIdx.x + r * SPEC_THREADS;
+    const int i = to_internal ? idx / TB : idx % TA, j = to_internal ? idx % TB : idx / TA;
+    if (a0 + i < N1 && b0 + j < H2)
+      tv[r] = to_internal ? gld(nat, (int64_t)(a0 + i) * H2 + b0 + j) : gld(jb.internal, (int64_t)(b0 + j) * N1 + a0 + i);
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int idx = (int)threadIdx.x + r * SPEC_THREADS;
+    const int i = to_internal ? idx / TB : idx % TA, j = to_internal ? idx % TB : idx / TA;
+    if (a0 + i < N1 && b0 + j < H2) tile[i][j] = tv[r];
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < TA * TB; idx += SPEC_THREADS) {
     if (to_internal) {
       const int i = idx % TA, j = idx / TA;
-      if (a0 + i < N1 && b0 + j < H2) jb.internal[(int64_t)(b0 + j) * N1 + a0 + i] = tile[i][j];
+      if (a0 + i < N1 && b0 + j < H2) gst(jb.internal, (int64_t)(b0 + j) * N1 + a0 + i, tile[i][j]);
     } else {
       const int i = idx / TB, j = idx % TB;
       const int f2 = b0 + j;
       if (a0 + i < N1 && f2 < H2) {
         float2 v = tile[i][j];
         if (jb.scale_mode) v = cscale(v, (f2 == 0 || f2 == H2 - 1) ? jb.inv_n : 2.f * jb.inv_n);
-        nat[(int64_t)(a0 + i) * H2 + f2] = v;
+        gst(nat, (int64_t)(a0 + i) * H2 + f2, v);
       }
     }
   }
