@@ -56,6 +56,25 @@ __device__ __forceinline__ float2 gld(const float2* p, int64_t i) {
 }
 __device__ __forceinline__ void gst(float2* p, int64_t i, float2 v) { ((PC_GLOBAL pc_f2*)p)[i] = pc_f2{v.x, v.y}; }
 __device__ __forceinline__ float gldf(const float* p, int64_t i) { return ((const PC_GLOBAL float*)p)[i]; }
+typedef float pc_f4 __attribute__((ext_vector_type(4)));
+// two consecutive complex entries (16 bytes, 16-byte aligned)
+__device__ __forceinline__ float4 gld2(const float2* p, int64_t i) {
+  const pc_f4 v = *(const PC_GLOBAL pc_f4*)(p + i);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst2(float2* p, int64_t i, float4 v) {
+  *(PC_GLOBAL pc_f4*)(p + i) = pc_f4{v.x, v.y, v.z, v.w};
+}
+
+// Row tiles in LDS: column f of a tile holds the tile's 2G rows as G row
+// pairs of 16 bytes; row pair rc sits at position rc ^ (f mod G), so that
+// the threads reading one row pair of consecutive columns hit different
+// banks (unswizzled, every column starts on the same bank).  G is a power
+// of two.
+template <int G>
+__device__ __forceinline__ int tile_pos(int f, int rc) {
+  return f * G + (rc ^ (f & (G - 1)));
+}
 __device__ __forceinline__ void gstf(float* p, int64_t i, float v) { ((PC_GLOBAL float*)p)[i] = v; }
 
 // The thread index, opaque to the compiler (an empty asm statement that
@@ -201,30 +220,32 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
     ub[e] = make_float2(0.5f * (cf.y + cm.y), -0.5f * (cf.x - cm.x));
   }
   __syncthreads();
-  // transpose through LDS: tile[f][row in block]
+  // transpose through LDS: column f's row pair c (swizzled, tile_pos)
+  float4* tl = reinterpret_cast<float4*>(lds);
 #pragma unroll
   for (int e = 0; e < P; ++e) {
     const int f = t + T * e;
-    if (f < H2) {
-      lds[f * (2 * G) + 2 * c] = ua[e];
-      lds[f * (2 * G) + 2 * c + 1] = ub[e];
-    }
+    if (f < H2) tl[tile_pos<G>(f, c)] = make_float4(ua[e].x, ua[e].y, ub[e].x, ub[e].y);
   }
   __syncthreads();
-  // the tile's LDS reads first, then its stores (a read-store loop waited
-  // for each read in turn)
-  constexpr int TILE = H2 * 2 * G, PT = (TILE + NT - 1) / NT;
-  float2 sv[PT];
+  // the tile's LDS reads first, then its 16-byte stores (a read-store loop
+  // waited for each read in turn); position ch holds column ch / G's row
+  // pair (ch mod G) ^ (column mod G)
+  constexpr int CH = H2 * G, PT = (CH + NT - 1) / NT;
+  float4 sv[PT];
 #pragma unroll
   for (int i = 0; i < PT; ++i) {
-    const int idx = tid + i * NT;
-    if (idx < TILE) sv[i] = lds[idx];
+    const int ch = tid + i * NT;
+    if (ch < CH) sv[i] = tl[ch];
   }
   float2* o = jb.sout + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
 #pragma unroll
   for (int i = 0; i < PT; ++i) {
-    const int idx = tid + i * NT;
-    if (idx < TILE) gst(o, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G), sv[i]);
+    const int ch = tid + i * NT;
+    if (ch < CH) {
+      const int f = ch / G, rc = (ch % G) ^ (f & (G - 1));
+      gst2(o, (int64_t)f * N1 + 2 * rc, sv[i]);
+    }
   }
 }
 
@@ -232,19 +253,19 @@ template <int L2, int G = row_pairs_per_block(L2)>
 __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
     const float2* __restrict__ tw, int64_t img_limit) {
-  __shared__ float2 lds[G * lds_len<L2>()];
+  __shared__ __attribute__((aligned(16))) float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
   rows_fwd_body<L2, G>(jobs, bm, x_arg, lds, twl, tw, threadIdx.x);
 }
 
-// The transposed tile [f][2G rows] (f < L2/2 + 1) of a plane whose rows
-// r0 .. r0 + 2G start at src (row stride N1 entries), copied straight from
-// global memory into LDS (global_load_lds_dwordx4: no registers, no wait
-// per load): chunk ch of the tile is entries 2 ch and 2 ch + 1, the rows
-// 2 (ch mod G) and 2 (ch mod G) + 1 of column f = ch / G, 16 bytes whose
-// global address is 16-byte aligned (N1, r0 and the plane offsets even).
+// The transposed tile (f < L2/2 + 1, tile_pos layout) of a plane whose
+// rows r0 .. r0 + 2G start at src (row stride N1 entries), copied straight
+// from global memory into LDS (global_load_lds_dwordx4: no registers, no
+// wait per load): each lane moves one row pair of one column, 16 bytes
+// whose global address is 16-byte aligned (N1, r0 and the plane offsets
+// even), the lanes of a wave to consecutive LDS positions.
 template <int L2, int G>
 __device__ __forceinline__ void tile_to_lds(const float2* __restrict__ src, int N1, float2* lds, int tid) {
   constexpr int T = fft_threads(L2), NT = G * T, CH = (L2 / 2 + 1) * G;
@@ -258,7 +279,8 @@ __device__ __forceinline__ void tile_to_lds(const float2* __restrict__ src, int 
     const int c0 = (j * NW + w) * WL;  // the wave's first chunk: its LDS destination
     const int ch = c0 + lane;
     if (ch < CH) {
-      const int f = ch / G, r = 2 * (ch % G);
+      // LDS position ch holds column f's row pair (ch mod G) ^ (f mod G)
+      const int f = ch / G, r = 2 * ((ch % G) ^ (f & (G - 1)));
       __builtin_amdgcn_global_load_lds((const PC_GLOBAL void*)(src + (int64_t)f * N1 + r),
                                        (__attribute__((address_space(3))) void*)(lds + 2 * c0), 16, 0, 0);
     }
@@ -290,16 +312,21 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
   float2 acc[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = make_float2(0.f, 0.f);
-  constexpr int TILE = H2 * 2 * G, PER = PIPE ? (TILE + NT - 1) / NT : 1;
+  // the tile: H2 columns of G row pairs (tile_pos layout)
+  constexpr int CH = H2 * G, PER = PIPE ? (CH + NT - 1) / NT : 1;
   const float2* src0 = jb.sin + img * ((int64_t)H2 * N1) + r0;
-  float2 nxt[PER];
+  float4* tl = reinterpret_cast<float4*>(lds);
+  float4 nxt[PER];
+  // LDS position ch of the tile holds column ch / G's row pair
+  // (ch mod G) ^ (column mod G)
+  auto tile_src = [&](int ch) { return (int64_t)(ch / G) * N1 + 2 * ((ch % G) ^ ((ch / G) & (G - 1))); };
   const int mode = jb.mode == RW_BOX ? RW_FACTOR : jb.mode;
   const float* ws = jb.mode == RW_BOX ? jb.wsrc + N1 : jb.wsrc;
   if constexpr (PIPE) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int idx = tid + i * NT;
-      if (idx < TILE) nxt[i] = gld(src0, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
+      const int ch = tid + i * NT;
+      if (ch < CH) nxt[i] = gld2(src0, tile_src(ch));
     }
   }
   // a factored window's row factors, staged in LDS (visible after the
@@ -312,16 +339,16 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
     if constexpr (PIPE) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < TILE) lds[idx] = nxt[i];
+        const int ch = tid + i * NT;
+        if (ch < CH) tl[ch] = nxt[i];
       }
       __syncthreads();
       if (q + 1 < jb.nq) {
         const float2* src = src0 + (int64_t)(q + 1) * jb.q_stride;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-          const int idx = tid + i * NT;
-          if (idx < TILE) nxt[i] = gld(src, (int64_t)(idx / (2 * G)) * N1 + idx % (2 * G));
+          const int ch = tid + i * NT;
+          if (ch < CH) nxt[i] = gld2(src, tile_src(ch));
         }
       }
     } else {
@@ -334,15 +361,17 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
       const int f = t + T * e;
       float2 a, b;
       if (f < H2) {
-        a = lds[f * (2 * G) + 2 * c];
-        b = lds[f * (2 * G) + 2 * c + 1];
+        const float4 ab = tl[tile_pos<G>(f, c)];
+        a = make_float2(ab.x, ab.y);
+        b = make_float2(ab.z, ab.w);
         if (f == 0 || f == L2 / 2) {  // the inverse real transform ignores these imaginary parts
           a.y = 0.f;
           b.y = 0.f;
         }
       } else {
-        a = cconj(lds[(L2 - f) * (2 * G) + 2 * c]);
-        b = cconj(lds[(L2 - f) * (2 * G) + 2 * c + 1]);
+        const float4 ab = tl[tile_pos<G>(L2 - f, c)];
+        a = make_float2(ab.x, -ab.y);
+        b = make_float2(ab.z, -ab.w);
       }
       v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
     }
@@ -418,7 +447,7 @@ template <int L2, int G, bool PIPE>
 __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
     const float2* __restrict__ tw, int64_t img_limit) {
-  __shared__ float2 lds[G * lds_len<L2>()];
+  __shared__ __attribute__((aligned(16))) float2 lds[G * lds_len<L2>()];
   __shared__ float2 twl[L2];
   __shared__ float rfac[2 * G];
   const BlockRef bm = bmap[blockIdx.x];
@@ -827,7 +856,7 @@ __device__ __forceinline__ void persist_item(const PItem& w, float2* smem, const
 template <int KIND, int PG>
 __global__ __launch_bounds__(PERSIST_THREADS) void k_persist(const PItem* __restrict__ items, int n_items,
                                                             const float* __restrict__ x_arg, float* __restrict__ y_arg) {
-  extern __shared__ float2 smem[];
+  extern __shared__ __attribute__((aligned(16))) float2 smem[];
   // workgroup b takes items b, b + grid, b + 2 grid, ... of the list (longest
   // first): no shared counter, whose same-address atomics would serialise
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
