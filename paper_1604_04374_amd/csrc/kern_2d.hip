@@ -67,13 +67,20 @@ __device__ __forceinline__ void gst2(float2* p, int64_t i, float4 v) {
 }
 
 // Row tiles in LDS: column f of a tile holds the tile's 2G rows as G row
-// pairs of 16 bytes; row pair rc sits at position rc ^ (f mod G), so that
-// the threads reading one row pair of consecutive columns hit different
-// banks (unswizzled, every column starts on the same bank).  G is a power
-// of two.
+// pairs of 16 bytes; row pair rc sits at position rc ^ tile_swz(f), so that
+// the lanes reading one row pair of 8 consecutive columns (one pass of a
+// 16-byte access over the 32 banks) hit 8 different 16-byte slots
+// (unswizzled, every column starts on the same bank).  G is a power of two;
+// for G < 8 the swizzle takes column bits above the ones the row pairs
+// already spread.
+template <int G>
+__device__ __forceinline__ int tile_swz(int f) {
+  constexpr int SH = G >= 8 ? 0 : G == 4 ? 1 : G == 2 ? 2 : 3;
+  return (f >> SH) & (G - 1);
+}
 template <int G>
 __device__ __forceinline__ int tile_pos(int f, int rc) {
-  return f * G + (rc ^ (f & (G - 1)));
+  return f * G + (rc ^ tile_swz<G>(f));
 }
 __device__ __forceinline__ void gstf(float* p, int64_t i, float v) { ((PC_GLOBAL float*)p)[i] = v; }
 
@@ -230,7 +237,7 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
   __syncthreads();
   // the tile's LDS reads first, then its 16-byte stores (a read-store loop
   // waited for each read in turn); position ch holds column ch / G's row
-  // pair (ch mod G) ^ (column mod G)
+  // pair (ch mod G) ^ tile_swz(column)
   constexpr int CH = H2 * G, PT = (CH + NT - 1) / NT;
   float4 sv[PT];
 #pragma unroll
@@ -243,7 +250,7 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
   for (int i = 0; i < PT; ++i) {
     const int ch = tid + i * NT;
     if (ch < CH) {
-      const int f = ch / G, rc = (ch % G) ^ (f & (G - 1));
+      const int f = ch / G, rc = (ch % G) ^ tile_swz<G>(f);
       gst2(o, (int64_t)f * N1 + 2 * rc, sv[i]);
     }
   }
@@ -279,8 +286,8 @@ __device__ __forceinline__ void tile_to_lds(const float2* __restrict__ src, int 
     const int c0 = (j * NW + w) * WL;  // the wave's first chunk: its LDS destination
     const int ch = c0 + lane;
     if (ch < CH) {
-      // LDS position ch holds column f's row pair (ch mod G) ^ (f mod G)
-      const int f = ch / G, r = 2 * ((ch % G) ^ (f & (G - 1)));
+      // LDS position ch holds column f's row pair (ch mod G) ^ tile_swz(f)
+      const int f = ch / G, r = 2 * ((ch % G) ^ tile_swz<G>(f));
       __builtin_amdgcn_global_load_lds((const PC_GLOBAL void*)(src + (int64_t)f * N1 + r),
                                        (__attribute__((address_space(3))) void*)(lds + 2 * c0), 16, 0, 0);
     }
@@ -318,8 +325,8 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
   float4* tl = reinterpret_cast<float4*>(lds);
   float4 nxt[PER];
   // LDS position ch of the tile holds column ch / G's row pair
-  // (ch mod G) ^ (column mod G)
-  auto tile_src = [&](int ch) { return (int64_t)(ch / G) * N1 + 2 * ((ch % G) ^ ((ch / G) & (G - 1))); };
+  // (ch mod G) ^ tile_swz(column)
+  auto tile_src = [&](int ch) { return (int64_t)(ch / G) * N1 + 2 * ((ch % G) ^ tile_swz<G>(ch / G)); };
   const int mode = jb.mode == RW_BOX ? RW_FACTOR : jb.mode;
   const float* ws = jb.mode == RW_BOX ? jb.wsrc + N1 : jb.wsrc;
   if constexpr (PIPE) {
