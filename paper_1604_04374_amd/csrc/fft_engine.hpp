@@ -161,6 +161,32 @@ __device__ __forceinline__ void dft16(float2* x) {
   }
 }
 
+// 12 points as a prime-factor 3 x 4 transform (no twiddles between the two
+// stages): input n = (4 n1 + 3 n2) mod 12, output k = (4 k1 + 9 k2) mod 12,
+// so that nk = 4 n1 k1 + 3 n2 k2 (mod 12): three-point transforms over n1,
+// then four-point transforms over n2.
+template <bool INV>
+__device__ __forceinline__ void dft12(float2* x) {
+  float2 a[3][4];
+#pragma unroll
+  for (int n1 = 0; n1 < 3; ++n1)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) a[n1][n2] = x[(4 * n1 + 3 * n2) % 12];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 t[3] = {a[0][n2], a[1][n2], a[2][n2]};
+    dft3<INV>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) a[k1][n2] = t[k1];
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) dft4<INV>(a[k1][0], a[k1][1], a[k1][2], a[k1][3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) x[(4 * k1 + 9 * k2) % 12] = a[k1][k2];
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dftR(float2* x) {
   if constexpr (R == 2) dft2<INV>(x[0], x[1]);
@@ -168,6 +194,7 @@ __device__ __forceinline__ void dftR(float2* x) {
   else if constexpr (R == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
   else if constexpr (R == 8) dft8<INV>(x);
   else if constexpr (R == 16) dft16<INV>(x);
+  else if constexpr (R == 12) dft12<INV>(x);
   else static_assert(R == 2, "unsupported radix");
 }
 
@@ -179,12 +206,17 @@ struct Sched {
   int r[12];
 };
 
-// A leading radix-3 pass for L = 3 * 2^a, then passes of the largest power of
-// two dividing P (capped at 16) with a smaller last pass if needed.
+// A leading radix-3 pass for L = 3 * 2^a (radix 12, the three-point and a
+// four-point stage in one pass, at 12 points per thread), then passes of
+// the largest power of two dividing P (capped at 16) with a smaller last
+// pass if needed.
 constexpr Sched make_sched(int L, int P) {
   Sched s{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
   int rem = L;
-  if (rem % 3 == 0) {
+  if (rem % 12 == 0 && P == 12) {
+    s.r[s.n++] = 12;
+    rem /= 12;
+  } else if (rem % 3 == 0) {
     s.r[s.n++] = 3;
     rem /= 3;
   }
