@@ -206,10 +206,10 @@ struct Sched {
   int r[12];
 };
 
-// A leading radix-3 pass for L = 3 * 2^a (radix 12, the three-point and a
-// four-point stage in one pass, at 12 points per thread), then passes of
-// the largest power of two dividing P (capped at 16) with a smaller last
-// pass if needed.
+// A radix-3 pass for L = 3 * 2^a (radix 12, the three-point and a
+// four-point stage in one pass, at 12 points per thread), and passes of
+// the largest power of two dividing P (capped at 16) with a smaller one if
+// needed.
 constexpr Sched make_sched(int L, int P) {
   Sched s{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
   int rem = L;
@@ -226,6 +226,13 @@ constexpr Sched make_sched(int L, int P) {
     int r = p2 < rem ? p2 : rem;
     s.r[s.n++] = r;
     rem /= r;
+  }
+  // the radix-12 pass last: a first pass writes its outputs at a stride of
+  // R entries, which the pad period keeps free of bank conflicts for the
+  // power-of-two radices but not for 12; the last pass writes registers
+  if (s.r[0] == 12 && s.n > 1) {
+    for (int i = 0; i + 1 < s.n; ++i) s.r[i] = s.r[i + 1];
+    s.r[s.n - 1] = 12;
   }
   return s;
 }
