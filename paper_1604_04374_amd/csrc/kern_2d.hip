@@ -702,6 +702,67 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
   cols_adj_body<L1, PF>(jobs, bm, lds, twl, tw, threadIdx.x);
 }
 
+// Column passes of single-term jobs (one term, one group: the sections of a
+// sectioned plan, one-term plans), one column per FFT slot, with nothing
+// carried across terms: forward dst = colIFFT(H . colFFT(a . src)), adjoint
+// dst = a . colIFFT(conj(H) . colFFT(src)), a the row factor of a separable
+// window (none for dense windows), rows n1 < nvalid_in read and
+// n1 < nvalid_out written.  The spectrum column is loaded after the first
+// transform.
+template <int L1, bool ADJ>
+__global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_1term(
+    const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw,
+    int64_t img_limit) {
+  constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
+  __shared__ float2 lds[NF * lds_len<L1>()];
+  __shared__ float2 twl[L1];
+  const BlockRef bm = bmap[blockIdx.x];
+  if (bm.img >= img_limit) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  TwStage<L1, NF * T> ts;
+  ts.load(tw, tid);
+  const ColJob& jb = jobs[bm.job];
+  const int H2 = jb.H2;
+  const int c = tid / T, t = tid % T;
+  const int f2raw = bm.blk * NF + c;
+  const bool valid = f2raw < H2;
+  const int f2 = valid ? f2raw : H2 - 1;  // idle slots recompute a valid column and store nothing
+  const int64_t coff = bm.img * ((int64_t)L1 * H2) + (int64_t)f2 * L1;
+  const int nvi = jb.nvalid_in == 0 ? L1 : jb.nvalid_in;
+  const int nvo = jb.nvalid_out == 0 ? L1 : jb.nvalid_out;
+  const int nei = nvi > t ? (nvi - t + T - 1) / T : 0, neo = nvo > t ? (nvo - t + T - 1) / T : 0;
+  float2 v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = e < nei ? gld(jb.src, coff + t + T * e) : make_float2(0.f, 0.f);
+  if (!ADJ && !jb.dense) {  // the row factor of the windowed input
+    float w[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) w[e] = gldf(jb.wrows, t + T * e);
+#pragma unroll
+    for (int e = 0; e < P; ++e) v[e] = cscale(v[e], w[e]);
+  }
+  float2* my = lds + c * lds_len<L1>();
+  ts.commit(twl, tid);
+  fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
+  const float2* Hk = jb.Hs + (int64_t)f2 * L1;
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = ADJ ? cmulc(v[e], gld(Hk, t + T * e)) : cmul(gld(Hk, t + T * e), v[e]);
+  fft_wv<L1, P, true, SYNC_WAVE>(v, my, twl, opaque(t));
+  if (ADJ && !jb.dense) {
+    float w[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) w[e] = gldf(jb.wrows, t + T * e);
+#pragma unroll
+    for (int e = 0; e < P; ++e) v[e] = cscale(v[e], w[e]);
+  }
+  if (valid) {
+    float2* dst = jb.dst + coff;
+#pragma unroll
+    for (int e = 0; e < P; ++e)
+      if (e < neo) gst(dst, t + T * e, v[e]);
+  }
+}
+
 // In-place column FFTs of dst: dst[img][f2][:] = colFFT(dst[img][f2][:]).
 template <int L1>
 __device__ __forceinline__ void cols_fft_body(const ColJob* __restrict__ jobs, const BlockRef bm,
@@ -1164,7 +1225,9 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    if (ls.keep && ls.late)    \
+    if (ls.one)                \
+      hipLaunchKernelGGL((k_cols_1term<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    else if (ls.keep && ls.late)    \
       hipLaunchKernelGGL((k_cols_fwd<LL, true, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     else if (ls.keep)          \
       hipLaunchKernelGGL((k_cols_fwd<LL, false, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
@@ -1191,7 +1254,9 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    if (ls.prefetch) \
+    if (ls.one) \
+      hipLaunchKernelGGL((k_cols_1term<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    else if (ls.prefetch) \
       hipLaunchKernelGGL((k_cols_adj<LL, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     else \
       hipLaunchKernelGGL((k_cols_adj<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \

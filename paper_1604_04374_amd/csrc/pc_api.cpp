@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -529,6 +530,23 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
   return PC_SUCCESS;
 }
 
+// Whether a column launch can take the single-term kernel: every job one
+// term in one group, keeping nothing (forward) or transforming its own input
+// (adjoint).
+template <class J>
+bool single_term_cols(int kind, const std::vector<J>& jobs) {
+  if constexpr (std::is_same<J, pc::ColJob>::value) {
+    if (kind != pc::KK_COLS_FWD && kind != pc::KK_COLS_ADJ) return false;
+    for (const pc::ColJob& j : jobs) {
+      if (j.m1 * j.m2 != 1 || j.ngroups != 1) return false;
+      if (kind == pc::KK_COLS_FWD && j.keep) return false;
+      if (kind == pc::KK_COLS_ADJ && !j.fft_src) return false;
+    }
+    return !jobs.empty();
+  }
+  return false;
+}
+
 template <class J>
 pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vector<J>& jobs,
                    const std::vector<pc::BlockRef>& bm, int64_t per_img, const float2* tw, hipStream_t s,
@@ -547,6 +565,7 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   ls.late = kind == pc::KK_COLS_FWD && pc::tune_get(key, PC_TUNE_COLS_FWD_LATE, L, pc::cols_fwd_late(L, multi_term));
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::tune_get(key, PC_TUNE_COLS_ADJ_PREFETCH, L, pc::cols_adj_prefetch(L));
   ls.pipe = kind == pc::KK_ROWS_INV && pc::tune_get(key, PC_TUNE_ROWS_INV_PIPE, L, pc::rows_inv_pipe(L, ls.small_rows));
+  ls.one = single_term_cols(kind, jobs);
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();
@@ -827,6 +846,7 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   ls.late = kind == pc::KK_COLS_FWD && pc::tune_get(key, PC_TUNE_COLS_FWD_LATE, L, pc::cols_fwd_late(L, multi_term));
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::tune_get(key, PC_TUNE_COLS_ADJ_PREFETCH, L, pc::cols_adj_prefetch(L));
   ls.pipe = kind == pc::KK_ROWS_INV && pc::tune_get(key, PC_TUNE_ROWS_INV_PIPE, L, pc::rows_inv_pipe(L, ls.small_rows));
+  ls.one = single_term_cols(kind, jobs);
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();

@@ -248,6 +248,7 @@ struct LaunchSet {
   bool prefetch = false;           // adjoint column kernel: the prefetching variant (cols_adj_prefetch)
   bool pipe = false;               // row-inverse kernel: the pipelined variant (rows_inv_pipe)
   bool keep = false;               // forward column kernel: the variant storing U_k (jobs' keep pointers)
+  bool one = false;                // column kernels: every job single-term (k_cols_1term)
   // persistent pass (persist >= 0: a PersistKind) of length group pgroup:
   // items (device PItem[]), their count and the dynamic LDS bytes
   int persist = -1;
