@@ -227,12 +227,14 @@ constexpr Sched make_sched(int L, int P) {
     s.r[s.n++] = r;
     rem /= r;
   }
-  // the radix-12 pass last: a first pass writes its outputs at a stride of
-  // R entries, which the pad period keeps free of bank conflicts for the
-  // power-of-two radices but not for 12; the last pass writes registers
+  // the radix-12 pass second: a first pass writes its outputs at a stride
+  // of R entries, which the pad period keeps free of bank conflicts for the
+  // power-of-two radices but not for 12, and after a radix-4 first pass
+  // its writes (runs of 4 entries, 48 apart) spread over the banks better
+  // than a second radix-4 pass's (runs of 4, 16 apart)
   if (s.r[0] == 12 && s.n > 1) {
-    for (int i = 0; i + 1 < s.n; ++i) s.r[i] = s.r[i + 1];
-    s.r[s.n - 1] = 12;
+    s.r[0] = s.r[1];
+    s.r[1] = 12;
   }
   return s;
 }
