@@ -19,6 +19,18 @@ namespace pc {
 // of a tile's list are taken SEC_GROUP at a time, every sample of the group
 // loaded before any is added (one wait per group instead of one per
 // section), then added in list order.
+//
+// Tiles are numbered XCD-major: workgroups are dispatched round-robin over
+// the 8 XCDs, so workgroup x runs on XCD x mod 8, and that XCD is given a
+// run of consecutive tiles (row-major: mostly horizontal neighbours).  A
+// section's row segment starts at an arbitrary column, so the 128-byte
+// lines at a tile's left and right edges are shared with the neighbouring
+// tiles; on one XCD they are fetched into its L2 once.
+constexpr int SEC_XCDS = 8;
+__device__ __forceinline__ int xcd_major_tile(int x, int n) {
+  const int q = n / SEC_XCDS;
+  return x < q * SEC_XCDS ? (x % SEC_XCDS) * q + x / SEC_XCDS : x;
+}
 constexpr int SEC_THREADS = 256, SEC_ROWS_PER_THREAD = SEC_TILE_R * SEC_TILE_C / SEC_THREADS,
               SEC_ROW_STEP = SEC_THREADS / SEC_TILE_C, SEC_GROUP = 4;
 __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
@@ -26,7 +38,7 @@ __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
     float* const* __restrict__ yp, int N1, int N2, int tiles2, const int* __restrict__ toff,
     const int* __restrict__ titems, int adjoint) {
   float* y = yp ? *yp : y_arg;
-  const int tile = blockIdx.x;
+  const int tile = xcd_major_tile(blockIdx.x, gridDim.x);
   const int64_t b = blockIdx.y;
   const int i10 = (tile / tiles2) * SEC_TILE_R + (int)threadIdx.x / SEC_TILE_C;  // rows i10 + SEC_ROW_STEP r
   const int i2 = (tile % tiles2) * SEC_TILE_C + (int)threadIdx.x % SEC_TILE_C;
