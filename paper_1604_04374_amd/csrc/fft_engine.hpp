@@ -4,7 +4,9 @@
 // P points x[t + T*e], e = 0..P-1, in registers, both before and after the
 // transform (natural order, stride T).  The transform is a Stockham
 // autosort sequence of radix-R passes (R divides P); between passes the data
-// go through LDS, the last pass writes straight back to registers.  Because
+// go through LDS (or, before a last radix-2 pass of a half-wavefront
+// transform, across lanes: see XlTab), the last pass writes straight back to
+// registers.  Because
 // input and output live at the same register slots, the spectral
 // multiply-accumulate and the inverse transform can follow the forward
 // transform without any reordering.
@@ -305,15 +307,108 @@ __device__ __forceinline__ void exchange_sync() {
 }
 
 // ---------------------------------------------------------------------------
+// Cross-lane exchange (a wavefront shuffle instead of an LDS round trip).
+// Take a transform carried by T = 32 threads, one T-aligned half of a
+// wavefront, whose last pass has radix 2, and the exchange that feeds that
+// pass.  Every output of the pass before it then either stays in its thread
+// or goes to the partner thread t xor 16.  Within each 16-lane half, one
+// register of the same index feeds each destination register.  The
+// exchange is then a register network: v_permlane16_swap (gfx950) swaps the
+// odd 16-lane rows of its first operand with the even rows of its second.
+// Lane t < 16 of the result's second register then holds the first
+// operand's lane t + 16, and lane t >= 16 of the result's first register
+// holds the second operand's lane t - 16.  So one swap per float component
+// gives every lower lane one register of its upper partner and every upper
+// lane one register of its lower partner.  make_xltab derives the network
+// from the Stockham index map and checks it by emulating it; no LDS, no
+// synchronisation.
+// ---------------------------------------------------------------------------
+struct XlTab {
+  bool ok;
+  int nsw;                  // swaps per float component
+  int sx1[16], sx2[16];     // swap s: first operand o[sx1[s]], second o[sx2[s]]
+  int lo[16], hi[16];       // destination e, lower / upper lanes: own o[x] (x >= 0) or swap -1 - x's result
+};
+
+template <int L, int P>
+constexpr XlTab make_xltab() {
+  XlTab x{};
+  x.ok = false;
+  constexpr int T = L / P;
+  const Sched s = make_sched(L, P);
+  if (T != 32 || P > 16 || s.n < 3 || s.r[s.n - 1] != 2) return x;
+  int Ns = 1;
+  for (int i = 0; i < s.n - 2; ++i) Ns *= s.r[i];
+  const int R = s.r[s.n - 2], B = P / R;
+  // destination (lane, register) <- source (lane, register) of the Stockham exchange
+  int sl[32][16] = {}, sr[32][16] = {};
+  for (int t = 0; t < T; ++t)
+    for (int b = 0; b < B; ++b)
+      for (int q = 0; q < R; ++q) {
+        const int j = t + T * b, k = j % Ns, pos = (j / Ns) * Ns * R + k + q * Ns;
+        sl[pos % T][pos / T] = t;
+        sr[pos % T][pos / T] = b + q * B;
+      }
+  int lo_src[16] = {}, hi_src[16] = {}, nlo = 0, nhi = 0;
+  for (int e = 0; e < P; ++e)
+    for (int h = 0; h < 2; ++h) {
+      const int t0 = 16 * h, d = sl[t0][e] ^ t0, r = sr[t0][e];
+      if (d != 0 && d != 16) return x;
+      for (int t = t0; t < t0 + 16; ++t)
+        if ((sl[t][e] ^ t) != d || sr[t][e] != r) return x;
+      if (h == 0) {
+        x.lo[e] = d == 0 ? r : -1 - nlo;
+        if (d != 0) lo_src[nlo++] = r;
+      } else {
+        x.hi[e] = d == 0 ? r : -1 - nhi;
+        if (d != 0) hi_src[nhi++] = r;
+      }
+    }
+  x.nsw = nlo > nhi ? nlo : nhi;
+  for (int i = 0; i < x.nsw; ++i) {
+    x.sx1[i] = i < nlo ? lo_src[i] : 0;
+    x.sx2[i] = i < nhi ? hi_src[i] : 0;
+  }
+  // emulate the network: lane t < 16 reads swap i's second result, which
+  // there is the first operand of lane t + 16; lane t >= 16 reads the first
+  // result, there the second operand of lane t - 16
+  for (int t = 0; t < T; ++t)
+    for (int e = 0; e < P; ++e) {
+      const bool lower = t < 16;
+      const int c = lower ? x.lo[e] : x.hi[e];
+      const int lane = c >= 0 ? t : (lower ? t + 16 : t - 16);
+      const int reg = c >= 0 ? c : (lower ? x.sx1[-1 - c] : x.sx2[-1 - c]);
+      if (lane != sl[t][e] || reg != sr[t][e]) return x;
+    }
+  x.ok = true;
+  return x;
+}
+
+template <int L, int P>
+struct Xl {
+  static constexpr XlTab tab = make_xltab<L, P>();
+};
+static_assert(make_xltab<384, 12>().ok && make_xltab<512, 16>().ok, "cross-lane exchange of the 384- and 512-point transforms");
+
+__device__ __forceinline__ float2 permlane16_swap_lower_upper(float2 a, float2 b, bool lower) {
+  const auto sx = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+  const auto sy = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+  return lower ? make_float2(__uint_as_float(sx[1]), __uint_as_float(sy[1]))
+               : make_float2(__uint_as_float(sx[0]), __uint_as_float(sy[0]));
+}
+
+// ---------------------------------------------------------------------------
 // the engine
 // ---------------------------------------------------------------------------
-template <int L, int P, bool INV, int S, int Ns, int TW, int PW, int SYNC = SYNC_WG>
+template <int L, int P, bool INV, int S, int Ns, int TW, int PW, int SYNC = SYNC_WG, bool XL = false>
 struct FftPass {
   static constexpr Sched sch = make_sched(L, P);
   static constexpr int R = sch.r[S];
   static constexpr int B = P / R;
   static constexpr int T = L / P;
   static constexpr bool LAST = (S == sch.n - 1);
+  // this pass feeds the last one across lanes
+  static constexpr bool XLANE = XL && S == sch.n - 2 && Xl<L, P>::tab.ok;
 
   __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
 #pragma unroll
@@ -333,7 +428,7 @@ struct FftPass {
         }
       }
       dftR<R, INV>(x);
-      if constexpr (LAST) {
+      if constexpr (LAST || XLANE) {
 #pragma unroll
         for (int q = 0; q < R; ++q) v[b + q * B] = x[q];
       } else {
@@ -356,7 +451,23 @@ struct FftPass {
         }
       }
     }
-    if constexpr (!LAST) {
+    if constexpr (XLANE) {
+      // the outputs sit at v[b + q B]; route them to the next pass's layout
+      constexpr XlTab X = Xl<L, P>::tab;
+      const bool lower = (t & 16) == 0;
+      float2 o[P], rcv[X.nsw > 0 ? X.nsw : 1];
+#pragma unroll
+      for (int e = 0; e < P; ++e) o[e] = v[e];
+#pragma unroll
+      for (int i = 0; i < X.nsw; ++i) rcv[i] = permlane16_swap_lower_upper(o[X.sx1[i]], o[X.sx2[i]], lower);
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const float2 a = X.lo[e] >= 0 ? o[X.lo[e] >= 0 ? X.lo[e] : 0] : rcv[X.lo[e] < 0 ? -1 - X.lo[e] : 0];
+        const float2 c = X.hi[e] >= 0 ? o[X.hi[e] >= 0 ? X.hi[e] : 0] : rcv[X.hi[e] < 0 ? -1 - X.hi[e] : 0];
+        v[e] = lower ? a : c;
+      }
+      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW, SYNC, XL>::run(v, lds, tw, t);
+    } else if constexpr (!LAST) {
       exchange_sync<SYNC, false>();
       if constexpr (T % PW == 0) {
         // (t + T e) / PW = t / PW + e T / PW
@@ -367,7 +478,7 @@ struct FftPass {
 #pragma unroll
         for (int e = 0; e < P; ++e) v[e] = lds[lpad<PW>(t + T * e)];
       }
-      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW, SYNC>::run(v, lds, tw, t);
+      FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW, SYNC, XL>::run(v, lds, tw, t);
     }
   }
 };
@@ -555,12 +666,13 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[P], float2* lds, const float2
 
 // The same transform with the exchange synchronisation SYNC (see SYNC_WG):
 // wave-local exchanges where the T = L/P threads of a transform share one
-// wavefront.  Threads of one transform must be consecutive and T-aligned
-// (transform slot c = threadIdx.x / T), as in every caller.
+// wavefront, and the cross-lane exchange of XlTab where it applies.  Threads
+// of one transform must be consecutive and T-aligned (transform slot
+// c = threadIdx.x / T, t = threadIdx.x mod T), as in every caller.
 template <int L, int P, bool INV, int SYNC, int PW = PAD>
 __device__ __forceinline__ void fft_wv(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
   static_assert(sched_ok(L, P), "unsupported (L, P)");
-  FftPass<L, P, INV, 0, 1, 0, PW, eff_sync<L / P, SYNC>()>::run(v, lds, tw, t);
+  FftPass<L, P, INV, 0, 1, 0, PW, eff_sync<L / P, SYNC>(), true>::run(v, lds, tw, t);
 }
 
 }  // namespace pc
