@@ -114,13 +114,35 @@ constexpr int row_pairs_per_block(int L2) {
   return g;
 }
 
+// Per-row-pair LDS region of the row-forward pass: the transform's buffer,
+// padded so that consecutive regions start 32 / G four-byte banks apart (of
+// 32): the 8-byte reads of one column's G row pairs, 16 lanes per pass,
+// then hit distinct banks.
+template <int L2, int G>
+constexpr int row_slot_len() {
+  constexpr int len = lds_len<L2>(), want = (16 / G) % 16;
+  return len + (want - len % 16 + 16) % 16;
+}
+
+// Orders the accesses of one transform slot to its own LDS region: a
+// wavefront barrier when the slot's T threads lie in one wavefront (whose
+// LDS operations complete in program order), else a workgroup barrier.
+template <int T>
+__device__ __forceinline__ void slot_sync() {
+  if constexpr (T <= 64 && 64 % T == 0)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
 // Row pairs per workgroup of the small-tile variant.
 constexpr int row_pairs_small(int L2) { return row_pairs_per_block(L2) < 2 ? row_pairs_per_block(L2) : 2; }
 
 // Half-spectra of windowed rows, transposed: sout[q][img][f2][n1], f2 < H2.
 // The body of a row-forward block bm (G row pairs, G * T threads), with the
-// workgroup's LDS (G * lds_len<L2>() entries) and the staged twiddles; the
-// per-length kernel and the persistent batch kernel both run it.
+// workgroup's LDS (G * row_slot_len<L2, G>() entries) and the staged
+// twiddles; the per-length kernel and the persistent batch kernel both run
+// it.
 template <int L2, int G>
 __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, const BlockRef bm,
                                               const float* __restrict__ x_arg, float2* __restrict__ lds,
@@ -209,50 +231,39 @@ __device__ __forceinline__ void rows_fwd_body(const RowJob* __restrict__ jobs, c
       v[e] = make_float2(in && la ? xa[e] : 0.f, in && lb ? xb[e] : 0.f);
     }
   }
-  float2* my = lds + c * lds_len<L2>();
+  constexpr int SL = row_slot_len<L2, G>();
+  float2* my = lds + c * SL;
   ts.commit(twl, tid);
   fft_wv<L2, P, false, SYNC_WAVE>(v, my, twl, t);
-  __syncthreads();
+  // the packed spectrum C of the slot's two rows into its own region (the
+  // transform's last reads of it were this slot's own)
+  slot_sync<T>();
 #pragma unroll
   for (int e = 0; e < P; ++e) my[lpad(t + T * e)] = v[e];
   __syncthreads();
-  // separate the two rows: U_a = (C[f] + conj C[-f]) / 2, U_b = (C[f] - conj C[-f]) / (2 i)
-  float2 ua[P], ub[P];
-#pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int f = t + T * e;
-    const float2 cf = my[lpad(f)];
-    const float2 cm = my[lpad(f == 0 ? 0 : L2 - f)];
-    ua[e] = make_float2(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y));
-    ub[e] = make_float2(0.5f * (cf.y + cm.y), -0.5f * (cf.x - cm.x));
-  }
-  __syncthreads();
-  // transpose through LDS: column f's row pair c (swizzled, tile_pos)
-  float4* tl = reinterpret_cast<float4*>(lds);
-#pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int f = t + T * e;
-    if (f < H2) tl[tile_pos<G>(f, c)] = make_float4(ua[e].x, ua[e].y, ub[e].x, ub[e].y);
-  }
-  __syncthreads();
-  // the tile's LDS reads first, then its 16-byte stores (a read-store loop
-  // waited for each read in turn); position ch holds column ch / G's row
-  // pair (ch mod G) ^ tile_swz(column)
+  // transposed output in 16-byte chunks: chunk ch is column f = ch / G of
+  // row pair rc = ch mod G, separated from that pair's C as
+  // U_a = (C[f] + conj C[-f]) / 2, U_b = (C[f] - conj C[-f]) / (2 i);
+  // every LDS read first, then the stores (a read-store loop waited for each
+  // read in turn)
   constexpr int CH = H2 * G, PT = (CH + NT - 1) / NT;
   float4 sv[PT];
 #pragma unroll
   for (int i = 0; i < PT; ++i) {
     const int ch = tid + i * NT;
-    if (ch < CH) sv[i] = tl[ch];
+    if (ch < CH) {
+      const int f = ch / G;
+      const float2* m = lds + (ch % G) * SL;
+      const float2 cf = m[lpad(f)];
+      const float2 cm = m[lpad(f == 0 ? 0 : L2 - f)];
+      sv[i] = make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), -0.5f * (cf.x - cm.x));
+    }
   }
   float2* o = jb.sout + (int64_t)q * jb.q_stride + img * ((int64_t)H2 * N1) + r0;
 #pragma unroll
   for (int i = 0; i < PT; ++i) {
     const int ch = tid + i * NT;
-    if (ch < CH) {
-      const int f = ch / G, rc = (ch % G) ^ tile_swz<G>(f);
-      gst2(o, (int64_t)f * N1 + 2 * rc, sv[i]);
-    }
+    if (ch < CH) gst2(o, (int64_t)(ch / G) * N1 + 2 * (ch % G), sv[i]);
   }
 }
 
@@ -260,7 +271,8 @@ template <int L2, int G = row_pairs_per_block(L2)>
 __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_fwd(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float* __restrict__ x_arg,
     const float2* __restrict__ tw, int64_t img_limit) {
-  __shared__ __attribute__((aligned(16))) float2 lds[G * lds_len<L2>()];
+  static_assert((G * row_slot_len<L2, G>() + L2) * sizeof(float2) <= 160 * 1024, "row-forward LDS");
+  __shared__ __attribute__((aligned(16))) float2 lds[G * row_slot_len<L2, G>()];
   __shared__ float2 twl[L2];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
@@ -894,8 +906,10 @@ constexpr int prow_pairs() { return PERSIST_THREADS / fft_threads(L); }
 template <int KIND, int L>
 constexpr int plds_entries() {
   // transform buffers, twiddles and (row-inverse) the 2G row factors
-  return ((KIND == PK_ROWS_FWD || KIND == PK_ROWS_INV) ? prow_pairs<L>() : ffts_per_block(L)) * lds_len<L>() + L +
-         (KIND == PK_ROWS_INV ? prow_pairs<L>() : 0);
+  return (KIND == PK_ROWS_FWD   ? prow_pairs<L>() * row_slot_len<L, prow_pairs<L>()>()
+          : KIND == PK_ROWS_INV ? prow_pairs<L>() * lds_len<L>()
+                                : ffts_per_block(L) * lds_len<L>()) +
+         L + (KIND == PK_ROWS_INV ? prow_pairs<L>() : 0);
 }
 
 template <int KIND, int L>
