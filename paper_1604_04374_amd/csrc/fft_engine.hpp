@@ -270,8 +270,26 @@ template <int PW = PAD>
 __device__ __forceinline__ int lpad(int i) {
   return i + i / PW;  // PW is a power of two: a shift
 }
+// The exchange after a radix-12 pass of stride Ns = 4 (the second pass at
+// 12 points per thread) writes runs of 4 entries, 48 apart.  Under the pad
+// above, the runs of one 16-lane pass overlap in the banks (two-way
+// conflicts on every write).  That exchange instead skews by SKEW entries
+// per block of SKEW_BLOCK: the runs start 4 entries (8 banks) apart, and a
+// 16-aligned read of 16 consecutive entries stays in one block.
+constexpr int SKEW_BLOCK = 48, SKEW = 4;
+constexpr bool skew_reads_ok(int T, int P) {
+  for (int e = 0; e < P; ++e)
+    if ((T * e) % SKEW_BLOCK + T - 1 >= 2 * SKEW_BLOCK) return false;
+  return true;
+}
+
+// Entries of one transform's LDS buffer: the padded layout, or the skewed
+// one where it is longer (lengths at 12 points per thread).
 template <int L, int PW = PAD>
-constexpr int lds_len() { return L + L / PW; }
+constexpr int lds_len() {
+  constexpr int pad = L + L / PW, skew = L + SKEW * ((L - 1) / SKEW_BLOCK);
+  return (L % SKEW_BLOCK == 0 && L < 1536 && skew > pad) ? skew : pad;
+}
 
 // ---------------------------------------------------------------------------
 // Synchronisation of the LDS exchanges.  A transform carried by T threads
@@ -409,6 +427,10 @@ struct FftPass {
   static constexpr bool LAST = (S == sch.n - 1);
   // this pass feeds the last one across lanes
   static constexpr bool XLANE = XL && S == sch.n - 2 && Xl<L, P>::tab.ok;
+  // this pass's exchange uses the skewed layout (see SKEW_BLOCK)
+  static constexpr bool SKW = !LAST && !XLANE && R == 12 && Ns == 4;
+  static_assert(!SKW || L + SKEW * ((L - 1) / SKEW_BLOCK) <= lds_len<L, PW>(), "LDS room for the skewed exchange");
+  static_assert(!SKW || skew_reads_ok(T, P), "a skewed read of t + T e crosses one block boundary at most");
 
   __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
 #pragma unroll
@@ -437,7 +459,12 @@ struct FftPass {
         // The padded index is base + constant whenever the R outputs stay
         // inside one PW-entry row (Ns R divides PW; base is then a multiple
         // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of PW).
-        if constexpr (Ns % PW == 0) {
+        if constexpr (SKW) {
+          // the R outputs stay in block j / Ns of Ns R = SKEW_BLOCK entries
+          float2* dst = lds + base + SKEW * (j / Ns);
+#pragma unroll
+          for (int q = 0; q < R; ++q) dst[q * Ns] = x[q];
+        } else if constexpr (Ns % PW == 0) {
           float2* dst = lds + lpad<PW>(base);
 #pragma unroll
           for (int q = 0; q < R; ++q) dst[q * (Ns + Ns / PW)] = x[q];
@@ -469,7 +496,14 @@ struct FftPass {
       FftPass<L, P, INV, S + 1, Ns * R, TW + Ns * (R - 1), PW, SYNC, XL>::run(v, lds, tw, t);
     } else if constexpr (!LAST) {
       exchange_sync<SYNC, false>();
-      if constexpr (T % PW == 0) {
+      if constexpr (SKW) {
+        // lskew(t + T e) = t + T e + SKEW (T e / SKEW_BLOCK) + SKEW [t + T e mod SKEW_BLOCK >= SKEW_BLOCK]
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+          const int m = (T * e) % SKEW_BLOCK;
+          v[e] = lds[t + T * e + SKEW * ((T * e) / SKEW_BLOCK) + (t + m >= SKEW_BLOCK ? SKEW : 0)];
+        }
+      } else if constexpr (T % PW == 0) {
         // (t + T e) / PW = t / PW + e T / PW
         const float2* src = lds + lpad<PW>(t);
 #pragma unroll
