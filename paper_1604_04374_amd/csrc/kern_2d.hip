@@ -306,6 +306,109 @@ __device__ __forceinline__ void tile_to_lds(const float2* __restrict__ src, int 
   }
 }
 
+// One plane's tile (in LDS, tile_pos layout) of a row-inverse block:
+// inverse row transforms of the G row pairs, the window of plane q applied
+// and added to acc (thread t of slot c: row pair r, columns t + T e).
+template <int L2, int G>
+__device__ __forceinline__ void rows_inv_plane(const RowJob& jb, const int q, const int mode, const float* ws,
+                                               const int r, const float4* tl, float2* my, const float2* twl,
+                                               const int c, const int t, float2 (&acc)[points_per_thread(L2)]) {
+  constexpr int P = points_per_thread(L2), T = L2 / P, H2 = L2 / 2 + 1;
+  const int N1 = jb.N1;
+  float2 v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int f = t + T * e;
+    float2 a, b;
+    if (f < H2) {
+      const float4 ab = tl[tile_pos<G>(f, c)];
+      a = make_float2(ab.x, ab.y);
+      b = make_float2(ab.z, ab.w);
+      if (f == 0 || f == L2 / 2) {  // the inverse real transform ignores these imaginary parts
+        a.y = 0.f;
+        b.y = 0.f;
+      }
+    } else {
+      const float4 ab = tl[tile_pos<G>(L2 - f, c)];
+      a = make_float2(ab.x, -ab.y);
+      b = make_float2(ab.z, -ab.w);
+    }
+    v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
+  }
+  fft_wv<L2, P, true, SYNC_WAVE_ENTRY>(v, my, twl, opaque(t));
+  // one branch per window mode around straight-line loads
+  if (mode == RW_DENSE) {
+    const float* wp = ws + ((int64_t)q * N1 + r) * L2 + t;
+    float wa[P], wb[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      wa[e] = gldf(wp, T * e);
+      wb[e] = gldf(wp, L2 + T * e);
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      acc[e].x = fmaf(wa[e], v[e].x, acc[e].x);
+      acc[e].y = fmaf(wb[e], v[e].y, acc[e].y);
+    }
+  } else if (mode == RW_FACTOR) {
+    const float* wp = ws + (int64_t)q * L2 + t;
+    float w[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) w[e] = gldf(wp, T * e);
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      acc[e].x = fmaf(w[e], v[e].x, acc[e].x);
+      acc[e].y = fmaf(w[e], v[e].y, acc[e].y);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      acc[e].x += v[e].x;
+      acc[e].y += v[e].y;
+    }
+  }
+}
+
+// The block's rows r, r + 1 (sums acc of thread t), scaled, to the output.
+template <int L2>
+__device__ __forceinline__ void rows_inv_store(const RowJob& jb, float* __restrict__ yout, const int64_t img,
+                                               const int r, const int t, const float sa, const float sb,
+                                               const float2 (&acc)[points_per_thread(L2)]) {
+  constexpr int P = points_per_thread(L2), T = L2 / P;
+  if (jb.oN2 > 0) {
+    // section evaluation: the leading orows x ocols block goes straight to
+    // its place in the output image (both axes wrapped)
+    int ia = jb.o1 + r;
+    if (ia >= jb.oN1) ia -= jb.oN1;
+    const int ib = ia + 1 == jb.oN1 ? 0 : ia + 1;
+    float* oa = yout + (img * jb.oN1 + ia) * jb.oN2;
+    float* ob = yout + (img * jb.oN1 + ib) * jb.oN2;
+    const bool wa = r < jb.orows, wb = r + 1 < jb.orows;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int n2 = t + T * e;
+      int o = jb.o2 + n2;
+      if (o >= jb.oN2) o -= jb.oN2;
+      if (n2 < jb.ocols) {
+        if (wa) gstf(oa, o, acc[e].x * sa);
+        if (wb) gstf(ob, o, acc[e].y * sb);
+      }
+    }
+    return;
+  }
+  // columns n2 < ocols only (0: all)
+  const int sc = jb.ocols > 0 ? jb.ocols : L2;
+  float* oa = yout + (img * jb.N1 + r) * L2;
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    const int n2 = t + T * e;
+    if (n2 < sc) {
+      gstf(oa, n2, acc[e].x * sa);
+      gstf(oa, n2 + L2, acc[e].y * sb);
+    }
+  }
+}
+
 // Real rows from transposed half-spectra:
 // y[img][n1][n2] = scale * sum_{q < nq} w_q . rowIFFT(sin[q][img][:, n1]).
 // PIPE: plane q + 1's tile is loaded into registers while plane q is
@@ -374,92 +477,10 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
       tile_to_lds<L2, G>(src0 + (int64_t)q * jb.q_stride, N1, lds, opaque(tid));
       __syncthreads();
     }
-    float2 v[P];
-#pragma unroll
-    for (int e = 0; e < P; ++e) {
-      const int f = t + T * e;
-      float2 a, b;
-      if (f < H2) {
-        const float4 ab = tl[tile_pos<G>(f, c)];
-        a = make_float2(ab.x, ab.y);
-        b = make_float2(ab.z, ab.w);
-        if (f == 0 || f == L2 / 2) {  // the inverse real transform ignores these imaginary parts
-          a.y = 0.f;
-          b.y = 0.f;
-        }
-      } else {
-        const float4 ab = tl[tile_pos<G>(L2 - f, c)];
-        a = make_float2(ab.x, -ab.y);
-        b = make_float2(ab.z, -ab.w);
-      }
-      v[e] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
-    }
-    fft_wv<L2, P, true, SYNC_WAVE_ENTRY>(v, my, twl, opaque(t));
-    // one branch per window mode around straight-line loads
-    if (mode == RW_DENSE) {
-      const float* wp = ws + ((int64_t)q * N1 + r) * L2 + t;
-      float wa[P], wb[P];
-#pragma unroll
-      for (int e = 0; e < P; ++e) {
-        wa[e] = gldf(wp, T * e);
-        wb[e] = gldf(wp, L2 + T * e);
-      }
-#pragma unroll
-      for (int e = 0; e < P; ++e) {
-        acc[e].x = fmaf(wa[e], v[e].x, acc[e].x);
-        acc[e].y = fmaf(wb[e], v[e].y, acc[e].y);
-      }
-    } else if (mode == RW_FACTOR) {
-      const float* wp = ws + (int64_t)q * L2 + t;
-      float w[P];
-#pragma unroll
-      for (int e = 0; e < P; ++e) w[e] = gldf(wp, T * e);
-#pragma unroll
-      for (int e = 0; e < P; ++e) {
-        acc[e].x = fmaf(w[e], v[e].x, acc[e].x);
-        acc[e].y = fmaf(w[e], v[e].y, acc[e].y);
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < P; ++e) {
-        acc[e].x += v[e].x;
-        acc[e].y += v[e].y;
-      }
-    }
+    rows_inv_plane<L2, G>(jb, q, mode, ws, r, tl, my, twl, c, t, acc);
   }
   const float sa = box ? rfac[2 * c] * jb.scale : jb.scale, sb = box ? rfac[2 * c + 1] * jb.scale : jb.scale;
-  if (jb.oN2 > 0) {
-    // section evaluation: the leading orows x ocols block goes straight to
-    // its place in the output image (both axes wrapped)
-    int ia = jb.o1 + r;
-    if (ia >= jb.oN1) ia -= jb.oN1;
-    const int ib = ia + 1 == jb.oN1 ? 0 : ia + 1;
-    float* oa = yout + (img * jb.oN1 + ia) * jb.oN2;
-    float* ob = yout + (img * jb.oN1 + ib) * jb.oN2;
-    const bool wa = r < jb.orows, wb = r + 1 < jb.orows;
-#pragma unroll
-    for (int e = 0; e < P; ++e) {
-      const int n2 = t + T * e;
-      int o = jb.o2 + n2;
-      if (o >= jb.oN2) o -= jb.oN2;
-      if (n2 < jb.ocols) {
-        if (wa) gstf(oa, o, acc[e].x * sa);
-        if (wb) gstf(ob, o, acc[e].y * sb);
-      }
-    }
-    return;
-  }
-  // columns n2 < ocols only (0: all)
-  const int sc = jb.ocols > 0 ? jb.ocols : L2;
-  float* oa = yout + (img * N1 + r) * L2;
-#pragma unroll
-  for (int e = 0; e < P; ++e) {
-    const int n2 = t + T * e;
-    if (n2 < sc) {
-      gstf(oa, n2, acc[e].x * sa);
-      gstf(oa, n2 + L2, acc[e].y * sb);
-    }
-  }
+  rows_inv_store<L2>(jb, yout, img, r, t, sa, sb, acc);
 }
 
 template <int L2, int G, bool PIPE>
