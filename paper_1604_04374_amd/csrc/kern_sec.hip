@@ -31,7 +31,7 @@ __device__ __forceinline__ int xcd_major_tile(int x, int n) {
   const int q = n / SEC_XCDS;
   return x < q * SEC_XCDS ? (x % SEC_XCDS) * q + x / SEC_XCDS : x;
 }
-constexpr int SEC_THREADS = 256, SEC_ROWS_PER_THREAD = SEC_TILE_R * SEC_TILE_C / SEC_THREADS,
+constexpr int SEC_THREADS = 128, SEC_ROWS_PER_THREAD = SEC_TILE_R * SEC_TILE_C / SEC_THREADS,
               SEC_ROW_STEP = SEC_THREADS / SEC_TILE_C, SEC_GROUP = 4;
 __global__ __launch_bounds__(SEC_THREADS) void k_sec_scatter(
     const SecTerm* __restrict__ terms, const float* __restrict__ S, float* __restrict__ y_arg,
