@@ -6,9 +6,11 @@ on-device pipeline TVIR -> h_k -> plan -> H_m u.
 Tolerance.  Interpolation solves an m x m system per lag in float64 from
 float32 samples: rel-L2 <= 1e-6.  Projection contracts n positions in FP32
 on the matrix cores (chunks of 2048 added in float64), so the right-hand
-sides carry a relative error of about sqrt(2048) 2^-24 ~ 3e-6, amplified by
-at most the condition number of the windows' Gram matrix (~17 for cubic
-B-splines): rel-L2 <= 1e-5 * max(1, kappa / 10) with kappa computed here."""
+sides carry a relative error of about sqrt(2048) 2^-24 ~ 3e-6; the solve
+with the windows' Gram matrix (condition number ~18.5 for cubic B-splines)
+could amplify it by up to that factor, but the measured errors stay at
+3.6e-7 to 4.0e-6 over these cases, so the test holds projection to the
+same rel-L2 <= 1e-5 as the rest of the path (kappa is printed)."""
 import numpy as np
 import pytest
 
@@ -53,7 +55,7 @@ def test_projection_matches_oracle(n, m, deg):
     kappa = np.linalg.cond(G)
     err = rel_l2(h, ref)
     print(f"n={n} m={m}: rows {len(lags)}, rel {err:.2e}, Gram condition {kappa:.1f}", flush=True)
-    assert err <= 1e-5 * max(1.0, kappa / 10)
+    assert err <= 1e-5
     unlisted = np.setdiff1d(np.arange(n), lags)
     assert np.all(h[:, unlisted] == 0)
 
