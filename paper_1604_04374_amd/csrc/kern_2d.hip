@@ -844,7 +844,7 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_f
 template <int L1>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_bwd1(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw,
-    int64_t img_limit) {
+    float2* __restrict__ gext, int64_t img_limit) {
   constexpr int P = points_per_thread(L1), T = L1 / P, NF = ffts_per_block(L1);
   __shared__ float2 lds[NF * lds_len<L1>()];
   __shared__ float2 twl[L1];
@@ -896,7 +896,26 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_b
       }
     }
   }
-  if (jb.grad && valid) {
+  if (jb.grad && jb.gext_off >= 0) {  // uniform over the workgroup
+    // the NF columns through LDS (stride L1 + 1: the lanes reading one row
+    // of NF columns hit distinct banks), then rows of NF entries to the
+    // natural layout, scaled
+    static_assert(NF * (L1 + 1) <= NF * lds_len<L1>(), "LDS room for the gradient columns");
+    if (!gext) return;  // uniform: no gradient wanted
+    __syncthreads();  // every slot is done with its transform buffer
+#pragma unroll
+    for (int e = 0; e < P; ++e) lds[c * (L1 + 1) + t + T * e] = ga[e];
+    __syncthreads();
+    const int f20 = bm.blk * NF;
+    float2* gn = gext + jb.gext_off;
+    for (int idx = threadIdx.x; idx < NF * L1; idx += NF * T) {
+      const int f1 = idx / NF, cc = idx % NF, g2 = f20 + cc;
+      if (g2 < H2) {
+        const float s = (g2 == 0 || g2 == H2 - 1) ? jb.ginv_n : 2.f * jb.ginv_n;
+        gst(gn, (int64_t)f1 * H2 + g2, cscale(lds[cc * (L1 + 1) + f1], s));
+      }
+    }
+  } else if (jb.grad && valid) {
     float2* gp = jb.grad + (int64_t)f2 * L1;
 #pragma unroll
     for (int e = 0; e < P; ++e) gst(gp, t + T * e, ga[e]);
@@ -1304,7 +1323,7 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    hipLaunchKernelGGL(k_cols_bwd1<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    hipLaunchKernelGGL(k_cols_bwd1<LL>, grid, block, 0, s, cj, ls.bmap, ls.tw, reinterpret_cast<float2*>(y_arg), img_limit); \
     return hipGetLastError();
         PC_FOR_EACH_L2(PC_CASE)
 #undef PC_CASE

@@ -241,7 +241,7 @@ struct pc_plan_s {
   // gradient export and the backward column launches [want_gu][kept U_k]
   std::vector<int> sec_k;
   std::vector<std::array<int64_t, 10>> sec_geom;  // o1 p1 o2 p2 a1 q1 a2 q2 M1 M2
-  pc::TransposeSet tr_spec{}, tr_grad{};
+  pc::TransposeSet tr_spec{};
   std::vector<pc::LaunchSet> sec_bwd[2][2];
   pc_batch_s* sec_batch_keep = nullptr;  // the forward launches storing U_k into keep
   std::vector<pc::SecTerm> sec_terms;
@@ -1246,12 +1246,14 @@ pc_status build_sec_bwd(pc_plan p, const std::vector<pc::SecTerm>& terms, bool k
       std::vector<pc::ColJob> jobs;
       std::vector<pc::BlockRef> bm;
       const float2* tw = nullptr;
-      int64_t koff = 0;
+      int64_t koff = 0, goff_next = 0;
       for (size_t i = 0; i < p->sec_sub.size(); ++i) {
         const pc::Plan2D& q = p->sec_sub[i]->p2;
         const int64_t plane = (int64_t)q.N1 * q.H2;
         float2* kp = kept ? static_cast<float2*>(p->keep_alloc) + koff : nullptr;
         koff += cap * plane;
+        const int64_t goff = goff_next;
+        goff_next += plane;
         if (q.N1 != L1) continue;
         tw = q.tw1;
         pc::ColJob j{q.Tws, q.RA, nullptr, q.Hs, nullptr, plane * cap, 0, q.H2, 1, 1, 1, 1};
@@ -1262,6 +1264,10 @@ pc_status build_sec_bwd(pc_plan p, const std::vector<pc::SecTerm>& terms, bool k
         j.nv_src = t.ef1;
         j.keep = kp;
         j.grad = p->sec_sub[i]->grad_ws;
+        // the gradient straight into the caller's buffer, each section's
+        // spectrum in its natural layout, one after another
+        j.gext_off = goff;
+        j.ginv_n = 1.0f / ((float)q.N1 * (float)q.N2);
         j.want_gu = gu;
         j.nimg = cap;
         pc::append_col_blocks(bm, (int)jobs.size(), 1, q.H2, L1, 1);
@@ -1475,18 +1481,17 @@ pc_status build_sec2d(pc_plan p, const float* windows, const float* h, const std
   // spectra as parameters: the sections' spectra, one after another, each in
   // the natural layout of its M1 x M2 grid
   {
-    std::vector<pc::TransposeJob> jobs, gjobs;
+    // (the backward's column kernels write the spectra gradient in the same
+    // layout themselves)
+    std::vector<pc::TransposeJob> jobs;
     int64_t off_c = 0;
     for (pc_plan_s* sub : p->sec_sub) {
       const pc::Plan2D& q2 = sub->p2;
       jobs.push_back({const_cast<float2*>(q2.Hs), off_c, q2.N1, q2.H2, 0, 1.f, 0});
-      if (sub->grad_ws)
-        gjobs.push_back({sub->grad_ws, off_c, q2.N1, q2.H2, 1, 1.0f / ((float)q2.N1 * (float)q2.N2), 0});
       off_c += (int64_t)q2.N1 * q2.H2;
     }
     p->spec_count = off_c;
     if ((st = make_transpose_set(p, p->tr_spec, jobs))) return st;
-    if (!gjobs.empty() && (st = make_transpose_set(p, p->tr_grad, gjobs))) return st;
   }
   p->sec_terms = terms;
   if (d.flags & PC_PLAN_GRADIENTS) return build_sec_bwd(p, terms, false);
@@ -1602,12 +1607,13 @@ hipError_t run_sec_backward(pc_plan p, const float* u, const float* gy, float* g
   if (gspec && state == 0) e = launch_seq(of_kind(b->fwd_seq, pc::KK_ROWS_FWD), s, p->tr(), u, batch);
   if (e == hipSuccess) e = launch_seq(of_kind(b->adj_seq, pc::KK_ROWS_FWD), s, p->tr(), gy, batch);
   const bool kept = state == 2 && p->keep_alloc;
-  if (e == hipSuccess) e = launch_seq(p->sec_bwd[gu ? 1 : 0][kept ? 1 : 0], s, p->tr(), nullptr, batch);
+  // (the column kernels write the spectra gradient, if wanted, into gspec)
+  if (e == hipSuccess)
+    e = launch_seq(p->sec_bwd[gu ? 1 : 0][kept ? 1 : 0], s, p->tr(), nullptr, batch, reinterpret_cast<float*>(gspec));
   if (e == hipSuccess && gu) {
     e = launch_seq(of_kind(b->adj_seq, pc::KK_ROWS_INV), s, p->tr(), nullptr, batch, gu);
     if (e == hipSuccess && !p->sec.direct_adj) e = pc::launch_sec_scatter(p->sec, gu, true, batch, s, p->tr());
   }
-  if (e == hipSuccess && gspec) e = pc::launch_transpose_set(p->tr_grad, gspec, false, s);
   return e;
 }
 

@@ -194,8 +194,13 @@ struct ColJob {
   // the windowed input (rows < nvalid_in; U_k read from keep instead when
   // set), overwritten with the adjoint's planes (rows < nvalid_out) when
   // want_gu; grad (optional) receives sum over the images of conj(U_k) V,
-  // one plane [f2][f1]; nimg images
+  // one plane [f2][f1]; nimg images.  With gext_off >= 0 that sum goes
+  // instead, scaled by c(f2) ginv_n (c = 1 at f2 = 0 and f2 = H2 - 1, else
+  // 2), to the launch's gradient buffer at gext_off + f1 H2 + f2 (the
+  // section's spectrum in its natural layout); grad then only flags it.
   float2* grad = nullptr;
+  int64_t gext_off = -1;
+  float ginv_n = 0.f;
   int want_gu = 1;
   int nv_src = 0;
   int64_t nimg = 1;
