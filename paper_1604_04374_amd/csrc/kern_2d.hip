@@ -741,8 +741,9 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_a
 // dst = a . colIFFT(conj(H) . colFFT(src)), a the row factor of a separable
 // window (none for dense windows), rows n1 < nvalid_in read and
 // n1 < nvalid_out written.  The spectrum column is loaded after the first
-// transform.
-template <int L1, bool ADJ>
+// transform.  KEEP (forward): the transformed windowed column U is also
+// stored at keep[img][f2][:] for the backward pass.
+template <int L1, bool ADJ, bool KEEP = false>
 __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_1term(
     const ColJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, const float2* __restrict__ tw,
     int64_t img_limit) {
@@ -777,6 +778,11 @@ __global__ __launch_bounds__(ffts_per_block(L1) * fft_threads(L1)) void k_cols_1
   float2* my = lds + c * lds_len<L1>();
   ts.commit(twl, tid);
   fft_wv<L1, P, false, SYNC_WAVE>(v, my, twl, opaque(t));
+  if (KEEP && valid) {
+    float2* kp = jb.keep + coff;
+#pragma unroll
+    for (int e = 0; e < P; ++e) gst(kp, t + T * e, v[e]);
+  }
   const float2* Hk = jb.Hs + (int64_t)f2 * L1;
 #pragma unroll
   for (int e = 0; e < P; ++e) v[e] = ADJ ? cmulc(v[e], gld(Hk, t + T * e)) : cmul(gld(Hk, t + T * e), v[e]);
@@ -1279,7 +1285,9 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
       switch (ls.L) {
 #define PC_CASE(LL) \
   case LL:          \
-    if (ls.one)                \
+    if (ls.one && ls.keep)     \
+      hipLaunchKernelGGL((k_cols_1term<LL, false, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
+    else if (ls.one)           \
       hipLaunchKernelGGL((k_cols_1term<LL, false>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \
     else if (ls.keep && ls.late)    \
       hipLaunchKernelGGL((k_cols_fwd<LL, true, true>), grid, block, 0, s, cj, ls.bmap, ls.tw, img_limit); \

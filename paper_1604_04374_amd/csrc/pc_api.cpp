@@ -531,15 +531,14 @@ pc_status build_large1d(pc_plan p, int L, int R, const float* windows, const flo
 }
 
 // Whether a column launch can take the single-term kernel: every job one
-// term in one group, keeping nothing (forward) or transforming its own input
-// (adjoint).
+// term in one group, and (adjoint) transforming its own input; a forward
+// launch that keeps U_k takes its KEEP variant.
 template <class J>
 bool single_term_cols(int kind, const std::vector<J>& jobs) {
   if constexpr (std::is_same<J, pc::ColJob>::value) {
     if (kind != pc::KK_COLS_FWD && kind != pc::KK_COLS_ADJ) return false;
     for (const pc::ColJob& j : jobs) {
       if (j.m1 * j.m2 != 1 || j.ngroups != 1) return false;
-      if (kind == pc::KK_COLS_FWD && j.keep) return false;
       if (kind == pc::KK_COLS_ADJ && !j.fft_src) return false;
     }
     return !jobs.empty();
