@@ -268,7 +268,9 @@ constexpr int PAD = PC_LDS_PAD;
 static_assert(PAD == 16 || PAD == 32, "pad period 16 or 32");
 template <int PW = PAD>
 __device__ __forceinline__ int lpad(int i) {
-  return i + i / PW;  // PW is a power of two: a shift
+  // i >= 0: unsigned division by the power of two PW is one shift (a signed
+  // one needs a sign fix-up)
+  return i + (int)((unsigned)i / PW);
 }
 // The exchange after a radix-12 pass of stride Ns = 4 (the second pass at
 // 12 points per thread) writes runs of 4 entries, 48 apart.  Under the pad
@@ -435,8 +437,9 @@ struct FftPass {
   __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds, const float2* __restrict__ tw, int t) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int j = t + T * b;
-      const int k = j % Ns;
+      // unsigned: j / Ns and j % Ns by constants without sign fix-ups
+      const unsigned j = (unsigned)t + T * b;
+      const int k = (int)(j % Ns);
       float2 x[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) x[q] = v[b + q * B];
@@ -455,13 +458,13 @@ struct FftPass {
         for (int q = 0; q < R; ++q) v[b + q * B] = x[q];
       } else {
         if (b == 0) exchange_sync<SYNC, S == 0>();  // previous readers of this LDS region are done
-        const int base = (j / Ns) * Ns * R + k;
+        const int base = (int)(j / Ns) * Ns * R + k;
         // The padded index is base + constant whenever the R outputs stay
         // inside one PW-entry row (Ns R divides PW; base is then a multiple
         // of Ns R plus k < Ns) or step by whole rows (Ns a multiple of PW).
         if constexpr (SKW) {
           // the R outputs stay in block j / Ns of Ns R = SKEW_BLOCK entries
-          float2* dst = lds + base + SKEW * (j / Ns);
+          float2* dst = lds + base + SKEW * (int)(j / Ns);
 #pragma unroll
           for (int q = 0; q < R; ++q) dst[q * Ns] = x[q];
         } else if constexpr (Ns % PW == 0) {
@@ -573,6 +576,9 @@ struct FftPassReg {
   __device__ __forceinline__ static void run(float2 (&v)[P], float2* lds0, float2* lds1, const float2 (&twr)[NTW],
                                              int t) {
     // exchange S goes through lds0 (S even) or lds1 (S odd, ping-pong only)
+    // (signed index arithmetic here: the unsigned form of FftPass took the
+    // 4096-point four-step forward kernel from 251 to 256 VGPRs, one wave
+    // per SIMD instead of two)
     float2* lds = (PP && (S & 1)) ? lds1 : lds0;
 #pragma unroll
     for (int b = 0; b < B; ++b) {

@@ -299,8 +299,10 @@ __device__ __forceinline__ void tile_to_lds(const float2* __restrict__ src, int 
     const int ch = c0 + lane;
     if (ch < CH) {
       // LDS position ch holds column f's row pair (ch mod G) ^ tile_swz(f)
-      const int f = ch / G, r = 2 * ((ch % G) ^ tile_swz<G>(f));
-      __builtin_amdgcn_global_load_lds((const PC_GLOBAL void*)(src + (int64_t)f * N1 + r),
+      // (ch >= 0 and the offset within the plane below 2^32: unsigned
+      // 32-bit arithmetic)
+      const unsigned f = (unsigned)ch / G, r = 2 * (((unsigned)ch % G) ^ tile_swz<G>((int)f));
+      __builtin_amdgcn_global_load_lds((const PC_GLOBAL void*)(src + (f * (unsigned)N1 + r)),
                                        (__attribute__((address_space(3))) void*)(lds + 2 * c0), 16, 0, 0);
     }
   }
