@@ -530,7 +530,9 @@ enum {
   PC_TUNE_COL_GROUPS = 6,         /* full-grid forward column pass: term groups */
   PC_TUNE_FOURSTEP_L = 7,         /* 1D four-step: inner transform length */
   PC_TUNE_BATCH_PERSISTENT = 8,   /* batches: persistent passes (length 0) */
-  PC_TUNE_SEC_STREAMS = 9         /* sectioned plans: two launch chains, on two streams (length 0) */
+  PC_TUNE_SEC_STREAMS = 9,        /* sectioned plans: two launch chains, on two streams (length 0) */
+  PC_TUNE_KEEP = 10               /* plans with gradients: keep the windowed spectra within the budget (1, the
+                                     rule) or recompute them in every backward (0) (length 0) */
 };
 typedef struct {
   uint64_t key;

@@ -85,7 +85,8 @@ class TuneEntry(ctypes.Structure):
 
 # knob names of the tuning table (include/pc.h PC_TUNE_*)
 TUNE_KNOBS = {"cols_fwd_late": 1, "cols_adj_prefetch": 2, "rows_inv_pipe": 3, "rows_fwd_small": 4,
-              "rows_inv_small": 5, "col_groups": 6, "fourstep_l": 7, "batch_persistent": 8, "sec_streams": 9}
+              "rows_inv_small": 5, "col_groups": 6, "fourstep_l": 7, "batch_persistent": 8, "sec_streams": 9,
+              "keep": 10}
 TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
 

@@ -1516,7 +1516,9 @@ int64_t keep_size(pc_plan p) {
 pc_status set_keep(pc_plan p, int64_t budget) {
   p->budget = budget;
   const int64_t need = keep_size(p);
-  const bool want = need > 0 && need <= budget;
+  // the budget bounds what is kept; the tuning table may prefer recomputing
+  // even within it (keeping writes U_k in every forward and reads it back)
+  const bool want = need > 0 && need <= budget && pc::tune_get(p->tune_key, PC_TUNE_KEEP, 0, 1) != 0;
   if (p->saved_state > 1) p->saved_state = 1;
   if (want == (p->keep_alloc != nullptr)) return PC_SUCCESS;
   if (!want) {
@@ -2063,7 +2065,7 @@ pc_status pc_tune_set(const pc_tune_entry* entries, int32_t count) {
   std::vector<pc::TuneEntry> t;
   for (int32_t i = 0; i < count; ++i) {
     const pc_tune_entry& e = entries[i];
-    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_SEC_STREAMS)
+    if (e.knob < PC_TUNE_COLS_FWD_LATE || e.knob > PC_TUNE_KEEP)
       return fail(PC_ERROR_INVALID_VALUE, "unknown knob " + std::to_string(e.knob) + " in entry " + std::to_string(i));
     t.push_back({e.key, e.knob, e.length, e.value});
   }

@@ -114,6 +114,8 @@ class Workload:
             out += [(k, L, KNOB_VALUES[k]) for k in ("rows_fwd_small", "rows_inv_small", "rows_inv_pipe")]
         if self.name == "c4":
             out += [("batch_persistent", 0, (0, 1))]
+        if self.name == "c5ad":
+            out += [("keep", 0, (0, 1))]
         if self.name == "c3":
             pl = self.plans[0]
             nq = pl.desc.m_cols if pl.desc.w_format == 1 else pl.desc.m

@@ -3,6 +3,8 @@ sectioned and full-grid 2D paths, the sections' spectra as parameters, and
 the kept-or-recomputed windowed spectra (the plan's budget), against the FP64
 oracle (the sectioned operator as a function of section spectra is pinned in
 test_oracle_sections.py)."""
+import os
+
 import numpy as np
 import pytest
 import scipy.fft as sfft
@@ -99,6 +101,41 @@ def test_sectioned_backward_matches_oracle(idx, mode):
     err = max(rel_l2(a, b) for a, b in zip(_split(gs, secs), ref))
     print(f"{p.name} ({mode}): section spectra gradient rel {err:.2e}", flush=True)
     assert err <= TOL
+
+
+def test_tuning_table_can_choose_recomputing():
+    # a table entry "keep" = 0 makes a gradient plan recompute the windowed
+    # spectra in the backward although they fit its budget; results unchanged
+    import torch
+    import paper_1604_04374_amd as pcm
+    p = _problems()[0]
+    print(f"[gpu] keep = 0 through the tuning table {p.name}", flush=True)
+    rng = np.random.default_rng(71)
+    gy = rng.standard_normal(p.u.shape).astype(np.float32)
+    u = torch.from_numpy(p.u).cuda()
+    with pcm.Plan(plan_args(p), p.h, batch=p.batch, gradients=True) as plan:
+        key = pcm.tune_key(plan.desc)
+        assert plan.info()["keep_bytes"] > 0
+    try:
+        pcm.tune_set([(key, pcm.TUNE_KNOBS["keep"], 0, 0)])
+        with pcm.Plan(plan_args(p), p.h, batch=p.batch, gradients=True) as plan:
+            assert plan.info()["keep_bytes"] == 0
+            secs = _secs(plan)
+            plan.apply_save(u)
+            gu, gs = plan.backward(u, torch.from_numpy(gy).cuda(), use_saved=True)
+            torch.cuda.synchronize()
+            gu, gs = gu.cpu().numpy(), gs.cpu().numpy()
+    finally:
+        path = pcm.tuning_table_path(pcm._device_arch())
+        if path and os.path.exists(path):
+            pcm.load_tuning(path)
+        else:
+            pcm.tune_set([])
+    w = p.dense_windows()
+    uu, g64 = p.u.astype(np.float64), gy.astype(np.float64)
+    assert max(rel_l2(a, b) for a, b in zip(gu, ex.adjoint_fft(g64, w, p.h.astype(np.float64)))) <= TOL
+    ref = sc.grad_section_spectra(uu, g64, w, secs)
+    assert max(rel_l2(a, b) for a, b in zip(_split(gs, secs), ref)) <= TOL
 
 
 def test_section_spectra_are_the_parameters():
@@ -211,19 +248,34 @@ def test_sectioned_autograd_finite_differences(idx):
 
 
 @pytest.mark.slow
-def test_c5_autograd_sectioned_full_size():
+@pytest.mark.parametrize("keep", [1, 0])
+def test_c5_autograd_sectioned_full_size(keep):
     # the autograd workload at its stated size: 2048^2, 64 tile windows,
     # model PSFs, loss 0.5 ||H u - f||^2; gradients with respect to u and to
-    # the 64 sections' spectra, against the oracle
+    # the 64 sections' spectra, against the oracle, with the windowed
+    # spectra kept (keep = 1) or recomputed (keep = 0; the tuning table's
+    # entry chooses it for the plan)
     import torch
+    import paper_1604_04374_amd as pcm
     from paper_1604_04374_amd.autograd import ExpansionOperator
     p = wl.config_c5()
     w = p.dense_windows()
-    print("[gpu] c5 autograd (sections): oracle observation", flush=True)
+    print(f"[gpu] c5 autograd (sections, keep {keep}): oracle observation", flush=True)
     f = (ex.apply_fft(p.extra["u_true"].astype(np.float64), w, p.h.astype(np.float64))
          + 0.01 * p.extra["noise"]).astype(np.float32)
     op = ExpansionOperator(plan_args(p), p.extra["h_model"], batch=1)
-    assert op.plan.info()["path"] == 3 and op.plan.info()["keep_bytes"] > 0
+    key = pcm.tune_key(op.plan.desc)
+    del op
+    try:
+        pcm.tune_set([(key, pcm.TUNE_KNOBS["keep"], 0, keep)])
+        op = ExpansionOperator(plan_args(p), p.extra["h_model"], batch=1)
+    finally:
+        path = pcm.tuning_table_path(pcm._device_arch())
+        if path and os.path.exists(path):
+            pcm.load_tuning(path)
+        else:
+            pcm.tune_set([])
+    assert op.plan.info()["path"] == 3 and (op.plan.info()["keep_bytes"] > 0) == (keep == 1)
     secs = _secs(op.plan)
     u = torch.from_numpy(p.u).cuda().requires_grad_(True)
     y = op(u)

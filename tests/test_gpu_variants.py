@@ -143,8 +143,8 @@ def test_every_tuning_table_entry_matches_oracle():
                 ry, rx = oracle_fft(p)
                 assert per_instance_rel(y, ry) <= TOL and per_instance_rel(x, rx) <= TOL, (knob, L, vv)
             continue
-        if knob in ("batch_persistent", "sec_streams"):
-            continue  # whole-launch choices, covered by the batch and section tests
+        if knob in ("batch_persistent", "sec_streams", "keep"):
+            continue  # whole-launch choices, covered by the batch, section and backward tests
         if knob == "col_groups":
             p = wl.small_2d(L, 128, 2, 8, 1, seed=721, kind="hat")
             choices = sorted({v, 1, 2, 8})
