@@ -898,6 +898,30 @@ struct GatherSpec {
   bool direct_adj = false;
 };
 
+// Block order for the XCDs.  Workgroup p of a launch runs on XCD p mod 8
+// (workgroups are dealt to the 8 XCDs round-robin, each with its own L2).
+// Blocks whose band key (band[i], one per block) is equal read the same
+// lines; they are placed at positions of one residue mod 8, so that those
+// lines are fetched into one L2 instead of several.  Every launch of the
+// list still covers every block once, in an order that only the scheduling
+// sees.
+void xcd_group_blocks(std::vector<pc::BlockRef>& bm, const std::vector<int64_t>& band) {
+  constexpr size_t X = 8;
+  const size_t n = bm.size();
+  std::vector<std::vector<size_t>> q(X);
+  for (size_t i = 0; i < n; ++i) q[(size_t)(band[i] % (int64_t)X)].push_back(i);
+  std::vector<pc::BlockRef> out;
+  out.reserve(n);
+  std::vector<size_t> head(X, 0);
+  for (size_t p = 0; p < n; ++p) {
+    size_t x = p % X;
+    // the XCD's own blocks, else the next XCD's that has blocks left
+    for (size_t k = 0; k < X && head[x] >= q[x].size(); ++k) x = (x + 1) % X;
+    out.push_back(bm[q[x][head[x]++]]);
+  }
+  bm.swap(out);
+}
+
 // Fixed pointers (in, fo, fa: the sections of a sectioned plan) or, with
 // in == nullptr, the entries of the batch's device table b->dtab.
 pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, float* const* fa,
@@ -1042,6 +1066,19 @@ pc_status build_batch(pc_batch b, const float* const* in, float* const* fo, floa
         return st;
       if ((st = batch_set(b, bl.f_rows_out, pc::KK_ROWS_INV, L2, jfo, bfo, tw, true, si, prow, pc::PK_ROWS_INV)))
         return st;
+      if (gather && !prow && !ba.empty()) {
+        // the sections' output boxes overlap: the adjoint's row-forward
+        // blocks over the same image rows (same band of the row-block
+        // height from the box origin) share their lines
+        const int br = pc::row_block_rows(L2, sf);
+        std::vector<int64_t> band(ba.size());
+        for (size_t k = 0; k < ba.size(); ++k) {
+          const pc::RowJob& j = ja[(size_t)ba[k].job];
+          const int64_t r = ((int64_t)j.g1 + (int64_t)ba[k].blk * br) % (j.gN1 > 0 ? j.gN1 : 1);
+          band[k] = (int64_t)ba[k].img * 1000003 + r / br;
+        }
+        xcd_group_blocks(ba, band);
+      }
       if ((st = batch_set(b, bl.a_rows_in, pc::KK_ROWS_FWD, L2, ja, ba, tw, true, sf, prow, pc::PK_ROWS_FWD)))
         return st;
       if ((st = batch_set(b, bl.a_rows_out, pc::KK_ROWS_INV, L2, jao, bao, tw, true, si, prow, pc::PK_ROWS_INV)))
