@@ -415,8 +415,10 @@ __device__ __forceinline__ void rows_inv_store(const RowJob& jb, float* __restri
 // y[img][n1][n2] = scale * sum_{q < nq} w_q . rowIFFT(sin[q][img][:, n1]).
 // PIPE: plane q + 1's tile is loaded into registers while plane q is
 // transformed (latency hidden inside the workgroup, for a tile's share of
-// registers per thread; see rows_inv_pipe for when that pays).
-template <int L2, int G, bool PIPE>
+// registers per thread; see rows_inv_pipe for when that pays).  ONE: every
+// job of the launch has one plane (nq = 1), so no sum is carried across a
+// transform (fewer registers, one more wave per SIMD at 384 points).
+template <int L2, int G, bool PIPE, bool ONE = false>
 __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, const BlockRef bm,
                                               float* __restrict__ y_arg, float2* __restrict__ lds,
                                               float2* __restrict__ twl, const float2* __restrict__ tw,
@@ -458,7 +460,8 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
   const bool box = jb.mode == RW_BOX;
   if (box && tid < 2 * G) rfac[tid] = gldf(jb.wsrc, r0 + tid);
   ts.commit(twl, tid);
-  for (int q = 0; q < jb.nq; ++q) {
+  const int nq = ONE ? 1 : jb.nq;
+  for (int q = 0; q < nq; ++q) {
     __syncthreads();  // the previous transform is done with LDS
     if constexpr (PIPE) {
 #pragma unroll
@@ -467,7 +470,7 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
         if (ch < CH) tl[ch] = nxt[i];
       }
       __syncthreads();
-      if (q + 1 < jb.nq) {
+      if (q + 1 < nq) {
         const float2* src = src0 + (int64_t)(q + 1) * jb.q_stride;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -485,7 +488,7 @@ __device__ __forceinline__ void rows_inv_body(const RowJob* __restrict__ jobs, c
   rows_inv_store<L2>(jb, yout, img, r, t, sa, sb, acc);
 }
 
-template <int L2, int G, bool PIPE>
+template <int L2, int G, bool PIPE, bool ONE = false>
 __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
     const RowJob* __restrict__ jobs, const BlockRef* __restrict__ bmap, float* __restrict__ y_arg,
     const float2* __restrict__ tw, int64_t img_limit) {
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(G * fft_threads(L2)) void k_rows_inv(
   __shared__ float rfac[2 * G];
   const BlockRef bm = bmap[blockIdx.x];
   if (bm.img >= img_limit) return;  // uniform over the workgroup
-  rows_inv_body<L2, G, PIPE>(jobs, bm, y_arg, lds, twl, tw, rfac, threadIdx.x);
+  rows_inv_body<L2, G, PIPE, ONE>(jobs, bm, y_arg, lds, twl, tw, rfac, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1272,10 +1275,14 @@ LaunchStatus launch_set(const LaunchSet& ls, int64_t nblocks, const float* x_arg
   case LL:          \
     if (ls.small_rows && ls.pipe)  \
       hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
+    else if (ls.small_rows && ls.one_plane)  \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), false, true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     else if (ls.small_rows)  \
       hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_small(LL), false>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     else if (ls.pipe)  \
       hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
+    else if (ls.one_plane)  \
+      hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), false, true>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     else  \
       hipLaunchKernelGGL((k_rows_inv<LL, row_pairs_per_block(LL), false>), grid, block, 0, s, rj, ls.bmap, y_arg, ls.tw, img_limit); \
     return hipGetLastError();

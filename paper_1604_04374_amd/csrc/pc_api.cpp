@@ -546,6 +546,15 @@ bool single_term_cols(int kind, const std::vector<J>& jobs) {
   return false;
 }
 
+// Most planes a row-inverse job of the list sums (0 for other jobs).
+template <class J>
+int max_planes(const std::vector<J>& jobs) {
+  int n = 0;
+  if constexpr (std::is_same<J, pc::RowJob>::value)
+    for (const pc::RowJob& j : jobs) n = std::max(n, j.nq);
+  return n;
+}
+
 template <class J>
 pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vector<J>& jobs,
                    const std::vector<pc::BlockRef>& bm, int64_t per_img, const float2* tw, hipStream_t s,
@@ -565,6 +574,7 @@ pc_status make_set(pc_plan p, pc::LaunchSet& ls, int kind, int L, const std::vec
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::tune_get(key, PC_TUNE_COLS_ADJ_PREFETCH, L, pc::cols_adj_prefetch(L));
   ls.pipe = kind == pc::KK_ROWS_INV && pc::tune_get(key, PC_TUNE_ROWS_INV_PIPE, L, pc::rows_inv_pipe(L, ls.small_rows));
   ls.one = single_term_cols(kind, jobs);
+  ls.one_plane = kind == pc::KK_ROWS_INV && max_planes(jobs) == 1;
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();
@@ -846,6 +856,7 @@ pc_status batch_set(pc_batch b, std::vector<pc::LaunchSet>& seq, int kind, int L
   ls.prefetch = kind == pc::KK_COLS_ADJ && pc::tune_get(key, PC_TUNE_COLS_ADJ_PREFETCH, L, pc::cols_adj_prefetch(L));
   ls.pipe = kind == pc::KK_ROWS_INV && pc::tune_get(key, PC_TUNE_ROWS_INV_PIPE, L, pc::rows_inv_pipe(L, ls.small_rows));
   ls.one = single_term_cols(kind, jobs);
+  ls.one_plane = kind == pc::KK_ROWS_INV && max_planes(jobs) == 1;
   ls.jobs = dj;
   ls.bmap = db;
   ls.blocks = (int64_t)bm.size();

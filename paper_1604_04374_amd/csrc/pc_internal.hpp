@@ -252,6 +252,7 @@ struct LaunchSet {
   bool late = false;               // forward column kernel: the late-spectrum variant (cols_fwd_late)
   bool prefetch = false;           // adjoint column kernel: the prefetching variant (cols_adj_prefetch)
   bool pipe = false;               // row-inverse kernel: the pipelined variant (rows_inv_pipe)
+  bool one_plane = false;          // row-inverse kernel: every job sums one plane (its ONE variant)
   bool keep = false;               // forward column kernel: the variant storing U_k (jobs' keep pointers)
   bool one = false;                // column kernels: every job single-term (k_cols_1term)
   // persistent pass (persist >= 0: a PersistKind) of length group pgroup:
